@@ -1,0 +1,415 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test ties an oracle function to something other than itself: exact
+rational solutions (golden fixtures), closed forms, brute force on tiny
+inputs, library routines solving a *different* formulation (the augmented
+system K2 instead of the condensed K1), and the invariants the paper
+states.  A plausible mistake in the oracle (a dropped term, a sign, a
+transposed operand) breaks at least one of them.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import dense as od
+from oracle import sparse as osp
+from paper_2405_14236_amd import workloads
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _f(v):
+    return np.array([float(Fraction(x)) for x in v])
+
+
+def _fm(rows):
+    return np.array([[float(Fraction(x)) for x in r] for r in rows])
+
+
+def rand_instance(rng, n, me, mi, wshift=1.0, sig=(-2, 2)):
+    A = rng.standard_normal((n, n))
+    W = A @ A.T / n + wshift * np.eye(n)
+    G = rng.standard_normal((me, n))
+    H = rng.standard_normal((mi, n))
+    sx = 10.0 ** rng.uniform(*sig, n)
+    sh = 10.0 ** rng.uniform(*sig, mi)
+    return W, G, H, sx, sh
+
+
+# ---------------------------------------------------------- golden (exact) --
+
+def test_golden_lifted_exact():
+    """Sec. 3.2 eq:liftedkkt: the condensed solve reproduces the exact K2 solution."""
+    g = json.load(open(os.path.join(GOLD, "tiny_lifted_k2.json")))
+    W, J, sx, Ds = _fm(g["W"]), _fm(g["J"]), _f(g["sigma_x"]), _f(g["Ds"])
+    r1, r2, r4 = _f(g["r1"]), _f(g["r2"]), _f(g["r4"])
+    b, _ = od.condensed_rhs(r1, r2, np.zeros(0), r4, J, Ds)
+    dx = od.solve_lifted(W, sx, J, Ds, b)
+    ds, dz = od.recover_slacks(dx, r2, r4, J, Ds)
+    ex_dx, ex_ds, ex_dz = _f(g["dx"]), _f(g["ds"]), _f(g["dz"])
+    # K is ill-conditioned (sigma up to 1e8): compare with a forward-error bound
+    assert np.allclose(dx, ex_dx, rtol=1e-7, atol=1e-9 * np.abs(ex_dx).max())
+    assert np.allclose(dz, ex_dz, rtol=1e-6, atol=1e-6 * np.abs(ex_dz).max())
+    assert np.allclose(ds, ex_ds, rtol=1e-6, atol=1e-8 * np.abs(ex_ds).max())
+
+
+def test_golden_hykkt_exact():
+    """Sec. 2.2 K1 and Sec. 3.1 eq:kkt:hykkt reproduce the exact K2 solution."""
+    g = json.load(open(os.path.join(GOLD, "tiny_hykkt_k2.json")))
+    W, G, H = _fm(g["W"]), _fm(g["G"]), _fm(g["H"])
+    sx, Ds = _f(g["sigma_x"]), _f(g["Ds"])
+    r1, r2, r3, r4 = _f(g["r1"]), _f(g["r2"]), _f(g["r3"]), _f(g["r4"])
+    r1b, r2b = od.condensed_rhs(r1, r2, r3, r4, H, Ds)
+    K = od.condensed_matrix(W, sx, H, Ds)
+    dx, dy = od.solve_k1(K, G, r1b, r2b)
+    assert np.allclose(dx, _f(g["dx"]), rtol=1e-10, atol=1e-12)
+    assert np.allclose(dy, _f(g["dy"]), rtol=1e-10, atol=1e-12)
+    for gamma in (1.0, 1e3, 1e6):
+        dxg, dyg = od.solve_hykkt_system(K, G, r1b, r2b, gamma)
+        assert np.allclose(dxg, _f(g["dx"]), rtol=1e-7, atol=1e-9)
+        assert np.allclose(dyg, _f(g["dy"]), rtol=1e-7, atol=1e-9)
+    ds, dz = od.recover_slacks(dx, r2, r4, H, Ds)
+    assert np.allclose(ds, _f(g["ds"]), rtol=1e-9, atol=1e-11)
+    assert np.allclose(dz, _f(g["dz"]), rtol=1e-9, atol=1e-11)
+
+
+# ------------------------------------------------------------ closed forms --
+
+def test_assembly_matches_bruteforce():
+    """K = W + diag(sx) + J^T diag(ss) J entry by entry (Sec. 2.2, K1)."""
+    rng = np.random.default_rng(1)
+    for n, m in [(5, 3), (9, 12), (17, 6)]:
+        W = rng.standard_normal((n, n)); W = W + W.T
+        J = rng.standard_normal((m, n)) * (rng.random((m, n)) < 0.4)
+        sx, ss = rng.random(n), 10.0 ** rng.uniform(-8, 8, m)
+        K1 = od.condensed_matrix(W, sx, J, ss)
+        K2 = od.assemble_bruteforce(W, sx, J, ss)
+        assert np.allclose(K1, K2, rtol=1e-13, atol=1e-13 * np.abs(K2).max())
+        assert np.array_equal(K1, K1.T) or np.allclose(K1, K1.T, rtol=1e-15, atol=0)
+
+
+def test_closed_form_no_constraints():
+    """J = 0 reduces K to W + diag(sigma_x)."""
+    rng = np.random.default_rng(2)
+    W, _, _, sx, _ = rand_instance(rng, 7, 0, 0)
+    K = od.condensed_matrix(W, sx, np.zeros((3, 7)), np.ones(3))
+    assert np.array_equal(K, W + np.diag(sx))
+
+
+def test_closed_form_identity():
+    """W = I, J = I: x_i = b_i / (1 + sx_i + ss_i)."""
+    rng = np.random.default_rng(3)
+    n = 11
+    sx, ss, b = rng.random(n), 10.0 ** rng.uniform(-8, 8, n), rng.standard_normal(n)
+    x = od.solve_lifted(np.eye(n), sx, np.eye(n), ss, b)
+    assert np.allclose(x, b / (1 + sx + ss), rtol=1e-14, atol=0)
+
+
+def test_closed_form_sherman_morrison():
+    """One constraint row h: K = K0 + s h h^T, solved by Sherman-Morrison."""
+    rng = np.random.default_rng(4)
+    n = 9
+    W, _, _, sx, _ = rand_instance(rng, n, 0, 0)
+    h = rng.standard_normal(n)
+    s = 37.0
+    b = rng.standard_normal(n)
+    K0 = W + np.diag(sx)
+    u = np.linalg.solve(K0, b)
+    v = np.linalg.solve(K0, h)
+    x_sm = u - v * (s * (h @ u)) / (1 + s * (h @ v))
+    x = od.solve_lifted(W, sx, h[None, :], np.array([s]), b)
+    assert np.allclose(x, x_sm, rtol=1e-12, atol=1e-13)
+
+
+def test_closed_form_block_diagonal():
+    """Diagonal W and rows with disjoint supports: K is block diagonal and each
+    block solves on its own."""
+    rng = np.random.default_rng(5)
+    n = 6
+    wd = rng.random(n) + 1
+    J = np.zeros((2, n)); J[0, :3] = rng.standard_normal(3); J[1, 3:] = rng.standard_normal(3)
+    ss, sx, b = np.array([2.0, 5.0]), rng.random(n), rng.standard_normal(n)
+    K = od.condensed_matrix(np.diag(wd), sx, J, ss)
+    assert np.all(K[:3, 3:] == 0) and np.all(K[3:, :3] == 0)
+    x = od.solve_lifted(np.diag(wd), sx, J, ss, b)
+    for blk, r in ((slice(0, 3), 0), (slice(3, 6), 1)):
+        Kb = np.diag(wd[blk] + sx[blk]) + ss[r] * np.outer(J[r, blk], J[r, blk])
+        assert np.allclose(x[blk], np.linalg.solve(Kb, b[blk]), rtol=1e-13)
+
+
+# ------------------------------------------- condensed == augmented (K2) --
+
+@pytest.mark.parametrize("seed", range(6))
+def test_lifted_condensed_equals_augmented(seed):
+    """Sec. 2.2: eliminating (d_s, d_z) from K2 gives K1; solved independently
+    with Bunch-Kaufman on K2 (scipy.linalg.ldl) the d_x must agree."""
+    rng = np.random.default_rng(100 + seed)
+    n, mi = int(rng.integers(2, 30)), int(rng.integers(1, 30))
+    W, _, H, sx, sh = rand_instance(rng, n, 0, mi)
+    r1, r2, r4 = rng.standard_normal(n), rng.standard_normal(mi), rng.standard_normal(mi)
+    M = od.augmented_k2(W, sx, np.zeros((0, n)), H, sh)
+    rhs = -np.concatenate([r1, r2, r4])
+    lu, d, perm = scipy.linalg.ldl(M)
+    # solve L D L^T x = rhs with the returned factors
+    sol = np.linalg.solve(lu.T, np.linalg.solve(d, np.linalg.solve(lu, rhs)))
+    assert np.allclose(M @ sol, rhs, atol=1e-9 * np.abs(rhs).max())
+    b, _ = od.condensed_rhs(r1, r2, np.zeros(0), r4, H, sh)
+    dx = od.solve_lifted(W, sx, H, sh, b)
+    assert np.allclose(dx, sol[:n], rtol=1e-8, atol=1e-9)
+    ds, dz = od.recover_slacks(dx, r2, r4, H, sh)
+    assert np.allclose(ds, sol[n:n + mi], rtol=1e-7, atol=1e-8)
+    assert np.allclose(dz, sol[n + mi:], rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_k1_equals_augmented_with_equalities(seed):
+    """K1 with an equality block matches K2 solved with LU (Sec. 2.2)."""
+    rng = np.random.default_rng(200 + seed)
+    n = int(rng.integers(4, 30)); me = int(rng.integers(1, n)); mi = int(rng.integers(1, 25))
+    W, G, H, sx, sh = rand_instance(rng, n, me, mi)
+    r1, r2, r3, r4 = (rng.standard_normal(k) for k in (n, mi, me, mi))
+    M = od.augmented_k2(W, sx, G, H, sh)
+    sol = scipy.linalg.solve(M, -np.concatenate([r1, r2, r3, r4]))
+    r1b, r2b = od.condensed_rhs(r1, r2, r3, r4, H, sh)
+    K = od.condensed_matrix(W, sx, H, sh)
+    dx, dy = od.solve_k1(K, G, r1b, r2b)
+    assert np.allclose(dx, sol[:n], rtol=1e-8, atol=1e-9)
+    assert np.allclose(dy, sol[n + mi:n + mi + me], rtol=1e-8, atol=1e-9)
+
+
+def test_rhs_sign_reading():
+    """The sign of rbar1 follows K1's definition; the restatement in the
+    error analysis (eq:cond:condensedrhs) flips the H^T term and fails."""
+    rng = np.random.default_rng(7)
+    n, mi = 8, 5
+    W, _, H, sx, sh = rand_instance(rng, n, 0, mi)
+    r1, r2, r4 = rng.standard_normal(n), rng.standard_normal(mi), rng.standard_normal(mi)
+    sol = scipy.linalg.solve(od.augmented_k2(W, sx, np.zeros((0, n)), H, sh),
+                             -np.concatenate([r1, r2, r4]))
+    b_alt = -r1 + H.T @ (sh * r4 - r2)
+    b, _ = od.condensed_rhs(r1, r2, np.zeros(0), r4, H, sh)
+    assert np.allclose(od.solve_lifted(W, sx, H, sh, b), sol[:n], rtol=1e-9)
+    assert not np.allclose(od.solve_lifted(W, sx, H, sh, b_alt), sol[:n], rtol=1e-3)
+
+
+# -------------------------------------------------------------- inertia --
+
+@pytest.mark.parametrize("seed", range(8))
+def test_inertia_equivalence(seed):
+    """eq:ipm:inertia: inertia(K2) = (n+mi, me+mi, 0) iff inertia(K1) = (n, me, 0),
+    checked on both sides of the boundary (planted negative curvature)."""
+    rng = np.random.default_rng(300 + seed)
+    n, me, mi = 8, 3, 4
+    W, G, H, sx, sh = rand_instance(rng, n, me, mi, wshift=0.0 if seed % 2 else 0.5)
+    if seed % 2:
+        W = W - (2.0 + 3 * rng.random()) * np.eye(n)  # indefinite W
+    K = od.condensed_matrix(W, sx, H, sh)
+    k1 = od.inertia(od.condensed_k1(K, G))
+    k2 = od.inertia(od.augmented_k2(W, sx, G, H, sh))
+    good1 = k1 == (n, me, 0)
+    good2 = k2 == (n + mi, me + mi, 0)
+    assert good1 == good2
+    # Sylvester: K2 inertia = K1 inertia + inertia of the slack block (+mi, +mi)
+    assert k2 == (k1[0] + mi, k1[1] + mi, k1[2])
+
+
+def test_inertia_planted_flip():
+    """A negative direction inside Ker(G) of W flips the K1 inertia."""
+    rng = np.random.default_rng(9)
+    n, me = 6, 2
+    G = rng.standard_normal((me, n))
+    Y, Z, _ = od.null_range_bases(G)
+    W = np.eye(n) - 3.0 * np.outer(Z[:, 0], Z[:, 0])
+    assert od.inertia(od.condensed_k1(W, G)) != (n, me, 0)
+    assert od.inertia(od.condensed_k1(np.eye(n), G)) == (n, me, 0)
+
+
+# ----------------------------------------------------------------- HyKKT --
+
+def test_hykkt_gamma_invariance():
+    """Sec. 3.1: eq:kkt:hykkt has the solution of K1 for every gamma."""
+    rng = np.random.default_rng(11)
+    n, me, mi = 12, 4, 7
+    W, G, H, sx, sh = rand_instance(rng, n, me, mi)
+    K = od.condensed_matrix(W, sx, H, sh)
+    r1b, r2b = rng.standard_normal(n), rng.standard_normal(me)
+    dx0, dy0 = od.solve_k1(K, G, r1b, r2b)
+    for gamma in (1e2, 1e4, 1e6, 1e8):
+        dx, dy = od.solve_hykkt_system(K, G, r1b, r2b, gamma)
+        assert np.allclose(dx, dx0, rtol=1e-6, atol=1e-7)
+        assert np.allclose(dy, dy0, rtol=1e-6, atol=1e-7)
+
+
+def test_hykkt_steps_match_k1_and_iterations_fall_with_gamma():
+    """Cholesky + CG + recovery (Sec. 3.1) reaches the K1 solution; CG needs
+    fewer iterations for larger gamma (eigenvalues of S_gamma cluster at 1/gamma)."""
+    rng = np.random.default_rng(12)
+    n, me, mi = 40, 15, 20
+    W, G, H, sx, sh = rand_instance(rng, n, me, mi)
+    K = od.condensed_matrix(W, sx, H, sh)
+    r1b, r2b = rng.standard_normal(n), rng.standard_normal(me)
+    dx0, dy0 = od.solve_k1(K, G, r1b, r2b)
+    its = []
+    for gamma in (1e0, 1e2, 1e4, 1e6):
+        dx, dy, k, ok = od.hykkt_steps(K, G, r1b, r2b, gamma, cg_tol=1e-12)
+        assert ok
+        its.append(k)
+        assert np.allclose(dx, dx0, rtol=1e-5, atol=1e-6)
+    assert all(a >= b for a, b in zip(its, its[1:])), its
+    assert its[-1] < its[0]
+
+
+def test_hykkt_k1_residual_identity():
+    """After step 3 solves K_gamma d_x = s - G^T d_y exactly, the K1 row-1
+    residual is gamma G^T times the row-2 residual (from eq:kkt:hykkt)."""
+    rng = np.random.default_rng(13)
+    n, me, mi = 20, 6, 9
+    W, G, H, sx, sh = rand_instance(rng, n, me, mi)
+    K = od.condensed_matrix(W, sx, H, sh)
+    r1b, r2b = rng.standard_normal(n), rng.standard_normal(me)
+    gamma = 1e3
+    dx, dy, k, ok = od.hykkt_steps(K, G, r1b, r2b, gamma, cg_tol=1e-3, cg_maxit=2)
+    row1 = r1b - (K @ dx + G.T @ dy)
+    row2 = r2b - G @ dx
+    assert np.abs(row2).max() > 1e-8  # CG stopped early on purpose
+    assert np.allclose(row1, -gamma * (G.T @ row2), rtol=1e-6, atol=1e-9 * gamma)
+
+
+def test_schur_eigenvalues_tend_to_inverse_gamma():
+    """Sec. 3.1: the eigenvalues of S_gamma converge to 1/gamma."""
+    rng = np.random.default_rng(14)
+    n, me, mi = 15, 5, 6
+    W, G, H, sx, sh = rand_instance(rng, n, me, mi)
+    K = od.condensed_matrix(W, sx, H, sh)
+    devs = []
+    for gamma in (1e1, 1e3, 1e5):
+        ev = np.linalg.eigvalsh(od.schur_gamma(K, G, gamma))
+        devs.append(np.abs(gamma * ev - 1).max())
+    assert devs[0] > devs[1] > devs[2]
+    assert devs[2] < 1e-2
+
+
+def test_gamma_threshold_gives_spd():
+    """Remark in Sec. 3.1 (eq:kkt:boundgamma): above the bound, K_gamma is SPD,
+    even when K itself is indefinite but Z^T K Z is positive definite."""
+    rng = np.random.default_rng(15)
+    n, me = 8, 3
+    G = rng.standard_normal((me, n))
+    Y, Z, _ = od.null_range_bases(G)
+    K = Z @ np.diag(1 + rng.random(n - me)) @ Z.T - Y @ np.diag(2 + rng.random(me)) @ Y.T
+    assert np.linalg.eigvalsh(K).min() < 0
+    gbar = od.gamma_threshold(K, G)
+    assert np.linalg.eigvalsh(K + 1.001 * gbar * G.T @ G).min() > 0
+    # and the true threshold is below the bound: some smaller gamma fails
+    assert np.linalg.eigvalsh(K + 1e-3 * G.T @ G).min() < 0
+
+
+def test_primal_schur_delta_c():
+    """Remark 1 (eqn:primal): for delta_c > 0 the primal Schur complement gives
+    the K1 (with -delta_c I) solution."""
+    rng = np.random.default_rng(16)
+    n, me, mi = 10, 4, 5
+    W, G, H, sx, sh = rand_instance(rng, n, me, mi)
+    K = od.condensed_matrix(W, sx, H, sh)
+    r1b, r2b = rng.standard_normal(n), rng.standard_normal(me)
+    dc = 1e-3
+    dx0, dy0 = od.solve_k1(K, G, r1b, r2b, delta_c=dc)
+    dx, dy = od.primal_schur_delta_c(K, G, r1b, r2b, dc)
+    assert np.allclose(dx, dx0, rtol=1e-9) and np.allclose(dy, dy0, rtol=1e-8)
+
+
+def test_structured_ill_conditioning():
+    """Theorem thm:cond: with l active rows at sigma-bar, K has l eigenvalues of
+    order sigma-bar and n - l of order one; cond(K) grows linearly in sigma-bar."""
+    rng = np.random.default_rng(17)
+    n, mi, l = 12, 8, 3
+    A = rng.standard_normal((n, n)); W = A @ A.T / n + np.eye(n)
+    H = rng.standard_normal((mi, n))
+    conds = []
+    for sbar in (1e4, 1e6, 1e8):
+        sh = np.full(mi, 1e-4); sh[:l] = sbar
+        ev = np.sort(np.linalg.eigvalsh(od.condensed_matrix(W, np.zeros(n), H, sh)))[::-1]
+        assert ev[l - 1] > 0.01 * sbar and ev[0] < 100 * sbar
+        assert ev[l] < 100 and ev[-1] > 1e-2
+        conds.append(ev[0] / ev[-1])
+    r1, r2 = conds[1] / conds[0], conds[2] / conds[1]
+    assert 50 < r1 < 200 and 50 < r2 < 200
+
+
+# --------------------------------------------- sparse oracle vs dense oracle --
+
+def test_sparse_oracle_matches_dense_lifted():
+    p = workloads.tiny_grid(seed=0)
+    W, G, H = od.problem_dense(p)
+    J = np.vstack([G, H])
+    P = osp.Problem(p)
+    x, hist = osp.solve_lifted(P, p.sigma_x, p.sigma_s, p.b)
+    assert hist[-1] < 1e-14
+    K = od.condensed_matrix(W, p.sigma_x, J, p.sigma_s)
+    # unassembled operator equals the dense assembled matrix
+    v = np.random.default_rng(0).standard_normal(p.n)
+    assert np.allclose(osp.apply_condensed(P.W, p.sigma_x, P.J, p.sigma_s, v), K @ v,
+                       rtol=1e-12, atol=1e-12 * np.abs(K).max())
+    x0 = np.linalg.solve(K, p.b)
+    # same solution as the dense LU, up to what the conditioning allows
+    assert np.abs(x - x0).max() <= 1e-6 * np.abs(x0).max()
+    assert od.omega_bruteforce(W, p.sigma_x, J, p.sigma_s, x, p.b) < 1e-14
+
+
+def test_sparse_oracle_matches_dense_hykkt():
+    p = workloads.tiny_grid(seed=1, sigma_range=(-3, 3))
+    W, G, H = od.problem_dense(p)
+    P = osp.Problem(p)
+    sh = p.sigma_s_ineq
+    dx, dy, hist = osp.solve_k1(P, p.sigma_x, sh, p.r1bar, p.r2bar)
+    K = od.condensed_matrix(W, p.sigma_x, H, sh)
+    dx0, dy0 = od.solve_k1(K, G, p.r1bar, p.r2bar)
+    assert np.allclose(dx, dx0, rtol=1e-8, atol=1e-10)
+    assert np.allclose(dy, dy0, rtol=1e-8, atol=1e-10)
+    dx2, dy2, it, ok = osp.hykkt_steps(P, p.sigma_x, sh, p.r1bar, p.r2bar, 1e4, cg_tol=1e-12)
+    assert ok and it > 0
+    dx3, dy3, it3, ok3 = od.hykkt_steps(K, G, p.r1bar, p.r2bar, 1e4, cg_tol=1e-12)
+    assert abs(it - it3) <= 2
+    assert np.allclose(dx2, dx3, rtol=1e-6, atol=1e-8)
+
+
+def test_residual_certificate_detects_planted_error():
+    """omega is sensitive to a single-entry mistake in x, at every position."""
+    p = workloads.tiny_grid(seed=2)
+    P = osp.Problem(p)
+    x, hist = osp.solve_lifted(P, p.sigma_x, p.sigma_s, p.b)
+    assert osp.omega_condensed(P.W, p.sigma_x, P.J, p.sigma_s, x, p.b) < 1e-14
+    for i in (0, 5, 150, 299):
+        y = x.copy(); y[i] += 1e-6 * max(abs(y[i]), 1e-3)
+        assert osp.omega_condensed(P.W, p.sigma_x, P.J, p.sigma_s, y, p.b) > 1e-12
+
+
+def test_omega_sparse_equals_bruteforce():
+    """The vectorised omega equals the row-by-row Oettli-Prager ratio."""
+    rng = np.random.default_rng(21)
+    p = workloads.tiny_grid(seed=3, nx=4, ny=3)
+    W, G, H = od.problem_dense(p)
+    J = np.vstack([G, H])
+    P = osp.Problem(p)
+    x = rng.standard_normal(p.n)
+    a = osp.omega_condensed(P.W, p.sigma_x, P.J, p.sigma_s, x, p.b)
+    b = od.omega_bruteforce(W, p.sigma_x, J, p.sigma_s, x, p.b)
+    assert np.isclose(a, b, rtol=1e-12)
+
+
+def test_omega_bounds_data_perturbation():
+    """Oettli-Prager: if x solves a system whose sigma_s entries are perturbed by
+    a relative eps, omega(x) <= eps (up to rounding), and it is of order eps."""
+    p = workloads.tiny_grid(seed=4, sigma_range=(-2, 2))
+    W, G, H = od.problem_dense(p)
+    J = np.vstack([G, H])
+    rng = np.random.default_rng(22)
+    for eps in (1e-6, 1e-9):
+        ss = p.sigma_s * (1 + eps * rng.choice([-1.0, 1.0], size=p.m))
+        x = np.linalg.solve(od.condensed_matrix(W, p.sigma_x, J, ss), p.b)
+        om = od.omega_bruteforce(W, p.sigma_x, J, p.sigma_s, x, p.b)
+        assert eps * 1e-3 < om <= eps * (1 + 1e-3) + 1e-14
