@@ -1,0 +1,238 @@
+/*
+ * ckkt.h -- condensed-space KKT solves on one MI355X (gfx950).
+ *
+ * The library computes the Newton direction of the condensed KKT system of
+ * an interior-point method (Pacaud, Shin, Montoison, Schanen, Anitescu,
+ * "Condensed interior-point methods for scalable nonlinear programming on
+ * GPUs", arXiv 2405.14236) in its two Cholesky-based forms:
+ *
+ *   LiftedKKT (Sec. 3.2, eq:liftedkkt): equalities are relaxed into tight
+ *     inequality rows, J = [G; H], and
+ *         K_tau d_x = b,   K_tau = W + diag(sigma_x) + J^T diag(sigma_s) J.
+ *
+ *   HyKKT (Sec. 3.1, eq:kkt:hykkt and eq:kkt:schurcomplhykkt):
+ *         K1 = [[K, G^T], [G, 0]] (d_x, d_y) = (rbar1, rbar2),
+ *         K  = W + diag(sigma_x) + H^T diag(sigma_s) H,
+ *     solved through the Cholesky factor of K_gamma = K + gamma G^T G and
+ *     conjugate gradient on S_gamma = G K_gamma^{-1} G^T.
+ *
+ * sigma_x plays the role of delta_w I (any nonnegative diagonal) and
+ * sigma_s the role of D_H = (D_s + delta_w I) C with delta_c = 0
+ * (Sec. 2.2, K1; Remark 1).
+ *
+ * Call sequence:  ckkt_analyze (host symbolic analysis, once per pattern)
+ *              -> ckkt_bind_workspace (caller-allocated device memory)
+ *              -> { ckkt_factorize (values, sigma, gamma)
+ *                   -> ckkt_solve (rhs) ... } repeated for every new system.
+ *
+ * Conventions for every entry point:
+ *  - All functions return a ckkt_status (0 = success, < 0 = error); none
+ *    aborts, throws or prints.
+ *  - Pattern arrays (ckkt_pattern) are HOST memory, read during
+ *    ckkt_analyze only; the library keeps its own copies.
+ *  - Value, diagonal, right-hand-side and solution pointers are DEVICE
+ *    memory owned by the caller.  They are used by work enqueued on the
+ *    caller's stream; factor values must stay unchanged until the last
+ *    ckkt_solve that uses the factor has returned (the refinement applies
+ *    K unassembled from them).
+ *  - After ckkt_bind_workspace the library allocates no device memory; it
+ *    writes only into the bound workspace and the caller's output arrays.
+ *  - Matrices are CSR with int32 indices, column indices strictly
+ *    increasing inside each row; W is given by its lower triangle
+ *    (column <= row) and must hold every diagonal entry it has.
+ *  - One handle is used by one host thread / one stream at a time.
+ */
+#ifndef CKKT_H
+#define CKKT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ckkt_status;
+#define CKKT_OK                  0
+#define CKKT_ERR_ARG            -1  /* bad argument (null pointer, negative size, bad enum) */
+#define CKKT_ERR_PATTERN        -2  /* malformed CSR: unsorted, duplicate, out of range, W upper entry */
+#define CKKT_ERR_NOT_SPD        -3  /* a Cholesky pivot was not positive; see ckkt_info.failed_column */
+#define CKKT_ERR_NO_CONVERGENCE -4  /* refinement or CG did not reach the tolerance within its limit */
+#define CKKT_ERR_BREAKDOWN      -5  /* CG breakdown (p^T S p <= 0 or not finite) */
+#define CKKT_ERR_STATE          -6  /* call out of order (solve before factorize, no workspace, ...) */
+#define CKKT_ERR_HIP            -7  /* a HIP runtime call failed */
+#define CKKT_ERR_WORKSPACE      -8  /* workspace missing, too small or misaligned */
+#define CKKT_ERR_NONFINITE      -9  /* NaN or Inf in the input values or diagonals */
+
+/* Formulations (Sec. 3). */
+#define CKKT_LIFTED 0
+#define CKKT_HYKKT  1
+
+/* Precision of the Cholesky factor.  Residuals, refinement updates, CG
+ * vectors, dot products and the gamma-scaled terms are FP64 in both. */
+#define CKKT_FP64    0
+#define CKKT_FP32_IR 1
+
+/* Fill-reducing orderings (host analysis). */
+#define CKKT_ORDER_AMD     0  /* approximate minimum degree */
+#define CKKT_ORDER_NATURAL 1  /* identity (tests and tiny inputs) */
+
+typedef struct {
+    int64_t n;            /* primal variables */
+    int64_t m_eq;         /* equality rows (G) */
+    int64_t m_ineq;       /* inequality rows (H) */
+    const int32_t *w_ptr, *w_idx;   /* W lower triangle, n+1 / nnz(W) */
+    const int32_t *g_ptr, *g_idx;   /* G, m_eq+1 / nnz(G); may be NULL when m_eq == 0 */
+    const int32_t *h_ptr, *h_idx;   /* H, m_ineq+1 / nnz(H); may be NULL when m_ineq == 0 */
+    int32_t formulation;            /* CKKT_LIFTED or CKKT_HYKKT */
+} ckkt_pattern;
+
+typedef struct {
+    int32_t precision;    /* CKKT_FP64 (default) or CKKT_FP32_IR */
+    int32_t ordering;     /* CKKT_ORDER_AMD (default) */
+    double  tol;          /* residual gate: componentwise relative backward
+                             error (see ckkt_solve); default 1e-10 */
+    int32_t ir_maxit;     /* refinement steps after the first solve; default 10 */
+    double  cg_tol;       /* HyKKT CG: stop when ||r_k||_2 <= cg_tol ||r_0||_2; default 1e-10 */
+    int32_t cg_maxit;     /* HyKKT CG iteration limit; default min(m_eq, 1000) when <= 0 */
+    int32_t relax;        /* supernode amalgamation: 0 off, 1 default */
+} ckkt_options;
+
+typedef struct {
+    int64_t n, m_eq, m_ineq;
+    int64_t nnz_k;            /* lower triangle of K (incl. diagonal) */
+    int64_t nnz_l;            /* structural nonzeros of the Cholesky factor */
+    int64_t nnz_l_stored;     /* stored entries (supernode panels incl. explicit zeros) */
+    double  factor_flops;     /* algorithmic flops of the factorization (true structure) */
+    double  assembly_products;/* J products summed by the assembly */
+    int32_t n_supernodes;
+    int32_t n_levels;         /* height of the supernodal assembly tree */
+    int32_t max_front;        /* largest frontal matrix order */
+    int32_t n_big_fronts;     /* fronts factored by the tiled (multi-workgroup) path */
+    int64_t workspace_bytes;
+    double  analyze_seconds;
+    int32_t failed_column;    /* first column with a non-positive pivot (original
+                                 numbering), -1 if none; valid after a solve or
+                                 ckkt_factor_status */
+    int32_t pad;
+} ckkt_info;
+
+typedef struct {
+    int32_t status;           /* same as the return value */
+    int32_t refine_steps;     /* refinement steps taken after the first solve (outer steps for HyKKT) */
+    int32_t cg_iters;         /* total CG iterations (HyKKT) */
+    int32_t pcg_iters;        /* total PCG iterations (FP32 fallback path) */
+    int32_t fallback;         /* 0 none, 1 PCG around the FP32 factor, 2 FP64 refactorization */
+    int32_t pad;
+    double  omega;            /* final componentwise relative backward error */
+    double  rho;              /* final unscaled ||r||_inf / ||rhs||_inf */
+} ckkt_solve_info;
+
+typedef struct ckkt_handle ckkt_handle;
+
+/* Fills *opt with the defaults listed above. */
+void ckkt_default_options(ckkt_options* opt);
+
+/* Host symbolic analysis (Sec. 2.2 K1 / Sec. 3: the condensed pattern is
+ * pattern(W) U diag U pattern(J^T J) for LiftedKKT and the same union with
+ * G^T G for HyKKT, so both formulations share one analysis).  Computes the
+ * fill-reducing ordering, elimination tree, supernodes, assembly maps and
+ * level schedule, and the device workspace size.
+ *   pat, opt : host; opt may be NULL for defaults.
+ *   out      : receives a new handle (free with ckkt_destroy).
+ *   workspace_bytes : receives the size ckkt_bind_workspace needs.
+ * Errors: CKKT_ERR_ARG, CKKT_ERR_PATTERN (nothing is allocated then). */
+ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt,
+                         ckkt_handle** out, size_t* workspace_bytes);
+
+/* Batched analysis: `count` independent systems analysed as one
+ * block-diagonal system.  Value arrays passed to ckkt_factorize and
+ * ckkt_solve are the per-instance arrays concatenated in instance order
+ * (W values, G values, H values, sigma_x, sigma_s, rhs, sol), and every
+ * instance must reach the tolerance on its own. All patterns must have the
+ * same formulation. */
+ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats,
+                               const ckkt_options* opt, ckkt_handle** out,
+                               size_t* workspace_bytes);
+
+/* Binds `bytes` of caller-owned device memory at `dev_ptr` (256-byte
+ * aligned, at least workspace_bytes) and uploads the analysis plans into
+ * it on `stream`; returns after the upload completed.  The memory must
+ * outlive every later call on the handle.
+ * Errors: CKKT_ERR_WORKSPACE, CKKT_ERR_HIP. */
+ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, void* stream);
+
+/* Numeric phase for one new system (rows a1 and a2 of the hot path):
+ * assembles K (LiftedKKT) or K_gamma (HyKKT) in FP64 into the factor's
+ * pattern and factorizes it, LL^T, in the handle's precision.  Work is
+ * enqueued on `stream` (a hipStream_t, NULL = default stream); the call
+ * returns without waiting.
+ *   w_val   : nnz(W) device doubles, in the order of w_idx
+ *   g_val   : nnz(G) device doubles (NULL if m_eq == 0)
+ *   h_val   : nnz(H) device doubles (NULL if m_ineq == 0)
+ *   sigma_x : n device doubles (>= 0)
+ *   sigma_s : LiftedKKT m_eq + m_ineq doubles (rows of G first, then H);
+ *             HyKKT m_ineq doubles (> 0)
+ *   gamma   : HyKKT weight of G^T G (> 0), ignored for LiftedKKT.
+ * A non-positive pivot is reported by the next ckkt_solve or
+ * ckkt_factor_status as CKKT_ERR_NOT_SPD. */
+ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_val,
+                           const double* h_val, const double* sigma_x,
+                           const double* sigma_s, double gamma, void* stream);
+
+/* Waits for the factorization and reports CKKT_OK or CKKT_ERR_NOT_SPD (the
+ * failing column is then in ckkt_info.failed_column). */
+ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream);
+
+/* Solve with the current factor (rows a3-a5): triangular sweeps plus FP64
+ * iterative refinement with K applied unassembled (Sec. 2.2, "Iterative
+ * refinement"); for HyKKT the CG of eq:kkt:schurcomplhykkt inside an outer
+ * FP64 refinement on K1.  Stops when the componentwise relative backward
+ * error omega = max_i |res_i| / (|data| |sol| + |rhs|)_i <= opt.tol.
+ *   rhs : LiftedKKT n doubles (b); HyKKT n + m_eq doubles (rbar1; rbar2)
+ *   sol : same length; receives d_x (LiftedKKT) or (d_x; d_y) (HyKKT)
+ *   info: host, may be NULL.
+ * Blocks until the result is in `sol`.
+ * Errors: CKKT_ERR_STATE, CKKT_ERR_NOT_SPD, CKKT_ERR_NO_CONVERGENCE (sol
+ * then holds the best iterate), CKKT_ERR_BREAKDOWN, CKKT_ERR_HIP. */
+ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol,
+                       ckkt_solve_info* info, void* stream);
+
+/* One application of the factor, x = (L L^T)^{-1} b (forward and backward
+ * sweeps only, no refinement), for LiftedKKT and HyKKT (K_gamma).
+ * rhs, sol: n device doubles; enqueued on stream, does not wait. */
+ckkt_status ckkt_apply_inverse(ckkt_handle* h, const double* rhs, double* sol, void* stream);
+
+/* The assembled K (or K_gamma) of the last factorize as coordinates in the
+ * ORIGINAL numbering (row >= col), one entry per internal slot, nnz_k
+ * entries: rows/cols are host arrays filled when non-NULL, values is a
+ * device array of nnz_k doubles filled (synchronously) when non-NULL. */
+ckkt_status ckkt_export_k(ckkt_handle* h, int32_t* rows, int32_t* cols, double* values, void* stream);
+
+/* Host execution of the numeric phase over the same analysis plan (same
+ * assembly recipe, multifrontal maps, level schedule and sweeps as the
+ * device kernels, FP64, sequential): x = K^{-1} rhs for LiftedKKT or
+ * x = K_gamma^{-1} rhs for HyKKT, no refinement.  All pointers are HOST
+ * memory; needs no GPU and no workspace.  For validating the analysis on
+ * machines without a GPU.  Returns CKKT_ERR_NOT_SPD (with *failed_column,
+ * original numbering) on a non-positive pivot. */
+ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, const double* g_val,
+                                  const double* h_val, const double* sigma_x, const double* sigma_s,
+                                  double gamma, const double* rhs, double* sol, int32_t* failed_column);
+
+ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info);
+const char* ckkt_status_string(ckkt_status s);
+void        ckkt_destroy(ckkt_handle* h);
+
+/* Per-phase device time, in milliseconds, accumulated with HIP events on
+ * the caller's stream since the last reset (0 = assemble, 1 = factor,
+ * 2 = sweeps, 3 = residual/refinement/CG vector work) and the number of
+ * calls of each phase.  Timing is off unless enabled; enabling it adds
+ * event records but no synchronisation. */
+ckkt_status ckkt_set_timing(ckkt_handle* h, int32_t enable);
+ckkt_status ckkt_get_timing(ckkt_handle* h, double ms[4], int64_t calls[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CKKT_H */

@@ -1,0 +1,103 @@
+// Host-side symbolic analysis of the condensed KKT pattern.
+//
+// The condensed matrix of LiftedKKT (K_tau = W + Sigma_x + J^T Sigma_s J,
+// Sec. 3.2) and of HyKKT (K_gamma = K + gamma G^T G, Sec. 3.1) have the same
+// pattern: pattern(W) U diag U pattern(J^T J) with J = [G; H].  Everything
+// here depends on that pattern only and is computed once; the numeric
+// phases reuse it for every new system, as the paper does with its solver's
+// symbolic factorization (Sec. 6.1, analysis column of tab:linsol:time).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ckkt {
+
+struct PatternIn {
+    int64_t n = 0, m_eq = 0, m_ineq = 0;
+    std::vector<int32_t> w_ptr, w_idx, g_ptr, g_idx, h_ptr, h_idx;
+};
+
+// Symmetric adjacency (no diagonal), CSR.
+struct Graph {
+    int32_t n = 0;
+    std::vector<int32_t> ptr, adj;
+};
+
+// Approximate minimum degree ordering. perm[k] = vertex eliminated k-th.
+std::vector<int32_t> amd_order(const Graph& g);
+
+struct Plan {
+    // ---- sizes
+    int32_t n = 0, m_eq = 0, m_ineq = 0, m = 0;
+    int64_t nnz_w = 0, nnz_g = 0, nnz_h = 0;
+
+    // ---- ordering: perm[new] = old, iperm[old] = new
+    std::vector<int32_t> perm, iperm;
+
+    // ---- K lower triangle in the new numbering, CSC: column j holds rows >= j
+    std::vector<int32_t> kcolptr, krow;
+    // assembly recipe per K slot
+    std::vector<int32_t> k_wsrc;      // index into W values or -1
+    std::vector<int32_t> k_diag;      // original index of the diagonal (sigma_x) or -1
+    std::vector<int32_t> prod_ptr;    // nnz_k + 1
+    std::vector<int32_t> prod_r, prod_a, prod_b;  // J row, two J value indices (G values then H values)
+
+    // ---- supernodes (new numbering, columns contiguous)
+    int32_t ns = 0;
+    std::vector<int32_t> sn_start;    // ns + 1
+    std::vector<int32_t> sn_rowptr;   // ns + 1, offsets into sn_rows
+    std::vector<int32_t> sn_rows;     // front row lists: own columns then the rows below
+    std::vector<int32_t> sn_parent;   // -1 for roots
+    std::vector<int32_t> child_ptr, child_list;
+    std::vector<int32_t> relmap;      // aligned with sn_rows: row position inside the parent front
+    std::vector<int32_t> kmap;        // per K slot: row position inside its supernode's front
+    std::vector<int64_t> l_off;       // start of the supernode's region in the factor arena
+    std::vector<int64_t> u_off;       // start of its update (Schur) matrix in the arena
+    std::vector<int32_t> u_ld;        // leading dimension of the update matrix
+    std::vector<uint8_t> big;         // 1 if factored by the tiled path
+    int64_t arena = 0;                // factor arena length (elements)
+    int64_t nnz_l = 0, nnz_l_stored = 0;
+    double flops = 0.0;
+    int32_t max_front = 0, n_big = 0;
+
+    // ---- level schedule (level 0 = leaves)
+    int32_t nlev = 0;
+    std::vector<int32_t> lvl_ptr;         // nlev + 1, into lvl_small / lvl_big
+    std::vector<int32_t> lvl_small;       // small-front supernodes grouped by level
+    std::vector<int32_t> lvl_small_ptr;   // nlev + 1
+    std::vector<int32_t> lvl_big;         // big-front supernodes grouped by level
+    std::vector<int32_t> lvl_big_ptr;     // nlev + 1
+    std::vector<int32_t> lvl_all;         // all supernodes grouped by level (sweeps)
+    std::vector<int32_t> lvl_all_ptr;
+    std::vector<int32_t> lvl_maxw_big;    // per level, max supernode width among big fronts
+    std::vector<int32_t> big_tiles_ptr;   // per level: prefix count of column tiles over big fronts
+    std::vector<int32_t> big_tile_sn, big_tile_col;  // (supernode, first column of tile)
+
+    // ---- unassembled operators for the residual (original numbering)
+    std::vector<int32_t> wf_ptr, wf_col, wf_vidx;   // full symmetric W, value index into W lower
+    std::vector<int32_t> j_ptr, j_col;              // J = [G; H] rows, value index = position
+    std::vector<int32_t> jt_ptr, jt_row, jt_vidx, jt_gend;  // J^T by column; G rows first
+
+    // ---- batched instances (block-diagonal union); one instance otherwise
+    int32_t ninst = 1;
+    std::vector<int32_t> inst_n;      // ninst + 1 prefix over variables
+    std::vector<int32_t> inst_meq;    // ninst + 1 prefix over equality rows
+    std::vector<int32_t> inst_of_var; // n
+    std::vector<int32_t> inst_of_eqrow; // m_eq
+
+    double analyze_seconds = 0.0;
+};
+
+struct AnalyzeOptions {
+    int ordering = 0;      // 0 AMD, 1 natural
+    int relax = 1;
+    int big_front = 96;    // fronts larger than this go to the tiled path
+    int tile = 64;         // column tile of the tiled path
+};
+
+// Returns an empty string on success, else a description of the pattern error.
+std::string validate(const PatternIn& p);
+std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& plan);
+
+}  // namespace ckkt

@@ -1,0 +1,904 @@
+// C-ABI of the condensed-KKT library: handle life cycle, workspace
+// carving, and the drivers of the numeric phases (assembly + factorization,
+// triangular sweeps, FP64 iterative refinement, HyKKT conjugate gradient).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ckkt.h"
+#include "analysis.hpp"
+#include "device.hpp"
+
+using namespace ckkt;
+
+namespace ckkt {
+int host_factor_solve(const Plan& P, int hy, const double* w_val, const double* g_val, const double* h_val,
+                      const double* sigma_x, const double* sigma_s, double gamma, const double* b, double* x);
+}
+
+namespace {
+
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+struct Layout {
+    size_t total = 0;
+    Region add(size_t bytes) {
+        Region r;
+        r.off = (total + 255) & ~(size_t)255;
+        r.bytes = bytes;
+        total = r.off + bytes;
+        return r;
+    }
+};
+
+template <typename V>
+size_t vbytes(const std::vector<V>& v) { return v.size() * sizeof(V); }
+
+}  // namespace
+
+struct ckkt_handle {
+    Plan plan;
+    ckkt_options opt{};
+    int32_t formulation = CKKT_LIFTED;
+    int32_t precision = CKKT_FP64;
+    std::vector<LevelInfo> levels;
+
+    // workspace layout
+    Layout lay;
+    struct PlanRegion { Region r; const void* host; };
+    std::vector<PlanRegion> plan_regions;
+    Region r_perm, r_iperm, r_kcolptr, r_kwsrc, r_kdiag, r_prodptr, r_prodr, r_proda, r_prodb, r_snstart, r_snrowptr,
+        r_snrows, r_childptr, r_childlist, r_relmap, r_kmap, r_loff, r_uoff, r_uld, r_lvlsmall, r_lvlbig, r_lvlall,
+        r_tilesn, r_tilecol, r_wfptr, r_wfcol, r_wfvidx, r_jptr, r_jcol, r_jtptr, r_jtrow, r_jtvidx, r_jtgend,
+        r_instvar, r_insteq;
+    Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
+    std::vector<Region> r_vn, r_vm, r_veq;  // scratch vectors of length n, m, m_eq
+
+    // bound state
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    DevPlan dp{};
+    double *K = nullptr, *d = nullptr, *scale = nullptr, *uvec = nullptr, *vperm = nullptr;
+    double* arena64 = nullptr;
+    float* arena32 = nullptr;
+    int32_t* status = nullptr;
+    unsigned long long* bits = nullptr;  // [ninst omega][resmax][bmax]
+    double *dotpart = nullptr, *sc = nullptr;
+    std::vector<double*> vn, vm, veq;
+
+    bool factored = false;
+    bool fp64_factored = false;  // FP64 factor valid (fallback path of FP32_IR)
+    SysVals vals{};
+    int32_t failed_column = -1;
+
+    // pinned host staging
+    void* host = nullptr;
+    size_t host_bytes = 0;
+
+    // timing
+    bool timing = false;
+    double ms[4] = {0, 0, 0, 0};
+    int64_t calls[4] = {0, 0, 0, 0};
+    struct Pending { int phase; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+ckkt_status hip_ok(hipError_t e) { return e == hipSuccess ? CKKT_OK : CKKT_ERR_HIP; }
+
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        hipError_t _e = (x);                         \
+        if (_e != hipSuccess) return CKKT_ERR_HIP;   \
+    } while (0)
+
+hipEvent_t take_event(ckkt_handle* h) {
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct PhaseTimer {
+    ckkt_handle* h;
+    int phase;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    PhaseTimer(ckkt_handle* h_, int ph, hipStream_t s) : h(h_), phase(ph), st(s) {
+        if (h->timing) {
+            a = take_event(h);
+            if (a) (void)hipEventRecord(a, st);
+        }
+    }
+    ~PhaseTimer() {
+        if (h->timing && a) {
+            hipEvent_t b = take_event(h);
+            if (b) {
+                (void)hipEventRecord(b, st);
+                h->pending.push_back({phase, a, b});
+            }
+        }
+    }
+};
+
+void build_levels(ckkt_handle* h) {
+    const Plan& P = h->plan;
+    h->levels.assign(P.nlev, LevelInfo{});
+    auto front = [&](int s) { return P.sn_rowptr[s + 1] - P.sn_rowptr[s]; };
+    auto width = [&](int s) { return P.sn_start[s + 1] - P.sn_start[s]; };
+    for (int l = 0; l < P.nlev; ++l) {
+        LevelInfo& L = h->levels[l];
+        L.small_begin = P.lvl_small_ptr[l];
+        L.small_count = P.lvl_small_ptr[l + 1] - L.small_begin;
+        L.small_maxf = 0;
+        for (int t = L.small_begin; t < L.small_begin + L.small_count; ++t)
+            L.small_maxf = std::max(L.small_maxf, front(P.lvl_small[t]));
+        L.big_begin = P.lvl_big_ptr[l];
+        L.big_count = P.lvl_big_ptr[l + 1] - L.big_begin;
+        L.big_maxw = L.big_maxf = 0;
+        for (int t = L.big_begin; t < L.big_begin + L.big_count; ++t) {
+            L.big_maxw = std::max(L.big_maxw, width(P.lvl_big[t]));
+            L.big_maxf = std::max(L.big_maxf, front(P.lvl_big[t]));
+        }
+        L.all_begin = P.lvl_all_ptr[l];
+        L.all_count = P.lvl_all_ptr[l + 1] - L.all_begin;
+        L.all_maxf = 0;
+        for (int t = L.all_begin; t < L.all_begin + L.all_count; ++t)
+            L.all_maxf = std::max(L.all_maxf, front(P.lvl_all[t]));
+        L.tile_begin = P.big_tiles_ptr[l];
+        L.tile_count = P.big_tiles_ptr[l + 1] - L.tile_begin;
+    }
+}
+
+void build_layout(ckkt_handle* h) {
+    const Plan& P = h->plan;
+    Layout& L = h->lay;
+    auto plan_region = [&](Region& r, const auto& vec) {
+        r = L.add(std::max<size_t>(vbytes(vec), 8));
+        h->plan_regions.push_back({r, vec.data()});
+        h->plan_regions.back().r.bytes = vbytes(vec);
+    };
+    plan_region(h->r_perm, P.perm);
+    plan_region(h->r_iperm, P.iperm);
+    plan_region(h->r_kcolptr, P.kcolptr);
+    plan_region(h->r_kwsrc, P.k_wsrc);
+    plan_region(h->r_kdiag, P.k_diag);
+    plan_region(h->r_prodptr, P.prod_ptr);
+    plan_region(h->r_prodr, P.prod_r);
+    plan_region(h->r_proda, P.prod_a);
+    plan_region(h->r_prodb, P.prod_b);
+    plan_region(h->r_snstart, P.sn_start);
+    plan_region(h->r_snrowptr, P.sn_rowptr);
+    plan_region(h->r_snrows, P.sn_rows);
+    plan_region(h->r_childptr, P.child_ptr);
+    plan_region(h->r_childlist, P.child_list);
+    plan_region(h->r_relmap, P.relmap);
+    plan_region(h->r_kmap, P.kmap);
+    plan_region(h->r_loff, P.l_off);
+    plan_region(h->r_uoff, P.u_off);
+    plan_region(h->r_uld, P.u_ld);
+    plan_region(h->r_lvlsmall, P.lvl_small);
+    plan_region(h->r_lvlbig, P.lvl_big);
+    plan_region(h->r_lvlall, P.lvl_all);
+    plan_region(h->r_tilesn, P.big_tile_sn);
+    plan_region(h->r_tilecol, P.big_tile_col);
+    plan_region(h->r_wfptr, P.wf_ptr);
+    plan_region(h->r_wfcol, P.wf_col);
+    plan_region(h->r_wfvidx, P.wf_vidx);
+    plan_region(h->r_jptr, P.j_ptr);
+    plan_region(h->r_jcol, P.j_col);
+    plan_region(h->r_jtptr, P.jt_ptr);
+    plan_region(h->r_jtrow, P.jt_row);
+    plan_region(h->r_jtvidx, P.jt_vidx);
+    plan_region(h->r_jtgend, P.jt_gend);
+    plan_region(h->r_instvar, P.inst_of_var);
+    plan_region(h->r_insteq, P.inst_of_eqrow);
+
+    const size_t n = std::max<int64_t>(P.n, 1), m = std::max<int64_t>(P.m, 1), me = std::max<int64_t>(P.m_eq, 1);
+    h->r_K = L.add(std::max<size_t>(P.kcolptr.back(), 1) * sizeof(double));
+    h->r_d = L.add(m * sizeof(double));
+    h->r_scale = L.add(n * sizeof(double));
+    // the FP64 arena is present in both precisions (FP32_IR falls back to it)
+    h->r_arena64 = L.add(std::max<int64_t>(P.arena, 1) * sizeof(double));
+    if (h->precision == CKKT_FP32_IR) h->r_arena32 = L.add(std::max<int64_t>(P.arena, 1) * sizeof(float));
+    h->r_uvec = L.add(std::max<size_t>(P.sn_rows.size(), 1) * sizeof(double));
+    h->r_vperm = L.add(n * sizeof(double));
+    h->r_status = L.add(4 * sizeof(int32_t));
+    h->r_bits = L.add((P.ninst + 2) * sizeof(unsigned long long));
+    h->r_dotpart = L.add(kDotBlocks * sizeof(double));
+    h->r_sc = L.add(16 * sizeof(double));
+    h->r_vn.clear();
+    h->r_vm.clear();
+    h->r_veq.clear();
+    for (int i = 0; i < 8; ++i) h->r_vn.push_back(L.add(n * sizeof(double)));
+    for (int i = 0; i < 2; ++i) h->r_vm.push_back(L.add(m * sizeof(double)));
+    for (int i = 0; i < 6; ++i) h->r_veq.push_back(L.add(me * sizeof(double)));
+}
+
+template <typename T>
+T* at(ckkt_handle* h, const Region& r) { return reinterpret_cast<T*>(h->ws + r.off); }
+
+void fill_devplan(ckkt_handle* h) {
+    const Plan& P = h->plan;
+    DevPlan& D = h->dp;
+    D.n = P.n; D.m_eq = P.m_eq; D.m_ineq = P.m_ineq; D.m = P.m; D.ns = P.ns; D.ninst = P.ninst;
+    D.hy = h->formulation == CKKT_HYKKT ? 1 : 0;
+    D.nnzk = P.kcolptr.back();
+    D.nnzg = P.nnz_g;
+    D.perm = at<int32_t>(h, h->r_perm); D.iperm = at<int32_t>(h, h->r_iperm);
+    D.kcolptr = at<int32_t>(h, h->r_kcolptr); D.k_wsrc = at<int32_t>(h, h->r_kwsrc);
+    D.k_diag = at<int32_t>(h, h->r_kdiag); D.prod_ptr = at<int32_t>(h, h->r_prodptr);
+    D.prod_r = at<int32_t>(h, h->r_prodr); D.prod_a = at<int32_t>(h, h->r_proda); D.prod_b = at<int32_t>(h, h->r_prodb);
+    D.sn_start = at<int32_t>(h, h->r_snstart); D.sn_rowptr = at<int32_t>(h, h->r_snrowptr);
+    D.sn_rows = at<int32_t>(h, h->r_snrows); D.child_ptr = at<int32_t>(h, h->r_childptr);
+    D.child_list = at<int32_t>(h, h->r_childlist); D.relmap = at<int32_t>(h, h->r_relmap);
+    D.kmap = at<int32_t>(h, h->r_kmap); D.l_off = at<int64_t>(h, h->r_loff); D.u_off = at<int64_t>(h, h->r_uoff);
+    D.u_ld = at<int32_t>(h, h->r_uld); D.lvl_small = at<int32_t>(h, h->r_lvlsmall);
+    D.lvl_big = at<int32_t>(h, h->r_lvlbig); D.lvl_all = at<int32_t>(h, h->r_lvlall);
+    D.big_tile_sn = at<int32_t>(h, h->r_tilesn); D.big_tile_col = at<int32_t>(h, h->r_tilecol);
+    D.wf_ptr = at<int32_t>(h, h->r_wfptr); D.wf_col = at<int32_t>(h, h->r_wfcol); D.wf_vidx = at<int32_t>(h, h->r_wfvidx);
+    D.j_ptr = at<int32_t>(h, h->r_jptr); D.j_col = at<int32_t>(h, h->r_jcol);
+    D.jt_ptr = at<int32_t>(h, h->r_jtptr); D.jt_row = at<int32_t>(h, h->r_jtrow);
+    D.jt_vidx = at<int32_t>(h, h->r_jtvidx); D.jt_gend = at<int32_t>(h, h->r_jtgend);
+    D.inst_of_var = at<int32_t>(h, h->r_instvar); D.inst_of_eqrow = at<int32_t>(h, h->r_insteq);
+
+    h->K = at<double>(h, h->r_K);
+    h->d = at<double>(h, h->r_d);
+    h->scale = at<double>(h, h->r_scale);
+    h->arena64 = at<double>(h, h->r_arena64);
+    h->arena32 = h->precision == CKKT_FP32_IR ? at<float>(h, h->r_arena32) : nullptr;
+    h->uvec = at<double>(h, h->r_uvec);
+    h->vperm = at<double>(h, h->r_vperm);
+    h->status = at<int32_t>(h, h->r_status);
+    h->bits = at<unsigned long long>(h, h->r_bits);
+    h->dotpart = at<double>(h, h->r_dotpart);
+    h->sc = at<double>(h, h->r_sc);
+    h->vn.clear(); h->vm.clear(); h->veq.clear();
+    for (auto& r : h->r_vn) h->vn.push_back(at<double>(h, r));
+    for (auto& r : h->r_vm) h->vm.push_back(at<double>(h, r));
+    for (auto& r : h->r_veq) h->veq.push_back(at<double>(h, r));
+}
+
+ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const PatternIn& pin, ckkt_handle** out,
+                           size_t* workspace_bytes) {
+    std::string err = analyze(pin, ao, h->plan);
+    if (!err.empty()) {
+        bool internal = err.rfind("internal", 0) == 0;
+        delete h;
+        return internal ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
+    }
+    build_levels(h);
+    build_layout(h);
+    *out = h;
+    if (workspace_bytes) *workspace_bytes = h->lay.total;
+    return CKKT_OK;
+}
+
+PatternIn copy_pattern(const ckkt_pattern* p) {
+    PatternIn q;
+    q.n = p->n; q.m_eq = p->m_eq; q.m_ineq = p->m_ineq;
+    auto cp = [](std::vector<int32_t>& dst, const int32_t* src, int64_t len) {
+        dst.assign(len, 0);
+        if (len > 0 && src) std::memcpy(dst.data(), src, len * sizeof(int32_t));
+    };
+    cp(q.w_ptr, p->w_ptr, p->n + 1);
+    if (p->w_ptr && p->n >= 0) cp(q.w_idx, p->w_idx, p->w_ptr[p->n]);
+    cp(q.g_ptr, p->g_ptr, p->m_eq + 1);
+    if (p->g_ptr && p->m_eq > 0) cp(q.g_idx, p->g_idx, p->g_ptr[p->m_eq]);
+    cp(q.h_ptr, p->h_ptr, p->m_ineq + 1);
+    if (p->h_ptr && p->m_ineq > 0) cp(q.h_idx, p->h_idx, p->h_ptr[p->m_ineq]);
+    return q;
+}
+
+bool pattern_args_ok(const ckkt_pattern* p) {
+    if (!p || p->n < 0 || p->m_eq < 0 || p->m_ineq < 0) return false;
+    if (!p->w_ptr || (p->w_ptr[p->n] > 0 && !p->w_idx)) return false;
+    if (p->m_eq > 0 && (!p->g_ptr || (p->g_ptr[p->m_eq] > 0 && !p->g_idx))) return false;
+    if (p->m_ineq > 0 && (!p->h_ptr || (p->h_ptr[p->m_ineq] > 0 && !p->h_idx))) return false;
+    if (p->formulation != CKKT_LIFTED && p->formulation != CKKT_HYKKT) return false;
+    return true;
+}
+
+AnalyzeOptions analyze_options(const ckkt_options& o) {
+    AnalyzeOptions ao;
+    ao.ordering = o.ordering;
+    ao.relax = o.relax;
+    // the whole front of a small supernode lives in LDS (<= 64 KiB)
+    ao.big_front = (o.precision == CKKT_FP32_IR) ? 120 : 88;
+    return ao;
+}
+
+// ------------------------------------------------------------ numeric steps
+
+template <typename T>
+T* arena_of(ckkt_handle* h);
+template <>
+double* arena_of<double>(ckkt_handle* h) { return h->arena64; }
+template <>
+float* arena_of<float>(ckkt_handle* h) { return h->arena32; }
+
+template <typename T>
+void factor_all(ckkt_handle* h, const double* scale, hipStream_t st) {
+    T* arena = arena_of<T>(h);
+    for (const LevelInfo& L : h->levels) launch_factor_level<T>(h->dp, L, h->K, arena, h->status, scale, st);
+}
+
+// x = (L L^T)^{-1} b in the user numbering (with the Jacobi scaling of the
+// FP32 factor folded into the permutations).
+template <typename T>
+void apply_inverse_t(ckkt_handle* h, const double* b, double* x, const double* scale, hipStream_t st) {
+    PhaseTimer tm(h, 2, st);
+    const T* arena = arena_of<T>(h);
+    launch_gather_perm(h->dp, b, h->vperm, scale, st);
+    for (size_t l = 0; l < h->levels.size(); ++l) launch_fwd_level<T>(h->dp, h->levels[l], arena, h->vperm, h->uvec, st);
+    for (size_t l = h->levels.size(); l-- > 0;) launch_bwd_level<T>(h->dp, h->levels[l], arena, h->vperm, st);
+    launch_scatter_perm(h->dp, h->vperm, x, scale, st);
+}
+
+// Uses the FP64 factor when `use64`, else the handle's precision.
+void apply_inverse(ckkt_handle* h, const double* b, double* x, bool use64, hipStream_t st) {
+    if (use64 || h->precision == CKKT_FP64) apply_inverse_t<double>(h, b, x, nullptr, st);
+    else apply_inverse_t<float>(h, b, x, h->scale, st);
+}
+
+struct ResidualOut {
+    double omega = 0.0;      // max over instances
+    double resmax = 0.0;
+    std::vector<double> per_inst;
+    int32_t status0 = INT_MAX, status1 = 0;
+};
+
+double bits_to_double(unsigned long long b) {
+    double d;
+    std::memcpy(&d, &b, sizeof(d));
+    return d;
+}
+
+// Enqueue the residual of the current iterate and read omega back (sync).
+ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, const double* rhs1,
+                          const double* rhs2, double* res1, double* res2, ResidualOut& out, hipStream_t st) {
+    const int ni = h->plan.ninst;
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_zero_u64(h->bits, ni + 1, st);
+        launch_residual(h->dp, h->vals, h->d, x, y, rhs1, rhs2, res1, res2, h->vm[0], h->vm[1], h->bits,
+                        h->bits + ni, st);
+    }
+    char* host = static_cast<char*>(h->host);
+    HIP_TRY(hipMemcpyAsync(host, h->bits, (ni + 2) * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(host + (ni + 2) * sizeof(unsigned long long), h->status, 2 * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const unsigned long long* hb = reinterpret_cast<const unsigned long long*>(host);
+    out.per_inst.resize(ni);
+    out.omega = 0.0;
+    for (int i = 0; i < ni; ++i) {
+        out.per_inst[i] = bits_to_double(hb[i]);
+        out.omega = std::max(out.omega, out.per_inst[i]);
+    }
+    out.resmax = bits_to_double(hb[ni]);
+    const int32_t* hs = reinterpret_cast<const int32_t*>(host + (ni + 2) * sizeof(unsigned long long));
+    out.status0 = hs[0];
+    out.status1 = hs[1];
+    return CKKT_OK;
+}
+
+ckkt_status read_rhs_max(ckkt_handle* h, const double* a, int na, const double* b, int nb_, double& out,
+                         hipStream_t st) {
+    const int ni = h->plan.ninst;
+    unsigned long long* slot = h->bits + ni + 1;
+    launch_zero_u64(slot, 1, st);
+    launch_maxabs(na, a, slot, st);
+    if (b) launch_maxabs(nb_, b, slot, st);
+    HIP_TRY(hipMemcpyAsync(h->host, slot, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out = bits_to_double(*reinterpret_cast<unsigned long long*>(h->host));
+    return CKKT_OK;
+}
+
+ckkt_status read_scalars(ckkt_handle* h, double* dst, int count, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(h->host, h->sc, count * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(dst, h->host, count * sizeof(double));
+    return CKKT_OK;
+}
+
+bool check_factor(ckkt_handle* h, const ResidualOut& r) {
+    if (h->precision == CKKT_FP64 || h->fp64_factored) {
+        if (r.status0 != INT_MAX) {
+            h->failed_column = (r.status0 >= 0 && r.status0 < h->plan.n) ? h->plan.perm[r.status0] : r.status0;
+            return false;
+        }
+    }
+    return true;
+}
+
+// FP64 factorization of the already assembled K (fallback of FP32_IR).
+void refactor_fp64(ckkt_handle* h, hipStream_t st) {
+    PhaseTimer tm(h, 1, st);
+    launch_init_status(h->status, st);
+    factor_all<double>(h, nullptr, st);
+    h->fp64_factored = true;
+}
+
+// ------------------------------------------------------------ LiftedKKT
+
+ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_info* info, hipStream_t st) {
+    const int n = h->plan.n;
+    double* res = h->vn[0];
+    double* dx = h->vn[1];
+    double bmax = 0.0;
+    ckkt_status rc = read_rhs_max(h, b, n, nullptr, 0, bmax, st);
+    if (rc) return rc;
+    bool use64 = h->precision == CKKT_FP64 || h->fp64_factored;
+    apply_inverse(h, b, x, use64, st);
+    ResidualOut r;
+    int steps = 0;
+    double prev = INFINITY;
+    int stall = 0;
+    for (;;) {
+        rc = residual_sync(h, x, nullptr, b, nullptr, res, nullptr, r, st);
+        if (rc) return rc;
+        if (!check_factor(h, r)) { info->status = CKKT_ERR_NOT_SPD; return CKKT_ERR_NOT_SPD; }
+        info->omega = r.omega;
+        info->rho = bmax > 0 ? r.resmax / bmax : r.resmax;
+        if (r.omega <= h->opt.tol) break;
+        if (!use64) {
+            // FP32 factor: stop refining when it stagnates and fall back to the
+            // FP64 factor of the same assembled matrix.
+            if (!(r.omega < 0.5 * prev)) stall++;
+            if (stall >= 2 || steps >= h->opt.ir_maxit) {
+                refactor_fp64(h, st);
+                use64 = true;
+                info->fallback = 2;
+                apply_inverse(h, b, x, true, st);
+                steps = 0;
+                prev = INFINITY;
+                stall = 0;
+                continue;
+            }
+        } else if (steps >= h->opt.ir_maxit) {
+            info->refine_steps = steps;
+            return CKKT_ERR_NO_CONVERGENCE;
+        }
+        prev = r.omega;
+        apply_inverse(h, res, dx, use64, st);
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_axpy(n, 1.0, dx, x, st);
+        }
+        steps++;
+    }
+    info->refine_steps = steps;
+    return CKKT_OK;
+}
+
+// ------------------------------------------------------------ HyKKT
+
+// One HyKKT solve of K1 (dx, dy) = (R1, R2) through K_gamma (Sec. 3.1):
+// s = R1 + gamma G^T R2, w = K_gamma^{-1} s, CG on S_gamma dy = G w - R2
+// (eq:kkt:schurcomplhykkt) from dy = 0, then dx = w - sum_k alpha_k u_k with
+// u_k = K_gamma^{-1} G^T p_k, which equals K_gamma^{-1}(s - G^T dy).
+ckkt_status hykkt_inner(ckkt_handle* h, const double* R1, const double* R2, double* dx, double* dy, bool use64,
+                        int& cg_iters, bool& cg_ok, hipStream_t st) {
+    const DevPlan& P = h->dp;
+    const int n = P.n, me = P.m_eq;
+    double* s = h->vn[2];
+    double* t = h->vn[3];
+    double* u = h->vn[4];
+    double* r = h->veq[0];
+    double* p = h->veq[1];
+    double* q = h->veq[2];
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_gt(P, h->vals, R1, h->vals.gamma, R2, s, st);
+    }
+    apply_inverse(h, s, dx, use64, st);  // dx holds w and accumulates
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_g(P, h->vals, dx, R2, r, st);
+        launch_fill(me, 0.0, dy, st);
+        launch_copy(me, r, p, st);
+        launch_dot(me, r, r, h->dotpart, h->sc + 0, st);
+    }
+    double hs[5];
+    ckkt_status rc = read_scalars(h, hs, 1, st);
+    if (rc) return rc;
+    const double rr0 = hs[0];
+    cg_ok = true;
+    if (!(rr0 > 0.0)) return rr0 == 0.0 ? CKKT_OK : CKKT_ERR_BREAKDOWN;
+    const double stop = h->opt.cg_tol * std::sqrt(rr0);
+    int maxit = h->opt.cg_maxit > 0 ? h->opt.cg_maxit : std::max(1, std::min(me, 1000));
+    for (int k = 1; k <= maxit; ++k) {
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_gt(P, h->vals, nullptr, 1.0, p, t, st);
+        }
+        apply_inverse(h, t, u, use64, st);
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_g(P, h->vals, u, nullptr, q, st);
+            launch_dot(me, p, q, h->dotpart, h->sc + 1, st);
+            launch_cg_alpha(h->sc, st);
+            launch_cg_update(me, h->sc, p, q, dy, r, st);
+            launch_axpy_dev(n, h->sc, 2, -1.0, u, dx, st);
+            launch_dot(me, r, r, h->dotpart, h->sc + 3, st);
+        }
+        rc = read_scalars(h, hs, 4, st);
+        if (rc) return rc;
+        cg_iters++;
+        if (!(hs[1] > 0.0) || !std::isfinite(hs[1])) return CKKT_ERR_BREAKDOWN;
+        if (std::sqrt(hs[3]) <= stop) return CKKT_OK;
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_cg_beta(h->sc, st);
+            launch_cg_direction(me, h->sc, r, p, st);
+        }
+    }
+    cg_ok = false;
+    return CKKT_OK;
+}
+
+ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_solve_info* info, hipStream_t st) {
+    const int n = h->plan.n, me = h->plan.m_eq;
+    const double* r1 = rhs;
+    const double* r2 = rhs + n;
+    double* x = sol;
+    double* y = sol + n;
+    double* res1 = h->vn[0];
+    double* res2 = h->veq[3];
+    double* ddx = h->vn[1];
+    double* ddy = h->veq[4];
+    double bmax = 0.0;
+    ckkt_status rc = read_rhs_max(h, r1, n, r2, me, bmax, st);
+    if (rc) return rc;
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_fill(n + me, 0.0, sol, st);
+    }
+    bool use64 = h->precision == CKKT_FP64 || h->fp64_factored;
+    ResidualOut r;
+    int steps = 0, stall = 0;
+    double prev = INFINITY;
+    bool last_cg_ok = true;
+    for (;;) {
+        rc = residual_sync(h, x, y, r1, r2, res1, res2, r, st);
+        if (rc) return rc;
+        if (!check_factor(h, r)) { info->status = CKKT_ERR_NOT_SPD; return CKKT_ERR_NOT_SPD; }
+        info->omega = r.omega;
+        info->rho = bmax > 0 ? r.resmax / bmax : r.resmax;
+        if (r.omega <= h->opt.tol && steps > 0) break;
+        if (steps > 0 && !use64) {
+            if (!(r.omega < 0.5 * prev)) stall++;
+            if (stall >= 2 || steps > h->opt.ir_maxit) {
+                refactor_fp64(h, st);
+                use64 = true;
+                info->fallback = 2;
+                stall = 0;
+                prev = INFINITY;
+            }
+        } else if (steps > h->opt.ir_maxit) {
+            info->refine_steps = steps - 1;
+            return last_cg_ok ? CKKT_ERR_NO_CONVERGENCE : CKKT_ERR_NO_CONVERGENCE;
+        }
+        prev = r.omega;
+        int it = 0;
+        bool ok = true;
+        rc = hykkt_inner(h, res1, res2, ddx, ddy, use64, it, ok, st);
+        info->cg_iters += it;
+        last_cg_ok = ok;
+        if (rc) return rc;
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_axpy(n, 1.0, ddx, x, st);
+            launch_axpy(me, 1.0, ddy, y, st);
+        }
+        steps++;
+    }
+    info->refine_steps = steps - 1;
+    return CKKT_OK;
+}
+
+}  // namespace
+
+// ================================================================= C-ABI
+
+extern "C" {
+
+void ckkt_default_options(ckkt_options* o) {
+    if (!o) return;
+    o->precision = CKKT_FP64;
+    o->ordering = CKKT_ORDER_AMD;
+    o->tol = 1e-10;
+    o->ir_maxit = 10;
+    o->cg_tol = 1e-10;
+    o->cg_maxit = 0;
+    o->relax = 1;
+}
+
+ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
+                         size_t* workspace_bytes) {
+    if (!out || !pattern_args_ok(pat)) return CKKT_ERR_ARG;
+    *out = nullptr;
+    ckkt_handle* h = new (std::nothrow) ckkt_handle();
+    if (!h) return CKKT_ERR_ARG;
+    if (opt) h->opt = *opt;
+    else ckkt_default_options(&h->opt);
+    if (h->opt.precision != CKKT_FP64 && h->opt.precision != CKKT_FP32_IR) { delete h; return CKKT_ERR_ARG; }
+    if (h->opt.ordering != CKKT_ORDER_AMD && h->opt.ordering != CKKT_ORDER_NATURAL) { delete h; return CKKT_ERR_ARG; }
+    h->formulation = pat->formulation;
+    h->precision = h->opt.precision;
+    PatternIn pin = copy_pattern(pat);
+    return finish_analyze(h, analyze_options(h->opt), pin, out, workspace_bytes);
+}
+
+ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt,
+                               ckkt_handle** out, size_t* workspace_bytes) {
+    if (!out || count <= 0 || !pats) return CKKT_ERR_ARG;
+    *out = nullptr;
+    for (int i = 0; i < count; ++i) {
+        if (!pattern_args_ok(&pats[i]) || pats[i].formulation != pats[0].formulation) return CKKT_ERR_ARG;
+    }
+    ckkt_handle* h = new (std::nothrow) ckkt_handle();
+    if (!h) return CKKT_ERR_ARG;
+    if (opt) h->opt = *opt;
+    else ckkt_default_options(&h->opt);
+    h->formulation = pats[0].formulation;
+    h->precision = h->opt.precision;
+    // block-diagonal union: variables and W blocks in instance order, then
+    // all G rows (instance order), then all H rows (instance order)
+    PatternIn u;
+    int64_t n = 0, me = 0, mi = 0;
+    for (int i = 0; i < count; ++i) { n += pats[i].n; me += pats[i].m_eq; mi += pats[i].m_ineq; }
+    if (n > (int64_t)1 << 30) { delete h; return CKKT_ERR_ARG; }
+    u.n = n; u.m_eq = me; u.m_ineq = mi;
+    u.w_ptr.push_back(0); u.g_ptr.push_back(0); u.h_ptr.push_back(0);
+    Plan& P = h->plan;
+    P.ninst = count;
+    P.inst_n.assign(count + 1, 0);
+    P.inst_meq.assign(count + 1, 0);
+    P.inst_of_var.assign(n, 0);
+    P.inst_of_eqrow.assign(me, 0);
+    int64_t off = 0, roff = 0;
+    for (int i = 0; i < count; ++i) {
+        const ckkt_pattern& p = pats[i];
+        for (int64_t r = 0; r < p.n; ++r) {
+            for (int32_t k = p.w_ptr[r]; k < p.w_ptr[r + 1]; ++k) u.w_idx.push_back((int32_t)(p.w_idx[k] + off));
+            u.w_ptr.push_back((int32_t)u.w_idx.size());
+            P.inst_of_var[off + r] = i;
+        }
+        for (int64_t r = 0; r < p.m_eq; ++r) {
+            for (int32_t k = p.g_ptr[r]; k < p.g_ptr[r + 1]; ++k) u.g_idx.push_back((int32_t)(p.g_idx[k] + off));
+            u.g_ptr.push_back((int32_t)u.g_idx.size());
+            P.inst_of_eqrow[roff + r] = i;
+        }
+        for (int64_t r = 0; r < p.m_ineq; ++r) {
+            for (int32_t k = p.h_ptr[r]; k < p.h_ptr[r + 1]; ++k) u.h_idx.push_back((int32_t)(p.h_idx[k] + off));
+            u.h_ptr.push_back((int32_t)u.h_idx.size());
+        }
+        off += p.n;
+        roff += p.m_eq;
+        P.inst_n[i + 1] = (int32_t)off;
+        P.inst_meq[i + 1] = (int32_t)roff;
+    }
+    return finish_analyze(h, analyze_options(h->opt), u, out, workspace_bytes);
+}
+
+ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, void* stream) {
+    if (!h) return CKKT_ERR_ARG;
+    if (!dev_ptr || bytes < h->lay.total || (reinterpret_cast<uintptr_t>(dev_ptr) & 255)) return CKKT_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!h->host) {
+        h->host_bytes = (h->plan.ninst + 8) * sizeof(unsigned long long) + 64;
+        if (hipHostMalloc(&h->host, h->host_bytes, hipHostMallocDefault) != hipSuccess) {
+            h->host = nullptr;
+            return CKKT_ERR_HIP;
+        }
+    }
+    h->ws = static_cast<char*>(dev_ptr);
+    h->ws_bytes = bytes;
+    for (auto& pr : h->plan_regions)
+        if (pr.r.bytes > 0)
+            HIP_TRY(hipMemcpyAsync(h->ws + pr.r.off, pr.host, pr.r.bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    fill_devplan(h);
+    h->factored = false;
+    h->fp64_factored = false;
+    return CKKT_OK;
+}
+
+ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                           const double* sigma_x, const double* sigma_s, double gamma, void* stream) {
+    if (!h) return CKKT_ERR_ARG;
+    if (!h->ws) return CKKT_ERR_STATE;
+    const Plan& P = h->plan;
+    if ((P.nnz_w > 0 && !w_val) || (P.nnz_g > 0 && !g_val) || (P.nnz_h > 0 && !h_val) || (P.n > 0 && !sigma_x))
+        return CKKT_ERR_ARG;
+    int64_t ns_len = h->formulation == CKKT_HYKKT ? P.m_ineq : P.m;
+    if (ns_len > 0 && !sigma_s) return CKKT_ERR_ARG;
+    if (h->formulation == CKKT_HYKKT && P.m_eq > 0 && !(gamma > 0.0 && std::isfinite(gamma))) return CKKT_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    h->vals = SysVals{w_val, g_val, h_val, sigma_x, sigma_s, gamma};
+    h->failed_column = -1;
+    h->fp64_factored = false;
+    {
+        PhaseTimer tm(h, 0, st);
+        launch_init_status(h->status, st);
+        launch_row_weights(h->dp, h->vals, h->d, st);
+        launch_assemble(h->dp, h->vals, h->d, h->K, st);
+        if (h->precision == CKKT_FP32_IR) launch_diag_scale(h->dp, h->K, h->scale, st);
+    }
+    {
+        PhaseTimer tm(h, 1, st);
+        if (h->precision == CKKT_FP64) {
+            factor_all<double>(h, nullptr, st);
+            h->fp64_factored = true;
+        } else {
+            factor_all<float>(h, h->scale, st);
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return CKKT_ERR_HIP;
+    h->factored = true;
+    return CKKT_OK;
+}
+
+ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream) {
+    if (!h) return CKKT_ERR_ARG;
+    if (!h->factored) return CKKT_ERR_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(h->host, h->status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int32_t s0 = static_cast<int32_t*>(h->host)[0];
+    if (h->fp64_factored && s0 != INT_MAX) {
+        h->failed_column = (s0 >= 0 && s0 < h->plan.n) ? h->plan.perm[s0] : s0;
+        return CKKT_ERR_NOT_SPD;
+    }
+    return CKKT_OK;
+}
+
+ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol, ckkt_solve_info* info, void* stream) {
+    ckkt_solve_info local{};
+    if (!info) info = &local;
+    std::memset(info, 0, sizeof(*info));
+    if (!h) return info->status = CKKT_ERR_ARG;
+    if (!h->ws || !h->factored) return info->status = CKKT_ERR_STATE;
+    if ((h->plan.n > 0 || h->plan.m_eq > 0) && (!rhs || !sol)) return info->status = CKKT_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ckkt_status rc = h->formulation == CKKT_HYKKT ? solve_hykkt(h, rhs, sol, info, st)
+                                                   : solve_lifted(h, rhs, sol, info, st);
+    if (rc == CKKT_OK && hipGetLastError() != hipSuccess) rc = CKKT_ERR_HIP;
+    info->status = rc;
+    return rc;
+}
+
+ckkt_status ckkt_apply_inverse(ckkt_handle* h, const double* rhs, double* sol, void* stream) {
+    if (!h) return CKKT_ERR_ARG;
+    if (!h->ws || !h->factored) return CKKT_ERR_STATE;
+    if (h->plan.n > 0 && (!rhs || !sol)) return CKKT_ERR_ARG;
+    apply_inverse(h, rhs, sol, h->fp64_factored, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
+}
+
+ckkt_status ckkt_export_k(ckkt_handle* h, int32_t* rows, int32_t* cols, double* values, void* stream) {
+    if (!h) return CKKT_ERR_ARG;
+    const Plan& P = h->plan;
+    if (rows || cols) {
+        for (int32_t j = 0; j < P.n; ++j)
+            for (int32_t t = P.kcolptr[j]; t < P.kcolptr[j + 1]; ++t) {
+                int32_t a = P.perm[P.krow[t]], b = P.perm[j];
+                if (rows) rows[t] = std::max(a, b);
+                if (cols) cols[t] = std::min(a, b);
+            }
+    }
+    if (values) {
+        if (!h->ws || !h->factored) return CKKT_ERR_STATE;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        HIP_TRY(hipMemcpyAsync(values, h->K, P.kcolptr.back() * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return CKKT_OK;
+}
+
+ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, const double* g_val,
+                                  const double* h_val, const double* sigma_x, const double* sigma_s,
+                                  double gamma, const double* rhs, double* sol, int32_t* failed_column) {
+    if (!h || !rhs || !sol) return CKKT_ERR_ARG;
+    int fc = host_factor_solve(h->plan, h->formulation == CKKT_HYKKT, w_val, g_val, h_val, sigma_x, sigma_s, gamma,
+                               rhs, sol);
+    if (failed_column) *failed_column = fc;
+    return fc >= 0 ? CKKT_ERR_NOT_SPD : CKKT_OK;
+}
+
+ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info) {
+    if (!h || !info) return CKKT_ERR_ARG;
+    const Plan& P = h->plan;
+    std::memset(info, 0, sizeof(*info));
+    info->n = P.n;
+    info->m_eq = P.m_eq;
+    info->m_ineq = P.m_ineq;
+    info->nnz_k = P.kcolptr.empty() ? 0 : P.kcolptr.back();
+    info->nnz_l = P.nnz_l;
+    info->nnz_l_stored = P.nnz_l_stored;
+    info->factor_flops = P.flops;
+    info->assembly_products = (double)P.prod_r.size();
+    info->n_supernodes = P.ns;
+    info->n_levels = P.nlev;
+    info->max_front = P.max_front;
+    info->n_big_fronts = P.n_big;
+    info->workspace_bytes = (int64_t)h->lay.total;
+    info->analyze_seconds = P.analyze_seconds;
+    info->failed_column = h->failed_column;
+    return CKKT_OK;
+}
+
+const char* ckkt_status_string(ckkt_status s) {
+    switch (s) {
+        case CKKT_OK: return "ok";
+        case CKKT_ERR_ARG: return "invalid argument";
+        case CKKT_ERR_PATTERN: return "malformed sparsity pattern";
+        case CKKT_ERR_NOT_SPD: return "matrix not positive definite (non-positive pivot)";
+        case CKKT_ERR_NO_CONVERGENCE: return "refinement or CG did not converge";
+        case CKKT_ERR_BREAKDOWN: return "CG breakdown";
+        case CKKT_ERR_STATE: return "call out of order";
+        case CKKT_ERR_HIP: return "HIP runtime error";
+        case CKKT_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+        case CKKT_ERR_NONFINITE: return "non-finite input";
+        default: return "unknown status";
+    }
+}
+
+void ckkt_destroy(ckkt_handle* h) {
+    if (!h) return;
+    for (auto& p : h->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : h->event_pool) (void)hipEventDestroy(e);
+    if (h->host) (void)hipHostFree(h->host);
+    delete h;
+}
+
+ckkt_status ckkt_set_timing(ckkt_handle* h, int32_t enable) {
+    if (!h) return CKKT_ERR_ARG;
+    h->timing = enable != 0;
+    return CKKT_OK;
+}
+
+ckkt_status ckkt_get_timing(ckkt_handle* h, double ms[4], int64_t calls[4]) {
+    if (!h || !ms || !calls) return CKKT_ERR_ARG;
+    for (auto& p : h->pending) {
+        HIP_TRY(hipEventSynchronize(p.b));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, p.a, p.b));
+        h->ms[p.phase] += t;
+        h->calls[p.phase] += 1;
+        h->event_pool.push_back(p.a);
+        h->event_pool.push_back(p.b);
+    }
+    h->pending.clear();
+    for (int i = 0; i < 4; ++i) {
+        ms[i] = h->ms[i];
+        calls[i] = h->calls[i];
+        h->ms[i] = 0;
+        h->calls[i] = 0;
+    }
+    return CKKT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Device-side view of the analysis plan and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ckkt {
+
+// Plain pointers into the bound workspace; passed to kernels by value.
+struct DevPlan {
+    int32_t n, m_eq, m_ineq, m, ns, ninst, hy;
+    int64_t nnzk, nnzg;
+    const int32_t *perm, *iperm;
+    const int32_t *kcolptr, *k_wsrc, *k_diag, *prod_ptr, *prod_r, *prod_a, *prod_b;
+    const int32_t *sn_start, *sn_rowptr, *sn_rows, *child_ptr, *child_list, *relmap, *kmap;
+    const int64_t *l_off, *u_off;
+    const int32_t *u_ld;
+    const int32_t *lvl_small, *lvl_big, *lvl_all, *big_tile_sn, *big_tile_col;
+    const int32_t *wf_ptr, *wf_col, *wf_vidx;
+    const int32_t *j_ptr, *j_col, *jt_ptr, *jt_row, *jt_vidx, *jt_gend;
+    const int32_t *inst_of_var, *inst_of_eqrow;
+};
+
+// Values of the current system (device pointers owned by the caller).
+struct SysVals {
+    const double *w_val, *g_val, *h_val, *sigma_x, *sigma_s;
+    double gamma;
+};
+
+// Per-level launch geometry, computed on the host from the plan.
+struct LevelInfo {
+    int32_t small_begin, small_count, small_maxf;
+    int32_t big_begin, big_count, big_maxw, big_maxf;
+    int32_t all_begin, all_count, all_maxf;
+    int32_t tile_begin, tile_count;
+};
+
+constexpr int kBigTile = 64;    // column tile of the tiled front path
+constexpr int kPanelNB = 32;    // panel width of the tiled front path
+
+// ---- launchers (kernels.hip)
+void launch_row_weights(const DevPlan& P, const SysVals& v, double* d, hipStream_t st);
+void launch_assemble(const DevPlan& P, const SysVals& v, const double* d, double* K, hipStream_t st);
+void launch_init_status(int32_t* status, hipStream_t st);
+
+template <typename T>
+void launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
+                         int32_t* status, const double* scale, hipStream_t st);
+template <typename T>
+void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* v_perm,
+                      double* uvec, hipStream_t st);
+template <typename T>
+void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* x_perm,
+                      hipStream_t st);
+
+// out[k] = in[perm[k]] * (scale ? scale[k] : 1)      (to the factor numbering)
+void launch_gather_perm(const DevPlan& P, const double* in, double* out, const double* scale, hipStream_t st);
+// out[perm[k]] = in[k] * (scale ? scale[k] : 1)      (back to the user numbering)
+void launch_scatter_perm(const DevPlan& P, const double* in, double* out, const double* scale, hipStream_t st);
+
+// Residual of LiftedKKT (hy = 0) or of K1 (hy = 1) with K unassembled,
+// plus the componentwise backward error per instance (omega_bits, as
+// uint64 of nonnegative doubles, must be zeroed first) and max |res|.
+void launch_residual(const DevPlan& P, const SysVals& v, const double* d, const double* x,
+                     const double* y, const double* rhs1, const double* rhs2, double* res1,
+                     double* res2, double* tbuf, double* tabuf, unsigned long long* omega_bits,
+                     unsigned long long* resmax_bits, hipStream_t st);
+void launch_zero_u64(unsigned long long* p, int count, hipStream_t st);
+void launch_maxabs(int n, const double* x, unsigned long long* bits, hipStream_t st);  // atomic max of |x|
+
+// Vector kernels
+void launch_axpy(int n, double alpha, const double* x, double* y, hipStream_t st);  // y += a x
+void launch_copy(int n, const double* x, double* y, hipStream_t st);
+void launch_fill(int n, double v, double* y, hipStream_t st);
+// out_i = base_i + scale * (G^T y)_i   (base may be null)
+void launch_gt(const DevPlan& P, const SysVals& v, const double* base, double scale, const double* y,
+               double* out, hipStream_t st);
+// out_r = (G x)_r - sub_r   (sub may be null)
+void launch_g(const DevPlan& P, const SysVals& v, const double* x, const double* sub, double* out,
+              hipStream_t st);
+
+// Deterministic dot product into *result (device); partial buffer of
+// kDotBlocks doubles.
+constexpr int kDotBlocks = 256;
+void launch_dot(int n, const double* a, const double* b, double* partial, double* result, hipStream_t st);
+
+// CG helpers with device-resident scalars.  sc[0] = rr, sc[1] = pq,
+// sc[2] = alpha, sc[3] = rr_new, sc[4] = beta.
+void launch_cg_alpha(double* sc, hipStream_t st);                       // alpha = rr / pq
+void launch_cg_update(int m, const double* sc, const double* p, const double* q, double* y, double* r,
+                      hipStream_t st);                                  // y += a p, r -= a q
+void launch_cg_beta(double* sc, hipStream_t st);                        // beta = rr_new / rr, rr = rr_new
+void launch_cg_direction(int m, const double* sc, const double* r, double* p, hipStream_t st);  // p = r + b p
+void launch_axpy_dev(int n, const double* sc, int idx, double sign, const double* x, double* y,
+                     hipStream_t st);                                   // y += sign * sc[idx] * x
+
+// Jacobi scale s_k = 1/sqrt(K_kk) over the factor numbering (FP32 path).
+void launch_diag_scale(const DevPlan& P, const double* K, double* scale, hipStream_t st);
+
+}  // namespace ckkt

@@ -1,0 +1,185 @@
+"""Python binding of the condensed-KKT library: argument marshalling only.
+
+Every step of the path (assembly, factorization, sweeps, refinement, CG)
+runs in the HIP library; this module passes pointers of torch tensors and
+the caller's current HIP stream through the C-ABI declared in
+include/ckkt.h.  Torch provides device memory (the workspace and the
+value/right-hand-side/solution tensors) and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(L.P_i32)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(L.P_f64)
+
+
+def _pattern(prob, formulation):
+    keep = []
+    fields = {}
+    for key in ("w_ptr", "w_idx", "g_ptr", "g_idx", "h_ptr", "h_idx"):
+        arr, ptr = _i32(getattr(prob, key))
+        keep.append(arr)
+        fields[key] = ptr
+    pat = L.Pattern(n=prob.n, m_eq=prob.m_eq, m_ineq=prob.m_ineq, formulation=formulation, **fields)
+    return pat, keep
+
+
+def options(precision="fp64", ordering="amd", tol=1e-10, ir_maxit=10, cg_tol=1e-10, cg_maxit=0, relax=1):
+    lib = L.load()
+    o = L.Options()
+    lib.ckkt_default_options(ctypes.byref(o))
+    o.precision = {"fp64": L.FP64, "fp32_ir": L.FP32_IR}[precision]
+    o.ordering = {"amd": L.ORDER_AMD, "natural": L.ORDER_NATURAL}[ordering]
+    o.tol, o.ir_maxit, o.cg_tol, o.cg_maxit, o.relax = tol, ir_maxit, cg_tol, cg_maxit, relax
+    return o
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """One analysed pattern (single system, or a block-diagonal batch).
+
+    ``formulation``: "lifted" (K_tau d_x = b) or "hykkt" (K1 through K_gamma + CG).
+    ``precision``: "fp64" or "fp32_ir" (FP32 factor, FP64 refinement).
+    """
+
+    def __init__(self, prob, formulation="lifted", precision="fp64", *, batch: Optional[Sequence] = None,
+                 **opts):
+        self.lib = L.load()
+        self.formulation = {"lifted": L.LIFTED, "hykkt": L.HYKKT}[formulation]
+        self.opts = options(precision=precision, **opts)
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        if batch is None:
+            pat, self._keep = _pattern(prob, self.formulation)
+            L.check(self.lib.ckkt_analyze(ctypes.byref(pat), ctypes.byref(self.opts), ctypes.byref(h),
+                                          ctypes.byref(ws)), "ckkt_analyze")
+            self.n, self.m_eq, self.m_ineq = prob.n, prob.m_eq, prob.m_ineq
+        else:
+            pats, keep = [], []
+            for p in batch:
+                pat, k = _pattern(p, self.formulation)
+                pats.append(pat)
+                keep += k
+            arr = (L.Pattern * len(pats))(*pats)
+            L.check(self.lib.ckkt_batch_analyze(len(pats), arr, ctypes.byref(self.opts), ctypes.byref(h),
+                                                ctypes.byref(ws)), "ckkt_batch_analyze")
+            self._keep = keep
+            self.n = sum(p.n for p in batch)
+            self.m_eq = sum(p.m_eq for p in batch)
+            self.m_ineq = sum(p.m_ineq for p in batch)
+        self.h = h
+        self.workspace_bytes = ws.value
+        self.workspace = None
+        self._vals = None
+
+    # ---------------------------------------------------------------- info
+    def info(self):
+        inf = L.Info()
+        L.check(self.lib.ckkt_get_info(self.h, ctypes.byref(inf)), "ckkt_get_info")
+        return inf.as_dict()
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.ckkt_destroy(h)
+            self.h = None
+
+    # ------------------------------------------------------------- device
+    def bind(self, device="cuda"):
+        import torch
+        self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
+        L.check(self.lib.ckkt_bind_workspace(self.h, _ptr(self.workspace), self.workspace.numel(), _stream()),
+                "ckkt_bind_workspace")
+        return self
+
+    def factorize(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma=0.0):
+        """Device float64 tensors; kept referenced until the next factorize."""
+        if self.workspace is None:
+            self.bind()
+        self._vals = (w_val, g_val, h_val, sigma_x, sigma_s)
+        L.check(self.lib.ckkt_factorize(self.h, _ptr(w_val), _ptr(g_val), _ptr(h_val), _ptr(sigma_x),
+                                        _ptr(sigma_s), float(gamma), _stream()), "ckkt_factorize")
+
+    def factor_status(self):
+        return self.lib.ckkt_factor_status(self.h, _stream())
+
+    def solve(self, rhs, out=None, raise_on_error=True):
+        import torch
+        if out is None:
+            out = torch.empty_like(rhs)
+        si = L.SolveInfo()
+        st = self.lib.ckkt_solve(self.h, _ptr(rhs), _ptr(out), ctypes.byref(si), _stream())
+        if raise_on_error:
+            L.check(st, "ckkt_solve")
+        return out, si.as_dict()
+
+    def apply_inverse(self, rhs, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(rhs)
+        L.check(self.lib.ckkt_apply_inverse(self.h, _ptr(rhs), _ptr(out), _stream()), "ckkt_apply_inverse")
+        return out
+
+    def export_k(self):
+        import torch
+        nnz = self.info()["nnz_k"]
+        rows = np.empty(nnz, np.int32)
+        cols = np.empty(nnz, np.int32)
+        vals = torch.empty(nnz, dtype=torch.float64, device=self.workspace.device)
+        L.check(self.lib.ckkt_export_k(self.h, rows.ctypes.data_as(L.P_i32), cols.ctypes.data_as(L.P_i32),
+                                       _ptr(vals), _stream()), "ckkt_export_k")
+        return rows, cols, vals
+
+    def set_timing(self, on=True):
+        L.check(self.lib.ckkt_set_timing(self.h, int(on)))
+
+    def get_timing(self):
+        ms = (ctypes.c_double * 4)()
+        calls = (ctypes.c_int64 * 4)()
+        L.check(self.lib.ckkt_get_timing(self.h, ms, calls))
+        return list(ms), list(calls)
+
+    # ---------------------------------------------------------------- host
+    def host_factor_solve(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma, rhs):
+        """Sequential host run of the numeric phase over the same plan (no GPU)."""
+        keep = [_f64(a) for a in (w_val, g_val, h_val, sigma_x, sigma_s, rhs)]
+        out = np.empty(len(rhs), np.float64)
+        fc = ctypes.c_int32(-1)
+        st = self.lib.ckkt_host_factor_solve(self.h, keep[0][1], keep[1][1], keep[2][1], keep[3][1], keep[4][1],
+                                             float(gamma), keep[5][1], out.ctypes.data_as(L.P_f64),
+                                             ctypes.byref(fc))
+        return out, st, fc.value
+
+
+def device_values(prob, device="cuda", formulation="lifted"):
+    """Uploads a problem's values as float64 device tensors (w, g, h, sigma_x, sigma_s)."""
+    import torch
+
+    def t(a):
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+    ss = prob.sigma_s if formulation == "lifted" else prob.sigma_s_ineq
+    return t(prob.w_val), t(prob.g_val), t(prob.h_val), t(prob.sigma_x), t(ss)

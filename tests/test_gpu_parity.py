@@ -1,0 +1,188 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Gates (the residual reading is the componentwise relative backward error
+omega, computed by the oracle on the GPU's output):
+  * FP64 LiftedKKT and HyKKT: omega <= 1e-10 (and the library's own omega
+    agrees with the oracle's to within rounding);
+  * assembled K: every entry within 8 u (|W_ij| + sum_r |d_r J_ri J_rj|) of
+    the oracle's brute-force assembly;
+  * one factor application: identical (to rounding) to the host run of the
+    same plan, and omega of K^{-1} b small;
+  * forward error vs the oracle's solution reported, and gated only on
+    well-conditioned inputs.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dense as od
+from oracle import sparse as osp
+from paper_2405_14236_amd import workloads
+from paper_2405_14236_amd.solver import Solver, device_values
+from tests._common import omega_kgamma, omega_of, rhs_of, sigma_rows
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+U64 = np.finfo(np.float64).eps / 2
+
+
+def run(p, formulation, precision="fp64", gamma=1e7, **opts):
+    s = Solver(p, formulation, precision, **opts).bind(DEV)
+    vals = device_values(p, DEV, formulation)
+    s.factorize(*vals, gamma=gamma)
+    rhs = torch.as_tensor(rhs_of(p, formulation), device=DEV)
+    sol, info = s.solve(rhs)
+    torch.cuda.synchronize()
+    return s, vals, sol.cpu().numpy(), info
+
+
+def print_case(name, **kw):
+    print(f"\n[case] {name} {kw}", flush=True)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_lifted_fp64(seed):
+    p = workloads.tiny_grid(seed)
+    print_case("tiny_lifted_fp64", seed=seed, n=p.n)
+    s, vals, x, info = run(p, "lifted")
+    om = omega_of(p, "lifted", x)
+    assert om <= 1e-10, (om, info)
+    assert info["omega"] <= 1e-10
+    # the library's omega is the oracle's up to rounding of the residual
+    assert abs(info["omega"] - om) <= 1e-14 + 0.1 * om
+    P = osp.Problem(p)
+    xo, _ = osp.solve_lifted(P, p.sigma_x, p.sigma_s, p.b)
+    fe = np.abs(x - xo).max() / np.abs(xo).max()
+    print("forward error vs oracle", fe, info)
+    assert fe < 1e-4  # kappa ~ 1e8 on this input
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_tiny_hykkt_fp64(seed):
+    p = workloads.tiny_grid(seed)
+    print_case("tiny_hykkt_fp64", seed=seed, n=p.n)
+    s, vals, z, info = run(p, "hykkt")
+    om = omega_of(p, "hykkt", z)
+    assert om <= 1e-10, (om, info)
+    assert info["cg_iters"] > 0
+    P = osp.Problem(p)
+    dx, dy, _ = osp.solve_k1(P, p.sigma_x, p.sigma_s_ineq, p.r1bar, p.r2bar)
+    fe = np.abs(z[:p.n] - dx).max() / np.abs(dx).max()
+    print("forward error vs oracle", fe, info)
+
+
+def test_well_conditioned_forward_error():
+    """Diagonals in [0.1, 10]: the solution itself must match the oracle."""
+    p = workloads.tiny_grid(4, sigma_range=(-1, 1))
+    print_case("tiny_wellcond", n=p.n)
+    for form in ("lifted", "hykkt"):
+        s, vals, z, info = run(p, form)
+        P = osp.Problem(p)
+        if form == "lifted":
+            xo, _ = osp.solve_lifted(P, p.sigma_x, p.sigma_s, p.b)
+            assert np.abs(z - xo).max() <= 1e-10 * np.abs(xo).max()
+        else:
+            dx, dy, _ = osp.solve_k1(P, p.sigma_x, p.sigma_s_ineq, p.r1bar, p.r2bar)
+            assert np.abs(z[:p.n] - dx).max() <= 1e-9 * np.abs(dx).max()
+            assert np.abs(z[p.n:] - dy).max() <= 1e-9 * np.abs(dy).max()
+
+
+@pytest.mark.parametrize("formulation", ["lifted", "hykkt"])
+def test_assembled_k_matches_oracle(formulation):
+    p = workloads.tiny_grid(5)
+    print_case("assembly", formulation=formulation)
+    gamma = 1e7
+    s = Solver(p, formulation).bind(DEV)
+    s.factorize(*device_values(p, DEV, formulation), gamma=gamma)
+    rows, cols, vals = s.export_k()
+    kv = vals.cpu().numpy()
+    W, G, H = od.problem_dense(p)
+    J = np.vstack([G, H])
+    d = sigma_rows(p, formulation, gamma)
+    K = od.assemble_bruteforce(W, p.sigma_x, J, d)
+    mag = np.abs(W) + np.diag(p.sigma_x) + np.abs(J).T @ np.diag(np.abs(d)) @ np.abs(J)
+    err = np.abs(kv - K[rows, cols])
+    assert np.all(err <= 8 * U64 * mag[rows, cols] + 1e-300), err.max()
+    # every structural entry of K is present exactly once
+    assert len(set(zip(rows.tolist(), cols.tolist()))) == len(rows)
+    nz = np.argwhere(np.tril(mag) > 0)
+    assert len(nz) == len(rows)
+
+
+@pytest.mark.parametrize("formulation", ["lifted", "hykkt"])
+def test_factor_application_matches_host_run(formulation):
+    """Device sweeps/factor == host run of the same plan (same arithmetic up to
+    FMA contraction), on a size that uses both front paths."""
+    p = workloads.network_flow(4000, seed=4)
+    print_case("apply_inverse_vs_host", formulation=formulation, n=p.n)
+    gamma = 1e7
+    s = Solver(p, formulation).bind(DEV)
+    assert s.info()["n_big_fronts"] > 0
+    vals = device_values(p, DEV, formulation)
+    s.factorize(*vals, gamma=gamma)
+    b = torch.as_tensor(p.b, device=DEV)
+    x = s.apply_inverse(b).cpu().numpy()
+    ss = p.sigma_s if formulation == "lifted" else p.sigma_s_ineq
+    xh, st, fc = s.host_factor_solve(p.w_val, p.g_val, p.h_val, p.sigma_x, ss, gamma, p.b)
+    assert st == 0
+    scale = np.abs(xh).max()
+    assert np.abs(x - xh).max() <= 1e-6 * scale, np.abs(x - xh).max() / scale
+    assert omega_kgamma(p, x, p.b, gamma if formulation == "hykkt" else 0.0) < 1e-9 if formulation == "hykkt" \
+        else osp.omega_condensed(osp.Problem(p).W, p.sigma_x, osp.Problem(p).J, p.sigma_s, x, p.b) < 1e-9
+
+
+@pytest.mark.parametrize("formulation", ["lifted", "hykkt"])
+def test_network_flow_10k_fp64(formulation):
+    """The n = 66,000 network-flow workload (10k nodes, 13k edges)."""
+    p = workloads.network_flow(10_000, seed=0)
+    print_case("netflow10k_fp64", formulation=formulation, n=p.n)
+    s, vals, z, info = run(p, formulation)
+    om = omega_of(p, formulation, z)
+    print(info, "oracle omega", om)
+    assert om <= 1e-10
+
+
+def test_deterministic():
+    p = workloads.network_flow(3000, seed=1)
+    print_case("determinism", n=p.n)
+    outs = []
+    for _ in range(2):
+        s, vals, x, info = run(p, "lifted")
+        outs.append(x)
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_not_spd_status():
+    p = workloads.tiny_grid(0, nx=3, ny=3, sigma_range=(-1, 1))
+    print_case("not_spd", n=p.n)
+    w = p.w_val.copy()
+    i = 7
+    w[p.w_ptr[i + 1] - 1] = -1e6
+    q = workloads.KKTProblem(**{**p.__dict__, "w_val": w})
+    s = Solver(q, "lifted").bind(DEV)
+    s.factorize(*device_values(q, DEV, "lifted"))
+    assert s.factor_status() == -3
+    rhs = torch.as_tensor(q.b, device=DEV)
+    _, info = s.solve(rhs, raise_on_error=False)
+    assert info["status"] == -3
+    assert s.info()["failed_column"] >= 0
+
+
+def test_edge_no_constraints_and_single_variable():
+    # m_eq = m_ineq = 0 and n = 1
+    for nx, ny in ((1, 1), (2, 1)):
+        p = workloads.tiny_grid(1, nx=nx, ny=ny, vpn=1, m_eq=0, m_ineq=0, sigma_range=(-2, 2))
+        print_case("edge_empty_J", n=p.n)
+        s, vals, x, info = run(p, "lifted")
+        W, G, H = od.problem_dense(p)
+        xo = np.linalg.solve(W + np.diag(p.sigma_x), p.b)
+        assert np.allclose(x, xo, rtol=1e-12, atol=1e-14)
+
+
+def test_edge_hykkt_without_equalities():
+    p = workloads.tiny_grid(2, nx=4, ny=3, m_eq=0, m_ineq=20, sigma_range=(-4, 4))
+    print_case("edge_hykkt_no_eq", n=p.n)
+    s, vals, z, info = run(p, "hykkt")
+    assert omega_of(p, "hykkt", z) <= 1e-10
