@@ -96,6 +96,10 @@ typedef struct {
     double  cg_tol;       /* HyKKT CG: stop when ||r_k||_2 <= cg_tol ||r_0||_2; default 1e-10 */
     int32_t cg_maxit;     /* HyKKT CG iteration limit; default min(m_eq, 1000) when <= 0 */
     int32_t relax;        /* supernode amalgamation: 0 off, 1 default */
+    int32_t lds_front_max;/* largest front order factored entirely in LDS by one
+                             workgroup; larger fronts take the tiled
+                             multi-workgroup path.  0 = what 160 KiB of LDS
+                             holds in FP64 (143), in both precisions. */
 } ckkt_options;
 
 typedef struct {

@@ -29,7 +29,7 @@ class Pattern(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("ordering", c_int32), ("tol", c_double), ("ir_maxit", c_int32),
-                ("cg_tol", c_double), ("cg_maxit", c_int32), ("relax", c_int32)]
+                ("cg_tol", c_double), ("cg_maxit", c_int32), ("relax", c_int32), ("lds_front_max", c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -366,6 +366,10 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
         }
     }
 
+    P.kcol.resize(nnzk);
+    for (int32_t j = 0; j < n; ++j)
+        for (int32_t t = P.kcolptr[j]; t < P.kcolptr[j + 1]; ++t) P.kcol[t] = j;
+
     // ---- factor arena layout
     P.l_off.resize(ns);
     P.u_off.resize(ns);
@@ -398,6 +402,37 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     }
     P.arena = (P.arena + 7) & ~(int64_t)7;
 
+    // ---- children contributions by destination front position
+    {
+        const size_t nrows = P.sn_rows.size();
+        P.cb_ptr.assign(nrows + 1, 0);
+        for (int32_t c = 0; c < ns; ++c) {
+            int32_t p = P.sn_parent[c];
+            if (p < 0) continue;
+            int32_t wc = P.sn_start[c + 1] - P.sn_start[c];
+            int32_t rc = P.sn_rowptr[c + 1] - P.sn_rowptr[c] - wc;
+            for (int32_t a = 0; a < rc; ++a) P.cb_ptr[P.sn_rowptr[p] + P.relmap[P.sn_rowptr[c] + wc + a] + 1]++;
+        }
+        for (size_t q = 0; q < nrows; ++q) P.cb_ptr[q + 1] += P.cb_ptr[q];
+        P.cb_src.resize(P.cb_ptr[nrows]);
+        P.cb_len.resize(P.cb_ptr[nrows]);
+        P.cb_uoff.resize(P.cb_ptr[nrows]);
+        std::vector<int32_t> fill(P.cb_ptr.begin(), P.cb_ptr.end() - 1);
+        for (int32_t p = 0; p < ns; ++p)
+            for (int32_t t = P.child_ptr[p]; t < P.child_ptr[p + 1]; ++t) {  // child order
+                int32_t c = P.child_list[t];
+                int32_t wc = P.sn_start[c + 1] - P.sn_start[c];
+                int32_t rc = P.sn_rowptr[c + 1] - P.sn_rowptr[c] - wc;
+                for (int32_t a = 0; a < rc; ++a) {
+                    int32_t src = P.sn_rowptr[c] + wc + a;
+                    int32_t at = fill[P.sn_rowptr[p] + P.relmap[src]]++;
+                    P.cb_src[at] = src;
+                    P.cb_len[at] = rc - a;
+                    P.cb_uoff[at] = P.u_off[c] + (int64_t)a * P.u_ld[c] + a;
+                }
+            }
+    }
+
     // ---- levels (0 = leaves)
     std::vector<int32_t> lev(ns, 0);
     int32_t nlev = ns ? 1 : 0;
@@ -417,6 +452,13 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
             if (pred(s)) list[fill[lev[s]]++] = s;
     };
     group_by_level([&](int32_t s) { return !P.big[s]; }, P.lvl_small_ptr, P.lvl_small);
+    // small fronts of a level in increasing front order, so that one launch
+    // per LDS size class covers a contiguous range
+    for (int32_t l = 0; l < nlev; ++l)
+        std::stable_sort(P.lvl_small.begin() + P.lvl_small_ptr[l], P.lvl_small.begin() + P.lvl_small_ptr[l + 1],
+                         [&](int32_t x, int32_t y) {
+                             return P.sn_rowptr[x + 1] - P.sn_rowptr[x] < P.sn_rowptr[y + 1] - P.sn_rowptr[y];
+                         });
     group_by_level([&](int32_t s) { return P.big[s] != 0; }, P.lvl_big_ptr, P.lvl_big);
     group_by_level([&](int32_t) { return true; }, P.lvl_all_ptr, P.lvl_all);
     P.lvl_maxw_big.assign(nlev, 0);

@@ -52,6 +52,15 @@ struct Plan {
     std::vector<int32_t> child_ptr, child_list;
     std::vector<int32_t> relmap;      // aligned with sn_rows: row position inside the parent front
     std::vector<int32_t> kmap;        // per K slot: row position inside its supernode's front
+    std::vector<int32_t> kcol;        // per K slot: its column (factor numbering)
+    // Children contributions bucketed by destination position of the parent
+    // front (aligned with sn_rows, children in child order): for front
+    // position q of supernode s, entries [cb_ptr[sn_rowptr[s]+q], ...+1) list
+    // child rows/columns landing on q.  cb_src indexes relmap/uvec (the
+    // child's row), cb_len = rows of that child column from there down,
+    // cb_uoff = arena offset of the child's update entry on its diagonal.
+    std::vector<int32_t> cb_ptr, cb_src, cb_len;
+    std::vector<int64_t> cb_uoff;
     std::vector<int64_t> l_off;       // start of the supernode's region in the factor arena
     std::vector<int64_t> u_off;       // start of its update (Schur) matrix in the arena
     std::vector<int32_t> u_ld;        // leading dimension of the update matrix

@@ -8,9 +8,11 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ckkt.h"
@@ -60,7 +62,7 @@ struct ckkt_handle {
     Region r_perm, r_iperm, r_kcolptr, r_kwsrc, r_kdiag, r_prodptr, r_prodr, r_proda, r_prodb, r_snstart, r_snrowptr,
         r_snrows, r_childptr, r_childlist, r_relmap, r_kmap, r_loff, r_uoff, r_uld, r_lvlsmall, r_lvlbig, r_lvlall,
         r_tilesn, r_tilecol, r_wfptr, r_wfcol, r_wfvidx, r_jptr, r_jcol, r_jtptr, r_jtrow, r_jtvidx, r_jtgend,
-        r_instvar, r_insteq;
+        r_instvar, r_insteq, r_kcol, r_cbptr, r_cbsrc, r_cblen, r_cbuoff;
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
     std::vector<Region> r_vn, r_vm, r_veq;  // scratch vectors of length n, m, m_eq
 
@@ -84,6 +86,13 @@ struct ckkt_handle {
     // pinned host staging
     void* host = nullptr;
     size_t host_bytes = 0;
+
+    // captured launch sequences (replayed with hipGraphLaunch on the
+    // caller's stream): [0] factor FP64, [1] factor FP32, [2] sweeps FP64,
+    // [3] sweeps FP32.  They reference only workspace memory.
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool use_graphs = true;
 
     // timing
     bool timing = false;
@@ -147,8 +156,14 @@ void build_levels(ckkt_handle* h) {
         L.small_begin = P.lvl_small_ptr[l];
         L.small_count = P.lvl_small_ptr[l + 1] - L.small_begin;
         L.small_maxf = 0;
-        for (int t = L.small_begin; t < L.small_begin + L.small_count; ++t)
-            L.small_maxf = std::max(L.small_maxf, front(P.lvl_small[t]));
+        L.small_split = L.small_split32 = 0;
+        L.small_maxf_a = L.small_maxf_a32 = 0;
+        for (int t = L.small_begin; t < L.small_begin + L.small_count; ++t) {
+            const int f = front(P.lvl_small[t]);
+            L.small_maxf = std::max(L.small_maxf, f);
+            if (f <= kCompactFront64) { L.small_split++; L.small_maxf_a = std::max(L.small_maxf_a, f); }
+            if (f <= kCompactFront32) { L.small_split32++; L.small_maxf_a32 = std::max(L.small_maxf_a32, f); }
+        }
         L.big_begin = P.lvl_big_ptr[l];
         L.big_count = P.lvl_big_ptr[l + 1] - L.big_begin;
         L.big_maxw = L.big_maxf = 0;
@@ -158,9 +173,11 @@ void build_levels(ckkt_handle* h) {
         }
         L.all_begin = P.lvl_all_ptr[l];
         L.all_count = P.lvl_all_ptr[l + 1] - L.all_begin;
-        L.all_maxf = 0;
-        for (int t = L.all_begin; t < L.all_begin + L.all_count; ++t)
+        L.all_maxf = L.all_maxw = 0;
+        for (int t = L.all_begin; t < L.all_begin + L.all_count; ++t) {
             L.all_maxf = std::max(L.all_maxf, front(P.lvl_all[t]));
+            L.all_maxw = std::max(L.all_maxw, width(P.lvl_all[t]));
+        }
         L.tile_begin = P.big_tiles_ptr[l];
         L.tile_count = P.big_tiles_ptr[l + 1] - L.tile_begin;
     }
@@ -209,6 +226,11 @@ void build_layout(ckkt_handle* h) {
     plan_region(h->r_jtgend, P.jt_gend);
     plan_region(h->r_instvar, P.inst_of_var);
     plan_region(h->r_insteq, P.inst_of_eqrow);
+    plan_region(h->r_kcol, P.kcol);
+    plan_region(h->r_cbptr, P.cb_ptr);
+    plan_region(h->r_cbsrc, P.cb_src);
+    plan_region(h->r_cblen, P.cb_len);
+    plan_region(h->r_cbuoff, P.cb_uoff);
 
     const size_t n = std::max<int64_t>(P.n, 1), m = std::max<int64_t>(P.m, 1), me = std::max<int64_t>(P.m_eq, 1);
     h->r_K = L.add(std::max<size_t>(P.kcolptr.back(), 1) * sizeof(double));
@@ -257,6 +279,9 @@ void fill_devplan(ckkt_handle* h) {
     D.jt_ptr = at<int32_t>(h, h->r_jtptr); D.jt_row = at<int32_t>(h, h->r_jtrow);
     D.jt_vidx = at<int32_t>(h, h->r_jtvidx); D.jt_gend = at<int32_t>(h, h->r_jtgend);
     D.inst_of_var = at<int32_t>(h, h->r_instvar); D.inst_of_eqrow = at<int32_t>(h, h->r_insteq);
+    D.kcol = at<int32_t>(h, h->r_kcol);
+    D.cb_ptr = at<int32_t>(h, h->r_cbptr); D.cb_src = at<int32_t>(h, h->r_cbsrc);
+    D.cb_len = at<int32_t>(h, h->r_cblen); D.cb_uoff = at<int64_t>(h, h->r_cbuoff);
 
     h->K = at<double>(h, h->r_K);
     h->d = at<double>(h, h->r_d);
@@ -319,8 +344,11 @@ AnalyzeOptions analyze_options(const ckkt_options& o) {
     AnalyzeOptions ao;
     ao.ordering = o.ordering;
     ao.relax = o.relax;
-    // the whole front of a small supernode lives in LDS (<= 64 KiB)
-    ao.big_front = (o.precision == CKKT_FP32_IR) ? 120 : 88;
+    // the whole front of a small supernode lives in LDS (f^2 elements <= 160 KiB)
+    // the FP64 factor is also built for FP32_IR handles (refactorization
+    // fallback), so the FP64 LDS capacity bounds both precisions
+    const int cap = kLdsFront64;
+    ao.big_front = (o.lds_front_max > 0) ? std::min(o.lds_front_max, cap) : cap;
     return ao;
 }
 
@@ -334,9 +362,46 @@ template <>
 float* arena_of<float>(ckkt_handle* h) { return h->arena32; }
 
 template <typename T>
-void factor_all(ckkt_handle* h, const double* scale, hipStream_t st) {
+void factor_levels(ckkt_handle* h, const double* scale, hipStream_t st) {
     T* arena = arena_of<T>(h);
     for (const LevelInfo& L : h->levels) launch_factor_level<T>(h->dp, L, h->K, arena, h->status, scale, st);
+}
+
+template <typename T>
+void sweep_levels(ckkt_handle* h, hipStream_t st) {
+    const T* arena = arena_of<T>(h);
+    for (size_t l = 0; l < h->levels.size(); ++l) launch_fwd_level<T>(h->dp, h->levels[l], arena, h->vperm, h->uvec, st);
+    for (size_t l = h->levels.size(); l-- > 0;) launch_bwd_level<T>(h->dp, h->levels[l], arena, h->vperm, st);
+}
+
+// Capture a launch sequence once on the private stream; replay it on `st`.
+// Falls back to direct launches if capture is unavailable.
+template <typename F>
+void run_captured(ckkt_handle* h, int slot, hipStream_t st, F&& launches) {
+    if (h->use_graphs && !h->graphs[slot] && h->capture_stream) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            launches(h->capture_stream);
+            if (hipStreamEndCapture(h->capture_stream, &g) == hipSuccess && g) {
+                hipGraphExec_t ex = nullptr;
+                if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) h->graphs[slot] = ex;
+                (void)hipGraphDestroy(g);
+            }
+        }
+        (void)hipGetLastError();
+        if (!h->graphs[slot]) h->use_graphs = false;
+    }
+    if (h->use_graphs && h->graphs[slot]) {
+        if (hipGraphLaunch(h->graphs[slot], st) == hipSuccess) return;
+        (void)hipGetLastError();
+    }
+    launches(st);
+}
+
+template <typename T>
+void factor_all(ckkt_handle* h, const double* scale, hipStream_t st) {
+    run_captured(h, std::is_same<T, double>::value ? 0 : 1, st,
+                 [&](hipStream_t s) { factor_levels<T>(h, scale, s); });
 }
 
 // x = (L L^T)^{-1} b in the user numbering (with the Jacobi scaling of the
@@ -344,10 +409,8 @@ void factor_all(ckkt_handle* h, const double* scale, hipStream_t st) {
 template <typename T>
 void apply_inverse_t(ckkt_handle* h, const double* b, double* x, const double* scale, hipStream_t st) {
     PhaseTimer tm(h, 2, st);
-    const T* arena = arena_of<T>(h);
     launch_gather_perm(h->dp, b, h->vperm, scale, st);
-    for (size_t l = 0; l < h->levels.size(); ++l) launch_fwd_level<T>(h->dp, h->levels[l], arena, h->vperm, h->uvec, st);
-    for (size_t l = h->levels.size(); l-- > 0;) launch_bwd_level<T>(h->dp, h->levels[l], arena, h->vperm, st);
+    run_captured(h, std::is_same<T, double>::value ? 2 : 3, st, [&](hipStream_t s) { sweep_levels<T>(h, s); });
     launch_scatter_perm(h->dp, h->vperm, x, scale, st);
 }
 
@@ -630,6 +693,7 @@ void ckkt_default_options(ckkt_options* o) {
     o->cg_tol = 1e-10;
     o->cg_maxit = 0;
     o->relax = 1;
+    o->lds_front_max = 0;
 }
 
 ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
@@ -711,6 +775,13 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
             return CKKT_ERR_HIP;
         }
     }
+    for (auto& g : h->graphs)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    if (!h->capture_stream) {
+        if (hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess) h->capture_stream = nullptr;
+    }
+    const char* ng = std::getenv("CKKT_NO_GRAPH");
+    h->use_graphs = !(ng && ng[0] == '1');
     h->ws = static_cast<char*>(dev_ptr);
     h->ws_bytes = bytes;
     for (auto& pr : h->plan_regions)
@@ -870,6 +941,9 @@ void ckkt_destroy(ckkt_handle* h) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : h->event_pool) (void)hipEventDestroy(e);
+    for (auto& g : h->graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     if (h->host) (void)hipHostFree(h->host);
     delete h;
 }

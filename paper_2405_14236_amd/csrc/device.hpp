@@ -12,7 +12,9 @@ struct DevPlan {
     int64_t nnzk, nnzg;
     const int32_t *perm, *iperm;
     const int32_t *kcolptr, *k_wsrc, *k_diag, *prod_ptr, *prod_r, *prod_a, *prod_b;
-    const int32_t *sn_start, *sn_rowptr, *sn_rows, *child_ptr, *child_list, *relmap, *kmap;
+    const int32_t *sn_start, *sn_rowptr, *sn_rows, *child_ptr, *child_list, *relmap, *kmap, *kcol;
+    const int32_t *cb_ptr, *cb_src, *cb_len;
+    const int64_t* cb_uoff;
     const int64_t *l_off, *u_off;
     const int32_t *u_ld;
     const int32_t *lvl_small, *lvl_big, *lvl_all, *big_tile_sn, *big_tile_col;
@@ -30,12 +32,17 @@ struct SysVals {
 // Per-level launch geometry, computed on the host from the plan.
 struct LevelInfo {
     int32_t small_begin, small_count, small_maxf;
+    int32_t small_split, small_split32;  // fronts [begin, begin+split) have f <= kCompactFront64 / 32
+    int32_t small_maxf_a, small_maxf_a32;  // largest front of that compact class
     int32_t big_begin, big_count, big_maxw, big_maxf;
-    int32_t all_begin, all_count, all_maxf;
+    int32_t all_begin, all_count, all_maxf, all_maxw;
     int32_t tile_begin, tile_count;
 };
 
 constexpr int kBigTile = 64;    // column tile of the tiled front path
+constexpr int kLdsFront64 = 143;     // largest FP64 front held whole in 160 KiB of LDS
+constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several workgroups per CU)
+constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
 
 // ---- launchers (kernels.hip)

@@ -38,15 +38,12 @@ int host_factor_solve(const Plan& P, int hy, const double* w_val, const double* 
             F.assign((size_t)f * f, 0.0);
             for (int j = c0; j < c0 + w; ++j)
                 for (int u = P.kcolptr[j]; u < P.kcolptr[j + 1]; ++u) F[P.kmap[u] + (size_t)(j - c0) * f] = K[u];
-            for (int q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q) {
-                const int c = P.child_list[q];
-                const int wc = P.sn_start[c + 1] - P.sn_start[c];
-                const int roc = P.sn_rowptr[c], rc = P.sn_rowptr[c + 1] - roc - wc;
-                const int* rel = P.relmap.data() + roc + wc;
-                const double* U = arena.data() + P.u_off[c];
-                for (int bb = 0; bb < rc; ++bb)
-                    for (int a = bb; a < rc; ++a) F[rel[a] + (size_t)rel[bb] * f] += U[a + (size_t)bb * P.u_ld[c]];
-            }
+            for (int j = 0; j < f; ++j)
+                for (int q = P.cb_ptr[ro + j]; q < P.cb_ptr[ro + j + 1]; ++q) {
+                    const double* Ucol = arena.data() + P.cb_uoff[q];
+                    const int* rel = P.relmap.data() + P.cb_src[q];
+                    for (int a = 0; a < P.cb_len[q]; ++a) F[rel[a] + (size_t)j * f] += Ucol[a];
+                }
             for (int k = 0; k < w; ++k) {
                 double dk = F[k + (size_t)k * f];
                 if (!(dk > 0.0)) { if (failed < 0) failed = P.perm[c0 + k]; dk = 1.0; }
@@ -72,12 +69,10 @@ int host_factor_solve(const Plan& P, int hy, const double* w_val, const double* 
             const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
             const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
             tmp.assign(f, 0.0);
-            for (int i = 0; i < w; ++i) tmp[i] = v[c0 + i];
-            for (int q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q) {
-                const int c = P.child_list[q];
-                const int wc = P.sn_start[c + 1] - P.sn_start[c];
-                const int roc = P.sn_rowptr[c], rc = P.sn_rowptr[c + 1] - roc - wc;
-                for (int a = 0; a < rc; ++a) tmp[P.relmap[roc + wc + a]] += uvec[roc + wc + a];
+            for (int i = 0; i < f; ++i) {
+                double acc = i < w ? v[c0 + i] : 0.0;
+                for (int q = P.cb_ptr[ro + i]; q < P.cb_ptr[ro + i + 1]; ++q) acc += uvec[P.cb_src[q]];
+                tmp[i] = acc;
             }
             const double* L = arena.data() + P.l_off[s];
             for (int k = 0; k < w; ++k) {

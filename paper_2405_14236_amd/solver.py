@@ -37,13 +37,15 @@ def _pattern(prob, formulation):
     return pat, keep
 
 
-def options(precision="fp64", ordering="amd", tol=1e-10, ir_maxit=10, cg_tol=1e-10, cg_maxit=0, relax=1):
+def options(precision="fp64", ordering="amd", tol=1e-10, ir_maxit=10, cg_tol=1e-10, cg_maxit=0, relax=1,
+            lds_front_max=0):
     lib = L.load()
     o = L.Options()
     lib.ckkt_default_options(ctypes.byref(o))
     o.precision = {"fp64": L.FP64, "fp32_ir": L.FP32_IR}[precision]
     o.ordering = {"amd": L.ORDER_AMD, "natural": L.ORDER_NATURAL}[ordering]
     o.tol, o.ir_maxit, o.cg_tol, o.cg_maxit, o.relax = tol, ir_maxit, cg_tol, cg_maxit, relax
+    o.lds_front_max = lds_front_max
     return o
 
 

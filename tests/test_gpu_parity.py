@@ -118,7 +118,7 @@ def test_factor_application_matches_host_run(formulation):
     p = workloads.network_flow(4000, seed=4)
     print_case("apply_inverse_vs_host", formulation=formulation, n=p.n)
     gamma = 1e7
-    s = Solver(p, formulation).bind(DEV)
+    s = Solver(p, formulation, lds_front_max=64).bind(DEV)
     assert s.info()["n_big_fronts"] > 0
     vals = device_values(p, DEV, formulation)
     s.factorize(*vals, gamma=gamma)
@@ -186,3 +186,25 @@ def test_edge_hykkt_without_equalities():
     print_case("edge_hykkt_no_eq", n=p.n)
     s, vals, z, info = run(p, "hykkt")
     assert omega_of(p, "hykkt", z) <= 1e-10
+
+
+def test_graph_replay_matches_direct_launches(monkeypatch):
+    """Captured launch sequences (hipGraph) give bitwise the direct-launch
+    result, on several replays with eager work in between."""
+    p = workloads.network_flow(2500, seed=7)
+    print_case("graph_vs_direct", n=p.n)
+    res = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("CKKT_NO_GRAPH", mode)
+        s = Solver(p, "hykkt").bind(DEV)
+        outs = []
+        for k in range(3):
+            q = p.with_sigma(p.sigma_x * (1 + k), p.sigma_s * (1 + 0.5 * k))
+            s.factorize(*device_values(q, DEV, "hykkt"), gamma=1e7)
+            z, info = s.solve(torch.as_tensor(rhs_of(q, "hykkt"), device=DEV))
+            torch.cuda.synchronize()
+            outs.append(z.cpu().numpy())
+            _ = torch.randn(1000, device=DEV).sum().item()  # unrelated eager work
+        res[mode] = outs
+    for a, b in zip(res["0"], res["1"]):
+        assert np.array_equal(a, b)

@@ -121,7 +121,7 @@ def test_host_run_orderings_and_relaxation(ordering, relax):
 def test_host_run_network_flow_with_big_fronts():
     """A network-flow problem large enough to use the tiled front layout."""
     p = workloads.network_flow(4000, seed=4)
-    s = Solver(p, "lifted")
+    s = Solver(p, "lifted", lds_front_max=64)
     inf = s.info()
     assert inf["n_big_fronts"] > 0 and inf["n_levels"] > 3
     x, st, fc = s.host_factor_solve(p.w_val, p.g_val, p.h_val, p.sigma_x, p.sigma_s, 0.0, p.b)
