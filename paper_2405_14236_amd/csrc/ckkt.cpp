@@ -15,7 +15,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "../../include/ckkt.h"
+#include "ckkt.h"
 #include "analysis.hpp"
 #include "device.hpp"
 
@@ -502,6 +502,56 @@ void refactor_fp64(ckkt_handle* h, hipStream_t st) {
 
 // ------------------------------------------------------------ LiftedKKT
 
+constexpr int kPcgMaxit = 50;
+
+// FP64 preconditioned CG on K x = b (K applied unassembled), preconditioned
+// by the FP32 factor, starting from the current x with its residual `res`.
+// The true residual is recomputed every iteration (it also yields omega).
+// Returns true when omega <= tol.
+bool pcg_fp32(ckkt_handle* h, const double* b, double* x, double* res, ResidualOut& r, ckkt_solve_info* info,
+              hipStream_t st, ckkt_status& rc) {
+    const int n = h->plan.n;
+    double* z = h->vn[1];
+    double* p = h->vn[2];
+    double* q = h->vn[3];
+    double* sc = h->sc + 8;  // [0] rz, [1] pq, [2] alpha, [3] rz_new, [4] beta
+    apply_inverse(h, res, z, false, st);
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_copy(n, z, p, st);
+        launch_dot(n, res, z, h->dotpart, sc + 0, st);
+    }
+    double omega_start = r.omega;
+    for (int k = 0; k < kPcgMaxit; ++k) {
+        {
+            PhaseTimer tm(h, 3, st);
+            // q = -K p through the residual kernels with a zero right-hand side
+            launch_zero_u64(h->bits, h->plan.ninst + 1, st);
+            launch_residual(h->dp, h->vals, h->d, p, nullptr, nullptr, nullptr, q, nullptr, h->vm[0], h->vm[1],
+                            h->bits, h->bits + h->plan.ninst, st);
+            launch_dot(n, p, q, h->dotpart, sc + 1, st);  // = -p^T K p
+            launch_cg_alpha(sc, st);                     // alpha = rz / (-pKp)
+            launch_axpy_dev(n, sc, 2, -1.0, p, x, st);   // x += (rz / pKp) p
+        }
+        info->pcg_iters++;
+        rc = residual_sync(h, x, nullptr, b, nullptr, res, nullptr, r, st);
+        if (rc) return false;
+        if (r.omega <= h->opt.tol) return true;
+        if (!std::isfinite(r.omega)) return false;
+        // give up early when the preconditioned iteration is not contracting
+        if (k == 0) omega_start = r.omega;
+        if (k == 7 && !(r.omega < 1e-2 * omega_start)) return false;
+        apply_inverse(h, res, z, false, st);
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_dot(n, res, z, h->dotpart, sc + 3, st);
+            launch_cg_beta(sc, st);
+            launch_cg_direction(n, sc, z, p, st);
+        }
+    }
+    return false;
+}
+
 ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_info* info, hipStream_t st) {
     const int n = h->plan.n;
     double* res = h->vn[0];
@@ -523,10 +573,20 @@ ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_
         info->rho = bmax > 0 ? r.resmax / bmax : r.resmax;
         if (r.omega <= h->opt.tol) break;
         if (!use64) {
-            // FP32 factor: stop refining when it stagnates and fall back to the
-            // FP64 factor of the same assembled matrix.
-            if (!(r.omega < 0.5 * prev)) stall++;
-            if (stall >= 2 || steps >= h->opt.ir_maxit) {
+            // FP32 factor: Richardson while it contracts; when it stagnates,
+            // FP64 PCG preconditioned by the same factor; if that fails too,
+            // FP64 refactorization of the already assembled matrix.
+            if (!(r.omega < 0.25 * prev) || !std::isfinite(r.omega)) stall++;
+            if (stall >= 1 || steps >= h->opt.ir_maxit) {
+                if (std::isfinite(r.omega) && info->fallback == 0) {
+                    info->fallback = 1;
+                    if (pcg_fp32(h, b, x, res, r, info, st, rc)) {
+                        info->omega = r.omega;
+                        info->rho = bmax > 0 ? r.resmax / bmax : r.resmax;
+                        break;
+                    }
+                    if (rc) return rc;
+                }
                 refactor_fp64(h, st);
                 use64 = true;
                 info->fallback = 2;
@@ -666,6 +726,16 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
         rc = hykkt_inner(h, res1, res2, ddx, ddy, use64, it, ok, st);
         info->cg_iters += it;
         last_cg_ok = ok;
+        if (rc == CKKT_ERR_BREAKDOWN && !use64) {
+            // the FP32 factor of K_gamma is too inexact for CG on S_gamma:
+            // refactorize in FP64 and redo this outer step
+            refactor_fp64(h, st);
+            use64 = true;
+            info->fallback = 2;
+            stall = 0;
+            prev = INFINITY;
+            continue;
+        }
         if (rc) return rc;
         {
             PhaseTimer tm(h, 3, st);
