@@ -183,6 +183,16 @@ void build_levels(ckkt_handle* h) {
     }
 }
 
+// Every launch of the plan fits the LDS of one workgroup (checked once at
+// analysis, so no launch is ever rejected by the device).
+bool plan_fits_lds(const ckkt_handle* h) {
+    for (const LevelInfo& L : h->levels) {
+        if ((size_t)L.small_maxf * L.small_maxf * sizeof(double) + kFactorStaticLds > (size_t)kLdsBytes) return false;
+        if (L.all_maxf > kSweepMaxFront) return false;
+    }
+    return true;
+}
+
 void build_layout(ckkt_handle* h) {
     const Plan& P = h->plan;
     Layout& L = h->lay;
@@ -309,6 +319,10 @@ ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const Patte
         return internal ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
     }
     build_levels(h);
+    if (!plan_fits_lds(h)) {
+        delete h;
+        return CKKT_ERR_ARG;  // a front beyond what the sweep kernels can stage
+    }
     build_layout(h);
     *out = h;
     if (workspace_bytes) *workspace_bytes = h->lay.total;
@@ -366,6 +380,7 @@ void factor_levels(ckkt_handle* h, const double* scale, hipStream_t st) {
     T* arena = arena_of<T>(h);
     for (const LevelInfo& L : h->levels) launch_factor_level<T>(h->dp, L, h->K, arena, h->status, scale, st);
 }
+
 
 template <typename T>
 void sweep_levels(ckkt_handle* h, hipStream_t st) {

@@ -40,7 +40,14 @@ struct LevelInfo {
 };
 
 constexpr int kBigTile = 64;    // column tile of the tiled front path
-constexpr int kLdsFront64 = 143;     // largest FP64 front held whole in 160 KiB of LDS
+constexpr int kLdsBytes = 160 * 1024;   // LDS per workgroup on gfx950
+constexpr int kFactorStaticLds = 2048;  // upper bound of k_factor_small's static LDS
+constexpr int kSweepStaticLds = 1024;   // upper bound of k_fwd / k_bwd static LDS
+// largest FP64 front held whole in LDS next to the kernel's static arrays:
+// 140^2 * 8 + 2048 <= 160 KiB
+constexpr int kLdsFront64 = 140;
+// largest front the sweep kernels can stage (front vector + 64 x 64 block)
+constexpr int kSweepMaxFront = (kLdsBytes - kSweepStaticLds) / 8 - 64 * 64;
 constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several workgroups per CU)
 constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
@@ -50,8 +57,9 @@ void launch_row_weights(const DevPlan& P, const SysVals& v, double* d, hipStream
 void launch_assemble(const DevPlan& P, const SysVals& v, const double* d, double* K, hipStream_t st);
 void launch_init_status(int32_t* status, hipStream_t st);
 
+// Returns false (and launches nothing) if a launch would exceed the LDS limit.
 template <typename T>
-void launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
+bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
                          int32_t* status, const double* scale, hipStream_t st);
 template <typename T>
 void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* v_perm,

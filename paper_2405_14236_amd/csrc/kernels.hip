@@ -820,8 +820,9 @@ void launch_diag_scale(const DevPlan& P, const double* K, double* scale, hipStre
 }
 
 template <typename T>
-void launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
+bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
                          int32_t* status, const double* scale, hipStream_t st) {
+    if ((size_t)L.small_maxf * L.small_maxf * sizeof(T) + kFactorStaticLds > (size_t)kLdsBytes) return false;
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_small<T, true>),
@@ -859,6 +860,7 @@ void launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                                    arena, L.big_begin, kb);
         }
     }
+    return true;
 }
 
 template <typename T>
@@ -882,9 +884,9 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
     hipLaunchKernelGGL(k_bwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, x_perm);
 }
 
-template void launch_factor_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, int32_t*,
+template bool launch_factor_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, int32_t*,
                                           const double*, hipStream_t);
-template void launch_factor_level<float>(const DevPlan&, const LevelInfo&, const double*, float*, int32_t*,
+template bool launch_factor_level<float>(const DevPlan&, const LevelInfo&, const double*, float*, int32_t*,
                                          const double*, hipStream_t);
 template void launch_fwd_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, double*,
                                        hipStream_t);

@@ -208,3 +208,15 @@ def test_graph_replay_matches_direct_launches(monkeypatch):
         res[mode] = outs
     for a, b in zip(res["0"], res["1"]):
         assert np.array_equal(a, b)
+
+
+def test_large_network_flow_fronts_at_lds_limit():
+    """The n = 528,000 network-flow workload (80k nodes): its fronts reach the
+    LDS capacity of one workgroup; every launch must fit and the FP64 solve
+    must meet the gate."""
+    p = workloads.network_flow(80_000, seed=0)
+    print_case("netflow80k_fp64", n=p.n)
+    s, vals, x, info = run(p, "lifted")
+    om = omega_of(p, "lifted", x)
+    print(info, "oracle omega", om, s.info()["max_front"])
+    assert om <= 1e-10
