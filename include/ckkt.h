@@ -99,7 +99,9 @@ typedef struct {
     int32_t lds_front_max;/* largest front order factored entirely in LDS by one
                              workgroup; larger fronts take the tiled
                              multi-workgroup path.  0 = what 160 KiB of LDS
-                             holds in FP64 (143), in both precisions. */
+                             holds in FP64 (140), in both precisions. */
+    int32_t learned;      /* 1: reserve workspace for the learned preconditioner
+                             (features, MLP cache, stale-system references) */
 } ckkt_options;
 
 typedef struct {
@@ -223,6 +225,70 @@ ckkt_status ckkt_export_k(ckkt_handle* h, int32_t* rows, int32_t* cols, double* 
 ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, const double* g_val,
                                   const double* h_val, const double* sigma_x, const double* sigma_s,
                                   double gamma, const double* rhs, double* sol, int32_t* failed_column);
+
+/* ---- Learned diagonal preconditioner (PCG around a stale factor) ----
+ *
+ * For a new system K (LiftedKKT) and the factor of an earlier system K_s
+ * (the last ckkt_factorize), PCG uses M^{-1} = D K_s^{-1} D with
+ * D = diag(exp(o)), o_j the output of an 8-64-64-1 tanh MLP evaluated on 8
+ * per-variable features that compare the new diagonals with those of K_s:
+ * f0 = log10 sigma_x / 8, f1 = its change / 8, f2 = log10 K_jj / 8, f3 = its
+ * change / 8, f4 = max over constraint rows r touching j of log10 d_r / 8,
+ * f5 / f6 = max / min over those rows of the change of log10 d_r / 8 (0 for a
+ * variable in no row), f7 = 1.  M is SPD for every parameter value.
+ * Parameters: CKKT_MLP_NPARAM FP32 values, W1[64][8], b1[64], W2[64][64],
+ * b2[64], w3[64], b3 (row-major).  The handle must be analysed with
+ * opt.learned = 1. */
+#define CKKT_MLP_FEATURES 8
+#define CKKT_MLP_HIDDEN   64
+#define CKKT_MLP_NPARAM   (64 * 8 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* Features (n x 8 FP32, device, row-major) of the system given by the value
+ * pointers (same meaning as ckkt_factorize) against the system of the
+ * current factor.  Enqueued on stream. */
+ckkt_status ckkt_features(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                          const double* sigma_x, const double* sigma_s, double gamma, float* features,
+                          void* stream);
+
+/* MLP forward on n rows of features: out[n]; cache (2 * 64 * n FP32, may be
+ * NULL) keeps the hidden activations for ckkt_mlp_backward.  Device
+ * pointers, no handle needed. */
+ckkt_status ckkt_mlp_forward(int64_t n, const float* features, const float* params, float* out, float* cache,
+                             void* stream);
+
+/* Bytes of scratch ckkt_mlp_backward needs for n rows. */
+size_t ckkt_mlp_workspace(int64_t n);
+
+/* Gradient (CKKT_MLP_NPARAM FP32) of sum_j g_out[j] * out_j with respect to
+ * the parameters, from the cache of ckkt_mlp_forward; ws has
+ * ckkt_mlp_workspace(n) bytes.  Fixed-order reductions (deterministic). */
+ckkt_status ckkt_mlp_backward(int64_t n, const float* features, const float* params, const float* cache,
+                              const float* g_out, float* grad, void* ws, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8); step counts from 1. */
+ckkt_status ckkt_adam(int32_t nparam, float* params, const float* grad, float* m, float* v, int32_t step,
+                      float lr, void* stream);
+
+/* One training step on a solver-generated pair (rhs, target = K^{-1} rhs) of
+ * the system given by the values, against the current (stale) factor: loss
+ * L = ||D K_s^{-1}(D rhs) - target||^2 / ||target||^2, its gradient through
+ * two stale solves and the MLP, and an Adam step on params/m/v.  *loss
+ * (host) receives L before the step.  Blocks until done. */
+ckkt_status ckkt_mlp_train_step(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                                const double* sigma_x, const double* sigma_s, double gamma, const double* rhs,
+                                const double* target, float* params, float* m, float* v, int32_t step, float lr,
+                                double* loss, void* stream);
+
+/* FP64 PCG on the new system K x = rhs (LiftedKKT, K applied unassembled)
+ * preconditioned by D K_s^{-1} D around the current factor; params NULL
+ * means D = I.  Stops when omega <= tol; after maxit iterations, if
+ * allow_refactor, factorizes the new system (which becomes the stale
+ * reference) and solves it with ckkt_solve (info->fallback = 2), else
+ * returns CKKT_ERR_NO_CONVERGENCE with the last iterate.  Blocks. */
+ckkt_status ckkt_pcg_solve(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                           const double* sigma_x, const double* sigma_s, double gamma, const float* params,
+                           const double* rhs, double* sol, int32_t maxit, double tol, int32_t allow_refactor,
+                           ckkt_solve_info* info, void* stream);
 
 ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info);
 const char* ckkt_status_string(ckkt_status s);

@@ -11,6 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libckkt.so")
 
 CKKT_OK = 0
+MLP_F, MLP_H = 8, 64
+MLP_NPARAM = MLP_H * MLP_F + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
 STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_PATTERN", -3: "ERR_NOT_SPD", -4: "ERR_NO_CONVERGENCE",
                 -5: "ERR_BREAKDOWN", -6: "ERR_STATE", -7: "ERR_HIP", -8: "ERR_WORKSPACE", -9: "ERR_NONFINITE"}
 LIFTED, HYKKT = 0, 1
@@ -29,7 +31,8 @@ class Pattern(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("ordering", c_int32), ("tol", c_double), ("ir_maxit", c_int32),
-                ("cg_tol", c_double), ("cg_maxit", c_int32), ("relax", c_int32), ("lds_front_max", c_int32)]
+                ("cg_tol", c_double), ("cg_maxit", c_int32), ("relax", c_int32), ("lds_front_max", c_int32),
+                ("learned", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -65,6 +68,17 @@ SIGNATURES = [
     ("ckkt_export_k", c_int32, [c_void_p, P_i32, P_i32, c_void_p, c_void_p]),
     ("ckkt_host_factor_solve", c_int32, [c_void_p, P_f64, P_f64, P_f64, P_f64, P_f64, c_double, P_f64, P_f64,
                                          P_i32]),
+    ("ckkt_features", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                                c_void_p]),
+    ("ckkt_mlp_forward", c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("ckkt_mlp_workspace", c_size_t, [c_int64]),
+    ("ckkt_mlp_backward", c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("ckkt_adam", c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p]),
+    ("ckkt_mlp_train_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float,
+                                      POINTER(c_double), c_void_p]),
+    ("ckkt_pcg_solve", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                                 c_void_p, c_void_p, c_int32, c_double, c_int32, POINTER(SolveInfo), c_void_p]),
     ("ckkt_get_info", c_int32, [c_void_p, POINTER(Info)]),
     ("ckkt_status_string", c_char_p, [c_int32]),
     ("ckkt_destroy", None, [c_void_p]),

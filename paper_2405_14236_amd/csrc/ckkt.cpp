@@ -65,6 +65,9 @@ struct ckkt_handle {
         r_instvar, r_insteq, r_kcol, r_cbptr, r_cbsrc, r_cblen, r_cbuoff;
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
     std::vector<Region> r_vn, r_vm, r_veq;  // scratch vectors of length n, m, m_eq
+    // learned preconditioner (opt.learned)
+    Region r_feat, r_o, r_cache, r_go, r_mlpws, r_grad, r_sxold, r_dold, r_kdold, r_kdnew, r_dnew;
+    std::vector<Region> r_lv;
 
     // bound state
     char* ws = nullptr;
@@ -77,6 +80,11 @@ struct ckkt_handle {
     unsigned long long* bits = nullptr;  // [ninst omega][resmax][bmax]
     double *dotpart = nullptr, *sc = nullptr;
     std::vector<double*> vn, vm, veq;
+    float *feat = nullptr, *mo = nullptr, *cache = nullptr, *go = nullptr, *grad = nullptr;
+    void* mlpws = nullptr;
+    double *sxold = nullptr, *dold = nullptr, *kdold = nullptr, *kdnew = nullptr, *dnew = nullptr;
+    std::vector<double*> lv;
+    bool stale_valid = false;
 
     bool factored = false;
     bool fp64_factored = false;  // FP64 factor valid (fallback path of FP32_IR)
@@ -261,6 +269,21 @@ void build_layout(ckkt_handle* h) {
     for (int i = 0; i < 8; ++i) h->r_vn.push_back(L.add(n * sizeof(double)));
     for (int i = 0; i < 2; ++i) h->r_vm.push_back(L.add(m * sizeof(double)));
     for (int i = 0; i < 6; ++i) h->r_veq.push_back(L.add(me * sizeof(double)));
+    h->r_lv.clear();
+    if (h->opt.learned) {
+        h->r_feat = L.add(n * kMlpF * sizeof(float));
+        h->r_o = L.add(n * sizeof(float));
+        h->r_cache = L.add(2 * kMlpH * n * sizeof(float));
+        h->r_go = L.add(n * sizeof(float));
+        h->r_mlpws = L.add(mlp_workspace_bytes((int64_t)n));
+        h->r_grad = L.add(kMlpNParam * sizeof(float));
+        h->r_sxold = L.add(n * sizeof(double));
+        h->r_dold = L.add(m * sizeof(double));
+        h->r_kdold = L.add(n * sizeof(double));
+        h->r_kdnew = L.add(n * sizeof(double));
+        h->r_dnew = L.add(m * sizeof(double));
+        for (int i = 0; i < 4; ++i) h->r_lv.push_back(L.add(n * sizeof(double)));
+    }
 }
 
 template <typename T>
@@ -308,6 +331,21 @@ void fill_devplan(ckkt_handle* h) {
     for (auto& r : h->r_vn) h->vn.push_back(at<double>(h, r));
     for (auto& r : h->r_vm) h->vm.push_back(at<double>(h, r));
     for (auto& r : h->r_veq) h->veq.push_back(at<double>(h, r));
+    h->lv.clear();
+    if (h->opt.learned) {
+        h->feat = at<float>(h, h->r_feat);
+        h->mo = at<float>(h, h->r_o);
+        h->cache = at<float>(h, h->r_cache);
+        h->go = at<float>(h, h->r_go);
+        h->mlpws = at<char>(h, h->r_mlpws);
+        h->grad = at<float>(h, h->r_grad);
+        h->sxold = at<double>(h, h->r_sxold);
+        h->dold = at<double>(h, h->r_dold);
+        h->kdold = at<double>(h, h->r_kdold);
+        h->kdnew = at<double>(h, h->r_kdnew);
+        h->dnew = at<double>(h, h->r_dnew);
+        for (auto& r : h->r_lv) h->lv.push_back(at<double>(h, r));
+    }
 }
 
 ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const PatternIn& pin, ckkt_handle** out,
@@ -567,6 +605,61 @@ bool pcg_fp32(ckkt_handle* h, const double* b, double* x, double* res, ResidualO
     return false;
 }
 
+// FP64 PCG on the current system (h->vals, unassembled) from x = 0,
+// preconditioned by D K_s^{-1} D with the current (stale) factor; o = NULL
+// means D = I.  Returns true when omega <= tol.
+bool pcg_stale(ckkt_handle* h, const double* b, double* x, const float* o, int maxit, double tol, ResidualOut& r,
+               ckkt_solve_info* info, hipStream_t st, ckkt_status& rc) {
+    const int n = h->plan.n;
+    double* res = h->vn[0];
+    double* z = h->vn[1];
+    double* p = h->vn[2];
+    double* q = h->vn[3];
+    double* t = h->vn[4];
+    double* sc = h->sc + 8;
+    const bool use64 = h->fp64_factored;
+    auto precond = [&](const double* in, double* out) {  // out = D K_s^{-1} (D in)
+        launch_dscale(n, o, in, t, st);
+        apply_inverse(h, t, out, use64, st);
+        launch_dscale(n, o, out, out, st);
+    };
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_fill(n, 0.0, x, st);
+        launch_copy(n, b, res, st);
+    }
+    precond(res, z);
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_copy(n, z, p, st);
+        launch_dot(n, res, z, h->dotpart, sc + 0, st);
+    }
+    for (int k = 0; k < maxit; ++k) {
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_zero_u64(h->bits, h->plan.ninst + 1, st);
+            launch_residual(h->dp, h->vals, h->d, p, nullptr, nullptr, nullptr, q, nullptr, h->vm[0], h->vm[1],
+                            h->bits, h->bits + h->plan.ninst, st);  // q = -K p
+            launch_dot(n, p, q, h->dotpart, sc + 1, st);
+            launch_cg_alpha(sc, st);
+            launch_axpy_dev(n, sc, 2, -1.0, p, x, st);
+        }
+        info->pcg_iters++;
+        rc = residual_sync(h, x, nullptr, b, nullptr, res, nullptr, r, st);
+        if (rc) return false;
+        if (r.omega <= tol) return true;
+        if (!std::isfinite(r.omega)) return false;
+        precond(res, z);
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_dot(n, res, z, h->dotpart, sc + 3, st);
+            launch_cg_beta(sc, st);
+            launch_cg_direction(n, sc, z, p, st);
+        }
+    }
+    return false;
+}
+
 ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_info* info, hipStream_t st) {
     const int n = h->plan.n;
     double* res = h->vn[0];
@@ -779,6 +872,7 @@ void ckkt_default_options(ckkt_options* o) {
     o->cg_maxit = 0;
     o->relax = 1;
     o->lds_front_max = 0;
+    o->learned = 0;
 }
 
 ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
@@ -899,6 +993,13 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
         launch_row_weights(h->dp, h->vals, h->d, st);
         launch_assemble(h->dp, h->vals, h->d, h->K, st);
         if (h->precision == CKKT_FP32_IR) launch_diag_scale(h->dp, h->K, h->scale, st);
+        if (h->opt.learned) {
+            // the factorized system becomes the stale reference of the learned PCG
+            launch_copy(h->plan.n, sigma_x, h->sxold, st);
+            launch_copy(h->plan.m, h->d, h->dold, st);
+            launch_kdiag(h->dp, h->vals, h->d, h->kdold, st);
+            h->stale_valid = true;
+        }
     }
     {
         PhaseTimer tm(h, 1, st);
@@ -979,6 +1080,146 @@ ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, co
                                rhs, sol);
     if (failed_column) *failed_column = fc;
     return fc >= 0 ? CKKT_ERR_NOT_SPD : CKKT_OK;
+}
+
+static ckkt_status set_new_values(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                                  const double* sigma_x, const double* sigma_s, double gamma, hipStream_t st) {
+    const Plan& P = h->plan;
+    if ((P.nnz_w > 0 && !w_val) || (P.nnz_g > 0 && !g_val) || (P.nnz_h > 0 && !h_val) || (P.n > 0 && !sigma_x))
+        return CKKT_ERR_ARG;
+    int64_t ns_len = h->formulation == CKKT_HYKKT ? P.m_ineq : P.m;
+    if (ns_len > 0 && !sigma_s) return CKKT_ERR_ARG;
+    h->vals = SysVals{w_val, g_val, h_val, sigma_x, sigma_s, gamma};
+    launch_row_weights(h->dp, h->vals, h->d, st);
+    return CKKT_OK;
+}
+
+static ckkt_status learned_ready(ckkt_handle* h) {
+    if (!h) return CKKT_ERR_ARG;
+    if (!h->opt.learned) return CKKT_ERR_ARG;
+    if (!h->ws || !h->factored || !h->stale_valid) return CKKT_ERR_STATE;
+    return CKKT_OK;
+}
+
+// features of the current values (h->vals, h->d) against the stale system
+static void compute_features(ckkt_handle* h, float* out, hipStream_t st) {
+    launch_copy(h->plan.m, h->d, h->dnew, st);
+    launch_kdiag(h->dp, h->vals, h->dnew, h->kdnew, st);
+    launch_features(h->dp, h->vals.sigma_x, h->dnew, h->kdnew, h->sxold, h->dold, h->kdold, out, st);
+}
+
+ckkt_status ckkt_features(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                          const double* sigma_x, const double* sigma_s, double gamma, float* features,
+                          void* stream) {
+    ckkt_status rc = learned_ready(h);
+    if (rc) return rc;
+    if (!features && h->plan.n > 0) return CKKT_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = set_new_values(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, st);
+    if (rc) return rc;
+    compute_features(h, features, st);
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
+}
+
+ckkt_status ckkt_mlp_forward(int64_t n, const float* features, const float* params, float* out, float* cache,
+                             void* stream) {
+    if (n < 0 || (n > 0 && (!features || !params || !out))) return CKKT_ERR_ARG;
+    launch_mlp_forward(n, features, params, out, cache, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
+}
+
+size_t ckkt_mlp_workspace(int64_t n) { return n < 0 ? 0 : mlp_workspace_bytes(n); }
+
+ckkt_status ckkt_mlp_backward(int64_t n, const float* features, const float* params, const float* cache,
+                              const float* g_out, float* grad, void* ws, void* stream) {
+    if (n < 0 || !params || !grad || !ws || (n > 0 && (!features || !cache || !g_out))) return CKKT_ERR_ARG;
+    launch_mlp_backward(n, features, params, cache, g_out, grad, ws, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
+}
+
+ckkt_status ckkt_adam(int32_t nparam, float* params, const float* grad, float* m, float* v, int32_t step,
+                      float lr, void* stream) {
+    if (nparam < 0 || step < 1 || (nparam > 0 && (!params || !grad || !m || !v))) return CKKT_ERR_ARG;
+    launch_adam(nparam, params, grad, m, v, step, lr, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
+}
+
+ckkt_status ckkt_mlp_train_step(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                                const double* sigma_x, const double* sigma_s, double gamma, const double* rhs,
+                                const double* target, float* params, float* m, float* v, int32_t step, float lr,
+                                double* loss, void* stream) {
+    ckkt_status rc = learned_ready(h);
+    if (rc) return rc;
+    if (h->formulation != CKKT_LIFTED) return CKKT_ERR_ARG;
+    const int n = h->plan.n;
+    if (n > 0 && (!rhs || !target)) return CKKT_ERR_ARG;
+    if (!params || !m || !v || step < 1) return CKKT_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = set_new_values(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, st);
+    if (rc) return rc;
+    const bool use64 = h->fp64_factored;
+    double *y = h->lv[0], *e = h->lv[1], *w = h->lv[2], *t = h->lv[3];
+    double* sc = h->sc + 13;  // [0] e.e, [1] x.x
+    compute_features(h, h->feat, st);
+    launch_mlp_forward(n, h->feat, params, h->mo, h->cache, st);
+    launch_dscale(n, h->mo, rhs, t, st);            // D b
+    apply_inverse(h, t, y, use64, st);               // y = K_s^{-1} D b
+    launch_train_err(n, h->mo, y, target, e, st);    // e = D y - x
+    launch_dot(n, e, e, h->dotpart, sc + 0, st);
+    launch_dot(n, target, target, h->dotpart, sc + 1, st);
+    launch_train_gzD(n, h->mo, e, sc, t, st);        // D g_z
+    apply_inverse(h, t, w, use64, st);               // w = K_s^{-1} D g_z
+    launch_train_go(n, h->mo, e, y, rhs, w, sc, h->go, st);
+    launch_mlp_backward(n, h->feat, params, h->cache, h->go, h->grad, h->mlpws, st);
+    launch_adam(kMlpNParam, params, h->grad, m, v, step, lr, st);
+    double hs[2];
+    HIP_TRY(hipMemcpyAsync(h->host, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::memcpy(hs, h->host, sizeof(hs));
+    if (loss) *loss = hs[1] > 0 ? hs[0] / hs[1] : 0.0;
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
+}
+
+ckkt_status ckkt_pcg_solve(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                           const double* sigma_x, const double* sigma_s, double gamma, const float* params,
+                           const double* rhs, double* sol, int32_t maxit, double tol, int32_t allow_refactor,
+                           ckkt_solve_info* info, void* stream) {
+    ckkt_solve_info local{};
+    if (!info) info = &local;
+    std::memset(info, 0, sizeof(*info));
+    ckkt_status rc = learned_ready(h);
+    if (rc) return info->status = rc;
+    if (h->formulation != CKKT_LIFTED) return info->status = CKKT_ERR_ARG;
+    const int n = h->plan.n;
+    if (n > 0 && (!rhs || !sol)) return info->status = CKKT_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = set_new_values(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, st);
+    if (rc) return info->status = rc;
+    const float* o = nullptr;
+    if (params) {
+        compute_features(h, h->feat, st);
+        launch_mlp_forward(n, h->feat, params, h->mo, nullptr, st);
+        o = h->mo;
+    }
+    ResidualOut r;
+    double bmax = 0.0;
+    rc = read_rhs_max(h, rhs, n, nullptr, 0, bmax, st);
+    if (rc) return info->status = rc;
+    bool ok = pcg_stale(h, rhs, sol, o, maxit, tol, r, info, st, rc);
+    if (rc) return info->status = rc;
+    info->omega = r.omega;
+    info->rho = bmax > 0 ? r.resmax / bmax : r.resmax;
+    if (ok) return info->status = CKKT_OK;
+    if (!allow_refactor) return info->status = CKKT_ERR_NO_CONVERGENCE;
+    // fallback (and judge): factorize the new system, which becomes the
+    // stale reference of the following solves, and solve it directly
+    int pcg_iters = info->pcg_iters;
+    rc = ckkt_factorize(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, stream);
+    if (rc) return info->status = rc;
+    rc = ckkt_solve(h, rhs, sol, info, stream);
+    info->pcg_iters += pcg_iters;
+    info->fallback = 2;
+    return info->status = rc;
 }
 
 ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info) {

@@ -112,4 +112,21 @@ void launch_axpy_dev(int n, const double* sc, int idx, double sign, const double
 // Jacobi scale s_k = 1/sqrt(K_kk) over the factor numbering (FP32 path).
 void launch_diag_scale(const DevPlan& P, const double* K, double* scale, hipStream_t st);
 
+// ---- learned diagonal preconditioner (kernels_mlp.hip)
+constexpr int kMlpF = 8, kMlpH = 64;
+constexpr int kMlpNParam = kMlpH * kMlpF + kMlpH + kMlpH * kMlpH + kMlpH + kMlpH + 1;
+void launch_kdiag(const DevPlan& P, const SysVals& v, const double* d, double* kd, hipStream_t st);
+void launch_features(const DevPlan& P, const double* sx_new, const double* d_new, const double* kd_new,
+                     const double* sx_old, const double* d_old, const double* kd_old, float* feat, hipStream_t st);
+void launch_mlp_forward(int64_t n, const float* feat, const float* prm, float* out, float* cache, hipStream_t st);
+size_t mlp_workspace_bytes(int64_t n);
+void launch_mlp_backward(int64_t n, const float* feat, const float* prm, const float* cache, const float* g_o,
+                         float* grad, void* ws, hipStream_t st);
+void launch_adam(int np, float* prm, const float* g, float* m, float* v, int step, float lr, hipStream_t st);
+void launch_dscale(int n, const float* o, const double* x, double* out, hipStream_t st);
+void launch_train_err(int n, const float* o, const double* y, const double* x, double* e, hipStream_t st);
+void launch_train_gzD(int n, const float* o, const double* e, const double* sc, double* out, hipStream_t st);
+void launch_train_go(int n, const float* o, const double* e, const double* y, const double* b, const double* w,
+                     const double* sc, float* g_o, hipStream_t st);
+
 }  // namespace ckkt

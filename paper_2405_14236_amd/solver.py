@@ -38,7 +38,7 @@ def _pattern(prob, formulation):
 
 
 def options(precision="fp64", ordering="amd", tol=1e-10, ir_maxit=10, cg_tol=1e-10, cg_maxit=0, relax=1,
-            lds_front_max=0):
+            lds_front_max=0, learned=0):
     lib = L.load()
     o = L.Options()
     lib.ckkt_default_options(ctypes.byref(o))
@@ -46,6 +46,7 @@ def options(precision="fp64", ordering="amd", tol=1e-10, ir_maxit=10, cg_tol=1e-
     o.ordering = {"amd": L.ORDER_AMD, "natural": L.ORDER_NATURAL}[ordering]
     o.tol, o.ir_maxit, o.cg_tol, o.cg_maxit, o.relax = tol, ir_maxit, cg_tol, cg_maxit, relax
     o.lds_front_max = lds_front_max
+    o.learned = int(learned)
     return o
 
 
@@ -164,6 +165,36 @@ class Solver:
         L.check(self.lib.ckkt_get_timing(self.h, ms, calls))
         return list(ms), list(calls)
 
+    # ------------------------------------------------------- learned PCG
+    def features(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma=0.0):
+        import torch
+        out = torch.empty((self.n, L.MLP_F), dtype=torch.float32, device=self.workspace.device)
+        L.check(self.lib.ckkt_features(self.h, _ptr(w_val), _ptr(g_val), _ptr(h_val), _ptr(sigma_x),
+                                       _ptr(sigma_s), float(gamma), _ptr(out), _stream()), "ckkt_features")
+        return out
+
+    def mlp_train_step(self, vals, gamma, rhs, target, params, m, v, step, lr):
+        loss = ctypes.c_double()
+        w, g, hv, sx, ss = vals
+        L.check(self.lib.ckkt_mlp_train_step(self.h, _ptr(w), _ptr(g), _ptr(hv), _ptr(sx), _ptr(ss), float(gamma),
+                                             _ptr(rhs), _ptr(target), _ptr(params), _ptr(m), _ptr(v), int(step),
+                                             float(lr), ctypes.byref(loss), _stream()), "ckkt_mlp_train_step")
+        return loss.value
+
+    def pcg_solve(self, vals, gamma, params, rhs, maxit=50, tol=1e-8, allow_refactor=True, out=None,
+                  raise_on_error=True):
+        import torch
+        if out is None:
+            out = torch.empty_like(rhs)
+        w, g, hv, sx, ss = vals
+        si = L.SolveInfo()
+        st = self.lib.ckkt_pcg_solve(self.h, _ptr(w), _ptr(g), _ptr(hv), _ptr(sx), _ptr(ss), float(gamma),
+                                     _ptr(params), _ptr(rhs), _ptr(out), int(maxit), float(tol), int(allow_refactor),
+                                     ctypes.byref(si), _stream())
+        if raise_on_error:
+            L.check(st, "ckkt_pcg_solve")
+        return out, si.as_dict()
+
     # ---------------------------------------------------------------- host
     def host_factor_solve(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma, rhs):
         """Sequential host run of the numeric phase over the same plan (no GPU)."""
@@ -185,3 +216,29 @@ def device_values(prob, device="cuda", formulation="lifted"):
 
     ss = prob.sigma_s if formulation == "lifted" else prob.sigma_s_ineq
     return t(prob.w_val), t(prob.g_val), t(prob.h_val), t(prob.sigma_x), t(ss)
+
+
+def mlp_forward(feat, params, cache=None):
+    import torch
+    n = feat.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device=feat.device)
+    lib = L.load()
+    L.check(lib.ckkt_mlp_forward(n, _ptr(feat), _ptr(params), _ptr(out), _ptr(cache), _stream()), "ckkt_mlp_forward")
+    return out
+
+
+def mlp_backward(feat, params, cache, g_out):
+    import torch
+    n = feat.shape[0]
+    lib = L.load()
+    ws = torch.empty(max(lib.ckkt_mlp_workspace(n), 16), dtype=torch.uint8, device=feat.device)
+    grad = torch.empty(L.MLP_NPARAM, dtype=torch.float32, device=feat.device)
+    L.check(lib.ckkt_mlp_backward(n, _ptr(feat), _ptr(params), _ptr(cache), _ptr(g_out), _ptr(grad), _ptr(ws),
+                                  _stream()), "ckkt_mlp_backward")
+    return grad
+
+
+def adam(params, grad, m, v, step, lr):
+    lib = L.load()
+    L.check(lib.ckkt_adam(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                          _stream()), "ckkt_adam")

@@ -1,0 +1,184 @@
+"""GPU tests of the learned diagonal preconditioner (PCG around a stale factor).
+
+* MLP forward and backward kernels against the FP64 oracle (FP32 tolerance);
+* features against the oracle's definition;
+* the fused training step: its first Adam update points along the oracle's
+  gradient of the loss through the stale solve, and the loss decreases;
+* PCG meets the gate (omega <= 1e-8) with and without the network, and
+  falls back to FP64 refactorization when it cannot;
+* on held-out systems of an IPM-like sequence the trained network needs
+  fewer PCG iterations than D = I.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp as om
+from oracle import sparse as osp
+from paper_2405_14236_amd import workloads
+from paper_2405_14236_amd.solver import Solver, adam, device_values, mlp_backward, mlp_forward
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def print_case(name, **kw):
+    print(f"\n[case] {name} {kw}", flush=True)
+
+
+def t32(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=DEV)
+
+
+def t64(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def test_mlp_forward_backward_match_oracle():
+    print_case("mlp_fwd_bwd")
+    rng = np.random.default_rng(0)
+    n = 1000
+    f = rng.standard_normal((n, om.F)) * 0.5
+    f[:, 7] = 1.0
+    theta = om.init_params(3) + 0.05 * rng.standard_normal(om.NPARAM)
+    g_o = rng.standard_normal(n)
+    feat, prm = t32(f), t32(theta)
+    cache = torch.empty(2 * om.H * n, dtype=torch.float32, device=DEV)
+    o = mlp_forward(feat, prm, cache).cpu().numpy()
+    # oracle on the FP32-rounded inputs
+    f32, th32 = f.astype(np.float32).astype(np.float64), theta.astype(np.float32).astype(np.float64)
+    o_ref, c_ref = om.forward(th32, f32)
+    assert np.abs(o - o_ref).max() <= 1e-4 * max(1.0, np.abs(o_ref).max())
+    g = mlp_backward(feat, prm, cache, t32(g_o)).cpu().numpy()
+    g_ref = om.backward(th32, f32, c_ref, g_o.astype(np.float32).astype(np.float64))
+    assert np.abs(g - g_ref).max() <= 1e-3 * max(1.0, np.abs(g_ref).max()), np.abs(g - g_ref).max()
+
+
+def test_adam_matches_oracle():
+    print_case("adam")
+    rng = np.random.default_rng(1)
+    th, g = rng.standard_normal(om.NPARAM), rng.standard_normal(om.NPARAM)
+    m, v = rng.random(om.NPARAM) * 0.1, rng.random(om.NPARAM) * 0.1
+    P, M, V = t32(th), t32(m), t32(v)
+    adam(P, t32(g), M, V, 3, 1e-2)
+    th_r, m_r, v_r = om.adam(th.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64),
+                             m.astype(np.float32).astype(np.float64), v.astype(np.float32).astype(np.float64), 3,
+                             lr=1e-2)
+    assert np.allclose(P.cpu().numpy(), th_r, rtol=1e-5, atol=1e-6)
+    assert np.allclose(M.cpu().numpy(), m_r, rtol=1e-5, atol=1e-7)
+
+
+def pde_sequence(side, num, seed=0):
+    p = workloads.pde_control(side, seed=seed)
+    seq = workloads.ipm_sigma_sequence(p, num, seed=seed)
+    rng = np.random.default_rng(seed + 11)
+    rhs = [rng.standard_normal(p.n) for _ in range(num)]
+    return p, seq, rhs
+
+
+def test_features_match_oracle():
+    p, seq, _ = pde_sequence(8, 10)
+    print_case("features", n=p.n)
+    s = Solver(p, "lifted", learned=1).bind(DEV)
+    sx0, ss0 = seq[3]
+    w, g, h, _, _ = device_values(p, DEV)
+    s.factorize(w, g, h, t64(sx0), t64(ss0))
+    sx1, ss1 = seq[7]
+    feat = s.features(w, g, h, t64(sx1), t64(ss1)).cpu().numpy()
+    P = osp.Problem(p)
+    ref = om.features(p.n, p.w_ptr, p.w_idx, p.w_val, P.J, sx1, ss1, sx0, ss0)
+    assert np.abs(feat - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+def test_train_step_follows_oracle_gradient_and_reduces_loss():
+    p, seq, rhs = pde_sequence(8, 12)
+    print_case("train_step", n=p.n)
+    s = Solver(p, "lifted", learned=1).bind(DEV)
+    w, g, h, _, _ = device_values(p, DEV)
+    sxs, sss = seq[5]
+    s.factorize(w, g, h, t64(sxs), t64(sss))
+    P = osp.Problem(p)
+    sx, ss = seq[9]
+    x, _ = osp.solve_lifted(P, sx, ss, rhs[9])
+    theta0 = om.init_params(7)
+    prm, m, v = t32(theta0), torch.zeros(om.NPARAM, device=DEV), torch.zeros(om.NPARAM, device=DEV)
+    loss0 = s.mlp_train_step((w, g, h, t64(sx), t64(ss)), 0.0, t64(rhs[9]), t64(x), prm, m, v, 1, 1e-3)
+    # oracle gradient through the stale solve (FP64, SuperLU of the stale K)
+    Ks = osp.assemble_condensed(P.W, sxs, P.J, sss)
+    lu = osp.spla.splu(Ks)
+    f = om.features(p.n, p.w_ptr, p.w_idx, p.w_val, P.J, sx, ss, sxs, sss)
+    L_ref, g_ref = om.loss_and_grad(theta0.astype(np.float32).astype(np.float64), f, rhs[9], x, lu.solve)
+    assert abs(loss0 - L_ref) <= 1e-3 * L_ref
+    step = theta0.astype(np.float32) - prm.cpu().numpy()   # = lr * sign-ish(g) on the first Adam step
+    big = np.abs(g_ref) > 1e-3 * np.abs(g_ref).max()
+    agree = np.mean(np.sign(step[big]) == np.sign(g_ref[big]))
+    assert agree > 0.98, agree
+    losses = [loss0]
+    for k in range(2, 40):
+        losses.append(s.mlp_train_step((w, g, h, t64(sx), t64(ss)), 0.0, t64(rhs[9]), t64(x), prm, m, v, k, 1e-3))
+    print("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.9 * losses[0]
+
+
+def test_pcg_meets_gate_and_falls_back():
+    p, seq, rhs = pde_sequence(8, 20)
+    print_case("pcg_gate", n=p.n)
+    s = Solver(p, "lifted", "fp32_ir", learned=1).bind(DEV)
+    w, g, h, _, _ = device_values(p, DEV)
+    s.factorize(w, g, h, t64(seq[10][0]), t64(seq[10][1]))
+    P = osp.Problem(p)
+    # a neighbour of the stale system: PCG with D = I converges
+    sx, ss = seq[11]
+    z, info = s.pcg_solve((w, g, h, t64(sx), t64(ss)), 0.0, None, t64(rhs[11]), maxit=50, tol=1e-8)
+    assert info["fallback"] == 0 and info["pcg_iters"] > 0
+    assert osp.omega_condensed(P.W, sx, P.J, ss, z.cpu().numpy(), rhs[11]) <= 1e-8
+    # far away with a 3-iteration budget: refactorization fallback, still gated
+    sx, ss = seq[19]
+    z, info = s.pcg_solve((w, g, h, t64(sx), t64(ss)), 0.0, None, t64(rhs[19]), maxit=3, tol=1e-8)
+    assert info["fallback"] == 2
+    assert osp.omega_condensed(P.W, sx, P.J, ss, z.cpu().numpy(), rhs[19]) <= 1e-8
+
+
+def test_learned_preconditioner_beats_identity_on_held_out_systems():
+    """Train on solver-generated pairs of systems 0..19 (stale factor of system
+    10), then run PCG around the factor of system 19 on systems 20..27 with
+    the trained network and with D = I."""
+    num = 80
+    p, seq, rhs = pde_sequence(10, num)
+    print_case("learned_gain", n=p.n)
+    P = osp.Problem(p)
+    s = Solver(p, "lifted", "fp32_ir", learned=1).bind(DEV)
+    w, g, h, _, _ = device_values(p, DEV)
+    pairs = []
+    for k in range(20):
+        sx, ss = seq[k]
+        s.factorize(w, g, h, t64(sx), t64(ss))
+        x, info = s.solve(t64(rhs[k]))
+        pairs.append((k, x.clone()))
+    s.factorize(w, g, h, t64(seq[10][0]), t64(seq[10][1]))
+    prm = t32(om.init_params(0))
+    m, v = torch.zeros(om.NPARAM, device=DEV), torch.zeros(om.NPARAM, device=DEV)
+    step = 0
+    for epoch in range(30):
+        for k, x in pairs:
+            if k == 10:
+                continue
+            step += 1
+            s.mlp_train_step((w, g, h, t64(seq[k][0]), t64(seq[k][1])), 0.0, t64(rhs[k]), x, prm, m, v, step, 3e-3)
+    s.factorize(w, g, h, t64(seq[19][0]), t64(seq[19][1]))
+    it_net, it_id = 0, 0
+    for k in range(20, 28):
+        vals = (w, g, h, t64(seq[k][0]), t64(seq[k][1]))
+        z1, i1 = s.pcg_solve(vals, 0.0, prm, t64(rhs[k]), maxit=200, tol=1e-8, allow_refactor=False,
+                             raise_on_error=False)
+        z2, i2 = s.pcg_solve(vals, 0.0, None, t64(rhs[k]), maxit=200, tol=1e-8, allow_refactor=False,
+                             raise_on_error=False)
+        it_net += i1["pcg_iters"]
+        it_id += i2["pcg_iters"]
+        for z, i in ((z1, i1), (z2, i2)):
+            if i["status"] == 0:
+                assert osp.omega_condensed(P.W, seq[k][0], P.J, seq[k][1], z.cpu().numpy(), rhs[k]) <= 1e-8
+    print("PCG iterations, learned D:", it_net, " D = I:", it_id)
+    assert it_net < it_id
