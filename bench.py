@@ -36,6 +36,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", default="netflow",
+                    choices=["netflow", "netflow_seq", "batch", "pde_learned"],
+                    help="netflow: the benchmark line; the others measure the other target forms")
+    ap.add_argument("--systems", type=int, default=60, help="sequence length (netflow_seq, pde_learned)")
+    ap.add_argument("--instances", type=int, default=512, help="batch size (batch)")
+    ap.add_argument("--side", type=int, default=48, help="grid side of the PDE workload")
     return ap.parse_args()
 
 
@@ -113,6 +119,171 @@ def cpu_baseline(p, sig, budget_s):
                        f"omega<=1e-10, single-threaded), worst omega {worst:.1e}")
 
 
+def _line(a, metric_value, ms, config, extra, dtype="f64"):
+    line = {
+        "metric": "condensed-KKT solves/s at 1e-8 rel. residual: FP64 vs FP32+IR/batched/PCG",
+        "value": metric_value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic", "config": config,
+    }
+    line.update(extra)
+    print(json.dumps(line))
+
+
+def run_sequence(a, torch, workloads, Solver, device_values):
+    """IPM-like 60-system sequence on the 80k-node network-flow problem:
+    every system is factorized and solved, FP64 versus FP32 + FP64 refinement."""
+    from oracle import sparse as osp
+    N = a.nodes if a.nodes != 10_000 else 80_000
+    p = workloads.network_flow(N, seed=a.seed)
+    seq = workloads.ipm_sigma_sequence(p, a.systems, seed=a.seed)
+    w, g, h, _, _ = device_values(p, "cuda", "lifted")
+    sx = [torch.as_tensor(x, device="cuda") for x, _ in seq]
+    ss = [torch.as_tensor(y, device="cuda") for _, y in seq]
+    b = torch.as_tensor(p.b, device="cuda")
+    out = {}
+    for prec in ("fp64", "fp32_ir"):
+        s = Solver(p, "lifted", prec, tol=1e-10 if prec == "fp64" else 1e-8).bind("cuda")
+        x = torch.empty_like(b)
+        s.factorize(w, g, h, sx[0], ss[0]); s.solve(b, x)
+        torch.cuda.synchronize()
+        per, infos = [], []
+        for k in range(a.systems):
+            t0 = time.perf_counter()
+            s.factorize(w, g, h, sx[k], ss[k])
+            _, si = s.solve(b, x, raise_on_error=False)
+            torch.cuda.synchronize()
+            per.append(time.perf_counter() - t0)
+            infos.append(si)
+            if k in (0, a.systems // 2, a.systems - 1):
+                P = osp.Problem(p)
+                si["oracle_omega"] = osp.omega_condensed(P.W, seq[k][0], P.J, seq[k][1], x.cpu().numpy(), p.b)
+        out[prec] = dict(solves_per_s=len(per) / sum(per), ms_per_solve=1e3 * float(np.mean(per)),
+                         ms_per_system=[round(1e3 * t, 3) for t in per],
+                         fallback=[si["fallback"] for si in infos],
+                         refine_steps=[si["refine_steps"] for si in infos],
+                         omega_max=max(si["omega"] for si in infos),
+                         gate_ok=all(si["status"] == 0 and si["omega"] <= 1e-8 for si in infos),
+                         oracle_spot_omega=[si.get("oracle_omega") for si in infos if "oracle_omega" in si])
+    inf = Solver(p, "lifted").info()
+    _line(a, out["fp32_ir"]["solves_per_s"], out["fp32_ir"]["ms_per_solve"],
+          {"workload": f"network-flow NLP {N} nodes ({p.n} vars), {a.systems}-system IPM-like sigma sequence "
+                       "(1 -> 1e+-8), LiftedKKT", "n": p.n, "nnz_l": inf["nnz_l"], "levels": inf["n_levels"]},
+          {"forms": out}, dtype="f32+f64")
+
+
+def run_batch(a, torch, workloads, Solver):
+    """512 independent network-flow instances of uneven size, analysed as one
+    block-diagonal system, autotuned, FP32 factor + FP64 refinement."""
+    probs = workloads.batch_network_flow(a.instances, seed=a.seed)
+    rng = np.random.default_rng(a.seed + 5)
+    cat = lambda xs: torch.as_tensor(np.concatenate(xs), device="cuda")
+    w = cat([q.w_val for q in probs]); g = cat([q.g_val for q in probs]); h = cat([q.h_val for q in probs])
+    b = cat([q.b for q in probs])
+    nsys = a.steps + a.warmup
+    sig = []
+    for _ in range(nsys):
+        sxs = [workloads.log_uniform(rng, q.n) for q in probs]
+        sss = [workloads.log_uniform(rng, q.m) for q in probs]
+        sig.append((cat(sxs), cat([x[:q.m_eq] for x, q in zip(sss, probs)] + [x[q.m_eq:] for x, q in zip(sss, probs)])))
+    out = {}
+    for prec in ("fp32_ir", "fp64"):
+        t0 = time.perf_counter()
+        s = Solver(None, "lifted", prec, batch=probs, tol=1e-8 if prec == "fp32_ir" else 1e-10).bind("cuda")
+        t_an = time.perf_counter() - t0
+        chosen, best = s.autotune(w, g, h, sig[0][0], sig[0][1])
+        x = torch.empty_like(b)
+        for k in range(a.warmup):
+            s.factorize(w, g, h, *sig[k]); s.solve(b, x)
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for k in range(a.warmup, nsys):
+            s.factorize(w, g, h, *sig[k])
+            _, si = s.solve(b, x, raise_on_error=False)
+            infos.append(si)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = dict(solves_per_s=a.instances * a.steps / dt, ms_per_batch=1e3 * dt / a.steps,
+                         analyze_s=t_an, autotune=chosen, autotune_best_ms=best,
+                         gate_ok=all(si["status"] == 0 and si["omega"] <= 1e-8 for si in infos),
+                         omega_max=max(si["omega"] for si in infos),
+                         fallbacks=int(sum(si["fallback"] != 0 for si in infos)))
+    inf = s.info()
+    _line(a, out["fp32_ir"]["solves_per_s"], out["fp32_ir"]["ms_per_batch"],
+          {"workload": f"{a.instances} network-flow instances, nodes uniform in [500, 2000], LiftedKKT, one "
+                       "block-diagonal analysis, graph-captured level launches, autotuned launch shapes",
+           "n_total": inf["n"], "levels": inf["n_levels"]}, {"forms": out}, dtype="f32+f64")
+
+
+def run_pde_learned(a, torch, workloads, Solver, device_values):
+    """PDE-constrained problem, IPM-like sequence: FP64 refactorization of
+    every system versus PCG around a stale FP32 factor, with and without the
+    learned diagonal (trained on systems 0..19 with the stale factor of
+    system 10, then used around the factor of system 19, refreshed on
+    fallback)."""
+    from oracle import mlp as om
+    from oracle import sparse as osp
+    p = workloads.pde_control(a.side, seed=a.seed)
+    num = a.systems
+    seq = workloads.ipm_sigma_sequence(p, num, seed=a.seed)
+    rng = np.random.default_rng(a.seed + 11)
+    rhs = [torch.as_tensor(rng.standard_normal(p.n), device="cuda") for _ in range(num)]
+    w, g, h, _, _ = device_values(p, "cuda", "lifted")
+    T = lambda v: torch.as_tensor(v, device="cuda")
+    sx = [T(x) for x, _ in seq]; ss = [T(y) for _, y in seq]
+    out = {}
+    # baseline: FP64 factorization of every system
+    s64 = Solver(p, "lifted", "fp64").bind("cuda")
+    x = torch.empty_like(rhs[0])
+    s64.factorize(w, g, h, sx[0], ss[0]); s64.solve(rhs[0], x); torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    targets = []
+    for k in range(num):
+        s64.factorize(w, g, h, sx[k], ss[k])
+        _, si = s64.solve(rhs[k], x)
+        if k < 20:
+            targets.append(x.clone())
+    torch.cuda.synchronize()
+    out["fp64_refactor"] = dict(solves_per_s=num / (time.perf_counter() - t0))
+    del s64
+    # training (systems 0..19 generated by the solver above, stale factor of system 10)
+    s = Solver(p, "lifted", "fp32_ir", learned=1).bind("cuda")
+    s.factorize(w, g, h, sx[10], ss[10])
+    prm = torch.as_tensor(om.init_params(a.seed).astype(np.float32), device="cuda")
+    m = torch.zeros_like(prm); v = torch.zeros_like(prm)
+    t0 = time.perf_counter()
+    step, losses = 0, []
+    for epoch in range(20):
+        for k in range(20):
+            if k == 10:
+                continue
+            step += 1
+            losses.append(s.mlp_train_step((w, g, h, sx[k], ss[k]), 0.0, rhs[k], targets[k], prm, m, v, step, 3e-3))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    for name, params in (("pcg_learned", prm), ("pcg_identity", None)):
+        s.factorize(w, g, h, sx[19], ss[19])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, fb, oms = [], 0, []
+        for k in range(20, num):
+            _, si = s.pcg_solve((w, g, h, sx[k], ss[k]), 0.0, params, rhs[k], maxit=50, tol=1e-8,
+                                allow_refactor=True, raise_on_error=False)
+            iters.append(si["pcg_iters"]); fb += si["fallback"] != 0; oms.append(si["omega"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = dict(solves_per_s=(num - 20) / dt, pcg_iters=iters, refactorizations=fb,
+                         omega_max=max(oms), gate_ok=max(oms) <= 1e-8)
+    out["training"] = dict(seconds=train_s, steps=step, loss_first=losses[0], loss_last=losses[-1])
+    inf = s.info()
+    _line(a, out["pcg_learned"]["solves_per_s"], 1e3 / out["pcg_learned"]["solves_per_s"],
+          {"workload": f"3-D Poisson control {a.side}^3 states + stride-2 controls (n={p.n}), {num}-system "
+                       "IPM-like sigma sequence, LiftedKKT, PCG around a stale FP32 factor",
+           "n": p.n, "nnz_l": inf["nnz_l"], "factor_flops": inf["factor_flops"], "max_front": inf["max_front"]},
+          {"forms": out}, dtype="f32+f64")
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -120,6 +291,14 @@ def main():
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
+    if a.workload != "netflow":
+        from paper_2405_14236_amd import workloads
+        from paper_2405_14236_amd.solver import Solver, device_values
+        if a.workload == "netflow_seq":
+            return run_sequence(a, torch, workloads, Solver, device_values)
+        if a.workload == "batch":
+            return run_batch(a, torch, workloads, Solver)
+        return run_pde_learned(a, torch, workloads, Solver, device_values)
     from paper_2405_14236_amd import workloads
     from paper_2405_14236_amd.solver import Solver, device_values
 

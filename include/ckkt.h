@@ -290,6 +290,19 @@ ckkt_status ckkt_pcg_solve(ckkt_handle* h, const double* w_val, const double* g_
                            const double* rhs, double* sol, int32_t maxit, double tol, int32_t allow_refactor,
                            ckkt_solve_info* info, void* stream);
 
+/* Autotuner of the launch shapes that leave the factor layout unchanged
+ * (boundary of the compact small-front class, workgroup sizes of the small
+ * fronts and of the sweeps).  Times `reps` factorize + factor applications of
+ * the given system for every candidate on `stream`, keeps the fastest for
+ * this handle and caches it for patterns with the same analysis (a later
+ * call on such a pattern applies the cached choice without timing and
+ * returns *best_ms = -1).  chosen (host, 4 int32, may be NULL) receives
+ * {compact front order, compact workgroup size, tiny workgroup size, sweep
+ * cutoff}.  Leaves a valid factor of the given system.  Blocks. */
+ckkt_status ckkt_autotune(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                          const double* sigma_x, const double* sigma_s, double gamma, int32_t reps,
+                          int32_t* chosen, double* best_ms, void* stream);
+
 ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info);
 const char* ckkt_status_string(ckkt_status s);
 void        ckkt_destroy(ckkt_handle* h);

@@ -79,6 +79,8 @@ SIGNATURES = [
                                       POINTER(c_double), c_void_p]),
     ("ckkt_pcg_solve", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
                                  c_void_p, c_void_p, c_int32, c_double, c_int32, POINTER(SolveInfo), c_void_p]),
+    ("ckkt_autotune", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
+                                P_i32, POINTER(c_double), c_void_p]),
     ("ckkt_get_info", c_int32, [c_void_p, POINTER(Info)]),
     ("ckkt_status_string", c_char_p, [c_int32]),
     ("ckkt_destroy", None, [c_void_p]),

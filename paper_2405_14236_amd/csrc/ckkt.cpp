@@ -48,7 +48,18 @@ size_t vbytes(const std::vector<V>& v) { return v.size() * sizeof(V); }
 
 }  // namespace
 
+// Launch shapes that do not change the factor layout; chosen by the
+// autotuner per pattern.
+struct Tune {
+    int compact64 = kCompactFront64;  // FP64 fronts up to this order form the compact class
+    int compact32 = kCompactFront32;  // same for FP32
+    int tiny_threads = 64;            // workgroup size when the compact class holds fronts <= 32
+    int compact_threads = 256;        // workgroup size of the compact class otherwise
+    int sweep_cutoff = 64;            // sweeps use 256 threads when a level's largest front exceeds this
+};
+
 struct ckkt_handle {
+    Tune tune;
     Plan plan;
     ckkt_options opt{};
     int32_t formulation = CKKT_LIFTED;
@@ -156,6 +167,7 @@ struct PhaseTimer {
 
 void build_levels(ckkt_handle* h) {
     const Plan& P = h->plan;
+    const Tune& T = h->tune;
     h->levels.assign(P.nlev, LevelInfo{});
     auto front = [&](int s) { return P.sn_rowptr[s + 1] - P.sn_rowptr[s]; };
     auto width = [&](int s) { return P.sn_start[s + 1] - P.sn_start[s]; };
@@ -169,9 +181,11 @@ void build_levels(ckkt_handle* h) {
         for (int t = L.small_begin; t < L.small_begin + L.small_count; ++t) {
             const int f = front(P.lvl_small[t]);
             L.small_maxf = std::max(L.small_maxf, f);
-            if (f <= kCompactFront64) { L.small_split++; L.small_maxf_a = std::max(L.small_maxf_a, f); }
-            if (f <= kCompactFront32) { L.small_split32++; L.small_maxf_a32 = std::max(L.small_maxf_a32, f); }
+            if (f <= T.compact64) { L.small_split++; L.small_maxf_a = std::max(L.small_maxf_a, f); }
+            if (f <= T.compact32) { L.small_split32++; L.small_maxf_a32 = std::max(L.small_maxf_a32, f); }
         }
+        const int fa = h->precision == CKKT_FP32_IR ? L.small_maxf_a32 : L.small_maxf_a;
+        L.small_threads_a = fa <= 32 ? T.tiny_threads : T.compact_threads;
         L.big_begin = P.lvl_big_ptr[l];
         L.big_count = P.lvl_big_ptr[l + 1] - L.big_begin;
         L.big_maxw = L.big_maxf = 0;
@@ -188,6 +202,7 @@ void build_levels(ckkt_handle* h) {
         }
         L.tile_begin = P.big_tiles_ptr[l];
         L.tile_count = P.big_tiles_ptr[l + 1] - L.tile_begin;
+        L.sweep_threads = L.all_maxf > T.sweep_cutoff ? 256 : 64;
     }
 }
 
@@ -1220,6 +1235,94 @@ ckkt_status ckkt_pcg_solve(ckkt_handle* h, const double* w_val, const double* g_
     info->pcg_iters += pcg_iters;
     info->fallback = 2;
     return info->status = rc;
+}
+
+// Per-pattern cache of autotuned launch shapes (signature of the plan).
+static std::vector<std::pair<uint64_t, Tune>>& tune_cache() {
+    static std::vector<std::pair<uint64_t, Tune>> c;
+    return c;
+}
+
+static uint64_t plan_signature(const ckkt_handle* h) {
+    const Plan& P = h->plan;
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { x = (x ^ v) * 1099511628211ull; };
+    mix(P.n); mix(P.m_eq); mix(P.m_ineq); mix(P.ns); mix(P.nlev); mix((uint64_t)P.nnz_l); mix(P.max_front);
+    mix(h->precision); mix(h->formulation);
+    for (int32_t v : P.sn_rowptr) mix((uint64_t)v);
+    return x;
+}
+
+static void apply_tune(ckkt_handle* h, const Tune& t) {
+    h->tune = t;
+    build_levels(h);
+    for (auto& g : h->graphs)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
+ckkt_status ckkt_autotune(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                          const double* sigma_x, const double* sigma_s, double gamma, int32_t reps,
+                          int32_t* chosen, double* best_ms, void* stream) {
+    if (!h) return CKKT_ERR_ARG;
+    if (!h->ws) return CKKT_ERR_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint64_t sig = plan_signature(h);
+    for (auto& e : tune_cache())
+        if (e.first == sig) {
+            apply_tune(h, e.second);
+            if (chosen) { chosen[0] = e.second.compact64; chosen[1] = e.second.compact_threads;
+                          chosen[2] = e.second.tiny_threads; chosen[3] = e.second.sweep_cutoff; }
+            if (best_ms) *best_ms = -1.0;
+            return CKKT_OK;
+        }
+    if (reps < 1) reps = 3;
+    std::vector<Tune> cands;
+    for (int compact : {32, 48, 64})
+        for (int cth : {128, 256})
+            for (int tth : {64, 128})
+                for (int cut : {32, 64, 128}) {
+                    Tune t;
+                    t.compact64 = compact;
+                    t.compact32 = compact == 64 ? kCompactFront32 : compact;
+                    t.compact_threads = cth;
+                    t.tiny_threads = tth;
+                    t.sweep_cutoff = cut;
+                    cands.push_back(t);
+                }
+    double* b = h->vn[6];
+    double* x = h->vn[7];
+    launch_fill(h->plan.n, 1.0, b, st);
+    hipEvent_t e0 = take_event(h), e1 = take_event(h);
+    if (!e0 || !e1) return CKKT_ERR_HIP;
+    double best = INFINITY;
+    Tune bt = h->tune;
+    for (const Tune& t : cands) {
+        apply_tune(h, t);
+        // warm (captures the graphs of this shape), then time
+        ckkt_status rc = ckkt_factorize(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, stream);
+        if (rc) return rc;
+        apply_inverse(h, b, x, h->fp64_factored, st);
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) {
+            rc = ckkt_factorize(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, stream);
+            if (rc) return rc;
+            apply_inverse(h, b, x, h->fp64_factored, st);
+        }
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / reps < best) { best = ms / reps; bt = t; }
+    }
+    h->event_pool.push_back(e0);
+    h->event_pool.push_back(e1);
+    apply_tune(h, bt);
+    tune_cache().push_back({sig, bt});
+    if (chosen) { chosen[0] = bt.compact64; chosen[1] = bt.compact_threads; chosen[2] = bt.tiny_threads;
+                  chosen[3] = bt.sweep_cutoff; }
+    if (best_ms) *best_ms = best;
+    // the timing runs left a valid factor of the given values
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
 }
 
 ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info) {

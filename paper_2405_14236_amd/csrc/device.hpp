@@ -36,6 +36,8 @@ struct LevelInfo {
     int32_t small_maxf_a, small_maxf_a32;  // largest front of that compact class
     int32_t big_begin, big_count, big_maxw, big_maxf;
     int32_t all_begin, all_count, all_maxf, all_maxw;
+    int32_t small_threads_a;   // workgroup size of the compact small-front class
+    int32_t sweep_threads;     // workgroup size of the sweep kernels on this level
     int32_t tile_begin, tile_count;
 };
 

@@ -839,7 +839,7 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         const int fa = d ? L.small_maxf_a : L.small_maxf_a32;
         const int nbig = L.small_count - na;
         if (na > 0)
-            hipLaunchKernelGGL((k_factor_small<T, false>), dim3(na), dim3(fa <= 32 ? 64 : 256),
+            hipLaunchKernelGGL((k_factor_small<T, false>), dim3(na), dim3(L.small_threads_a),
                                (size_t)fa * fa * sizeof(T), st, P, K, arena, L.small_begin, status, scale);
         if (nbig > 0) {
             size_t lds = (size_t)L.small_maxf * L.small_maxf * sizeof(T);
@@ -867,7 +867,7 @@ template <typename T>
 void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* v_perm,
                       double* uvec, hipStream_t st) {
     if (L.all_count == 0) return;
-    int threads = L.all_maxf > 64 ? 256 : 64;
+    const int threads = L.sweep_threads;
     const int ldd = std::min(kWave, std::max(L.all_maxw, 1));
     size_t lds = (size_t)(((L.all_maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
     hipLaunchKernelGGL(k_fwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, v_perm,
@@ -878,7 +878,7 @@ template <typename T>
 void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* x_perm,
                       hipStream_t st) {
     if (L.all_count == 0) return;
-    int threads = L.all_maxf > 64 ? 256 : 64;
+    const int threads = L.sweep_threads;
     const int ldd = std::min(kWave, std::max(L.all_maxw, 1));
     size_t lds = (size_t)(((L.all_maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
     hipLaunchKernelGGL(k_bwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, x_perm);

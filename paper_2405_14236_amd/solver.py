@@ -165,6 +165,18 @@ class Solver:
         L.check(self.lib.ckkt_get_timing(self.h, ms, calls))
         return list(ms), list(calls)
 
+    def autotune(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma=0.0, reps=3):
+        """Times candidate launch shapes on this pattern and keeps the fastest."""
+        if self.workspace is None:
+            self.bind()
+        chosen = (ctypes.c_int32 * 4)()
+        best = ctypes.c_double()
+        L.check(self.lib.ckkt_autotune(self.h, _ptr(w_val), _ptr(g_val), _ptr(h_val), _ptr(sigma_x), _ptr(sigma_s),
+                                       float(gamma), int(reps), chosen, ctypes.byref(best), _stream()),
+                "ckkt_autotune")
+        keys = ("compact_front", "compact_threads", "tiny_threads", "sweep_cutoff")
+        return dict(zip(keys, list(chosen))), best.value
+
     # ------------------------------------------------------- learned PCG
     def features(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma=0.0):
         import torch

@@ -129,3 +129,18 @@ def test_batched_equals_single_solves():
     for q, zi in zip(probs, parts):
         zs, _ = solve_once(q, "lifted", "fp64", 1e-10)
         assert np.abs(zi - zs).max() <= 1e-9 * np.abs(zs).max()
+
+
+def test_autotune_keeps_gate_and_caches():
+    probs = [workloads.network_flow(int(N), seed=90 + i) for i, N in enumerate([700, 1200, 900, 1500])]
+    print_case("autotune", count=len(probs))
+    vals, rhs = _batch_values(probs, "lifted")
+    s = Solver(None, "lifted", "fp32_ir", batch=probs, tol=1e-8).bind(DEV)
+    chosen, best = s.autotune(*vals, reps=1)
+    assert best > 0 and chosen["compact_front"] in (32, 48, 64)
+    z, info = s.solve(rhs)
+    parts = _split(probs, z.cpu().numpy(), "lifted")
+    assert max(omega_of(q, "lifted", zi) for q, zi in zip(probs, parts)) <= 1e-8
+    s2 = Solver(None, "lifted", "fp32_ir", batch=probs, tol=1e-8).bind(DEV)
+    chosen2, best2 = s2.autotune(*vals)
+    assert best2 == -1.0 and chosen2 == chosen
