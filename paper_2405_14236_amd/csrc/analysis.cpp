@@ -441,6 +441,7 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
         nlev = std::max(nlev, lev[s] + 1);
     }
     P.nlev = nlev;
+    P.sn_level = lev;
     auto group_by_level = [&](auto pred, std::vector<int32_t>& ptr, std::vector<int32_t>& list) {
         ptr.assign(nlev + 1, 0);
         for (int32_t s = 0; s < ns; ++s)

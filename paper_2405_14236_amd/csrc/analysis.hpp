@@ -72,6 +72,7 @@ struct Plan {
 
     // ---- level schedule (level 0 = leaves)
     int32_t nlev = 0;
+    std::vector<int32_t> sn_level;        // level of each supernode (0 = leaf, parent > child)
     std::vector<int32_t> lvl_ptr;         // nlev + 1, into lvl_small / lvl_big
     std::vector<int32_t> lvl_small;       // small-front supernodes grouped by level
     std::vector<int32_t> lvl_small_ptr;   // nlev + 1

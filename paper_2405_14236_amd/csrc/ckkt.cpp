@@ -71,10 +71,11 @@ struct ckkt_handle {
     struct PlanRegion { Region r; const void* host; };
     std::vector<PlanRegion> plan_regions;
     Region r_perm, r_iperm, r_kcolptr, r_kwsrc, r_kdiag, r_prodptr, r_prodr, r_proda, r_prodb, r_snstart, r_snrowptr,
-        r_snrows, r_childptr, r_childlist, r_relmap, r_kmap, r_loff, r_uoff, r_uld, r_lvlsmall, r_lvlbig, r_lvlall,
+        r_snrows, r_snparent, r_snlevel, r_childptr, r_childlist, r_relmap, r_kmap, r_loff, r_uoff, r_uld, r_lvlsmall, r_lvlbig, r_lvlall,
         r_tilesn, r_tilecol, r_wfptr, r_wfcol, r_wfvidx, r_jptr, r_jcol, r_jtptr, r_jtrow, r_jtvidx, r_jtgend,
         r_instvar, r_insteq, r_kcol, r_cbptr, r_cbsrc, r_cblen, r_cbuoff;
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
+    Region r_ctl, r_done;  // dependency-driven sweeps: control words, per-supernode flags
     std::vector<Region> r_vn, r_vm, r_veq;  // scratch vectors of length n, m, m_eq
     // learned preconditioner (opt.learned)
     Region r_feat, r_o, r_cache, r_go, r_mlpws, r_grad, r_sxold, r_dold, r_kdold, r_kdnew, r_dnew;
@@ -87,7 +88,11 @@ struct ckkt_handle {
     double *K = nullptr, *d = nullptr, *scale = nullptr, *uvec = nullptr, *vperm = nullptr;
     double* arena64 = nullptr;
     float* arena32 = nullptr;
-    int32_t* status = nullptr;
+    int32_t* status = nullptr;  // [0] failing column, [1] FP32 pivot floors, [2] sweep wait failure
+    unsigned* ctl = nullptr;
+    unsigned* done = nullptr;
+    SweepSched sched;
+    bool sched_ok = false;
     unsigned long long* bits = nullptr;  // [ninst omega][resmax][bmax]
     double *dotpart = nullptr, *sc = nullptr;
     std::vector<double*> vn, vm, veq;
@@ -236,6 +241,8 @@ void build_layout(ckkt_handle* h) {
     plan_region(h->r_snstart, P.sn_start);
     plan_region(h->r_snrowptr, P.sn_rowptr);
     plan_region(h->r_snrows, P.sn_rows);
+    plan_region(h->r_snparent, P.sn_parent);
+    plan_region(h->r_snlevel, P.sn_level);
     plan_region(h->r_childptr, P.child_ptr);
     plan_region(h->r_childlist, P.child_list);
     plan_region(h->r_relmap, P.relmap);
@@ -275,6 +282,8 @@ void build_layout(ckkt_handle* h) {
     h->r_uvec = L.add(std::max<size_t>(P.sn_rows.size(), 1) * sizeof(double));
     h->r_vperm = L.add(n * sizeof(double));
     h->r_status = L.add(4 * sizeof(int32_t));
+    h->r_ctl = L.add(kSweepCtlWords * sizeof(unsigned));
+    h->r_done = L.add(std::max<size_t>(P.ns, 1) * sizeof(unsigned));
     h->r_bits = L.add((P.ninst + 2) * sizeof(unsigned long long));
     h->r_dotpart = L.add(kDotBlocks * sizeof(double));
     h->r_sc = L.add(16 * sizeof(double));
@@ -316,7 +325,9 @@ void fill_devplan(ckkt_handle* h) {
     D.k_diag = at<int32_t>(h, h->r_kdiag); D.prod_ptr = at<int32_t>(h, h->r_prodptr);
     D.prod_r = at<int32_t>(h, h->r_prodr); D.prod_a = at<int32_t>(h, h->r_proda); D.prod_b = at<int32_t>(h, h->r_prodb);
     D.sn_start = at<int32_t>(h, h->r_snstart); D.sn_rowptr = at<int32_t>(h, h->r_snrowptr);
-    D.sn_rows = at<int32_t>(h, h->r_snrows); D.child_ptr = at<int32_t>(h, h->r_childptr);
+    D.sn_rows = at<int32_t>(h, h->r_snrows);
+    D.sn_parent = at<int32_t>(h, h->r_snparent); D.sn_level = at<int32_t>(h, h->r_snlevel);
+    D.child_ptr = at<int32_t>(h, h->r_childptr);
     D.child_list = at<int32_t>(h, h->r_childlist); D.relmap = at<int32_t>(h, h->r_relmap);
     D.kmap = at<int32_t>(h, h->r_kmap); D.l_off = at<int64_t>(h, h->r_loff); D.u_off = at<int64_t>(h, h->r_uoff);
     D.u_ld = at<int32_t>(h, h->r_uld); D.lvl_small = at<int32_t>(h, h->r_lvlsmall);
@@ -339,6 +350,8 @@ void fill_devplan(ckkt_handle* h) {
     h->uvec = at<double>(h, h->r_uvec);
     h->vperm = at<double>(h, h->r_vperm);
     h->status = at<int32_t>(h, h->r_status);
+    h->ctl = at<unsigned>(h, h->r_ctl);
+    h->done = at<unsigned>(h, h->r_done);
     h->bits = at<unsigned long long>(h, h->r_bits);
     h->dotpart = at<double>(h, h->r_dotpart);
     h->sc = at<double>(h, h->r_sc);
@@ -435,9 +448,41 @@ void factor_levels(ckkt_handle* h, const double* scale, hipStream_t st) {
 }
 
 
+// Split of the supernodes between the single-wave and the workgroup
+// workers of the dependency-driven sweeps, and their launch shapes.
+bool build_sweep_sched(ckkt_handle* h) {
+    const Plan& P = h->plan;
+    SweepSched S;
+    S.ns = P.ns;
+    int lw = 0;
+    while (lw < (int)h->levels.size() && h->levels[lw].all_maxf <= kSweepWaveFront) ++lw;
+    S.wave_lvl = lw;
+    S.wave_t1 = P.ns ? P.lvl_all_ptr[lw] : 0;
+    int maxf = 1, maxw = 1;
+    for (int l = lw; l < (int)h->levels.size(); ++l) {
+        maxf = std::max(maxf, h->levels[l].all_maxf);
+        maxw = std::max(maxw, h->levels[l].all_maxw);
+    }
+    S.ldd = std::min(64, maxw);
+    S.group_lds = (size_t)(((maxf + 1) & ~1) + S.ldd * S.ldd) * sizeof(double);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || !sweep_sched_grids(S, dev)) {
+        (void)hipGetLastError();
+        return false;
+    }
+    h->sched = S;
+    return true;
+}
+
 template <typename T>
 void sweep_levels(ckkt_handle* h, hipStream_t st) {
     const T* arena = arena_of<T>(h);
+    if (h->sched_ok) {
+        launch_sweep_prep(h->ctl, st);
+        launch_fwd_sched<T>(h->dp, h->sched, arena, h->vperm, h->uvec, h->ctl, h->done, h->status + 2, st);
+        launch_bwd_sched<T>(h->dp, h->sched, arena, h->vperm, h->ctl, h->done, h->status + 2, st);
+        return;
+    }
     for (size_t l = 0; l < h->levels.size(); ++l) launch_fwd_level<T>(h->dp, h->levels[l], arena, h->vperm, h->uvec, st);
     for (size_t l = h->levels.size(); l-- > 0;) launch_bwd_level<T>(h->dp, h->levels[l], arena, h->vperm, st);
 }
@@ -492,7 +537,7 @@ struct ResidualOut {
     double omega = 0.0;      // max over instances
     double resmax = 0.0;
     std::vector<double> per_inst;
-    int32_t status0 = INT_MAX, status1 = 0;
+    int32_t status0 = INT_MAX, status1 = 0, status2 = 0;
 };
 
 double bits_to_double(unsigned long long b) {
@@ -513,7 +558,7 @@ ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, cons
     }
     char* host = static_cast<char*>(h->host);
     HIP_TRY(hipMemcpyAsync(host, h->bits, (ni + 2) * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(host + (ni + 2) * sizeof(unsigned long long), h->status, 2 * sizeof(int32_t),
+    HIP_TRY(hipMemcpyAsync(host + (ni + 2) * sizeof(unsigned long long), h->status, 3 * sizeof(int32_t),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const unsigned long long* hb = reinterpret_cast<const unsigned long long*>(host);
@@ -527,7 +572,8 @@ ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, cons
     const int32_t* hs = reinterpret_cast<const int32_t*>(host + (ni + 2) * sizeof(unsigned long long));
     out.status0 = hs[0];
     out.status1 = hs[1];
-    return CKKT_OK;
+    out.status2 = hs[2];
+    return out.status2 ? CKKT_ERR_TIMEOUT : CKKT_OK;
 }
 
 ckkt_status read_rhs_max(ckkt_handle* h, const double* a, int na, const double* b, int nb_, double& out,
@@ -981,8 +1027,14 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
     for (auto& pr : h->plan_regions)
         if (pr.r.bytes > 0)
             HIP_TRY(hipMemcpyAsync(h->ws + pr.r.off, pr.host, pr.r.bytes, hipMemcpyHostToDevice, st));
+    // sweep flags start below every epoch the sweeps will use
+    HIP_TRY(hipMemsetAsync(h->ws + h->r_ctl.off, 0, h->r_ctl.bytes, st));
+    HIP_TRY(hipMemsetAsync(h->ws + h->r_done.off, 0, h->r_done.bytes, st));
+    HIP_TRY(hipMemsetAsync(h->ws + h->r_status.off, 0, h->r_status.bytes, st));
     HIP_TRY(hipStreamSynchronize(st));
     fill_devplan(h);
+    const char* ls = std::getenv("CKKT_LEVEL_SWEEPS");
+    h->sched_ok = !(ls && ls[0] == '1') && build_sweep_sched(h);
     h->factored = false;
     h->fp64_factored = false;
     return CKKT_OK;
@@ -1034,9 +1086,10 @@ ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream) {
     if (!h) return CKKT_ERR_ARG;
     if (!h->factored) return CKKT_ERR_STATE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    HIP_TRY(hipMemcpyAsync(h->host, h->status, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h->host, h->status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     int32_t s0 = static_cast<int32_t*>(h->host)[0];
+    if (static_cast<int32_t*>(h->host)[2] != 0) return CKKT_ERR_TIMEOUT;
     if (h->fp64_factored && s0 != INT_MAX) {
         h->failed_column = (s0 >= 0 && s0 < h->plan.n) ? h->plan.perm[s0] : s0;
         return CKKT_ERR_NOT_SPD;
@@ -1359,6 +1412,7 @@ const char* ckkt_status_string(ckkt_status s) {
         case CKKT_ERR_HIP: return "HIP runtime error";
         case CKKT_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
         case CKKT_ERR_NONFINITE: return "non-finite input";
+        case CKKT_ERR_TIMEOUT: return "dependency wait in a triangular sweep timed out";
         default: return "unknown status";
     }
 }

@@ -13,6 +13,7 @@ struct DevPlan {
     const int32_t *perm, *iperm;
     const int32_t *kcolptr, *k_wsrc, *k_diag, *prod_ptr, *prod_r, *prod_a, *prod_b;
     const int32_t *sn_start, *sn_rowptr, *sn_rows, *child_ptr, *child_list, *relmap, *kmap, *kcol;
+    const int32_t *sn_parent, *sn_level;
     const int32_t *cb_ptr, *cb_src, *cb_len;
     const int64_t* cb_uoff;
     const int64_t *l_off, *u_off;
@@ -69,6 +70,29 @@ void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
 template <typename T>
 void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* x_perm,
                       hipStream_t st);
+
+// Dependency-driven sweeps: the supernodes lvl_all[0, wave_t1) (whole
+// levels below wave_lvl, every front of order <= 64) are processed by
+// single-wave workers, the rest by workgroup workers; both take supernodes
+// from ticket counters in level order and wait on per-supernode flags.
+struct SweepSched {
+    int32_t wave_t1 = 0, wave_lvl = 0, ns = 0;
+    int32_t wave_grid = 1, group_grid = 1, ldd = 1;
+    size_t group_lds = 0;
+    unsigned long long ticks = 0;  // wait limit in wall-clock ticks
+};
+constexpr int kSweepWaveFront = 64;   // largest front of the single-wave class
+constexpr int kSweepWaitSeconds = 4;  // a dependency wait longer than this is reported as an error
+constexpr int kSweepCtlWords = 8;     // ticket counters and epoch
+void launch_sweep_prep(unsigned* ctl, hipStream_t st);  // reset the tickets, advance the epoch
+template <typename T>
+void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* v_perm, double* uvec,
+                      unsigned* ctl, unsigned* done, int32_t* err, hipStream_t st);
+template <typename T>
+void launch_bwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* x_perm, unsigned* ctl,
+                      unsigned* done, int32_t* err, hipStream_t st);
+// Grid sizes (resident workgroups) and the wait limit for the current device.
+bool sweep_sched_grids(SweepSched& S, int device);
 
 // out[k] = in[perm[k]] * (scale ? scale[k] : 1)      (to the factor numbering)
 void launch_gather_perm(const DevPlan& P, const double* in, double* out, const double* scale, hipStream_t st);

@@ -104,7 +104,7 @@ __global__ void k_assemble(DevPlan P, SysVals v, const double* __restrict__ d, d
 }
 
 __global__ void k_init_status(int32_t* status) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) { status[0] = INT_MAX; status[1] = 0; }
+    if (threadIdx.x == 0 && blockIdx.x == 0) { status[0] = INT_MAX; status[1] = 0; status[2] = 0; }
 }
 
 __global__ void k_diag_scale(DevPlan P, const double* __restrict__ K, double* __restrict__ scale) {
@@ -473,43 +473,64 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb) {
 
 // ---------------------------------------------------------------- sweeps
 
-// Forward sweep L y = b, one workgroup per supernode of a level: gather the
-// children's update vectors (fixed order), then per block of 64 columns one
-// wave solves the diagonal block with lane shuffles and the workgroup
-// applies the block to every row below it; rows beyond the supernode's own
-// columns end up holding this front's update vector.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_fwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* __restrict__ v_perm,
-      double* __restrict__ uvec) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* v = reinterpret_cast<double*>(smem_raw);
-    const int s = P.lvl_all[list_begin + blockIdx.x];
-    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
-    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid % kWave, wid = tid / kWave;
-    for (int i = tid; i < f; i += nt) {
-        double acc = (i < w) ? v_perm[c0 + i] : 0.0;
-        const int q1 = P.cb_ptr[ro + i + 1];
-        for (int q = P.cb_ptr[ro + i]; q < q1; ++q) acc += uvec[P.cb_src[q]];
-        v[i] = acc;
+// Wave-uniform broadcast of lane k's value (k must be the same in every lane).
+__device__ __forceinline__ double lane_bcast(double x, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), k);
+    return __hiloint2double(hi, lo);
+}
+
+// Completion flags of the dependency-driven sweeps.  A producer makes its
+// stores visible at device scope before raising its flag; a consumer that
+// saw the flag orders its later loads after it.
+__device__ __forceinline__ unsigned flag_load(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_store(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void release_device() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_device() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Bounded wait for *flag == want.  Gives up after `ticks` of the constant
+// wall clock, or as soon as another wait has given up, and then records
+// the failure in *err; the caller carries on, so every wave still exits.
+__device__ void wait_flag(const unsigned* flag, unsigned want, int32_t* err, unsigned long long ticks) {
+    if (flag_load(flag) == want) return;
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        if (flag_load(flag) == want) return;
+        if (wall_clock64() - t0 > ticks || flag_load(reinterpret_cast<unsigned*>(err)) != 0u) {
+            flag_store(reinterpret_cast<unsigned*>(err), 1u);
+            return;
+        }
     }
-    __syncthreads();
-    const T* L = arena + P.l_off[s];
-    double* D = v + ((f + 1) & ~1);  // nb x nb diagonal block, column-major, ld kWave
+}
+
+// Forward sweep of one supernode by a workgroup: v (LDS, f entries) holds
+// the gathered right-hand side on entry; per block of 64 columns one wave
+// solves the diagonal block (staged in LDS with reciprocal pivots) with
+// lane broadcasts and the workgroup applies the block to every row below
+// it.  Rows beyond the supernode's own columns end up holding this front's
+// update vector.
+template <typename T>
+__device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double* v, double* D) {
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid % kWave, wid = tid / kWave;
     for (int kb = 0; kb < w; kb += kWave) {
         const int nb = min(kWave, w - kb);
         for (int idx = tid; idx < nb * nb; idx += nt) {
             const int i = idx % nb, k = idx / nb;
-            D[i + k * ldd] = (i >= k) ? (double)L[(kb + i) + (int64_t)(kb + k) * f] : 0.0;
+            const double lik = (i >= k) ? (double)L[(kb + i) + (int64_t)(kb + k) * f] : 0.0;
+            D[i + k * ldd] = (i == k) ? 1.0 / lik : lik;
         }
         __syncthreads();
         if (wid == 0) {
             double vi = lane < nb ? v[kb + lane] : 0.0;
             for (int k = 0; k < nb; ++k) {
-                const double yk = __shfl(vi, k, kWave) / D[k + k * ldd];
+                const double yk = lane_bcast(vi, k) * D[k + k * ldd];
                 if (lane == k) vi = yk;
-                else if (lane > k) vi -= D[lane + k * ldd] * yk;
+                else if (lane > k && lane < nb) vi = fma(-D[lane + k * ldd], yk, vi);
             }
             if (lane < nb) v[kb + lane] = vi;
         }
@@ -522,32 +543,16 @@ k_fwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* _
         }
         __syncthreads();
     }
-    for (int i = tid; i < f; i += nt) {
-        if (i < w) v_perm[c0 + i] = v[i];
-        else uvec[ro + i] = v[i];
-    }
 }
 
-// Backward sweep L^T x = y, one workgroup per supernode (levels root to
-// leaves): gather the already solved rows below, then per block of 64
-// columns (last block first) form the dot products with everything solved
-// so far (one wave per column) and back-substitute the diagonal block in
-// one wave with lane shuffles.
+// Backward sweep of one supernode by a workgroup: z (LDS, f entries) holds
+// y on the own columns and the solved x on the rows below; per block of 64
+// columns (last block first) one wave per column forms the dot product with
+// everything solved so far and one wave back-substitutes the diagonal block.
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_bwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* __restrict__ x_perm) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* z = reinterpret_cast<double*>(smem_raw);
-    __shared__ double tb[kWave];
-    const int s = P.lvl_all[list_begin + blockIdx.x];
-    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
-    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+__device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double* z, double* D, double* tb) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nw = nt / kWave, lane = tid % kWave, wid = tid / kWave;
-    double* D = z + ((f + 1) & ~1);
-    for (int i = tid; i < f; i += nt) z[i] = x_perm[P.sn_rows[ro + i]];
-    __syncthreads();
-    const T* L = arena + P.l_off[s];
     const int nblk = (w + kWave - 1) / kWave;
     for (int b = nblk - 1; b >= 0; --b) {
         const int kb = b * kWave, nb = min(kWave, w - kb), r0 = kb + nb;
@@ -558,25 +563,276 @@ k_bwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* _
             part = wave_sum(part);
             if (lane == 0) tb[k] = part;
         }
-        __syncthreads();
-        // diagonal block, stored transposed: D[k + j * kWave] = L(kb+k, kb+j)
+        // diagonal block, stored transposed: D[k + j * ldd] = L(kb+k, kb+j), pivots inverted
         for (int idx = tid; idx < nb * nb; idx += nt) {
             const int k = idx % nb, j = idx / nb;
-            D[k + j * ldd] = (k >= j) ? (double)L[(kb + k) + (int64_t)(kb + j) * f] : 0.0;
+            const double lkj = (k >= j) ? (double)L[(kb + k) + (int64_t)(kb + j) * f] : 0.0;
+            D[k + j * ldd] = (k == j) ? 1.0 / lkj : lkj;
         }
         __syncthreads();
         if (wid == 0) {
             double ri = lane < nb ? z[kb + lane] - tb[lane] : 0.0;
             for (int k = nb - 1; k >= 0; --k) {
-                const double xk = __shfl(ri, k, kWave) / D[k + k * ldd];
+                const double xk = lane_bcast(ri, k) * D[k + k * ldd];
                 if (lane == k) ri = xk;
-                else if (lane < k) ri -= D[k + lane * ldd] * xk;
+                else if (lane < k) ri = fma(-D[k + lane * ldd], xk, ri);
             }
             if (lane < nb) z[kb + lane] = ri;
         }
         __syncthreads();
     }
+}
+
+// Level-synchronous forward sweep: one workgroup per supernode of a level.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* __restrict__ v_perm,
+      double* __restrict__ uvec) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* v = reinterpret_cast<double*>(smem_raw);
+    const int s = P.lvl_all[list_begin + blockIdx.x];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < f; i += nt) {
+        double acc = (i < w) ? v_perm[c0 + i] : 0.0;
+        const int q1 = P.cb_ptr[ro + i + 1];
+        for (int q = P.cb_ptr[ro + i]; q < q1; ++q) acc += uvec[P.cb_src[q]];
+        v[i] = acc;
+    }
+    __syncthreads();
+    fwd_front(arena + P.l_off[s], w, f, ldd, v, v + ((f + 1) & ~1));
+    for (int i = tid; i < f; i += nt) {
+        if (i < w) v_perm[c0 + i] = v[i];
+        else uvec[ro + i] = v[i];
+    }
+}
+
+// Level-synchronous backward sweep (levels root to leaves).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* __restrict__ x_perm) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* z = reinterpret_cast<double*>(smem_raw);
+    __shared__ double tb[kWave];
+    const int s = P.lvl_all[list_begin + blockIdx.x];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < f; i += nt) z[i] = x_perm[P.sn_rows[ro + i]];
+    __syncthreads();
+    bwd_front(arena + P.l_off[s], w, f, ldd, z, z + ((f + 1) & ~1), tb);
     for (int i = tid; i < w; i += nt) x_perm[c0 + i] = z[i];
+}
+
+// Control words of the dependency-driven sweeps (one array per handle):
+// four ticket counters and the sweep epoch.  A supernode's flag holds
+// 2*epoch after its forward step and 2*epoch+1 after its backward step.
+enum { kCtlFwdWave = 0, kCtlFwdGroup = 1, kCtlBwdGroup = 2, kCtlBwdWave = 3, kCtlEpoch = 4 };
+
+__global__ void k_sweep_prep(unsigned* ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl[kCtlFwdWave] = ctl[kCtlFwdGroup] = ctl[kCtlBwdGroup] = ctl[kCtlBwdWave] = 0u;
+        ctl[kCtlEpoch] = ctl[kCtlEpoch] + 1u;
+    }
+}
+
+// Dependency-driven forward sweep over the supernodes lvl_all[t0, t1)
+// (whole levels from the leaves up, every front of order <= 64) by
+// one-wave workgroups: each takes the next supernode in level order from a
+// ticket counter (read through LDS after a barrier, so that every lane of
+// the wave sees the same ticket), so every
+// child of its supernode is held by a wave that started earlier and the
+// oldest unfinished ticket can always proceed.  The wave loads its lane's
+// row of the panel, the reciprocal pivot and the gather positions before
+// it waits for the children; then lane i gathers row i of the front and
+// one pass over the columns solves the diagonal block and forms the update
+// vector (lane k broadcasts y_k, rows below subtract their multiple).
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_fwd_wave(DevPlan P, const T* __restrict__ arena, int t0, int t1, double* __restrict__ v_perm,
+           double* __restrict__ uvec, unsigned* ctl, unsigned* done, int32_t* err, unsigned long long ticks) {
+    __shared__ int s_ticket[2];
+    const int lane = threadIdx.x;
+    const unsigned want = 2u * ctl[kCtlEpoch];
+    if (lane == 0) s_ticket[0] = (int)atomicAdd(&ctl[kCtlFwdWave], 1u);
+    __syncthreads();
+    for (int it = 0;; ++it) {
+        const int t = s_ticket[it & 1] + t0;
+        if (t >= t1) break;
+        if (lane == 0) s_ticket[(it + 1) & 1] = (int)atomicAdd(&ctl[kCtlFwdWave], 1u);
+        const int s = P.lvl_all[t];
+        const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+        const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+        const T* L = arena + P.l_off[s];
+        const bool act = lane < f;
+        double lr[kWave];
+#pragma unroll
+        for (int k = 0; k < kWave; ++k) lr[k] = (k < w && act) ? (double)L[lane + (int64_t)k * f] : 0.0;
+        const double rd = lane < w ? 1.0 / (double)L[lane + (int64_t)lane * f] : 0.0;
+        int q0 = 0, q1 = 0;
+        if (act) { q0 = P.cb_ptr[ro + lane]; q1 = P.cb_ptr[ro + lane + 1]; }
+        const int src0 = q0 < q1 ? P.cb_src[q0] : -1;
+        const int src1 = q0 + 1 < q1 ? P.cb_src[q0 + 1] : -1;
+        double vi = lane < w ? v_perm[c0 + lane] : 0.0;
+        for (int c = P.child_ptr[s] + lane; c < P.child_ptr[s + 1]; c += kWave)
+            wait_flag(&done[P.child_list[c]], want, err, ticks);
+        __syncthreads();
+        acquire_device();
+        if (src0 >= 0) vi += uvec[src0];
+        if (src1 >= 0) vi += uvec[src1];
+        for (int q = q0 + 2; q < q1; ++q) vi += uvec[P.cb_src[q]];
+#pragma unroll
+        for (int k = 0; k < kWave; ++k) {
+            if (k < w) {
+                const double yk = lane_bcast(vi, k) * lane_bcast(rd, k);
+                if (lane == k) vi = yk;
+                else if (lane > k) vi = fma(-lr[k], yk, vi);
+            }
+        }
+        if (lane < w) v_perm[c0 + lane] = vi;
+        else if (act) uvec[ro + lane] = vi;
+        release_device();
+        __syncthreads();
+        if (lane == 0) flag_store(&done[s], want);
+    }
+}
+
+// Dependency-driven backward sweep over lvl_all[t0, t1) (fronts of order
+// <= 64), tickets handed out root side first.  Lane j holds column j of
+// the panel; after the parent's flag (when the parent is in the range) it
+// forms the product with the solved rows below and back-substitutes the
+// diagonal block with lane broadcasts.
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_bwd_wave(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_hi, double* __restrict__ x_perm,
+           unsigned* ctl, unsigned* done, int32_t* err, unsigned long long ticks) {
+    __shared__ int s_ticket[2];
+    const int lane = threadIdx.x;
+    const unsigned want = 2u * ctl[kCtlEpoch] + 1u;
+    if (lane == 0) s_ticket[0] = (int)atomicAdd(&ctl[kCtlBwdWave], 1u);
+    __syncthreads();
+    for (int it = 0;; ++it) {
+        const int t = t1 - 1 - s_ticket[it & 1];
+        if (t < t0) break;
+        if (lane == 0) s_ticket[(it + 1) & 1] = (int)atomicAdd(&ctl[kCtlBwdWave], 1u);
+        const int s = P.lvl_all[t];
+        const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+        const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+        const T* L = arena + P.l_off[s];
+        const bool act = lane < f, own = lane < w;
+        double lc[kWave];
+        const T* Lc = L + (int64_t)lane * f;
+#pragma unroll
+        for (int k = 0; k < kWave; ++k) lc[k] = (k < f && own) ? (double)Lc[k] : 0.0;
+        const double rd = own ? 1.0 / (double)Lc[lane] : 0.0;
+        const int row = act ? P.sn_rows[ro + lane] : 0;
+        const int par = P.sn_parent[s];
+        if (lane == 0 && par >= 0 && P.sn_level[par] < lvl_hi) wait_flag(&done[par], want, err, ticks);
+        __syncthreads();
+        acquire_device();
+        const double z = act ? x_perm[row] : 0.0;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kWave; ++k)
+            if (k >= w && k < f) acc = fma(lc[k], lane_bcast(z, k), acc);
+        double ri = own ? z - acc : 0.0;
+#pragma unroll
+        for (int k = kWave - 1; k >= 0; --k) {
+            if (k < w) {
+                const double xk = lane_bcast(ri, k) * lane_bcast(rd, k);
+                if (lane == k) ri = xk;
+                else if (lane < k) ri = fma(-lc[k], xk, ri);
+            }
+        }
+        if (own) x_perm[c0 + lane] = ri;
+        release_device();
+        __syncthreads();
+        if (lane == 0) flag_store(&done[s], want);
+    }
+}
+
+// Dependency-driven forward sweep by workgroups over lvl_all[t0, t1)
+// (levels from lvl_lo up); children below lvl_lo were finished by an
+// earlier launch.  The next ticket is fetched while the current supernode
+// is processed.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_lo, int ldd,
+            double* __restrict__ v_perm, double* __restrict__ uvec, unsigned* ctl, unsigned* done, int32_t* err,
+            unsigned long long ticks) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* v = reinterpret_cast<double*>(smem_raw);
+    __shared__ int s_ticket[2];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const unsigned want = 2u * ctl[kCtlEpoch];
+    if (tid == 0) s_ticket[0] = (int)atomicAdd(&ctl[kCtlFwdGroup], 1u);
+    __syncthreads();
+    for (int it = 0;; ++it) {
+        const int t = s_ticket[it & 1] + t0;
+        if (t >= t1) break;
+        if (tid == 0) s_ticket[(it + 1) & 1] = (int)atomicAdd(&ctl[kCtlFwdGroup], 1u);
+        const int s = P.lvl_all[t];
+        const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+        const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+        for (int c = P.child_ptr[s] + tid; c < P.child_ptr[s + 1]; c += nt) {
+            const int ch = P.child_list[c];
+            if (P.sn_level[ch] >= lvl_lo) wait_flag(&done[ch], want, err, ticks);
+        }
+        __syncthreads();
+        acquire_device();
+        for (int i = tid; i < f; i += nt) {
+            double acc = (i < w) ? v_perm[c0 + i] : 0.0;
+            const int q1 = P.cb_ptr[ro + i + 1];
+            for (int q = P.cb_ptr[ro + i]; q < q1; ++q) acc += uvec[P.cb_src[q]];
+            v[i] = acc;
+        }
+        __syncthreads();
+        fwd_front(arena + P.l_off[s], w, f, ldd, v, v + ((f + 1) & ~1));
+        for (int i = tid; i < f; i += nt) {
+            if (i < w) v_perm[c0 + i] = v[i];
+            else uvec[ro + i] = v[i];
+        }
+        release_device();
+        __syncthreads();
+        if (tid == 0) flag_store(&done[s], want);
+    }
+}
+
+// Dependency-driven backward sweep by workgroups over lvl_all[t0, t1),
+// root side first; the whole range is above every level a later launch
+// handles, so the parent is always inside it (or is a root).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int ldd, double* __restrict__ x_perm,
+            unsigned* ctl, unsigned* done, int32_t* err, unsigned long long ticks) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* z = reinterpret_cast<double*>(smem_raw);
+    __shared__ double tb[kWave];
+    __shared__ int s_ticket[2];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const unsigned want = 2u * ctl[kCtlEpoch] + 1u;
+    if (tid == 0) s_ticket[0] = (int)atomicAdd(&ctl[kCtlBwdGroup], 1u);
+    __syncthreads();
+    for (int it = 0;; ++it) {
+        const int t = t1 - 1 - s_ticket[it & 1];
+        if (t < t0) break;
+        if (tid == 0) s_ticket[(it + 1) & 1] = (int)atomicAdd(&ctl[kCtlBwdGroup], 1u);
+        const int s = P.lvl_all[t];
+        const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+        const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+        const int par = P.sn_parent[s];
+        if (tid == 0 && par >= 0) wait_flag(&done[par], want, err, ticks);
+        __syncthreads();
+        acquire_device();
+        for (int i = tid; i < f; i += nt) z[i] = x_perm[P.sn_rows[ro + i]];
+        __syncthreads();
+        bwd_front(arena + P.l_off[s], w, f, ldd, z, z + ((f + 1) & ~1), tb);
+        for (int i = tid; i < w; i += nt) x_perm[c0 + i] = z[i];
+        release_device();
+        __syncthreads();
+        if (tid == 0) flag_store(&done[s], want);
+    }
 }
 
 // ---------------------------------------------------------------- vectors
@@ -894,6 +1150,88 @@ template void launch_fwd_level<float>(const DevPlan&, const LevelInfo&, const fl
                                       hipStream_t);
 template void launch_bwd_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, hipStream_t);
 template void launch_bwd_level<float>(const DevPlan&, const LevelInfo&, const float*, double*, hipStream_t);
+
+namespace {
+template <typename T>
+void set_sweep_attrs() {
+    static bool done_once = false;
+    if (done_once) return;
+    const int cap = kLdsBytes - kSweepStaticLds;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd<T>), hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bwd<T>), hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_group<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bwd_group<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    done_once = true;
+}
+}  // namespace
+
+void launch_sweep_prep(unsigned* ctl, hipStream_t st) {
+    hipLaunchKernelGGL(k_sweep_prep, dim3(1), dim3(64), 0, st, ctl);
+}
+
+template <typename T>
+void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* v_perm, double* uvec,
+                      unsigned* ctl, unsigned* done, int32_t* err, hipStream_t st) {
+    set_sweep_attrs<T>();
+    if (S.wave_t1 > 0)
+        hipLaunchKernelGGL(k_fwd_wave<T>, dim3(S.wave_grid), dim3(kWave), 0, st, P, arena, 0, S.wave_t1, v_perm, uvec,
+                           ctl, done, err, S.ticks);
+    if (S.ns > S.wave_t1)
+        hipLaunchKernelGGL(k_fwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, S.wave_t1, S.ns,
+                           S.wave_lvl, S.ldd, v_perm, uvec, ctl, done, err, S.ticks);
+}
+
+template <typename T>
+void launch_bwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* x_perm, unsigned* ctl,
+                      unsigned* done, int32_t* err, hipStream_t st) {
+    set_sweep_attrs<T>();
+    if (S.ns > S.wave_t1)
+        hipLaunchKernelGGL(k_bwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, S.wave_t1, S.ns,
+                           S.ldd, x_perm, ctl, done, err, S.ticks);
+    if (S.wave_t1 > 0)
+        hipLaunchKernelGGL(k_bwd_wave<T>, dim3(S.wave_grid), dim3(kWave), 0, st, P, arena, 0, S.wave_t1, S.wave_lvl,
+                           x_perm, ctl, done, err, S.ticks);
+}
+
+bool sweep_sched_grids(SweepSched& S, int device) {
+    int cus = 0, khz = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        return false;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0) return false;
+    S.ticks = (unsigned long long)khz * 1000ull * kSweepWaitSeconds;
+    set_sweep_attrs<double>();
+    set_sweep_attrs<float>();
+    auto occ = [&](const void* fn, int threads, size_t lds) {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, threads, lds) != hipSuccess) return 0;
+        return b;
+    };
+    int ow = std::min({occ(reinterpret_cast<const void*>(&k_fwd_wave<double>), kWave, 0),
+                       occ(reinterpret_cast<const void*>(&k_bwd_wave<double>), kWave, 0),
+                       occ(reinterpret_cast<const void*>(&k_fwd_wave<float>), kWave, 0),
+                       occ(reinterpret_cast<const void*>(&k_bwd_wave<float>), kWave, 0)});
+    int og = std::min({occ(reinterpret_cast<const void*>(&k_fwd_group<double>), 256, S.group_lds),
+                       occ(reinterpret_cast<const void*>(&k_bwd_group<double>), 256, S.group_lds),
+                       occ(reinterpret_cast<const void*>(&k_fwd_group<float>), 256, S.group_lds),
+                       occ(reinterpret_cast<const void*>(&k_bwd_group<float>), 256, S.group_lds)});
+    (void)hipGetLastError();
+    ow = std::max(ow, 1);
+    og = std::max(og, 1);
+    S.wave_grid = std::max(1, std::min(ow * cus, S.wave_t1));
+    S.group_grid = std::max(1, std::min(og * cus, S.ns - S.wave_t1));
+    return true;
+}
+
+template void launch_fwd_sched<double>(const DevPlan&, const SweepSched&, const double*, double*, double*, unsigned*,
+                                       unsigned*, int32_t*, hipStream_t);
+template void launch_fwd_sched<float>(const DevPlan&, const SweepSched&, const float*, double*, double*, unsigned*,
+                                      unsigned*, int32_t*, hipStream_t);
+template void launch_bwd_sched<double>(const DevPlan&, const SweepSched&, const double*, double*, unsigned*,
+                                       unsigned*, int32_t*, hipStream_t);
+template void launch_bwd_sched<float>(const DevPlan&, const SweepSched&, const float*, double*, unsigned*, unsigned*,
+                                      int32_t*, hipStream_t);
 
 void launch_gather_perm(const DevPlan& P, const double* in, double* out, const double* scale, hipStream_t st) {
     if (P.n == 0) return;
