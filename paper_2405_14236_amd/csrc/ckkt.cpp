@@ -8,6 +8,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -117,6 +118,7 @@ struct ckkt_handle {
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
     bool use_graphs = true;
+    bool debug_launch = false;  // CKKT_DEBUG_LAUNCH=1: report the first failing launch per factor level
 
     // timing
     bool timing = false;
@@ -444,7 +446,15 @@ float* arena_of<float>(ckkt_handle* h) { return h->arena32; }
 template <typename T>
 void factor_levels(ckkt_handle* h, const double* scale, hipStream_t st) {
     T* arena = arena_of<T>(h);
-    for (const LevelInfo& L : h->levels) launch_factor_level<T>(h->dp, L, h->K, arena, h->status, scale, st);
+    for (size_t l = 0; l < h->levels.size(); ++l) {
+        launch_factor_level<T>(h->dp, h->levels[l], h->K, arena, h->status, scale, st);
+        if (h->debug_launch) {
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                std::fprintf(stderr, "ckkt: factor level %zu (%s): %s\n", l, sizeof(T) == 8 ? "fp64" : "fp32",
+                             hipGetErrorString(e));
+        }
+    }
 }
 
 
@@ -1008,6 +1018,7 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
     if (!h) return CKKT_ERR_ARG;
     if (!dev_ptr || bytes < h->lay.total || (reinterpret_cast<uintptr_t>(dev_ptr) & 255)) return CKKT_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
     if (!h->host) {
         h->host_bytes = (h->plan.ninst + 8) * sizeof(unsigned long long) + 64;
         if (hipHostMalloc(&h->host, h->host_bytes, hipHostMallocDefault) != hipSuccess) {
@@ -1022,6 +1033,8 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
     }
     const char* ng = std::getenv("CKKT_NO_GRAPH");
     h->use_graphs = !(ng && ng[0] == '1');
+    const char* dl = std::getenv("CKKT_DEBUG_LAUNCH");
+    h->debug_launch = dl && dl[0] == '1';
     h->ws = static_cast<char*>(dev_ptr);
     h->ws_bytes = bytes;
     for (auto& pr : h->plan_regions)
@@ -1033,8 +1046,12 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
     HIP_TRY(hipMemsetAsync(h->ws + h->r_status.off, 0, h->r_status.bytes, st));
     HIP_TRY(hipStreamSynchronize(st));
     fill_devplan(h);
-    const char* ls = std::getenv("CKKT_LEVEL_SWEEPS");
-    h->sched_ok = !(ls && ls[0] == '1') && build_sweep_sched(h);
+    // Level-by-level sweeps are the default: on this chip a device-scope
+    // release per supernode (an L2 write-back on every producer) costs more
+    // than the kernel boundaries it saves.  CKKT_DEP_SWEEPS=1 selects the
+    // dependency-driven schedule.
+    const char* ds = std::getenv("CKKT_DEP_SWEEPS");
+    h->sched_ok = (ds && ds[0] == '1') && build_sweep_sched(h);
     h->factored = false;
     h->fp64_factored = false;
     return CKKT_OK;
@@ -1051,6 +1068,7 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
     if (ns_len > 0 && !sigma_s) return CKKT_ERR_ARG;
     if (h->formulation == CKKT_HYKKT && P.m_eq > 0 && !(gamma > 0.0 && std::isfinite(gamma))) return CKKT_ERR_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
     h->vals = SysVals{w_val, g_val, h_val, sigma_x, sigma_s, gamma};
     h->failed_column = -1;
     h->fp64_factored = false;
@@ -1086,6 +1104,7 @@ ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream) {
     if (!h) return CKKT_ERR_ARG;
     if (!h->factored) return CKKT_ERR_STATE;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
     HIP_TRY(hipMemcpyAsync(h->host, h->status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     int32_t s0 = static_cast<int32_t*>(h->host)[0];
@@ -1105,6 +1124,7 @@ ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol, ckkt_solv
     if (!h->ws || !h->factored) return info->status = CKKT_ERR_STATE;
     if ((h->plan.n > 0 || h->plan.m_eq > 0) && (!rhs || !sol)) return info->status = CKKT_ERR_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
     ckkt_status rc = h->formulation == CKKT_HYKKT ? solve_hykkt(h, rhs, sol, info, st)
                                                    : solve_lifted(h, rhs, sol, info, st);
     if (rc == CKKT_OK && hipGetLastError() != hipSuccess) rc = CKKT_ERR_HIP;
@@ -1116,6 +1136,7 @@ ckkt_status ckkt_apply_inverse(ckkt_handle* h, const double* rhs, double* sol, v
     if (!h) return CKKT_ERR_ARG;
     if (!h->ws || !h->factored) return CKKT_ERR_STATE;
     if (h->plan.n > 0 && (!rhs || !sol)) return CKKT_ERR_ARG;
+    (void)hipGetLastError();  // report only errors of this call's own launches
     apply_inverse(h, rhs, sol, h->fp64_factored, static_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
 }
@@ -1134,6 +1155,7 @@ ckkt_status ckkt_export_k(ckkt_handle* h, int32_t* rows, int32_t* cols, double* 
     if (values) {
         if (!h->ws || !h->factored) return CKKT_ERR_STATE;
         hipStream_t st = static_cast<hipStream_t>(stream);
+        (void)hipGetLastError();  // report only errors of this call's own launches
         HIP_TRY(hipMemcpyAsync(values, h->K, P.kcolptr.back() * sizeof(double), hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
@@ -1183,6 +1205,7 @@ ckkt_status ckkt_features(ckkt_handle* h, const double* w_val, const double* g_v
     if (rc) return rc;
     if (!features && h->plan.n > 0) return CKKT_ERR_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
     rc = set_new_values(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, st);
     if (rc) return rc;
     compute_features(h, features, st);
@@ -1223,6 +1246,7 @@ ckkt_status ckkt_mlp_train_step(ckkt_handle* h, const double* w_val, const doubl
     if (n > 0 && (!rhs || !target)) return CKKT_ERR_ARG;
     if (!params || !m || !v || step < 1) return CKKT_ERR_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
     rc = set_new_values(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, st);
     if (rc) return rc;
     const bool use64 = h->fp64_factored;
@@ -1261,6 +1285,7 @@ ckkt_status ckkt_pcg_solve(ckkt_handle* h, const double* w_val, const double* g_
     const int n = h->plan.n;
     if (n > 0 && (!rhs || !sol)) return info->status = CKKT_ERR_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
     rc = set_new_values(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, st);
     if (rc) return info->status = rc;
     const float* o = nullptr;
@@ -1319,6 +1344,7 @@ ckkt_status ckkt_autotune(ckkt_handle* h, const double* w_val, const double* g_v
     if (!h) return CKKT_ERR_ARG;
     if (!h->ws) return CKKT_ERR_STATE;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
     const uint64_t sig = plan_signature(h);
     for (auto& e : tune_cache())
         if (e.first == sig) {

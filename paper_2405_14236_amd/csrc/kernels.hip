@@ -18,6 +18,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -42,6 +43,20 @@ __device__ __forceinline__ double wave_max(double x) {
 }
 
 __device__ __forceinline__ double nan_to_inf(double x) { return (x == x) ? x : INFINITY; }
+// Value of lane k (k the same in every lane: a register read, no LDS trip).
+template <typename T>
+__device__ __forceinline__ T bcast(T x, int k);
+template <>
+__device__ __forceinline__ double bcast<double>(double x, int k) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), k);
+    return __hiloint2double(hi, lo);
+}
+template <>
+__device__ __forceinline__ float bcast<float>(float x, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
+}
+
 
 // Per-block maxima of (ratio, |res|) pushed with one atomic each when the
 // whole block belongs to one instance, else one atomic per element.  The
@@ -157,12 +172,12 @@ __device__ void wave_potrf(T* A, int ld, int nb, int col0, int32_t* status) {
     const bool own = lane < nb;
     for (int k = 0; k < nb; ++k) {
         const T a = (own && lane >= k) ? A[lane + k * ld] : T(0);
-        const T akk = __shfl(a, k, kWave);
+        const T akk = bcast(a, k);
         const T lkk = pivot_root<T>(akk, col0 + k, status, lane == k);
         const T lik = (lane == k) ? lkk : a / lkk;
         if (own && lane >= k) A[lane + k * ld] = lik;
         for (int j = k + 1; j < nb; ++j) {
-            const T ljk = __shfl(lik, j, kWave);
+            const T ljk = bcast(lik, j);
             if (own && lane >= j) A[lane + j * ld] -= lik * ljk;
         }
     }
@@ -195,14 +210,14 @@ __device__ __forceinline__ void wave_potrf_reg(T* A, int ld, int nb, int col0, i
 #pragma unroll
     for (int k = 0; k < kDiag; ++k) {
         if (k < nb) {
-            const T akk = __shfl(row[k], k, kWave);
+            const T akk = bcast(row[k], k);
             const T lkk = pivot_root<T>(akk, col0 + k, status, lane == k);
             const T lik = (lane == k) ? lkk : row[k] / lkk;
             if (lane >= k) row[k] = lik;
 #pragma unroll
             for (int j = k + 1; j < kDiag; ++j) {
                 if (j < nb) {
-                    const T ljk = __shfl(lik, j, kWave);
+                    const T ljk = bcast(lik, j);
                     if (lane >= j) row[j] -= lik * ljk;
                 }
             }
@@ -237,6 +252,44 @@ __device__ __forceinline__ void rows_trsm_reg(T* B, int ld, const T* D, int ldd,
     }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Lower-triangular rank-k update on the matrix cores (FP64):
+//   out(i, j, (P P^T)_ij)  for i in [i0, i1), j in [j0, j1), i >= j,
+// where P holds columns [t0, t1) of the LDS front F (leading dimension f).
+// One 16 x 16 output tile per wave at a time, K in steps of 4 with
+// v_mfma_f64_16x16x4f64: lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16) and receives D(4 r + l / 16, l % 16) in register r.
+// Tiles entirely above the diagonal are skipped (wave-uniform), so every
+// matrix instruction runs with all lanes active.
+template <typename Out>
+__device__ __forceinline__ void syrk_mfma(const double* F, int f, int i0, int i1, int j0, int j1, int t0, int t1,
+                                          Out out) {
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int li = lane % 16, lk = lane / 16;
+    const int ni = (i1 - i0 + 15) / 16, nj = (j1 - j0 + 15) / 16;
+    for (int q = wid; q < ni * nj; q += nw) {
+        const int ib = i0 + 16 * (q % ni), jb = j0 + 16 * (q / ni);
+        if (ib + 15 < jb) continue;
+        const int ia = ib + li, ja = jb + li;
+        const bool ai = ia < i1, bj = ja < j1;
+        dbl4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int t = t0; t < t1; t += 4) {
+            const int tk = t + lk;
+            const bool kin = tk < t1;
+            const double a = (ai && kin) ? F[ia + tk * f] : 0.0;
+            const double b = (bj && kin) ? F[ja + tk * f] : 0.0;
+            c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = ib + 4 * r + lk, j = jb + li;
+            if (i < i1 && j < j1 && i >= j) out(i, j, c[r]);
+        }
+    }
+}
+
 // Fronts that fit in LDS (f^2 elements <= 160 KiB): one workgroup per front.
 // Assemble (K columns + extend-add of the children's update matrices in
 // child order), blocked partial Cholesky of the first w columns (32-column
@@ -255,19 +308,39 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < f * f; i += nt) F[i] = T(0);
     __syncthreads();
-    // K entries of the w columns: one contiguous slot range
-    for (int t = P.kcolptr[c0] + tid; t < P.kcolptr[c1]; t += nt) {
-        const int pr = P.kmap[t], j = P.kcol[t];
-        double val = K[t];
-        if (scale) val *= scale[j] * scale[P.sn_rows[ro + pr]];
-        F[pr + (j - c0) * f] = (T)val;
+    // K entries of the w columns: one contiguous slot range (four entries
+    // per thread in flight)
+    {
+        const int t0 = P.kcolptr[c0], t1 = P.kcolptr[c1];
+        for (int base = t0; base < t1; base += 4 * nt) {
+            int pr[4], j[4];
+            double val[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = base + u * nt + tid;
+                const bool in = t < t1;
+                pr[u] = in ? P.kmap[t] : 0;
+                j[u] = in ? P.kcol[t] : c0;
+                val[u] = in ? K[t] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (base + u * nt + tid < t1) {
+                    double x = val[u];
+                    if (scale) x *= scale[j[u]] * scale[P.sn_rows[ro + pr[u]]];
+                    F[pr[u] + (j[u] - c0) * f] = (T)x;
+                }
+            }
+        }
     }
     __syncthreads();
     // extend-add, one child after the other (fixed order), each child's
-    // lower update entries in one parallel pass; child metadata prefetched
+    // lower update entries in one parallel pass with eight loads per thread
+    // in flight; child metadata prefetched, the child's row map staged in LDS
     {
         __shared__ int64_t c_uoff[kMaxChildBatch];
         __shared__ int c_rel[kMaxChildBatch], c_rc[kMaxChildBatch], c_ld[kMaxChildBatch];
+        __shared__ int s_rel[kLdsFront64];
         const int q0 = P.child_ptr[s], nch = P.child_ptr[s + 1] - q0;
         for (int base = 0; base < nch; base += kMaxChildBatch) {
             const int nb_ch = min(kMaxChildBatch, nch - base);
@@ -285,9 +358,23 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
                 const int rc = c_rc[q], ld = c_ld[q];
                 const int* rel = P.relmap + c_rel[q];
                 const T* U = arena + c_uoff[q];
-                for (int idx = tid; idx < rc * rc; idx += nt) {
-                    const int a = idx % rc, b = idx / rc;
-                    if (a >= b) F[rel[a] + rel[b] * f] += U[a + (int64_t)b * ld];
+                for (int a = tid; a < rc; a += nt) s_rel[a] = rel[a];
+                __syncthreads();
+                const int tot = rc * rc;
+                for (int base = 0; base < tot; base += 8 * nt) {
+                    T u8[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int idx = base + u * nt + tid;
+                        const int a = idx % rc, b = idx / rc;
+                        u8[u] = (idx < tot && a >= b) ? U[a + (int64_t)b * ld] : T(0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int idx = base + u * nt + tid;
+                        const int a = idx % rc, b = idx / rc;
+                        if (idx < tot && a >= b) F[s_rel[a] + s_rel[b] * f] += u8[u];
+                    }
                 }
                 __syncthreads();
             }
@@ -306,12 +393,18 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
         __syncthreads();
         // remaining panel columns [kb+nb, w), rows >= column
         const int j0 = kb + nb, mr = f - j0, mc = w - j0;
-        for (int idx = tid; idx < mr * mc; idx += nt) {
-            const int i = j0 + idx % mr, j = j0 + idx / mr;
-            if (i >= j) {
-                T acc = F[i + j * f];
-                for (int t = 0; t < nb; ++t) acc -= F[i + (kb + t) * f] * F[j + (kb + t) * f];
-                F[i + j * f] = acc;
+        if constexpr (std::is_same<T, double>::value) {
+            if (mc > 0)
+                syrk_mfma(F, f, j0, f, j0, w, kb, kb + nb,
+                          [&](int i, int j, double v) { F[i + j * f] -= v; });
+        } else {
+            for (int idx = tid; idx < mr * mc; idx += nt) {
+                const int i = j0 + idx % mr, j = j0 + idx / mr;
+                if (i >= j) {
+                    T acc = F[i + j * f];
+                    for (int t = 0; t < nb; ++t) acc -= F[i + (kb + t) * f] * F[j + (kb + t) * f];
+                    F[i + j * f] = acc;
+                }
             }
         }
         __syncthreads();
@@ -319,12 +412,19 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
     T* L = arena + P.l_off[s];
     for (int idx = tid; idx < f * w; idx += nt) L[idx] = F[idx];
     T* U = arena + P.u_off[s];
-    for (int idx = tid; idx < r * r; idx += nt) {
-        const int a = idx % r, b = idx / r;
-        if (a >= b) {
-            T acc = F[(w + a) + (w + b) * f];
-            for (int k = 0; k < w; ++k) acc -= F[(w + a) + k * f] * F[(w + b) + k * f];
-            U[idx] = acc;
+    if constexpr (std::is_same<T, double>::value) {
+        if (r > 0)
+            syrk_mfma(F, f, w, f, w, f, 0, w, [&](int i, int j, double v) {
+                U[(i - w) + (int64_t)(j - w) * r] = F[i + j * f] - v;
+            });
+    } else {
+        for (int idx = tid; idx < r * r; idx += nt) {
+            const int a = idx % r, b = idx / r;
+            if (a >= b) {
+                T acc = F[(w + a) + (w + b) * f];
+                for (int k = 0; k < w; ++k) acc -= F[(w + a) + k * f] * F[(w + b) + k * f];
+                U[idx] = acc;
+            }
         }
     }
 }
@@ -387,9 +487,19 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
     const int nb = min(kPanelNB, w - kb);
     T* F = arena + P.l_off[s];
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int idx = tid; idx < nb * nb; idx += nt) {
-        const int i = idx % nb, j = idx / nb;
-        D[i + j * kPanelNB] = (i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
+    for (int base = 0; base < nb * nb; base += 4 * nt) {
+        T t4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = base + u * nt + tid;
+            const int i = idx % nb, j = idx / nb;
+            t4[u] = (idx < nb * nb && i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = base + u * nt + tid;
+            if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelNB] = t4[u];
+        }
     }
     __syncthreads();
     if (tid < kWave) wave_potrf_reg<T>(D, kPanelNB, nb, c0 + kb, status);
@@ -401,9 +511,18 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
 #pragma unroll 1
     for (int r0 = kb + nb; r0 < f; r0 += 256) {
         const int nr = min(256, f - r0);
-        for (int idx = tid; idx < nr * nb; idx += nt) {
-            const int i = idx % nr, j = idx / nr;
-            R[i + j * 256] = F[(r0 + i) + (int64_t)(kb + j) * f];
+        for (int base = 0; base < nr * nb; base += 8 * nt) {
+            T t8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * nt + tid;
+                t8[u] = idx < nr * nb ? F[(r0 + idx % nr) + (int64_t)(kb + idx / nr) * f] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * nt + tid;
+                if (idx < nr * nb) R[idx % nr + (idx / nr) * 256] = t8[u];
+            }
         }
         __syncthreads();
         rows_trsm_reg<T>(R, 256, D, kPanelNB, nb, 0, nr);
@@ -436,11 +555,23 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb) {
     if (i0 >= f) return;
     T* F = arena + P.l_off[s];
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < 64 * kPanelNB; idx += 256) {
-        const int ii = idx % 64, t = idx / 64;
-        const int gi = i0 + ii, gj = j0 + ii;
-        A[ii][t] = (gi < f && t < nb) ? F[gi + (int64_t)(kb + t) * f] : T(0);
-        B[ii][t] = (gj < f && t < nb) ? F[gj + (int64_t)(kb + t) * f] : T(0);
+    {
+        constexpr int kPer = 64 * kPanelNB / 256;
+        T ta[kPer], tb[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int idx = u * 256 + tid;
+            const int ii = idx % 64, t = idx / 64;
+            const int gi = i0 + ii, gj = j0 + ii;
+            ta[u] = (gi < f && t < nb) ? F[gi + (int64_t)(kb + t) * f] : T(0);
+            tb[u] = (gj < f && t < nb) ? F[gj + (int64_t)(kb + t) * f] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int idx = u * 256 + tid;
+            A[idx % 64][idx / 64] = ta[u];
+            B[idx % 64][idx / 64] = tb[u];
+        }
     }
     __syncthreads();
     const int tx = tid % 16, ty = tid / 16;
@@ -508,25 +639,47 @@ __device__ void wait_flag(const unsigned* flag, unsigned want, int32_t* err, uns
     }
 }
 
+// Stage the nb x nb lower triangle of the diagonal block at src (leading
+// dimension f) into D[r + c * ldd] with reciprocal pivots; eight loads per
+// thread are issued before their LDS stores so that their latencies overlap.
+template <typename T>
+__device__ __forceinline__ void stage_diag_block(const T* __restrict__ src, int f, int nb, double* D, int ldd) {
+    const int tid = threadIdx.x, nt = blockDim.x, tot = nb * nb;
+    for (int base = 0; base < tot; base += 8 * nt) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * nt + tid;
+            const int i = idx % nb, k = idx / nb;
+            t[u] = (idx < tot && i >= k) ? (double)src[i + (int64_t)k * f] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * nt + tid;
+            if (idx < tot) {
+                const int i = idx % nb, k = idx / nb;
+                D[i + k * ldd] = (i == k) ? 1.0 / t[u] : t[u];
+            }
+        }
+    }
+}
+
 // Forward sweep of one supernode by a workgroup: v (LDS, f entries) holds
 // the gathered right-hand side on entry; per block of 64 columns one wave
 // solves the diagonal block (staged in LDS with reciprocal pivots) with
 // lane broadcasts and the workgroup applies the block to every row below
-// it.  Rows beyond the supernode's own columns end up holding this front's
-// update vector.
+// it (one thread per row, loads in batches of 16).  Rows beyond the
+// supernode's own columns end up holding this front's update vector.
 template <typename T>
 __device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double* v, double* D) {
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid % kWave, wid = tid / kWave;
     for (int kb = 0; kb < w; kb += kWave) {
         const int nb = min(kWave, w - kb);
-        for (int idx = tid; idx < nb * nb; idx += nt) {
-            const int i = idx % nb, k = idx / nb;
-            const double lik = (i >= k) ? (double)L[(kb + i) + (int64_t)(kb + k) * f] : 0.0;
-            D[i + k * ldd] = (i == k) ? 1.0 / lik : lik;
-        }
+        stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
         __syncthreads();
         if (wid == 0) {
             double vi = lane < nb ? v[kb + lane] : 0.0;
+#pragma unroll 4
             for (int k = 0; k < nb; ++k) {
                 const double yk = lane_bcast(vi, k) * D[k + k * ldd];
                 if (lane == k) vi = yk;
@@ -536,9 +689,17 @@ __device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double
         }
         __syncthreads();
         for (int i = kb + nb + tid; i < f; i += nt) {
-            double acc = 0.0;
             const T* Li = L + i + (int64_t)kb * f;
-            for (int k = 0; k < nb; ++k) acc += (double)Li[(int64_t)k * f] * v[kb + k];
+            double acc = 0.0;
+            int k = 0;
+            for (; k + 16 <= nb; k += 16) {
+                double l[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) l[u] = (double)Li[(int64_t)(k + u) * f];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc = fma(l[u], v[kb + k + u], acc);
+            }
+            for (; k < nb; ++k) acc = fma((double)Li[(int64_t)k * f], v[kb + k], acc);
             v[i] -= acc;
         }
         __syncthreads();
@@ -547,8 +708,9 @@ __device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double
 
 // Backward sweep of one supernode by a workgroup: z (LDS, f entries) holds
 // y on the own columns and the solved x on the rows below; per block of 64
-// columns (last block first) one wave per column forms the dot product with
-// everything solved so far and one wave back-substitutes the diagonal block.
+// columns (last block first) each wave forms the dot products of eight
+// columns at a time with everything solved so far, then one wave
+// back-substitutes the diagonal block.
 template <typename T>
 __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double* z, double* D, double* tb) {
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -556,22 +718,29 @@ __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double
     const int nblk = (w + kWave - 1) / kWave;
     for (int b = nblk - 1; b >= 0; --b) {
         const int kb = b * kWave, nb = min(kWave, w - kb), r0 = kb + nb;
-        for (int k = wid; k < nb; k += nw) {
-            const T* col = L + (int64_t)(kb + k) * f;
-            double part = 0.0;
-            for (int i = r0 + lane; i < f; i += kWave) part += (double)col[i] * z[i];
-            part = wave_sum(part);
-            if (lane == 0) tb[k] = part;
+        for (int k0 = wid * 8; k0 < nb; k0 += nw * 8) {
+            double part[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) part[c] = 0.0;
+            for (int i = r0 + lane; i < f; i += kWave) {
+                const double zi = z[i];
+                double l[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) l[c] = (k0 + c < nb) ? (double)L[i + (int64_t)(kb + k0 + c) * f] : 0.0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) part[c] = fma(l[c], zi, part[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const double sc = wave_sum(part[c]);
+                if (lane == 0 && k0 + c < nb) tb[k0 + c] = sc;
+            }
         }
-        // diagonal block, stored transposed: D[k + j * ldd] = L(kb+k, kb+j), pivots inverted
-        for (int idx = tid; idx < nb * nb; idx += nt) {
-            const int k = idx % nb, j = idx / nb;
-            const double lkj = (k >= j) ? (double)L[(kb + k) + (int64_t)(kb + j) * f] : 0.0;
-            D[k + j * ldd] = (k == j) ? 1.0 / lkj : lkj;
-        }
+        stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
         __syncthreads();
         if (wid == 0) {
             double ri = lane < nb ? z[kb + lane] - tb[lane] : 0.0;
+#pragma unroll 4
             for (int k = nb - 1; k >= 0; --k) {
                 const double xk = lane_bcast(ri, k) * D[k + k * ldd];
                 if (lane == k) ri = xk;
@@ -623,6 +792,92 @@ k_bwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* _
     __syncthreads();
     bwd_front(arena + P.l_off[s], w, f, ldd, z, z + ((f + 1) & ~1), tb);
     for (int i = tid; i < w; i += nt) x_perm[c0 + i] = z[i];
+}
+
+// Forward step of one supernode with f <= 64 by one wave: lane i holds
+// row i of the panel in registers (loaded before the gather, so the two
+// overlap), gathers row i of the front, and one pass over the columns
+// solves the diagonal block and forms the update vector (lane k broadcasts
+// y_k, rows below subtract their multiple).
+template <typename T>
+__device__ __forceinline__ void fwd_wave_front(const DevPlan& P, const T* __restrict__ arena, int s,
+                                               double* __restrict__ v_perm, double* __restrict__ uvec) {
+    const int lane = threadIdx.x % kWave;
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const T* L = arena + P.l_off[s];
+    const bool act = lane < f;
+    double lr[kWave];
+#pragma unroll
+    for (int k = 0; k < kWave; ++k) lr[k] = (k < w && act) ? (double)L[lane + (int64_t)k * f] : 0.0;
+    const double rd = lane < w ? 1.0 / (double)L[lane + (int64_t)lane * f] : 0.0;
+    double vi = 0.0;
+    if (act) {
+        vi = lane < w ? v_perm[c0 + lane] : 0.0;
+        const int q1 = P.cb_ptr[ro + lane + 1];
+        for (int q = P.cb_ptr[ro + lane]; q < q1; ++q) vi += uvec[P.cb_src[q]];
+    }
+#pragma unroll
+    for (int k = 0; k < kWave; ++k) {
+        if (k < w) {
+            const double yk = lane_bcast(vi, k) * lane_bcast(rd, k);
+            if (lane == k) vi = yk;
+            else if (lane > k) vi = fma(-lr[k], yk, vi);
+        }
+    }
+    if (lane < w) v_perm[c0 + lane] = vi;
+    else if (act) uvec[ro + lane] = vi;
+}
+
+// Backward step of one supernode with f <= 64 by one wave: lane j holds
+// column j of the panel, forms the product with the solved rows below and
+// back-substitutes the diagonal block with lane broadcasts.
+template <typename T>
+__device__ __forceinline__ void bwd_wave_front(const DevPlan& P, const T* __restrict__ arena, int s,
+                                               double* __restrict__ x_perm) {
+    const int lane = threadIdx.x % kWave;
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const T* Lc = arena + P.l_off[s] + (int64_t)lane * f;
+    const bool act = lane < f, own = lane < w;
+    double lc[kWave];
+#pragma unroll
+    for (int k = 0; k < kWave; ++k) lc[k] = (k < f && own) ? (double)Lc[k] : 0.0;
+    const double rd = own ? 1.0 / (double)Lc[lane] : 0.0;
+    const double z = act ? x_perm[P.sn_rows[ro + lane]] : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kWave; ++k)
+        if (k >= w && k < f) acc = fma(lc[k], lane_bcast(z, k), acc);
+    double ri = own ? z - acc : 0.0;
+#pragma unroll
+    for (int k = kWave - 1; k >= 0; --k) {
+        if (k < w) {
+            const double xk = lane_bcast(ri, k) * lane_bcast(rd, k);
+            if (lane == k) ri = xk;
+            else if (lane < k) ri = fma(-lc[k], xk, ri);
+        }
+    }
+    if (own) x_perm[c0 + lane] = ri;
+}
+
+// Level-synchronous sweeps for levels whose fronts all have order <= 64:
+// four supernodes per 256-thread workgroup, one per wave.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fwd_waves(DevPlan P, const T* __restrict__ arena, int list_begin, int count, double* __restrict__ v_perm,
+            double* __restrict__ uvec) {
+    const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (t >= count) return;
+    fwd_wave_front(P, arena, P.lvl_all[list_begin + t], v_perm, uvec);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bwd_waves(DevPlan P, const T* __restrict__ arena, int list_begin, int count, double* __restrict__ x_perm) {
+    const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (t >= count) return;
+    bwd_wave_front(P, arena, P.lvl_all[list_begin + t], x_perm);
 }
 
 // Control words of the dependency-driven sweeps (one array per handle):
@@ -1082,9 +1337,9 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
     static bool attr_set = false;
     if (!attr_set) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_small<T, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kFactorStaticLds);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_small<T, false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kFactorStaticLds);
         attr_set = true;
     }
     if (L.small_count > 0) {
@@ -1123,6 +1378,11 @@ template <typename T>
 void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* v_perm,
                       double* uvec, hipStream_t st) {
     if (L.all_count == 0) return;
+    if (L.all_maxf <= kWave) {
+        hipLaunchKernelGGL(k_fwd_waves<T>, dim3((L.all_count + 3) / 4), dim3(256), 0, st, P, arena, L.all_begin,
+                           L.all_count, v_perm, uvec);
+        return;
+    }
     const int threads = L.sweep_threads;
     const int ldd = std::min(kWave, std::max(L.all_maxw, 1));
     size_t lds = (size_t)(((L.all_maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
@@ -1134,6 +1394,11 @@ template <typename T>
 void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* x_perm,
                       hipStream_t st) {
     if (L.all_count == 0) return;
+    if (L.all_maxf <= kWave) {
+        hipLaunchKernelGGL(k_bwd_waves<T>, dim3((L.all_count + 3) / 4), dim3(256), 0, st, P, arena, L.all_begin,
+                           L.all_count, x_perm);
+        return;
+    }
     const int threads = L.sweep_threads;
     const int ldd = std::min(kWave, std::max(L.all_maxw, 1));
     size_t lds = (size_t)(((L.all_maxf + 1) & ~1) + ldd * ldd) * sizeof(double);

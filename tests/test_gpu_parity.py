@@ -233,8 +233,8 @@ def test_dependency_driven_sweeps_match_level_sweeps(monkeypatch, precision):
     print_case("sweep_schedules", n=p.n, precision=precision)
     tol = 1e-10 if precision == "fp64" else 1e-8
     out = {}
-    for mode in ("1", "0"):
-        monkeypatch.setenv("CKKT_LEVEL_SWEEPS", mode)
+    for mode in ("0", "1"):
+        monkeypatch.setenv("CKKT_DEP_SWEEPS", mode)
         s = Solver(p, "lifted", precision, tol=tol).bind(DEV)
         s.factorize(*device_values(p, DEV, "lifted"))
         b = torch.as_tensor(p.b, device=DEV)
@@ -245,5 +245,5 @@ def test_dependency_driven_sweeps_match_level_sweeps(monkeypatch, precision):
         assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
         assert omega_of(p, "lifted", z.cpu().numpy()) <= tol
         out[mode] = x1.cpu().numpy()
-    a, c = out["1"], out["0"]
+    a, c = out["0"], out["1"]
     assert np.abs(a - c).max() <= 1e-8 * np.abs(a).max()
