@@ -44,10 +44,10 @@ struct LevelInfo {
 
 constexpr int kBigTile = 64;    // column tile of the tiled front path
 constexpr int kLdsBytes = 160 * 1024;   // LDS per workgroup on gfx950
-constexpr int kFactorStaticLds = 2048;  // upper bound of k_factor_small's static LDS
+constexpr int kFactorStaticLds = 2304;  // upper bound of k_factor_small's static LDS
 constexpr int kSweepStaticLds = 1024;   // upper bound of k_fwd / k_bwd static LDS
 // largest FP64 front held whole in LDS next to the kernel's static arrays:
-// 140^2 * 8 + 2048 <= 160 KiB
+// 140^2 * 8 + 2304 <= 160 KiB
 constexpr int kLdsFront64 = 140;
 // largest front the sweep kernels can stage (front vector + 64 x 64 block)
 constexpr int kSweepMaxFront = (kLdsBytes - kSweepStaticLds) / 8 - 64 * 64;

@@ -161,94 +161,54 @@ __device__ __forceinline__ float pivot_root<float>(float d, int col, int32_t* st
 constexpr int kDiag = 32;  // diagonal block of the blocked front factorization
 constexpr int kMaxChildBatch = 64;  // children whose metadata is staged at once
 
-// One wave factors the nb x nb (nb <= 64) diagonal block at A (LDS,
-// column-major, leading dimension ld) in place.  Lane i owns row i: it
-// reads and writes only its own row, and column k reaches the other lanes
-// through shuffles, so no barrier is needed inside.  The caller
-// synchronises before and after.
+// One wave factors the nb x nb diagonal block at A (LDS, column-major,
+// leading dimension ld) in place and leaves the reciprocal pivots in
+// rdiag[0, nb).  Left-looking: at step j lane i (i >= j) forms
+// A(i, j) - sum_{t<j} L(i, t) L(j, t) from its own finished row and row j
+// (an LDS broadcast), the pivot comes from lane j by a register broadcast,
+// and the column is scaled.  No read-modify-write chains through LDS, and
+// the loops stay rolled (small code).  Rows written by other lanes in
+// earlier steps are visible because one wave's LDS operations complete in
+// order.  The caller synchronises before and after.
 template <typename T>
-__device__ void wave_potrf(T* A, int ld, int nb, int col0, int32_t* status) {
+__device__ void wave_potrf(T* A, int ld, int nb, int col0, int32_t* status, T* rdiag) {
     const int lane = threadIdx.x % kWave;
-    const bool own = lane < nb;
-    for (int k = 0; k < nb; ++k) {
-        const T a = (own && lane >= k) ? A[lane + k * ld] : T(0);
-        const T akk = bcast(a, k);
-        const T lkk = pivot_root<T>(akk, col0 + k, status, lane == k);
-        const T lik = (lane == k) ? lkk : a / lkk;
-        if (own && lane >= k) A[lane + k * ld] = lik;
-        for (int j = k + 1; j < nb; ++j) {
-            const T ljk = bcast(lik, j);
-            if (own && lane >= j) A[lane + j * ld] -= lik * ljk;
+    for (int j = 0; j < nb; ++j) {
+        const bool act = lane < nb && lane >= j;
+        const int ri = act ? lane : j;  // inactive lanes read a valid row and discard it
+        T acc0 = T(0), acc1 = T(0);
+        int t = 0;
+        for (; t + 1 < j; t += 2) {
+            acc0 += A[ri + t * ld] * A[j + t * ld];
+            acc1 += A[ri + (t + 1) * ld] * A[j + (t + 1) * ld];
         }
+        if (t < j) acc0 += A[ri + t * ld] * A[j + t * ld];
+        const T d = A[ri + j * ld] - (acc0 + acc1);
+        const T djj = bcast(d, j);
+        const T ljj = pivot_root<T>(djj, col0 + j, status, lane == j);
+        const T r = T(1) / ljj;
+        if (act) A[lane + j * ld] = (lane == j) ? ljj : d * r;
+        if (lane == j) rdiag[j] = r;
     }
 }
 
 // Rows [i0, i1) of B (column-major, leading dimension ld) times D^{-T} in
-// place, D the factored nb x nb diagonal block (leading dimension ldd);
-// one thread per row, each thread touching only its own row.
+// place, D the factored nb x nb diagonal block (leading dimension ldd) with
+// reciprocal pivots rdiag; one thread per row, left-looking (x_j from the
+// already solved x_t, t < j, and row j of D by LDS broadcast).
 template <typename T>
-__device__ void rows_trsm(T* B, int ld, const T* D, int ldd, int nb, int i0, int i1) {
+__device__ void rows_trsm(T* B, int ld, const T* D, int ldd, int nb, int i0, int i1, const T* rdiag) {
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
         for (int j = 0; j < nb; ++j) {
-            const T xj = B[i + j * ld] / D[j + j * ldd];
-            B[i + j * ld] = xj;
-            for (int t = j + 1; t < nb; ++t) B[i + t * ld] -= xj * D[t + j * ldd];
-        }
-    }
-}
-
-// Register variants for wide blocks: the row lives in registers and the
-// triangular loops are unrolled, which removes the LDS round trip from every
-// step of the dependency chain.  Used for the large-front class only (the
-// unrolled code is large).
-template <typename T>
-__device__ __forceinline__ void wave_potrf_reg(T* A, int ld, int nb, int col0, int32_t* status) {
-    const int lane = threadIdx.x % kWave;
-    T row[kDiag];
-#pragma unroll
-    for (int j = 0; j < kDiag; ++j) row[j] = (lane < nb && j < nb && j <= lane) ? A[lane + j * ld] : T(0);
-#pragma unroll
-    for (int k = 0; k < kDiag; ++k) {
-        if (k < nb) {
-            const T akk = bcast(row[k], k);
-            const T lkk = pivot_root<T>(akk, col0 + k, status, lane == k);
-            const T lik = (lane == k) ? lkk : row[k] / lkk;
-            if (lane >= k) row[k] = lik;
-#pragma unroll
-            for (int j = k + 1; j < kDiag; ++j) {
-                if (j < nb) {
-                    const T ljk = bcast(lik, j);
-                    if (lane >= j) row[j] -= lik * ljk;
-                }
+            T acc0 = T(0), acc1 = T(0);
+            int t = 0;
+            for (; t + 1 < j; t += 2) {
+                acc0 += B[i + t * ld] * D[j + t * ldd];
+                acc1 += B[i + (t + 1) * ld] * D[j + (t + 1) * ldd];
             }
+            if (t < j) acc0 += B[i + t * ld] * D[j + t * ldd];
+            B[i + j * ld] = (B[i + j * ld] - (acc0 + acc1)) * rdiag[j];
         }
-    }
-    if (lane < nb) {
-#pragma unroll
-        for (int j = 0; j < kDiag; ++j)
-            if (j < nb && j <= lane) A[lane + j * ld] = row[j];
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void rows_trsm_reg(T* B, int ld, const T* D, int ldd, int nb, int i0, int i1) {
-#pragma unroll 1
-    for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
-        T x[kDiag];
-#pragma unroll
-        for (int j = 0; j < kDiag; ++j) x[j] = (j < nb) ? B[i + j * ld] : T(0);
-#pragma unroll
-        for (int j = 0; j < kDiag; ++j) {
-            if (j < nb) {
-                x[j] /= D[j + j * ldd];
-#pragma unroll
-                for (int t = j + 1; t < kDiag; ++t)
-                    if (t < nb) x[t] -= x[j] * D[t + j * ldd];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kDiag; ++j)
-            if (j < nb) B[i + j * ld] = x[j];
     }
 }
 
@@ -380,16 +340,13 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
             }
         }
     }
+    __shared__ T s_rdiag[kDiag];
     for (int kb = 0; kb < w; kb += kDiag) {
         const int nb = min(kDiag, w - kb);
         T* Dg = F + kb + kb * f;
-        if (tid < kWave) {
-            if (REG) wave_potrf_reg<T>(Dg, f, nb, c0 + kb, status);
-            else wave_potrf<T>(Dg, f, nb, c0 + kb, status);
-        }
+        if (tid < kWave) wave_potrf<T>(Dg, f, nb, c0 + kb, status, s_rdiag);
         __syncthreads();
-        if (REG) rows_trsm_reg<T>(F + kb * f, f, Dg, f, nb, kb + nb, f);
-        else rows_trsm<T>(F + kb * f, f, Dg, f, nb, kb + nb, f);
+        rows_trsm<T>(F + kb * f, f, Dg, f, nb, kb + nb, f, s_rdiag);
         __syncthreads();
         // remaining panel columns [kb+nb, w), rows >= column
         const int j0 = kb + nb, mr = f - j0, mc = w - j0;
@@ -502,7 +459,8 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
         }
     }
     __syncthreads();
-    if (tid < kWave) wave_potrf_reg<T>(D, kPanelNB, nb, c0 + kb, status);
+    __shared__ T s_rdiag[kPanelNB];
+    if (tid < kWave) wave_potrf<T>(D, kPanelNB, nb, c0 + kb, status, s_rdiag);
     __syncthreads();
     for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
@@ -525,7 +483,7 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
             }
         }
         __syncthreads();
-        rows_trsm_reg<T>(R, 256, D, kPanelNB, nb, 0, nr);
+        rows_trsm<T>(R, 256, D, kPanelNB, nb, 0, nr, s_rdiag);
         __syncthreads();
         for (int idx = tid; idx < nr * nb; idx += nt) {
             const int i = idx % nr, j = idx / nr;
