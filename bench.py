@@ -39,10 +39,34 @@ def parse():
     ap.add_argument("--workload", default="netflow",
                     choices=["netflow", "netflow_seq", "batch", "pde_learned"],
                     help="netflow: the benchmark line; the others measure the other target forms")
-    ap.add_argument("--systems", type=int, default=60, help="sequence length (netflow_seq, pde_learned)")
+    ap.add_argument("--systems", type=int, default=None,
+                    help="sequence length (netflow_seq: 60, pde_learned: 80)")
     ap.add_argument("--instances", type=int, default=512, help="batch size (batch)")
     ap.add_argument("--side", type=int, default=48, help="grid side of the PDE workload")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="first run one plain device copy of 512 MiB (scale of the HBM byte counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_factor_netflow10k.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2405_14236_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per factorization from the committed counter summary, or
+    None when the factor kernels changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for ln in open(TRAFFIC_FILE):
+        if ":" in ln and ln.strip().startswith(("source_sha256", "traffic_bytes_per_factorization")):
+            k, v = ln.strip().split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if "source_sha256" not in vals or "traffic_bytes_per_factorization" not in vals:
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    return float(vals["traffic_bytes_per_factorization"]) if sha == vals["source_sha256"] else None
 
 
 def algorithmic_counts(p, info, formulation):
@@ -136,6 +160,7 @@ def run_sequence(a, torch, workloads, Solver, device_values):
     from oracle import sparse as osp
     N = a.nodes if a.nodes != 10_000 else 80_000
     p = workloads.network_flow(N, seed=a.seed)
+    a.systems = a.systems or 60
     seq = workloads.ipm_sigma_sequence(p, a.systems, seed=a.seed)
     w, g, h, _, _ = device_values(p, "cuda", "lifted")
     sx = [torch.as_tensor(x, device="cuda") for x, _ in seq]
@@ -155,6 +180,8 @@ def run_sequence(a, torch, workloads, Solver, device_values):
             torch.cuda.synchronize()
             per.append(time.perf_counter() - t0)
             infos.append(si)
+            print(f"[{prec}] system {k}: {1e3 * per[-1]:.2f} ms, omega {si['omega']:.2e}, "
+                  f"fallback {si['fallback']}", file=sys.stderr, flush=True)
             if k in (0, a.systems // 2, a.systems - 1):
                 P = osp.Problem(p)
                 si["oracle_omega"] = osp.omega_condensed(P.W, seq[k][0], P.J, seq[k][1], x.cpu().numpy(), p.b)
@@ -191,6 +218,7 @@ def run_batch(a, torch, workloads, Solver):
         t0 = time.perf_counter()
         s = Solver(None, "lifted", prec, batch=probs, tol=1e-8 if prec == "fp32_ir" else 1e-10).bind("cuda")
         t_an = time.perf_counter() - t0
+        print(f"[{prec}] batch analysed in {t_an:.2f} s", file=sys.stderr, flush=True)
         chosen, best = s.autotune(w, g, h, sig[0][0], sig[0][1])
         x = torch.empty_like(b)
         for k in range(a.warmup):
@@ -225,7 +253,7 @@ def run_pde_learned(a, torch, workloads, Solver, device_values):
     from oracle import mlp as om
     from oracle import sparse as osp
     p = workloads.pde_control(a.side, seed=a.seed)
-    num = a.systems
+    num = a.systems or 80
     seq = workloads.ipm_sigma_sequence(p, num, seed=a.seed)
     rng = np.random.default_rng(a.seed + 11)
     rhs = [torch.as_tensor(rng.standard_normal(p.n), device="cuda") for _ in range(num)]
@@ -244,6 +272,9 @@ def run_pde_learned(a, torch, workloads, Solver, device_values):
         _, si = s64.solve(rhs[k], x)
         if k < 20:
             targets.append(x.clone())
+        if k % 10 == 0:
+            torch.cuda.synchronize()
+            print(f"[fp64 refactor] system {k}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     out["fp64_refactor"] = dict(solves_per_s=num / (time.perf_counter() - t0))
     del s64
@@ -260,6 +291,7 @@ def run_pde_learned(a, torch, workloads, Solver, device_values):
                 continue
             step += 1
             losses.append(s.mlp_train_step((w, g, h, sx[k], ss[k]), 0.0, rhs[k], targets[k], prm, m, v, step, 3e-3))
+        print(f"[train] epoch {epoch}: mean loss {np.mean(losses[-19:]):.4f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     for name, params in (("pcg_learned", prm), ("pcg_identity", None)):
@@ -271,6 +303,8 @@ def run_pde_learned(a, torch, workloads, Solver, device_values):
             _, si = s.pcg_solve((w, g, h, sx[k], ss[k]), 0.0, params, rhs[k], maxit=50, tol=1e-8,
                                 allow_refactor=True, raise_on_error=False)
             iters.append(si["pcg_iters"]); fb += si["fallback"] != 0; oms.append(si["omega"])
+            print(f"[{name}] system {k}: {si['pcg_iters']} PCG iterations, fallback {si['fallback']}",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[name] = dict(solves_per_s=(num - 20) / dt, pcg_iters=iters, refactorizations=fb,
@@ -302,6 +336,13 @@ def main():
     from paper_2405_14236_amd import workloads
     from paper_2405_14236_amd.solver import Solver, device_values
 
+    if a.pmc_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"pmc calibration: one device copy of {src.numel() * 8} bytes read and written", file=sys.stderr)
+        del src, dst
     p = workloads.network_flow(a.nodes, seed=a.seed)
     rng = np.random.default_rng(a.seed + 1)
     nsys = a.steps + a.warmup
@@ -329,8 +370,12 @@ def main():
         bound, unit_bytes, flops = "hbm", cnt["resid_bytes"], None
     achieved = unit_bytes / (per_call[dom] * 1e-3) / 1e9
     roofline = {"bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
-                "unit_bytes": unit_bytes, "avg_ms": per_call[dom]}
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic() if dom == "factor" else None,
+                "kernel": dom, "unit_bytes": unit_bytes, "avg_ms": per_call[dom]}
+    if flops:
+        roofline["fp64_tflops"] = flops / (per_call[dom] * 1e-3) / 1e12
+        roofline["fp64_frac"] = roofline["fp64_tflops"] / FP64_PEAK_TFLOPS
 
     cpu = None
     if not a.no_cpu_baseline:
