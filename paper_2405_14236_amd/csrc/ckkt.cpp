@@ -116,6 +116,7 @@ struct ckkt_handle {
     // caller's stream): [0] factor FP64, [1] factor FP32, [2] sweeps FP64,
     // [3] sweeps FP32.  They reference only workspace memory.
     hipStream_t capture_stream = nullptr;
+    SideStream side;  // second stream of the factorization (tiled fronts)
     hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
     bool use_graphs = true;
     bool debug_launch = false;  // CKKT_DEBUG_LAUNCH=1: report the first failing launch per factor level
@@ -447,7 +448,7 @@ template <typename T>
 void factor_levels(ckkt_handle* h, const double* scale, hipStream_t st) {
     T* arena = arena_of<T>(h);
     for (size_t l = 0; l < h->levels.size(); ++l) {
-        launch_factor_level<T>(h->dp, h->levels[l], h->K, arena, h->status, scale, st);
+        launch_factor_level<T>(h->dp, h->levels[l], h->K, arena, h->status, scale, st, &h->side);
         if (h->debug_launch) {
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess)
@@ -1031,6 +1032,14 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
     if (!h->capture_stream) {
         if (hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess) h->capture_stream = nullptr;
     }
+    if (!h->side.stream) {
+        if (hipStreamCreateWithFlags(&h->side.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming) != hipSuccess) {
+            h->side = SideStream{};
+            (void)hipGetLastError();
+        }
+    }
     const char* ng = std::getenv("CKKT_NO_GRAPH");
     h->use_graphs = !(ng && ng[0] == '1');
     const char* dl = std::getenv("CKKT_DEBUG_LAUNCH");
@@ -1453,6 +1462,9 @@ void ckkt_destroy(ckkt_handle* h) {
     for (auto& g : h->graphs)
         if (g) (void)hipGraphExecDestroy(g);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    if (h->side.stream) (void)hipStreamDestroy(h->side.stream);
+    if (h->side.fork) (void)hipEventDestroy(h->side.fork);
+    if (h->side.join) (void)hipEventDestroy(h->side.join);
     if (h->host) (void)hipHostFree(h->host);
     delete h;
 }

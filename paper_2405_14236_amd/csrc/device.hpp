@@ -60,10 +60,18 @@ void launch_row_weights(const DevPlan& P, const SysVals& v, double* d, hipStream
 void launch_assemble(const DevPlan& P, const SysVals& v, const double* d, double* K, hipStream_t st);
 void launch_init_status(int32_t* status, hipStream_t st);
 
+// A second stream with its fork/join events (default priority): the
+// tiled path of a level runs there, concurrently with its LDS fronts.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kMergeCompactFronts = 512;  // one launch for both LDS classes up to this many compact fronts
+
 // Returns false (and launches nothing) if a launch would exceed the LDS limit.
 template <typename T>
 bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
-                         int32_t* status, const double* scale, hipStream_t st);
+                         int32_t* status, const double* scale, hipStream_t st, const SideStream* side);
 template <typename T>
 void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* v_perm,
                       double* uvec, hipStream_t st);

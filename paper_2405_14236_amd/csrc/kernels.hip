@@ -1290,7 +1290,7 @@ void launch_diag_scale(const DevPlan& P, const double* K, double* scale, hipStre
 
 template <typename T>
 bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
-                         int32_t* status, const double* scale, hipStream_t st) {
+                         int32_t* status, const double* scale, hipStream_t st, const SideStream* side) {
     if ((size_t)L.small_maxf * L.small_maxf * sizeof(T) + kFactorStaticLds > (size_t)kLdsBytes) return false;
     static bool attr_set = false;
     if (!attr_set) {
@@ -1300,34 +1300,56 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kFactorStaticLds);
         attr_set = true;
     }
-    if (L.small_count > 0) {
-        // two LDS size classes so that small fronts keep several workgroups
-        // per CU; one wave per front when the class is tiny
-        const bool d = sizeof(T) == 8;
-        const int na = d ? L.small_split : L.small_split32;
-        const int fa = d ? L.small_maxf_a : L.small_maxf_a32;
-        const int nbig = L.small_count - na;
-        if (na > 0)
-            hipLaunchKernelGGL((k_factor_small<T, false>), dim3(na), dim3(L.small_threads_a),
-                               (size_t)fa * fa * sizeof(T), st, P, K, arena, L.small_begin, status, scale);
-        if (nbig > 0) {
-            size_t lds = (size_t)L.small_maxf * L.small_maxf * sizeof(T);
-            hipLaunchKernelGGL((k_factor_small<T, true>), dim3(nbig), dim3(256), lds, st, P, K, arena,
-                               L.small_begin + na, status, scale);
-        }
+    // fronts above the LDS limit run on the side stream, concurrently with
+    // the LDS-resident fronts of the same level (both depend only on lower
+    // levels and write disjoint arena regions)
+    const bool fork = L.big_count > 0 && L.small_count > 0 && side && side->stream;
+    hipStream_t sb = st;
+    if (fork) {
+        (void)hipEventRecord(side->fork, st);
+        (void)hipStreamWaitEvent(side->stream, side->fork, 0);
+        sb = side->stream;
     }
     if (L.big_count > 0) {
-        hipLaunchKernelGGL(k_big_init<T>, dim3(L.tile_count), dim3(256), 0, st, P, K, arena, L.tile_begin,
+        hipLaunchKernelGGL(k_big_init<T>, dim3(L.tile_count), dim3(256), 0, sb, P, K, arena, L.tile_begin,
                            scale);
         for (int kb = 0; kb < L.big_maxw; kb += kPanelNB) {
-            hipLaunchKernelGGL(k_big_panel<T>, dim3(L.big_count), dim3(256), 0, st, P, arena, L.big_begin,
+            hipLaunchKernelGGL(k_big_panel<T>, dim3(L.big_count), dim3(256), 0, sb, P, arena, L.big_begin,
                                kb, status);
             int rest = L.big_maxf - kb - 1;  // upper bound of trailing rows
             int tiles = rest > 0 ? (rest + 63) / 64 : 0;
             if (tiles > 0)
-                hipLaunchKernelGGL(k_big_update<T>, dim3(tiles, tiles, L.big_count), dim3(256), 0, st, P,
+                hipLaunchKernelGGL(k_big_update<T>, dim3(tiles, tiles, L.big_count), dim3(256), 0, sb, P,
                                    arena, L.big_begin, kb);
         }
+    }
+    if (L.small_count > 0) {
+        // two LDS size classes so that small fronts keep several workgroups
+        // per CU (one wave per front when the class is tiny); when a level
+        // holds both classes and few compact fronts, one launch covers all
+        // of them so that the classes run concurrently
+        const bool d = sizeof(T) == 8;
+        const int na = d ? L.small_split : L.small_split32;
+        const int fa = d ? L.small_maxf_a : L.small_maxf_a32;
+        const int nbig = L.small_count - na;
+        if (na > 0 && nbig > 0 && na <= kMergeCompactFronts) {
+            size_t lds = (size_t)L.small_maxf * L.small_maxf * sizeof(T);
+            hipLaunchKernelGGL((k_factor_small<T, true>), dim3(L.small_count), dim3(256), lds, st, P, K, arena,
+                               L.small_begin, status, scale);
+        } else {
+            if (na > 0)
+                hipLaunchKernelGGL((k_factor_small<T, false>), dim3(na), dim3(L.small_threads_a),
+                                   (size_t)fa * fa * sizeof(T), st, P, K, arena, L.small_begin, status, scale);
+            if (nbig > 0) {
+                size_t lds = (size_t)L.small_maxf * L.small_maxf * sizeof(T);
+                hipLaunchKernelGGL((k_factor_small<T, true>), dim3(nbig), dim3(256), lds, st, P, K, arena,
+                                   L.small_begin + na, status, scale);
+            }
+        }
+    }
+    if (fork) {
+        (void)hipEventRecord(side->join, side->stream);
+        (void)hipStreamWaitEvent(st, side->join, 0);
     }
     return true;
 }
@@ -1364,9 +1386,9 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
 }
 
 template bool launch_factor_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, int32_t*,
-                                          const double*, hipStream_t);
+                                          const double*, hipStream_t, const SideStream*);
 template bool launch_factor_level<float>(const DevPlan&, const LevelInfo&, const double*, float*, int32_t*,
-                                         const double*, hipStream_t);
+                                         const double*, hipStream_t, const SideStream*);
 template void launch_fwd_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, double*,
                                        hipStream_t);
 template void launch_fwd_level<float>(const DevPlan&, const LevelInfo&, const float*, double*, double*,
