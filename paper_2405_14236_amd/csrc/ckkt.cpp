@@ -77,6 +77,7 @@ struct ckkt_handle {
         r_instvar, r_insteq, r_kcol, r_cbptr, r_cbsrc, r_cblen, r_cbuoff;
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
     Region r_ctl, r_done;  // dependency-driven sweeps: control words, per-supernode flags
+    Region r_dscr;         // factored diagonal blocks of tiled fronts between launches
     std::vector<Region> r_vn, r_vm, r_veq;  // scratch vectors of length n, m, m_eq
     // learned preconditioner (opt.learned)
     Region r_feat, r_o, r_cache, r_go, r_mlpws, r_grad, r_sxold, r_dold, r_kdold, r_kdnew, r_dnew;
@@ -91,6 +92,7 @@ struct ckkt_handle {
     float* arena32 = nullptr;
     int32_t* status = nullptr;  // [0] failing column, [1] FP32 pivot floors, [2] sweep wait failure
     unsigned* ctl = nullptr;
+    double* dscr = nullptr;
     unsigned* done = nullptr;
     SweepSched sched;
     bool sched_ok = false;
@@ -287,6 +289,11 @@ void build_layout(ckkt_handle* h) {
     h->r_status = L.add(4 * sizeof(int32_t));
     h->r_ctl = L.add(kSweepCtlWords * sizeof(unsigned));
     h->r_done = L.add(std::max<size_t>(P.ns, 1) * sizeof(unsigned));
+    {
+        int maxbig = 1;
+        for (int l = 0; l < P.nlev; ++l) maxbig = std::max(maxbig, P.lvl_big_ptr[l + 1] - P.lvl_big_ptr[l]);
+        h->r_dscr = L.add((size_t)maxbig * kPanelNB * kPanelNB * sizeof(double));
+    }
     h->r_bits = L.add((P.ninst + 2) * sizeof(unsigned long long));
     h->r_dotpart = L.add(kDotBlocks * sizeof(double));
     h->r_sc = L.add(16 * sizeof(double));
@@ -355,6 +362,7 @@ void fill_devplan(ckkt_handle* h) {
     h->status = at<int32_t>(h, h->r_status);
     h->ctl = at<unsigned>(h, h->r_ctl);
     h->done = at<unsigned>(h, h->r_done);
+    h->dscr = at<double>(h, h->r_dscr);
     h->bits = at<unsigned long long>(h, h->r_bits);
     h->dotpart = at<double>(h, h->r_dotpart);
     h->sc = at<double>(h, h->r_sc);
@@ -448,7 +456,7 @@ template <typename T>
 void factor_levels(ckkt_handle* h, const double* scale, hipStream_t st) {
     T* arena = arena_of<T>(h);
     for (size_t l = 0; l < h->levels.size(); ++l) {
-        launch_factor_level<T>(h->dp, h->levels[l], h->K, arena, h->status, scale, st, &h->side);
+        launch_factor_level<T>(h->dp, h->levels[l], h->K, arena, h->status, scale, st, &h->side, h->dscr);
         if (h->debug_launch) {
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess)

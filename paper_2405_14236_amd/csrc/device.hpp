@@ -54,6 +54,7 @@ constexpr int kSweepMaxFront = (kLdsBytes - kSweepStaticLds) / 8 - 64 * 64;
 constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several workgroups per CU)
 constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
+constexpr int kPanelRows = 256; // rows of the panel solved per workgroup
 
 // ---- launchers (kernels.hip)
 void launch_row_weights(const DevPlan& P, const SysVals& v, double* d, hipStream_t st);
@@ -69,9 +70,12 @@ struct SideStream {
 constexpr int kMergeCompactFronts = 512;  // one launch for both LDS classes up to this many compact fronts
 
 // Returns false (and launches nothing) if a launch would exceed the LDS limit.
+// dscr: kPanelNB^2 doubles per tiled front of the level (factored diagonal
+// blocks in transit between the panel and update launches).
 template <typename T>
 bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
-                         int32_t* status, const double* scale, hipStream_t st, const SideStream* side);
+                         int32_t* status, const double* scale, hipStream_t st, const SideStream* side,
+                         double* dscr);
 template <typename T>
 void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* v_perm,
                       double* uvec, hipStream_t st);

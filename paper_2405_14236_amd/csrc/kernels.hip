@@ -142,7 +142,7 @@ __device__ __forceinline__ T pivot_root(T d, int col, int32_t* status, bool repo
 template <>
 __device__ __forceinline__ double pivot_root<double>(double d, int col, int32_t* status, bool report) {
     if (!(d > 0.0)) {
-        if (report) atomicMin(status, col);
+        if (report && status) atomicMin(status, col);
         return 1.0;
     }
     return sqrt(d);
@@ -152,7 +152,7 @@ template <>
 __device__ __forceinline__ float pivot_root<float>(float d, int col, int32_t* status, bool report) {
     const float floor_ = 1e-5f;
     if (!(d > floor_)) {
-        if (report) atomicAdd(status + 1, 1);
+        if (report && status) atomicAdd(status + 1, 1);
         return sqrtf(floor_);
     }
     return sqrtf(d);
@@ -426,24 +426,30 @@ k_big_init(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int t
     }
 }
 
-// Large fronts, step 2 (per block column kb): one wave factors the 32 x 32
-// diagonal block in LDS, then the rows below are solved in LDS-staged
-// chunks of 256 rows (one thread per row).
+// Large fronts, step 2 (per block column kb), grid (row chunk, front):
+// every workgroup stages the 32 x 32 diagonal block, one wave factors it
+// (the same arithmetic in every workgroup), and the workgroup solves its
+// chunk of kPanelRows rows below (one thread per row).  With one chunk the
+// factored block is written back in place; with several, chunk 0 leaves it
+// in dscr (another chunk may still be reading the original block) and the
+// trailing-update launch copies it into the front.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status) {
+k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status, T* __restrict__ dscr) {
     // one buffer for both, so that the compiler keeps D in LDS instead of
     // hoisting the whole block into registers across the row loop
-    __shared__ T buf[kPanelNB * kPanelNB + 256 * kPanelNB];
+    __shared__ T buf[kPanelNB * kPanelNB + kPanelRows * kPanelNB];
     T* D = buf;
     T* R = buf + kPanelNB * kPanelNB;
-    const int s = P.lvl_big[list_begin + blockIdx.x];
+    const int s = P.lvl_big[list_begin + blockIdx.y];
     const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
     const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
     if (kb >= w) return;
     const int nb = min(kPanelNB, w - kb);
     T* F = arena + P.l_off[s];
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int r0 = kb + nb + blockIdx.x * kPanelRows;
+    if (blockIdx.x > 0 && r0 >= f) return;
     for (int base = 0; base < nb * nb; base += 4 * nt) {
         T t4[4];
 #pragma unroll
@@ -460,36 +466,37 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
     }
     __syncthreads();
     __shared__ T s_rdiag[kPanelNB];
-    if (tid < kWave) wave_potrf<T>(D, kPanelNB, nb, c0 + kb, status, s_rdiag);
+    if (tid < kWave) wave_potrf<T>(D, kPanelNB, nb, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
     __syncthreads();
-    for (int idx = tid; idx < nb * nb; idx += nt) {
-        const int i = idx % nb, j = idx / nb;
-        if (i >= j) F[(kb + i) + (int64_t)(kb + j) * f] = D[i + j * kPanelNB];
+    if (blockIdx.x == 0) {
+        T* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * kPanelNB * kPanelNB;
+        const int64_t ld = gridDim.x == 1 ? f : kPanelNB;
+        for (int idx = tid; idx < nb * nb; idx += nt) {
+            const int i = idx % nb, j = idx / nb;
+            if (i >= j) dst[i + j * ld] = D[i + j * kPanelNB];
+        }
     }
-#pragma unroll 1
-    for (int r0 = kb + nb; r0 < f; r0 += 256) {
-        const int nr = min(256, f - r0);
-        for (int base = 0; base < nr * nb; base += 8 * nt) {
-            T t8[8];
+    if (r0 >= f) return;
+    const int nr = min(kPanelRows, f - r0);
+    for (int base = 0; base < nr * nb; base += 8 * nt) {
+        T t8[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int idx = base + u * nt + tid;
-                t8[u] = idx < nr * nb ? F[(r0 + idx % nr) + (int64_t)(kb + idx / nr) * f] : T(0);
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * nt + tid;
+            t8[u] = idx < nr * nb ? F[(r0 + idx % nr) + (int64_t)(kb + idx / nr) * f] : T(0);
+        }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int idx = base + u * nt + tid;
-                if (idx < nr * nb) R[idx % nr + (idx / nr) * 256] = t8[u];
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * nt + tid;
+            if (idx < nr * nb) R[idx % nr + (idx / nr) * kPanelRows] = t8[u];
         }
-        __syncthreads();
-        rows_trsm<T>(R, 256, D, kPanelNB, nb, 0, nr, s_rdiag);
-        __syncthreads();
-        for (int idx = tid; idx < nr * nb; idx += nt) {
-            const int i = idx % nr, j = idx / nr;
-            F[(r0 + i) + (int64_t)(kb + j) * f] = R[i + j * 256];
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    rows_trsm<T>(R, kPanelRows, D, kPanelNB, nb, 0, nr, s_rdiag);
+    __syncthreads();
+    for (int idx = tid; idx < nr * nb; idx += nt) {
+        const int i = idx % nr, j = idx / nr;
+        F[(r0 + i) + (int64_t)(kb + j) * f] = R[i + j * kPanelRows];
     }
 }
 
@@ -498,13 +505,23 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
 // column, front).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb) {
+k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* __restrict__ dscr, int copy_d) {
     __shared__ T A[64][kPanelNB + 1];
     __shared__ T B[64][kPanelNB + 1];
     const int s = P.lvl_big[list_begin + blockIdx.z];
     const int w = P.sn_start[s + 1] - P.sn_start[s];
     const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
     if (kb >= w) return;
+    if (copy_d && blockIdx.x == 0 && blockIdx.y == 0) {
+        // the factored diagonal block left by a multi-chunk panel launch
+        const int nb = min(kPanelNB, w - kb);
+        const T* src = dscr + (size_t)blockIdx.z * kPanelNB * kPanelNB;
+        T* F = arena + P.l_off[s];
+        for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
+            const int i = idx % nb, j = idx / nb;
+            if (i >= j) F[(kb + i) + (int64_t)(kb + j) * f] = src[i + j * kPanelNB];
+        }
+    }
     const int ti = blockIdx.x, tj = blockIdx.y;
     if (tj > ti) return;
     const int nb = min(kPanelNB, w - kb);
@@ -532,30 +549,63 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb) {
         }
     }
     __syncthreads();
-    const int tx = tid % 16, ty = tid / 16;
-    T acc[4][4];
+    if constexpr (std::is_same<T, double>::value) {
+        // four waves, one 32 x 32 quadrant each, 2 x 2 MFMA tiles of 16 x 16
+        const int lane = tid % kWave, wv = tid / kWave;
+        const int qi = wv % 2, qj = wv / 2;
+        if (ti == tj && qj > qi) return;  // quadrant above the diagonal (wave-uniform)
+        const int li = lane % 16, lk = lane / 16;
+        dbl4 c[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-    for (int t = 0; t < nb; ++t) {
-        T av[4], bv[4];
+            for (int b = 0; b < 2; ++b) c[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < nb; t += 4) {
+            double av[2], bv[2];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = A[tx + 16 * a][t];
+            for (int a = 0; a < 2; ++a) av[a] = A[qi * 32 + a * 16 + li][t + lk];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = B[ty + 16 * b][t];
+            for (int b = 0; b < 2; ++b) bv[b] = B[qj * 32 + b * 16 + li][t + lk];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], c[a][b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = i0 + qi * 32 + a * 16 + 4 * r + lk, col = j0 + qj * 32 + b * 16 + li;
+                    if (row < f && col < f && row >= col) F[row + (int64_t)col * f] -= c[a][b][r];
+                }
+    } else {
+        const int tx = tid % 16, ty = tid / 16;
+        T acc[4][4];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-    }
+            for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+        for (int t = 0; t < nb; ++t) {
+            T av[4], bv[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int col = j0 + ty + 16 * b;
+            for (int a = 0; a < 4; ++a) av[a] = A[tx + 16 * a][t];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int row = i0 + tx + 16 * a;
-            if (row < f && col < f && row >= col) F[row + (int64_t)col * f] -= acc[a][b];
+            for (int b = 0; b < 4; ++b) bv[b] = B[ty + 16 * b][t];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int col = j0 + ty + 16 * b;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int row = i0 + tx + 16 * a;
+                if (row < f && col < f && row >= col) F[row + (int64_t)col * f] -= acc[a][b];
+            }
         }
     }
 }
@@ -1290,7 +1340,8 @@ void launch_diag_scale(const DevPlan& P, const double* K, double* scale, hipStre
 
 template <typename T>
 bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
-                         int32_t* status, const double* scale, hipStream_t st, const SideStream* side) {
+                         int32_t* status, const double* scale, hipStream_t st, const SideStream* side,
+                         double* dscr) {
     if ((size_t)L.small_maxf * L.small_maxf * sizeof(T) + kFactorStaticLds > (size_t)kLdsBytes) return false;
     static bool attr_set = false;
     if (!attr_set) {
@@ -1314,13 +1365,15 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         hipLaunchKernelGGL(k_big_init<T>, dim3(L.tile_count), dim3(256), 0, sb, P, K, arena, L.tile_begin,
                            scale);
         for (int kb = 0; kb < L.big_maxw; kb += kPanelNB) {
-            hipLaunchKernelGGL(k_big_panel<T>, dim3(L.big_count), dim3(256), 0, sb, P, arena, L.big_begin,
-                               kb, status);
+            const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
+            const int chunks = below > 0 ? (below + kPanelRows - 1) / kPanelRows : 1;
+            hipLaunchKernelGGL(k_big_panel<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena, L.big_begin,
+                               kb, status, reinterpret_cast<T*>(dscr));
             int rest = L.big_maxf - kb - 1;  // upper bound of trailing rows
             int tiles = rest > 0 ? (rest + 63) / 64 : 0;
             if (tiles > 0)
                 hipLaunchKernelGGL(k_big_update<T>, dim3(tiles, tiles, L.big_count), dim3(256), 0, sb, P,
-                                   arena, L.big_begin, kb);
+                                   arena, L.big_begin, kb, reinterpret_cast<const T*>(dscr), chunks > 1 ? 1 : 0);
         }
     }
     if (L.small_count > 0) {
@@ -1386,9 +1439,9 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
 }
 
 template bool launch_factor_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, int32_t*,
-                                          const double*, hipStream_t, const SideStream*);
+                                          const double*, hipStream_t, const SideStream*, double*);
 template bool launch_factor_level<float>(const DevPlan&, const LevelInfo&, const double*, float*, int32_t*,
-                                         const double*, hipStream_t, const SideStream*);
+                                         const double*, hipStream_t, const SideStream*, double*);
 template void launch_fwd_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, double*,
                                        hipStream_t);
 template void launch_fwd_level<float>(const DevPlan&, const LevelInfo&, const float*, double*, double*,
