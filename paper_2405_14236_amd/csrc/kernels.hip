@@ -161,6 +161,30 @@ __device__ __forceinline__ float pivot_root<float>(float d, int col, int32_t* st
 constexpr int kDiag = 32;  // diagonal block of the blocked front factorization
 constexpr int kMaxChildBatch = 64;  // children whose metadata is staged at once
 
+// sum_{t < n} x[t * ldx] * y[t * ldy] over LDS operands, eight products per
+// step with all sixteen loads issued first (their latencies overlap), two
+// partial sums.
+template <typename T>
+__device__ __forceinline__ T row_dot(const T* x, const T* y, int ldx, int ldy, int n) {
+    T acc0 = T(0), acc1 = T(0);
+    int t = 0;
+    for (; t + 8 <= n; t += 8) {
+        T a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = x[(t + u) * ldx];
+            b[u] = y[(t + u) * ldy];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+            acc0 += a[u] * b[u];
+            acc1 += a[u + 1] * b[u + 1];
+        }
+    }
+    for (; t < n; ++t) acc0 += x[t * ldx] * y[t * ldy];
+    return acc0 + acc1;
+}
+
 // One wave factors the nb x nb diagonal block at A (LDS, column-major,
 // leading dimension ld) in place and leaves the reciprocal pivots in
 // rdiag[0, nb).  Left-looking: at step j lane i (i >= j) forms
@@ -176,14 +200,7 @@ __device__ void wave_potrf(T* A, int ld, int nb, int col0, int32_t* status, T* r
     for (int j = 0; j < nb; ++j) {
         const bool act = lane < nb && lane >= j;
         const int ri = act ? lane : j;  // inactive lanes read a valid row and discard it
-        T acc0 = T(0), acc1 = T(0);
-        int t = 0;
-        for (; t + 1 < j; t += 2) {
-            acc0 += A[ri + t * ld] * A[j + t * ld];
-            acc1 += A[ri + (t + 1) * ld] * A[j + (t + 1) * ld];
-        }
-        if (t < j) acc0 += A[ri + t * ld] * A[j + t * ld];
-        const T d = A[ri + j * ld] - (acc0 + acc1);
+        const T d = A[ri + j * ld] - row_dot<T>(A + ri, A + j, ld, ld, j);
         const T djj = bcast(d, j);
         const T ljj = pivot_root<T>(djj, col0 + j, status, lane == j);
         const T r = T(1) / ljj;
@@ -199,16 +216,8 @@ __device__ void wave_potrf(T* A, int ld, int nb, int col0, int32_t* status, T* r
 template <typename T>
 __device__ void rows_trsm(T* B, int ld, const T* D, int ldd, int nb, int i0, int i1, const T* rdiag) {
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
-        for (int j = 0; j < nb; ++j) {
-            T acc0 = T(0), acc1 = T(0);
-            int t = 0;
-            for (; t + 1 < j; t += 2) {
-                acc0 += B[i + t * ld] * D[j + t * ldd];
-                acc1 += B[i + (t + 1) * ld] * D[j + (t + 1) * ldd];
-            }
-            if (t < j) acc0 += B[i + t * ld] * D[j + t * ldd];
-            B[i + j * ld] = (B[i + j * ld] - (acc0 + acc1)) * rdiag[j];
-        }
+        for (int j = 0; j < nb; ++j)
+            B[i + j * ld] = (B[i + j * ld] - row_dot<T>(B + i, D + j, ld, ldd, j)) * rdiag[j];
     }
 }
 
