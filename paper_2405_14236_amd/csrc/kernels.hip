@@ -158,7 +158,7 @@ __device__ __forceinline__ float pivot_root<float>(float d, int col, int32_t* st
     return sqrtf(d);
 }
 
-constexpr int kDiag = 32;  // diagonal block of the blocked front factorization
+constexpr int kDiag = 16;  // diagonal block of the blocked front factorization
 constexpr int kMaxChildBatch = 64;  // children whose metadata is staged at once
 
 // sum_{t < n} x[t * ldx] * y[t * ldy] over LDS operands, eight products per
