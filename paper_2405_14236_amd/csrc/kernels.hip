@@ -399,10 +399,14 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
 // the arena.  Zero the lower part of the tile, scatter the K entries of its
 // columns, then add every child's update entries whose destination column
 // lies in the tile (children in fixed order; each entry has one writer).
+// When the tile fits in LDS (lds_rows >= f) it is assembled there, child by
+// child with eight loads per thread in flight, and written out once;
+// otherwise it is assembled in place in the arena column by column.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_big_init(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int tile_begin,
-           const double* __restrict__ scale) {
+           const double* __restrict__ scale, int lds_rows) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tix = tile_begin + blockIdx.x;
     const int s = P.big_tile_sn[tix], col0 = P.big_tile_col[tix];
     const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
@@ -410,6 +414,63 @@ k_big_init(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int t
     const int col1 = min(col0 + kBigTile, f);
     T* F = arena + P.l_off[s];
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (f <= lds_rows) {
+        T* Tl = reinterpret_cast<T*>(smem_raw);  // tile column j - col0 at (j - col0) * f
+        const int nc = col1 - col0;
+        for (int i = tid; i < nc * f; i += nt) Tl[i] = T(0);
+        __syncthreads();
+        if (col0 < w) {
+            const int ce = c0 + min(col1, w);
+            for (int t = P.kcolptr[c0 + col0] + tid; t < P.kcolptr[ce]; t += nt) {
+                const int pr = P.kmap[t], j = P.kcol[t];
+                double val = K[t];
+                if (scale) val *= scale[j] * scale[P.sn_rows[ro + pr]];
+                Tl[pr + (j - c0 - col0) * f] = (T)val;
+            }
+        }
+        __syncthreads();
+        __shared__ int s_b[2];
+        for (int q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q) {
+            const int c = P.child_list[q];
+            const int wc = P.sn_start[c + 1] - P.sn_start[c];
+            const int roc = P.sn_rowptr[c], rc = P.sn_rowptr[c + 1] - roc - wc;
+            const int* rel = P.relmap + roc + wc;
+            const T* U = arena + P.u_off[c];
+            const int ld = P.u_ld[c];
+            // child columns landing in the tile: a contiguous range (rel increases)
+            if (tid == 0) { s_b[0] = rc; s_b[1] = 0; }
+            __syncthreads();
+            for (int b2 = tid; b2 < rc; b2 += nt) {
+                const int d = rel[b2];
+                if (d >= col0 && d < col1) { atomicMin(&s_b[0], b2); atomicMax(&s_b[1], b2 + 1); }
+            }
+            __syncthreads();
+            const int b0 = s_b[0], nbc = s_b[1] - s_b[0];
+            const int tot = nbc > 0 ? nbc * rc : 0;
+            for (int base = 0; base < tot; base += 8 * nt) {
+                T u8[8];
+                int dr[8], dc[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = base + u * nt + tid;
+                    const int a2 = idx % rc, b2 = b0 + idx / rc;
+                    const bool in = idx < tot && a2 >= b2;
+                    u8[u] = in ? U[a2 + (int64_t)b2 * ld] : T(0);
+                    dr[u] = in ? rel[a2] : -1;
+                    dc[u] = in ? rel[b2] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (dr[u] >= 0) Tl[dr[u] + (dc[u] - col0) * f] += u8[u];
+            }
+            __syncthreads();
+        }
+        for (int i = tid; i < nc * f; i += nt) {
+            const int r = i % f, jj = i / f;
+            if (r >= col0 + jj) F[r + (int64_t)(col0 + jj) * f] = Tl[i];
+        }
+        return;
+    }
     for (int j = col0; j < col1; ++j)
         for (int i = j + tid; i < f; i += nt) F[i + (int64_t)j * f] = T(0);
     __syncthreads();
@@ -1358,6 +1419,8 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kFactorStaticLds);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_small<T, false>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kFactorStaticLds);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_big_init<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - 1024);
         attr_set = true;
     }
     // fronts above the LDS limit run on the side stream, concurrently with
@@ -1371,8 +1434,11 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         sb = side->stream;
     }
     if (L.big_count > 0) {
-        hipLaunchKernelGGL(k_big_init<T>, dim3(L.tile_count), dim3(256), 0, sb, P, K, arena, L.tile_begin,
-                           scale);
+        // assemble the tiles in LDS when a whole tile (64 columns x f rows) fits
+        const size_t tile_bytes = (size_t)kBigTile * L.big_maxf * sizeof(T);
+        const bool lds_tile = tile_bytes + 1024 <= (size_t)kLdsBytes;
+        hipLaunchKernelGGL(k_big_init<T>, dim3(L.tile_count), dim3(256), lds_tile ? tile_bytes : 0, sb, P, K, arena,
+                           L.tile_begin, scale, lds_tile ? L.big_maxf : 0);
         for (int kb = 0; kb < L.big_maxw; kb += kPanelNB) {
             const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
             const int chunks = below > 0 ? (below + kPanelRows - 1) / kPanelRows : 1;
