@@ -520,19 +520,31 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
     const int tid = threadIdx.x, nt = blockDim.x;
     const int r0 = kb + nb + blockIdx.x * kPanelRows;
     if (blockIdx.x > 0 && r0 >= f) return;
-    for (int base = 0; base < nb * nb; base += 4 * nt) {
-        T t4[4];
+    const int nr = r0 < f ? min(kPanelRows, f - r0) : 0;
+    // issue the loads of the diagonal block and of this chunk's rows together
+    // (the rows do not depend on the block's factorization)
+    constexpr int kRPer = kPanelRows * kPanelNB / 256;
+    T t4[4], tr[kRPer];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int idx = base + u * nt + tid;
-            const int i = idx % nb, j = idx / nb;
-            t4[u] = (idx < nb * nb && i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
-        }
+    for (int u = 0; u < 4; ++u) {
+        const int idx = u * nt + tid;
+        const int i = idx % nb, j = idx / nb;
+        t4[u] = (idx < nb * nb && i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
+    }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int idx = base + u * nt + tid;
-            if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelNB] = t4[u];
-        }
+    for (int u = 0; u < kRPer; ++u) {
+        const int idx = u * nt + tid;
+        tr[u] = idx < nr * nb ? F[(r0 + idx % nr) + (int64_t)(kb + idx / nr) * f] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int idx = u * nt + tid;
+        if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelNB] = t4[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kRPer; ++u) {
+        const int idx = u * nt + tid;
+        if (idx < nr * nb) R[idx % nr + (idx / nr) * kPanelRows] = tr[u];
     }
     __syncthreads();
     __shared__ T s_rdiag[kPanelNB];
@@ -546,22 +558,7 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
             if (i >= j) dst[i + j * ld] = D[i + j * kPanelNB];
         }
     }
-    if (r0 >= f) return;
-    const int nr = min(kPanelRows, f - r0);
-    for (int base = 0; base < nr * nb; base += 8 * nt) {
-        T t8[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = base + u * nt + tid;
-            t8[u] = idx < nr * nb ? F[(r0 + idx % nr) + (int64_t)(kb + idx / nr) * f] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = base + u * nt + tid;
-            if (idx < nr * nb) R[idx % nr + (idx / nr) * kPanelRows] = t8[u];
-        }
-    }
-    __syncthreads();
+    if (nr == 0) return;
     rows_trsm<T>(R, kPanelRows, D, kPanelNB, nb, 0, nr, s_rdiag);
     __syncthreads();
     for (int idx = tid; idx < nr * nb; idx += nt) {
