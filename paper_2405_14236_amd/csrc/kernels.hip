@@ -135,35 +135,48 @@ __global__ void k_diag_scale(DevPlan P, const double* __restrict__ K, double* __
 // factorization is reported as failed.  FP32 (factor of the Jacobi-scaled
 // matrix, unit diagonal): pivots below a floor are raised to it (static
 // pivoting); the count is recorded and the factor serves as a
-// preconditioner for the FP64 refinement.
+// preconditioner for the FP64 refinement.  Both return the pivot sqrt(d)
+// and its reciprocal, from the hardware reciprocal square root refined by
+// Newton's iteration y <- y (3 - d y^2) / 2 (two steps for FP64, one for
+// FP32), which keeps the square root and the division off the chain.
 template <typename T>
-__device__ __forceinline__ T pivot_root(T d, int col, int32_t* status, bool report);
+__device__ __forceinline__ T pivot_root(T d, int col, int32_t* status, bool report, T& rinv);
 
 template <>
-__device__ __forceinline__ double pivot_root<double>(double d, int col, int32_t* status, bool report) {
+__device__ __forceinline__ double pivot_root<double>(double d, int col, int32_t* status, bool report,
+                                                     double& rinv) {
     if (!(d > 0.0)) {
         if (report && status) atomicMin(status, col);
+        rinv = 1.0;
         return 1.0;
     }
-    return sqrt(d);
+    double y = __builtin_amdgcn_rsq(d);
+    const double hd = 0.5 * d;
+    y = y * fma(-hd * y, y, 1.5);
+    y = y * fma(-hd * y, y, 1.5);
+    rinv = y;
+    return d * y;
 }
 
 template <>
-__device__ __forceinline__ float pivot_root<float>(float d, int col, int32_t* status, bool report) {
+__device__ __forceinline__ float pivot_root<float>(float d, int col, int32_t* status, bool report, float& rinv) {
     const float floor_ = 1e-5f;
     if (!(d > floor_)) {
         if (report && status) atomicAdd(status + 1, 1);
-        return sqrtf(floor_);
+        d = floor_;
     }
-    return sqrtf(d);
+    float y = __builtin_amdgcn_rsqf(d);
+    y = y * fmaf(-0.5f * d * y, y, 1.5f);
+    rinv = y;
+    return d * y;
 }
 
 constexpr int kDiag = 16;  // diagonal block of the blocked front factorization
 constexpr int kMaxChildBatch = 64;  // children whose metadata is staged at once
 
 // sum_{t < n} x[t * ldx] * y[t * ldy] over LDS operands, eight products per
-// step with all sixteen loads issued first (their latencies overlap), two
-// partial sums.
+// step with all sixteen loads issued first (their latencies overlap), the
+// rest in steps of four, two and one; two partial sums.
 template <typename T>
 __device__ __forceinline__ T row_dot(const T* x, const T* y, int ldx, int ldy, int n) {
     T acc0 = T(0), acc1 = T(0);
@@ -181,7 +194,23 @@ __device__ __forceinline__ T row_dot(const T* x, const T* y, int ldx, int ldy, i
             acc1 += a[u + 1] * b[u + 1];
         }
     }
-    for (; t < n; ++t) acc0 += x[t * ldx] * y[t * ldy];
+    if (t + 4 <= n) {
+        const T a0 = x[t * ldx], a1 = x[(t + 1) * ldx], a2 = x[(t + 2) * ldx], a3 = x[(t + 3) * ldx];
+        const T b0 = y[t * ldy], b1 = y[(t + 1) * ldy], b2 = y[(t + 2) * ldy], b3 = y[(t + 3) * ldy];
+        acc0 += a0 * b0;
+        acc1 += a1 * b1;
+        acc0 += a2 * b2;
+        acc1 += a3 * b3;
+        t += 4;
+    }
+    if (t + 2 <= n) {
+        const T a0 = x[t * ldx], a1 = x[(t + 1) * ldx];
+        const T b0 = y[t * ldy], b1 = y[(t + 1) * ldy];
+        acc0 += a0 * b0;
+        acc1 += a1 * b1;
+        t += 2;
+    }
+    if (t < n) acc0 += x[t * ldx] * y[t * ldy];
     return acc0 + acc1;
 }
 
@@ -202,8 +231,8 @@ __device__ void wave_potrf(T* A, int ld, int nb, int col0, int32_t* status, T* r
         const int ri = act ? lane : j;  // inactive lanes read a valid row and discard it
         const T d = A[ri + j * ld] - row_dot<T>(A + ri, A + j, ld, ld, j);
         const T djj = bcast(d, j);
-        const T ljj = pivot_root<T>(djj, col0 + j, status, lane == j);
-        const T r = T(1) / ljj;
+        T r;
+        const T ljj = pivot_root<T>(djj, col0 + j, status, lane == j, r);
         if (act) A[lane + j * ld] = (lane == j) ? ljj : d * r;
         if (lane == j) rdiag[j] = r;
     }
