@@ -57,6 +57,7 @@ struct Tune {
     int tiny_threads = 64;            // workgroup size when the compact class holds fronts <= 32
     int compact_threads = 256;        // workgroup size of the compact class otherwise
     int sweep_cutoff = 64;            // sweeps use 256 threads when a level's largest front exceeds this
+    int tiled_front = kSweepTiledFront;  // fronts with at least this many rows use the tiled sweeps
 };
 
 struct ckkt_handle {
@@ -206,13 +207,16 @@ void build_levels(ckkt_handle* h) {
         L.all_begin = P.lvl_all_ptr[l];
         L.all_count = P.lvl_all_ptr[l + 1] - L.all_begin;
         L.all_maxf = L.all_maxw = 0;
+        L.sweep_small_count = 0;
         for (int t = L.all_begin; t < L.all_begin + L.all_count; ++t) {
             L.all_maxf = std::max(L.all_maxf, front(P.lvl_all[t]));
             L.all_maxw = std::max(L.all_maxw, width(P.lvl_all[t]));
+            L.sweep_small_count += front(P.lvl_all[t]) < T.tiled_front;
         }
         L.tile_begin = P.big_tiles_ptr[l];
         L.tile_count = P.big_tiles_ptr[l + 1] - L.tile_begin;
         L.sweep_threads = L.all_maxf > T.sweep_cutoff ? 256 : 64;
+        L.sweep_tiled_f = T.tiled_front;
     }
 }
 
@@ -221,7 +225,6 @@ void build_levels(ckkt_handle* h) {
 bool plan_fits_lds(const ckkt_handle* h) {
     for (const LevelInfo& L : h->levels) {
         if ((size_t)L.small_maxf * L.small_maxf * sizeof(double) + kFactorStaticLds > (size_t)kLdsBytes) return false;
-        if (L.all_maxf > kSweepMaxFront) return false;
     }
     return true;
 }
@@ -395,10 +398,18 @@ ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const Patte
         delete h;
         return internal ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
     }
+    // CKKT_TILED_SWEEP_FRONT moves the size from which fronts are swept by
+    // the tiled kernels; it stays above the LDS front limit (so that every
+    // such front is in its level's big list) and at most the largest front
+    // one sweep workgroup can stage.
+    if (const char* tf = std::getenv("CKKT_TILED_SWEEP_FRONT")) {
+        const int v = std::atoi(tf);
+        if (v > 0) h->tune.tiled_front = std::min(std::max(v, ao.big_front + 1), kSweepMaxFront);
+    }
     build_levels(h);
     if (!plan_fits_lds(h)) {
         delete h;
-        return CKKT_ERR_ARG;  // a front beyond what the sweep kernels can stage
+        return CKKT_ERR_ARG;  // a small front beyond the LDS of one workgroup
     }
     build_layout(h);
     *out = h;
@@ -482,6 +493,7 @@ bool build_sweep_sched(ckkt_handle* h) {
         maxf = std::max(maxf, h->levels[l].all_maxf);
         maxw = std::max(maxw, h->levels[l].all_maxw);
     }
+    if (maxf > kSweepMaxFront) return false;  // a workgroup stages its whole front vector
     S.ldd = std::min(64, maxw);
     S.group_lds = (size_t)(((maxf + 1) & ~1) + S.ldd * S.ldd) * sizeof(double);
     int dev = 0;

@@ -40,6 +40,8 @@ struct LevelInfo {
     int32_t small_threads_a;   // workgroup size of the compact small-front class
     int32_t sweep_threads;     // workgroup size of the sweep kernels on this level
     int32_t tile_begin, tile_count;
+    int32_t sweep_tiled_f;      // fronts with f >= this are swept by the tiled kernels
+    int32_t sweep_small_count;  // fronts of the level swept one workgroup each (f < sweep_tiled_f)
 };
 
 constexpr int kBigTile = 64;    // column tile of the tiled front path
@@ -55,6 +57,12 @@ constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several w
 constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
 constexpr int kPanelRows = 256; // rows of the panel solved per workgroup
+// fronts with at least this many rows are swept by the tiled kernels (many
+// workgroups, one launch per 64-column block); every such front is in the
+// level's big list, whose fronts all exceed the LDS front limit
+constexpr int kSweepTiledFront = 1024;
+static_assert(kSweepTiledFront > kLdsFront64, "tiled sweep fronts must be big fronts");
+static_assert(kSweepTiledFront <= kSweepMaxFront, "fronts below the tiled size fit the sweep LDS");
 
 // ---- launchers (kernels.hip)
 void launch_row_weights(const DevPlan& P, const SysVals& v, double* d, hipStream_t st);

@@ -859,13 +859,14 @@ __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double
 // Level-synchronous forward sweep: one workgroup per supernode of a level.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_fwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* __restrict__ v_perm,
+k_fwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, int skip_f, double* __restrict__ v_perm,
       double* __restrict__ uvec) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* v = reinterpret_cast<double*>(smem_raw);
     const int s = P.lvl_all[list_begin + blockIdx.x];
     const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
     const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    if (f >= skip_f) return;  // swept by the tiled kernels
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < f; i += nt) {
         double acc = (i < w) ? v_perm[c0 + i] : 0.0;
@@ -884,18 +885,209 @@ k_fwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* _
 // Level-synchronous backward sweep (levels root to leaves).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_bwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, double* __restrict__ x_perm) {
+k_bwd(DevPlan P, const T* __restrict__ arena, int list_begin, int ldd, int skip_f, double* __restrict__ x_perm) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* z = reinterpret_cast<double*>(smem_raw);
     __shared__ double tb[kWave];
     const int s = P.lvl_all[list_begin + blockIdx.x];
     const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
     const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    if (f >= skip_f) return;  // swept by the tiled kernels
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < f; i += nt) z[i] = x_perm[P.sn_rows[ro + i]];
     __syncthreads();
     bwd_front(arena + P.l_off[s], w, f, ldd, z, z + ((f + 1) & ~1), tb);
     for (int i = tid; i < w; i += nt) x_perm[c0 + i] = z[i];
+}
+
+// ---------------------------------------------------------------- tiled sweeps of large fronts
+//
+// A front with at least kSweepTiledFront rows (the default size) is swept
+// by many workgroups, one launch per 64-column block of its panel, instead
+// of by one workgroup.
+// Between launches the front vector lives in global memory: entry i is
+// v_perm[c0 + i] for the own columns (i < w) and this front's update slot
+// uvec[ro + i] below them, so no flags are needed (launch order on the
+// stream orders the blocks).  Every sum runs in a fixed order.
+
+// Forward gather: entry i = own right-hand side (i < w) plus the children's
+// contributions, written to its global slot.  Grid (row tiles, big list).
+__global__ void __launch_bounds__(256)
+k_fwd_tiled_gather(DevPlan P, int list_begin, int min_f, double* __restrict__ v_perm, double* __restrict__ uvec) {
+    const int s = P.lvl_big[list_begin + blockIdx.y];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < min_f || i >= f) return;
+    double acc = (i < w) ? v_perm[c0 + i] : 0.0;
+    const int q1 = P.cb_ptr[ro + i + 1];
+    for (int q = P.cb_ptr[ro + i]; q < q1; ++q) acc += uvec[P.cb_src[q]];
+    if (i < w) v_perm[c0 + i] = acc;
+    else uvec[ro + i] = acc;
+}
+
+// Forward step j of the tiled fronts (j = 0 .. number of column blocks):
+// each workgroup takes 64 rows from row min(64 j, w) on, subtracts the
+// contribution of block j - 1 (already solved; its four waves take 16 of
+// its columns each and their partial sums are added in wave order), and
+// the first workgroup then solves diagonal block j on its rows.  Grid
+// (row tiles, big list), 256 threads.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fwd_tiled_step(DevPlan P, const T* __restrict__ arena, int list_begin, int min_f, int j,
+                 double* __restrict__ v_perm, double* __restrict__ uvec) {
+    __shared__ double D[kWave * kWave];
+    __shared__ double yb[kWave];
+    __shared__ double red[4][kWave];
+    const int s = P.lvl_big[list_begin + blockIdx.y];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const int nblk = (w + kWave - 1) / kWave;
+    if (f < min_f || j > nblk) return;
+    const int r0 = min(j * kWave, w) + blockIdx.x * kWave;
+    if (r0 >= f) return;
+    const T* L = arena + P.l_off[s];
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    const bool solve = blockIdx.x == 0 && j < nblk;
+    const int kb = j * kWave, nb = min(kWave, w - kb);
+    const int pk = (j - 1) * kWave, pnb = j > 0 ? min(kWave, w - pk) : 0;
+    if (solve) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, kWave);
+    if (tid < pnb) yb[tid] = v_perm[c0 + pk + tid];
+    __syncthreads();
+    const int i = r0 + lane;
+    const bool row = i < f;
+    double acc = 0.0;
+    if (pnb > 0) {
+        const int k0 = wid * 16;
+        const T* Li = L + (row ? i : r0) + (int64_t)(pk + k0) * f;
+        double l[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) l[u] = (row && k0 + u < pnb) ? (double)Li[(int64_t)u * f] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = fma(l[u], (k0 + u < pnb) ? yb[k0 + u] : 0.0, acc);
+    }
+    red[wid][lane] = acc;
+    __syncthreads();
+    if (wid != 0) return;
+    double vi = 0.0;
+    if (row) vi = ((i < w) ? v_perm[c0 + i] : uvec[ro + i]) - (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+    if (solve) {
+#pragma unroll 4
+        for (int k = 0; k < nb; ++k) {
+            const double yk = lane_bcast(vi, k) * D[k + k * kWave];
+            if (lane == k) vi = yk;
+            else if (lane > k && lane < nb) vi = fma(-D[lane + k * kWave], yk, vi);
+        }
+    }
+    if (row) {
+        if (i < w) v_perm[c0 + i] = vi;
+        else uvec[ro + i] = vi;
+    }
+}
+
+// Backward, part below the diagonal blocks: for every own column c of a
+// tiled front, x_perm[c0 + c] -= sum over rows i >= w of L[i, c] x_i (the
+// rows below are ancestors' columns, already solved).  One workgroup per
+// eight columns; its four waves split the rows and their sums are added in
+// wave order.  Grid (column groups, big list).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bwd_tiled_rect(DevPlan P, const T* __restrict__ arena, int list_begin, int min_f, double* __restrict__ x_perm) {
+    __shared__ double red[4][8];
+    const int s = P.lvl_big[list_begin + blockIdx.y];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const int cb = blockIdx.x * 8;
+    if (f < min_f || f == w || cb >= w) return;
+    const int nc = min(8, w - cb);
+    const T* L = arena + P.l_off[s] + (int64_t)cb * f;
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    double part[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) part[c] = 0.0;
+    for (int i0 = w + wid * kWave; i0 < f; i0 += 8 * kWave) {
+        const int ia = i0 + lane, ib = i0 + 4 * kWave + lane;
+        const bool va = ia < f, vb = ib < f;
+        const int ra = va ? P.sn_rows[ro + ia] : 0, rb = vb ? P.sn_rows[ro + ib] : 0;
+        double la[8], lb[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            la[c] = (va && c < nc) ? (double)L[ia + (int64_t)c * f] : 0.0;
+            lb[c] = (vb && c < nc) ? (double)L[ib + (int64_t)c * f] : 0.0;
+        }
+        const double xa = va ? x_perm[ra] : 0.0, xb = vb ? x_perm[rb] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) part[c] = fma(lb[c], xb, fma(la[c], xa, part[c]));
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const double sc = wave_sum(part[c]);
+        if (lane == 0) red[wid][c] = sc;
+    }
+    __syncthreads();
+    if (tid < nc) x_perm[c0 + cb + tid] -= ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
+// Backward step b of the tiled fronts (b = last column block .. 0): the
+// workgroup of column tile t <= b subtracts from its 64 columns the
+// contribution of block b + 1 (solved by the previous step): lanes take
+// the block's rows, the products go through LDS and four threads per
+// column add 16 rows each, in a fixed order.  The workgroup of tile b
+// then back-substitutes diagonal block b.  Grid (b + 1, big list).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bwd_tiled_step(DevPlan P, const T* __restrict__ arena, int list_begin, int min_f, int b,
+                 double* __restrict__ x_perm) {
+    __shared__ double D[kWave * kWave];
+    __shared__ double S[kWave * (kWave + 1)];
+    __shared__ double tb[kWave];
+    const int s = P.lvl_big[list_begin + blockIdx.y];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const int nblk = (w + kWave - 1) / kWave;
+    const int t = blockIdx.x;
+    if (f < min_f || b >= nblk || t > b) return;
+    (void)ro;
+    const T* L = arena + P.l_off[s];
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    const bool solve = t == b;
+    const int kb = b * kWave, nb = min(kWave, w - kb);
+    const int ct = t * kWave, tnb = min(kWave, w - ct);
+    const int q = kb + kWave, qnb = b + 1 < nblk ? min(kWave, w - q) : 0;
+    if (solve) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, kWave);
+    if (qnb > 0) {
+        const bool r = lane < qnb;
+        const double xr = r ? x_perm[c0 + q + lane] : 0.0;
+        const int k0 = wid * 16;
+        const T* Lr = L + (r ? q + lane : q) + (int64_t)(ct + k0) * f;
+        double l[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) l[u] = (r && k0 + u < tnb) ? (double)Lr[(int64_t)u * f] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) S[(k0 + u) * (kWave + 1) + lane] = l[u] * xr;
+        __syncthreads();
+        const int c = tid >> 2, rq = tid & 3;
+        double sum = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sum += S[c * (kWave + 1) + rq * 16 + u];
+        sum += __shfl_xor(sum, 1, kWave);
+        sum += __shfl_xor(sum, 2, kWave);
+        if (rq == 0) tb[c] = sum;
+    } else if (tid < kWave) {
+        tb[tid] = 0.0;
+    }
+    __syncthreads();
+    if (wid != 0) return;
+    double ri = lane < tnb ? x_perm[c0 + ct + lane] - tb[lane] : 0.0;
+    if (solve) {
+#pragma unroll 4
+        for (int k = nb - 1; k >= 0; --k) {
+            const double xk = lane_bcast(ri, k) * D[k + k * kWave];
+            if (lane == k) ri = xk;
+            else if (lane < k) ri = fma(-D[k + lane * kWave], xk, ri);
+        }
+    }
+    if (lane < tnb) x_perm[c0 + ct + lane] = ri;
 }
 
 // Forward step of one supernode with f <= 64 by one wave: lane i holds
@@ -1238,7 +1430,7 @@ k_resid_rows(DevPlan P, SysVals v, const double* __restrict__ d, const double* _
         res2[r] = res;
         num = fabs(res);
         double den = mag + fabs(rhs2[r]);
-        ratio = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+        ratio = den > 0.0 ? num / den : (num == 0.0 ? 0.0 : INFINITY);  // NaN -> INFINITY
         inst = P.inst_of_eqrow[r];
     } else if (in) {
         double dr = d[r];
@@ -1293,7 +1485,7 @@ k_resid_vars(DevPlan P, SysVals v, const double* __restrict__ x, const double* _
         res1[i] = res;
         num = fabs(res);
         double den = mag + fabs(bi);
-        ratio = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+        ratio = den > 0.0 ? num / den : (num == 0.0 ? 0.0 : INFINITY);  // NaN -> INFINITY
         inst = P.inst_of_var[i];
     }
     block_max_push(in, inst, ratio, num, omega_bits, resmax_bits);
@@ -1517,11 +1709,25 @@ void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
                            L.all_count, v_perm, uvec);
         return;
     }
+    const int tf = L.sweep_tiled_f;
+    const bool tiled = L.big_count > 0 && L.big_maxf >= tf;
+    const int skip_f = tiled ? tf : INT_MAX;
+    const int maxf = tiled ? std::min(L.all_maxf, tf - 1) : L.all_maxf;
     const int threads = L.sweep_threads;
     const int ldd = std::min(kWave, std::max(L.all_maxw, 1));
-    size_t lds = (size_t)(((L.all_maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
-    hipLaunchKernelGGL(k_fwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, v_perm,
-                       uvec);
+    size_t lds = (size_t)(((maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
+    if (!tiled || L.sweep_small_count > 0)
+        hipLaunchKernelGGL(k_fwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, skip_f,
+                           v_perm, uvec);
+    if (!tiled) return;
+    hipLaunchKernelGGL(k_fwd_tiled_gather, dim3((L.big_maxf + 255) / 256, L.big_count), dim3(256), 0, st, P,
+                       L.big_begin, tf, v_perm, uvec);
+    const int nblk = (L.big_maxw + kWave - 1) / kWave;
+    for (int j = 0; j <= nblk; ++j) {
+        const int rows = L.big_maxf - std::max(0, (j - 1) * kWave);
+        hipLaunchKernelGGL(k_fwd_tiled_step<T>, dim3((rows + kWave - 1) / kWave, L.big_count), dim3(256), 0, st,
+                           P, arena, L.big_begin, tf, j, v_perm, uvec);
+    }
 }
 
 template <typename T>
@@ -1533,10 +1739,23 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
                            L.all_count, x_perm);
         return;
     }
+    const int tf = L.sweep_tiled_f;
+    const bool tiled = L.big_count > 0 && L.big_maxf >= tf;
+    const int skip_f = tiled ? tf : INT_MAX;
+    const int maxf = tiled ? std::min(L.all_maxf, tf - 1) : L.all_maxf;
     const int threads = L.sweep_threads;
     const int ldd = std::min(kWave, std::max(L.all_maxw, 1));
-    size_t lds = (size_t)(((L.all_maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
-    hipLaunchKernelGGL(k_bwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, x_perm);
+    size_t lds = (size_t)(((maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
+    if (!tiled || L.sweep_small_count > 0)
+        hipLaunchKernelGGL(k_bwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, skip_f,
+                           x_perm);
+    if (!tiled) return;
+    hipLaunchKernelGGL(k_bwd_tiled_rect<T>, dim3((L.big_maxw + 7) / 8, L.big_count), dim3(256), 0, st, P, arena,
+                       L.big_begin, tf, x_perm);
+    const int nblk = (L.big_maxw + kWave - 1) / kWave;
+    for (int b = nblk - 1; b >= 0; --b)
+        hipLaunchKernelGGL(k_bwd_tiled_step<T>, dim3(b + 1, L.big_count), dim3(256), 0, st, P, arena, L.big_begin,
+                           tf, b, x_perm);
 }
 
 template bool launch_factor_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, int32_t*,

@@ -247,3 +247,66 @@ def test_dependency_driven_sweeps_match_level_sweeps(monkeypatch, precision):
         out[mode] = x1.cpu().numpy()
     a, c = out["0"], out["1"]
     assert np.abs(a - c).max() <= 1e-8 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("case,precision,tiled", [
+    ("pde20", "fp64", "1024"),
+    ("pde20", "fp64", "141"),
+    ("netflow4000_lds64", "fp64", "65"),
+    ("netflow4000_lds64", "fp32_ir", "65"),
+    ("netflow40k", "fp32_ir", "141"),
+])
+def test_tiled_sweeps_match_workgroup_sweeps(monkeypatch, case, precision, tiled):
+    """Fronts swept by the tiled kernels (many workgroups, one launch per
+    64-column block) and by one workgroup each apply the same factor: both
+    meet the gate, repeated applications are bitwise identical, and the two
+    agree to rounding.  pde20 has fronts up to 1507 rows (ragged last
+    blocks, rows below the own columns; with 141 every front above the LDS
+    limit is tiled); netflow4000 with a 64-row LDS limit tiles every front
+    from 65 rows on (one or two column blocks); netflow40k covers the FP32
+    factor on fronts up to 328 rows."""
+    if case == "pde20":
+        p, opts = workloads.pde_control(20), {}
+    elif case == "netflow40k":
+        p, opts = workloads.network_flow(40_000, seed=3, sigma_range=(-2, 2)), {}
+    else:
+        p, opts = workloads.network_flow(4000, seed=4, sigma_range=(-2, 2)), {"lds_front_max": 64}
+    print_case("tiled_sweeps", case=case, n=p.n, precision=precision, tiled=tiled)
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    out = {}
+    for mode in (tiled, "16000"):
+        monkeypatch.setenv("CKKT_TILED_SWEEP_FRONT", mode)
+        s = Solver(p, "lifted", precision, tol=tol, **opts).bind(DEV)
+        s.factorize(*device_values(p, DEV, "lifted"))
+        b = torch.as_tensor(p.b, device=DEV)
+        x1 = s.apply_inverse(b)
+        x2 = s.apply_inverse(b)
+        z, info = s.solve(b)
+        torch.cuda.synchronize()
+        assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+        om = omega_of(p, "lifted", z.cpu().numpy())
+        print(mode, info, "oracle omega", om)
+        assert om <= tol
+        out[mode] = x1.cpu().numpy()
+    # different summation orders, amplified by the conditioning of K
+    a, c = out[tiled], out["16000"]
+    assert np.all(np.isfinite(a)) and np.abs(a - c).max() <= 1e-6 * np.abs(a).max()
+
+
+def test_fp32_factor_overflow_falls_back_to_fp64():
+    """pde12's lifted matrix is beyond FP32 (its FP32 factor overflows to
+    non-finite values): the solve must see a non-finite residual, refactor
+    in FP64 and meet the gate, never report the non-finite iterate as
+    converged."""
+    p = workloads.pde_control(12)
+    print_case("fp32_overflow_fallback", n=p.n)
+    z, info = None, None
+    s = Solver(p, "lifted", "fp32_ir", tol=1e-8).bind(DEV)
+    s.factorize(*device_values(p, DEV, "lifted"))
+    z, info = s.solve(torch.as_tensor(p.b, device=DEV))
+    torch.cuda.synchronize()
+    z = z.cpu().numpy()
+    print(info)
+    assert info["fallback"] == 2
+    assert np.all(np.isfinite(z))
+    assert omega_of(p, "lifted", z) <= 1e-8
