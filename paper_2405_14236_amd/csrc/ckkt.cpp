@@ -58,6 +58,7 @@ struct Tune {
     int compact_threads = 256;        // workgroup size of the compact class otherwise
     int sweep_cutoff = 64;            // sweeps use 256 threads when a level's largest front exceeds this
     int tiled_front = kSweepTiledFront;  // fronts with at least this many rows use the tiled sweeps
+    int wide_front = kWideFront;         // FP64 levels with fronts this large use wide panels
 };
 
 struct ckkt_handle {
@@ -217,6 +218,7 @@ void build_levels(ckkt_handle* h) {
         L.tile_count = P.big_tiles_ptr[l + 1] - L.tile_begin;
         L.sweep_threads = L.all_maxf > T.sweep_cutoff ? 256 : 64;
         L.sweep_tiled_f = T.tiled_front;
+        L.wide_front = T.wide_front;
     }
 }
 
@@ -405,6 +407,12 @@ ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const Patte
     if (const char* tf = std::getenv("CKKT_TILED_SWEEP_FRONT")) {
         const int v = std::atoi(tf);
         if (v > 0) h->tune.tiled_front = std::min(std::max(v, ao.big_front + 1), kSweepMaxFront);
+    }
+    // CKKT_WIDE_FRONT moves the front size from which FP64 levels use
+    // wide panels (any value above the LDS front limit)
+    if (const char* wf = std::getenv("CKKT_WIDE_FRONT")) {
+        const int v = std::atoi(wf);
+        if (v > 0) h->tune.wide_front = std::max(v, ao.big_front + 1);
     }
     build_levels(h);
     if (!plan_fits_lds(h)) {

@@ -40,6 +40,7 @@ struct LevelInfo {
     int32_t small_threads_a;   // workgroup size of the compact small-front class
     int32_t sweep_threads;     // workgroup size of the sweep kernels on this level
     int32_t tile_begin, tile_count;
+    int32_t wide_front;         // FP64 levels whose largest big front reaches this use wide panels
     int32_t sweep_tiled_f;      // fronts with f >= this are swept by the tiled kernels
     int32_t sweep_small_count;  // fronts of the level swept one workgroup each (f < sweep_tiled_f)
 };
@@ -57,6 +58,12 @@ constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several w
 constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
 constexpr int kPanelRows = 256; // rows of the panel solved per workgroup
+// FP64 levels with fronts of at least kWideFront rows update their trailing
+// matrices once per kWideRank columns (rank-kWideRank MFMA updates)
+constexpr int kWideRank = 128;
+constexpr int kWideFront = 2048;
+constexpr int kWideTile = 64;  // trailing-matrix tile of the wide update
+static_assert(kWideRank % kPanelNB == 0, "a wide panel is a whole number of panels");
 // fronts with at least this many rows are swept by the tiled kernels (many
 // workgroups, one launch per 64-column block); every such front is in the
 // level's big list, whose fronts all exceed the LDS front limit

@@ -513,33 +513,79 @@ k_big_init(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int t
         }
     }
     __syncthreads();
+    // one wave per column; a child's column lands on distinct rows, so the
+    // eight entries of a batch are loaded, added and stored together
     const int lane = tid % kWave, wid = tid / kWave, nw = nt / kWave;
     for (int j = col0 + wid; j < col1; j += nw) {
+        T* Fj = F + (int64_t)j * f;
         const int q1 = P.cb_ptr[ro + j + 1];
         for (int q = P.cb_ptr[ro + j]; q < q1; ++q) {
             const int src = P.cb_src[q], len = P.cb_len[q];
             const T* Ucol = arena + P.cb_uoff[q];
             const int* rel = P.relmap + src;
-            for (int a = lane; a < len; a += kWave) F[rel[a] + (int64_t)j * f] += Ucol[a];
+            for (int a0 = 0; a0 < len; a0 += 8 * kWave) {
+                int r[8];
+                T u[8], fv[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const int a = a0 + v * kWave + lane;
+                    r[v] = a < len ? rel[a] : -1;
+                    u[v] = a < len ? Ucol[a] : T(0);
+                }
+#pragma unroll
+                for (int v = 0; v < 8; ++v) fv[v] = r[v] >= 0 ? Fj[r[v]] : T(0);
+#pragma unroll
+                for (int v = 0; v < 8; ++v)
+                    if (r[v] >= 0) Fj[r[v]] = fv[v] + u[v];
+            }
+        }
+    }
+}
+
+// Cholesky of the nb x nb (nb <= 32) lower triangle D (LDS, leading
+// dimension kPanelNB) by one wave, right-looking with the rows in
+// registers: lane i keeps row i; per column j the pivot comes from lane j,
+// the column is scaled and written back to LDS, and every lane subtracts
+// l_ij l_kj from its entries k > j, reading l_kj as LDS broadcasts (one
+// address for the whole wave).  The chain per column is a lane read, the
+// pivot's reciprocal square root and a multiply; the updates overlap it.
+template <typename T>
+__device__ __forceinline__ void potrf32_reg(T* D, int nb, int col0, int32_t* status, T* rdiag) {
+    const int lane = threadIdx.x % kWave;
+    const bool act = lane < nb;
+    T a[kPanelNB];
+#pragma unroll
+    for (int t = 0; t < kPanelNB; ++t) a[t] = (act && t <= lane && t < nb) ? D[lane + t * kPanelNB] : T(0);
+#pragma unroll
+    for (int j = 0; j < kPanelNB; ++j) {
+        if (j < nb) {
+            T r;
+            const T ljj = pivot_root<T>(bcast<T>(a[j], j), col0 + j, status, lane == j, r);
+            const T lij = lane == j ? ljj : a[j] * r;
+            if (act && lane >= j) D[lane + j * kPanelNB] = lij;
+            if (lane == j) rdiag[j] = r;
+#pragma unroll
+            for (int k = j + 1; k < kPanelNB; ++k)
+                if (k < nb) a[k] = fma(-lij, D[k + j * kPanelNB], a[k]);
         }
     }
 }
 
 // Large fronts, step 2 (per block column kb), grid (row chunk, front):
 // every workgroup stages the 32 x 32 diagonal block, one wave factors it
-// (the same arithmetic in every workgroup), and the workgroup solves its
-// chunk of kPanelRows rows below (one thread per row).  With one chunk the
-// factored block is written back in place; with several, chunk 0 leaves it
-// in dscr (another chunk may still be reading the original block) and the
-// trailing-update launch copies it into the front.
+// (the same arithmetic in every workgroup) while the workgroup's rows are
+// loaded, and each thread then solves its row of the chunk (kPanelRows
+// rows below the block) in registers, right-looking, with the factored
+// block read as LDS broadcasts.  With one chunk the factored block is
+// written back in place; with several, chunk 0 leaves it in dscr (another
+// chunk may still be reading the original block) and the trailing-update
+// launch copies it into the front.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status, T* __restrict__ dscr) {
-    // one buffer for both, so that the compiler keeps D in LDS instead of
-    // hoisting the whole block into registers across the row loop
-    __shared__ T buf[kPanelNB * kPanelNB + kPanelRows * kPanelNB];
-    T* D = buf;
-    T* R = buf + kPanelNB * kPanelNB;
+    static_assert(kPanelRows == 256, "one row per thread");
+    __shared__ T D[kPanelNB * kPanelNB];
+    __shared__ T s_rdiag[kPanelNB];
     const int s = P.lvl_big[list_begin + blockIdx.y];
     const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
     const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
@@ -550,34 +596,26 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
     const int r0 = kb + nb + blockIdx.x * kPanelRows;
     if (blockIdx.x > 0 && r0 >= f) return;
     const int nr = r0 < f ? min(kPanelRows, f - r0) : 0;
-    // issue the loads of the diagonal block and of this chunk's rows together
-    // (the rows do not depend on the block's factorization)
-    constexpr int kRPer = kPanelRows * kPanelNB / 256;
-    T t4[4], tr[kRPer];
+    // the diagonal block's loads and this thread's row are issued together
+    T t4[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int idx = u * nt + tid;
         const int i = idx % nb, j = idx / nb;
         t4[u] = (idx < nb * nb && i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
     }
+    const bool row = tid < nr;
+    T* Fr = F + (row ? r0 + tid : kb) + (int64_t)kb * f;
+    T x[kPanelNB];
 #pragma unroll
-    for (int u = 0; u < kRPer; ++u) {
-        const int idx = u * nt + tid;
-        tr[u] = idx < nr * nb ? F[(r0 + idx % nr) + (int64_t)(kb + idx / nr) * f] : T(0);
-    }
+    for (int t = 0; t < kPanelNB; ++t) x[t] = (row && t < nb) ? Fr[(int64_t)t * f] : T(0);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int idx = u * nt + tid;
         if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelNB] = t4[u];
     }
-#pragma unroll
-    for (int u = 0; u < kRPer; ++u) {
-        const int idx = u * nt + tid;
-        if (idx < nr * nb) R[idx % nr + (idx / nr) * kPanelRows] = tr[u];
-    }
     __syncthreads();
-    __shared__ T s_rdiag[kPanelNB];
-    if (tid < kWave) wave_potrf<T>(D, kPanelNB, nb, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
+    if (tid < kWave) potrf32_reg<T>(D, nb, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
     __syncthreads();
     if (blockIdx.x == 0) {
         T* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * kPanelNB * kPanelNB;
@@ -587,23 +625,31 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
             if (i >= j) dst[i + j * ld] = D[i + j * kPanelNB];
         }
     }
-    if (nr == 0) return;
-    rows_trsm<T>(R, kPanelRows, D, kPanelNB, nb, 0, nr, s_rdiag);
-    __syncthreads();
-    for (int idx = tid; idx < nr * nb; idx += nt) {
-        const int i = idx % nr, j = idx / nr;
-        F[(r0 + i) + (int64_t)(kb + j) * f] = R[i + j * kPanelRows];
+    if (!row) return;
+#pragma unroll
+    for (int j = 0; j < kPanelNB; ++j) {
+        if (j < nb) {
+            x[j] *= s_rdiag[j];
+#pragma unroll
+            for (int k = j + 1; k < kPanelNB; ++k)
+                if (k < nb) x[k] = fma(-x[j], D[k + j * kPanelNB], x[k]);
+        }
     }
+#pragma unroll
+    for (int t = 0; t < kPanelNB; ++t)
+        if (t < nb) Fr[(int64_t)t * f] = x[t];
 }
 
 // Large fronts, step 3: trailing update C -= P P^T of the lower triangle
 // below the panel, one 64 x 64 tile per workgroup (grid: tile row, tile
-// column, front).
+// column, front); only columns below col_end are updated (the rest of a
+// wide panel when the trailing part gets one wide update later).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* __restrict__ dscr, int copy_d) {
-    __shared__ T A[64][kPanelNB + 1];
-    __shared__ T B[64][kPanelNB + 1];
+k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* __restrict__ dscr, int copy_d,
+             int col_end) {
+    __shared__ T A[kPanelNB][64];  // panel column t of the tile's rows in A[t]
+    __shared__ T B[kPanelNB][64];
     const int s = P.lvl_big[list_begin + blockIdx.z];
     const int w = P.sn_start[s + 1] - P.sn_start[s];
     const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
@@ -623,9 +669,10 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
     const int nb = min(kPanelNB, w - kb);
     const int base = kb + nb;
     const int i0 = base + ti * 64, j0 = base + tj * 64;
-    if (i0 >= f) return;
+    if (i0 >= f || j0 >= col_end) return;
     T* F = arena + P.l_off[s];
     const int tid = threadIdx.x;
+    const int cmax = min(f, col_end);
     {
         constexpr int kPer = 64 * kPanelNB / 256;
         T ta[kPer], tb[kPer];
@@ -640,8 +687,8 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int idx = u * 256 + tid;
-            A[idx % 64][idx / 64] = ta[u];
-            B[idx % 64][idx / 64] = tb[u];
+            A[idx / 64][idx % 64] = ta[u];
+            B[idx / 64][idx % 64] = tb[u];
         }
     }
     __syncthreads();
@@ -659,9 +706,9 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
         for (int t = 0; t < nb; t += 4) {
             double av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = A[qi * 32 + a * 16 + li][t + lk];
+            for (int a = 0; a < 2; ++a) av[a] = A[t + lk][qi * 32 + a * 16 + li];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = B[qj * 32 + b * 16 + li][t + lk];
+            for (int b = 0; b < 2; ++b) bv[b] = B[t + lk][qj * 32 + b * 16 + li];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -674,7 +721,7 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = i0 + qi * 32 + a * 16 + 4 * r + lk, col = j0 + qj * 32 + b * 16 + li;
-                    if (row < f && col < f && row >= col) F[row + (int64_t)col * f] -= c[a][b][r];
+                    if (row < f && col < cmax && row >= col) F[row + (int64_t)col * f] -= c[a][b][r];
                 }
     } else {
         const int tx = tid % 16, ty = tid / 16;
@@ -686,9 +733,9 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
         for (int t = 0; t < nb; ++t) {
             T av[4], bv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = A[tx + 16 * a][t];
+            for (int a = 0; a < 4; ++a) av[a] = A[t][tx + 16 * a];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = B[ty + 16 * b][t];
+            for (int b = 0; b < 4; ++b) bv[b] = B[t][ty + 16 * b];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -700,10 +747,121 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 const int row = i0 + tx + 16 * a;
-                if (row < f && col < f && row >= col) F[row + (int64_t)col * f] -= acc[a][b];
+                if (row < f && col < cmax && row >= col) F[row + (int64_t)col * f] -= acc[a][b];
             }
         }
     }
+}
+
+// Large FP64 fronts, wide trailing update: C -= P P^T on the lower triangle
+// of the columns from kb + kWideRank on, P the (up to) kWideRank factored
+// columns from kb (rank-kWideRank instead of rank-kPanelNB updates, so the
+// trailing matrix is read and written a quarter as often).  One 64 x 64
+// tile per workgroup of four waves, each a 32 x 32 quadrant of 16 x 16
+// v_mfma_f64_16x16x4f64 tiles.  P's rows come through LDS in 32-column
+// chunks stored column by column (the sixteen lanes that read one MFMA
+// operand column touch sixteen consecutive doubles), the next chunk's loads
+// in flight during the current chunk's MFMAs; the tile's old values are
+// loaded first.  The lower-triangle tiles of a front are numbered column by
+// column (only tiles on or below the diagonal are launched).  Grid
+// (tiles, front), 256 threads.
+__global__ void __launch_bounds__(256)
+k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb, int nt, int ntri) {
+    constexpr int kT = kWideTile, kThreads = 256, kMA = 2, KC = kPanelNB;
+    __shared__ double A[KC][kT];
+    __shared__ double B[KC][kT];
+    const int s = P.lvl_big[list_begin + blockIdx.y];
+    const int w = P.sn_start[s + 1] - P.sn_start[s];
+    const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
+    if (kb >= w) return;
+    // lower-triangle tiles of a front with nt tile rows, column by column:
+    // column tj holds tiles (tj .. nt - 1, tj) and starts at
+    // S(tj) = tj nt - tj (tj - 1) / 2
+    const int lin = blockIdx.x;
+    if (lin >= ntri) return;
+    auto col_start = [&](int c) { return c * nt - c * (c - 1) / 2; };
+    const double q = 2.0 * nt + 1.0;
+    int tj = (int)((q - sqrt(q * q - 8.0 * lin)) * 0.5);
+    tj = max(0, min(tj, nt - 1));
+    while (tj > 0 && col_start(tj) > lin) --tj;
+    while (tj + 1 < nt && col_start(tj + 1) <= lin) ++tj;
+    const int ti = tj + (lin - col_start(tj));
+    const int base = kb + kWideRank;
+    const int i0 = base + ti * kT, j0 = base + tj * kT;
+    if (i0 >= f) return;
+    double* F = arena + P.l_off[s];
+    const int rank = min(kWideRank, w - kb);
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int qi = wv % 2, qj = wv / 2;  // rows qi * TILE / 2, columns qj * 32 of the tile
+    const bool idle = ti == tj && qj * 32 >= (qi + 1) * (kT / 2);  // block above the diagonal (wave-uniform)
+    const int li = lane % 16, lk = lane / 16;
+    // the tile's old values, loaded first so that their latency overlaps
+    // the MFMAs
+    double cv[kMA][2][4];
+#pragma unroll
+    for (int a = 0; a < kMA; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = i0 + qi * (kT / 2) + a * 16 + 4 * r + lk, col = j0 + qj * 32 + b * 16 + li;
+                cv[a][b][r] = (!idle && row < f && col < f && row >= col) ? F[row + (int64_t)col * f] : 0.0;
+            }
+    constexpr int kPer = kT * KC / kThreads;
+    double ta[kPer], tb[kPer];
+    auto load_chunk = [&](int t0) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int idx = u * kThreads + tid;
+            const int ii = idx % kT, t = idx / kT;
+            const int gi = i0 + ii, gj = j0 + ii;
+            const bool tin = t0 + t < rank;
+            ta[u] = (gi < f && tin) ? F[gi + (int64_t)(kb + t0 + t) * f] : 0.0;
+            tb[u] = (gj < f && tin) ? F[gj + (int64_t)(kb + t0 + t) * f] : 0.0;
+        }
+    };
+    load_chunk(0);
+    dbl4 c[kMA][2];
+#pragma unroll
+    for (int a = 0; a < kMA; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) c[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < rank; t0 += KC) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int idx = u * kThreads + tid;
+            A[idx / kT][idx % kT] = ta[u];
+            B[idx / kT][idx % kT] = tb[u];
+        }
+        __syncthreads();
+        if (t0 + KC < rank) load_chunk(t0 + KC);
+        const int kc = min(KC, rank - t0);
+        if (!idle) {
+            for (int t = 0; t < kc; t += 4) {
+                double av[kMA], bv[2];
+#pragma unroll
+                for (int a = 0; a < kMA; ++a) av[a] = A[t + lk][qi * (kT / 2) + a * 16 + li];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bv[b] = B[t + lk][qj * 32 + b * 16 + li];
+#pragma unroll
+                for (int a = 0; a < kMA; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], c[a][b], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    if (idle) return;
+#pragma unroll
+    for (int a = 0; a < kMA; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = i0 + qi * (kT / 2) + a * 16 + 4 * r + lk, col = j0 + qj * 32 + b * 16 + li;
+                if (row < f && col < f && row >= col) F[row + (int64_t)col * f] = cv[a][b][r] - c[a][b][r];
+            }
 }
 
 // ---------------------------------------------------------------- sweeps
@@ -1657,16 +1815,37 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         const bool lds_tile = tile_bytes + 1024 <= (size_t)kLdsBytes;
         hipLaunchKernelGGL(k_big_init<T>, dim3(L.tile_count), dim3(256), lds_tile ? tile_bytes : 0, sb, P, K, arena,
                            L.tile_begin, scale, lds_tile ? L.big_maxf : 0);
-        for (int kb = 0; kb < L.big_maxw; kb += kPanelNB) {
-            const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
-            const int chunks = below > 0 ? (below + kPanelRows - 1) / kPanelRows : 1;
-            hipLaunchKernelGGL(k_big_panel<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena, L.big_begin,
-                               kb, status, reinterpret_cast<T*>(dscr));
-            int rest = L.big_maxf - kb - 1;  // upper bound of trailing rows
-            int tiles = rest > 0 ? (rest + 63) / 64 : 0;
-            if (tiles > 0)
-                hipLaunchKernelGGL(k_big_update<T>, dim3(tiles, tiles, L.big_count), dim3(256), 0, sb, P,
-                                   arena, L.big_begin, kb, reinterpret_cast<const T*>(dscr), chunks > 1 ? 1 : 0);
+        // FP64 levels with large fronts: panels of kWideRank columns, each
+        // factored as kPanelNB-column panels whose updates stop at the wide
+        // panel's end, then one rank-kWideRank update of the trailing part
+        const bool wide = sizeof(T) == 8 && L.big_maxf >= L.wide_front;
+        const int step = wide ? kWideRank : kPanelNB;
+        for (int kw = 0; kw < L.big_maxw; kw += step) {
+            for (int kb = kw; kb < std::min(kw + step, L.big_maxw); kb += kPanelNB) {
+                const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
+                const int chunks = below > 0 ? (below + kPanelRows - 1) / kPanelRows : 1;
+                hipLaunchKernelGGL(k_big_panel<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena,
+                                   L.big_begin, kb, status, reinterpret_cast<T*>(dscr));
+                // in a wide panel the update stops at the panel's end (after
+                // its last panel it only reaches fronts whose own columns end
+                // inside the wide panel, for their columns up to its end)
+                const int col_end = wide ? kw + step : INT_MAX;
+                const int rest = L.big_maxf - kb - 1;  // upper bound of trailing rows
+                const int tiles = rest > 0 ? (rest + 63) / 64 : 0;
+                // columns: at most up to col_end (a front whose last panel is
+                // narrower starts its trailing part up to kPanelNB - 1 earlier)
+                const int tcols = wide ? std::min(tiles, (kw + step - kb) / 64 + 1) : tiles;
+                if (tiles > 0)
+                    hipLaunchKernelGGL(k_big_update<T>, dim3(tiles, tcols, L.big_count), dim3(256), 0, sb, P,
+                                       arena, L.big_begin, kb, reinterpret_cast<const T*>(dscr), chunks > 1 ? 1 : 0,
+                                       col_end);
+            }
+            if (!wide) continue;
+            const int rest = L.big_maxf - kw - step;  // upper bound of trailing rows
+            if (rest <= 0) continue;
+            const int t64 = (rest + kWideTile - 1) / kWideTile, ntri = t64 * (t64 + 1) / 2;
+            hipLaunchKernelGGL(k_big_update_wide, dim3(ntri, L.big_count), dim3(256), 0, sb, P,
+                               reinterpret_cast<double*>(arena), L.big_begin, kw, t64, ntri);
         }
     }
     if (L.small_count > 0) {

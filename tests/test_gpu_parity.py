@@ -310,3 +310,40 @@ def test_fp32_factor_overflow_falls_back_to_fp64():
     assert info["fallback"] == 2
     assert np.all(np.isfinite(z))
     assert omega_of(p, "lifted", z) <= 1e-8
+
+
+@pytest.mark.parametrize("case,wide", [("pde20", "141"), ("pde20", "2048"), ("netflow4000_lds64", "65")])
+def test_wide_panels_match_narrow_panels(monkeypatch, case, wide):
+    """FP64 levels factored with wide panels (kPanelNB-column panels whose
+    updates stop at the wide panel's end, then one rank-128 MFMA update of
+    the trailing matrix) give the factor of the rank-32 schedule: both meet
+    the gate and their solutions agree to rounding.  pde20 with 141 puts
+    every level with a front above the LDS limit on wide panels (fronts
+    whose own columns end inside a wide panel, several row chunks); with
+    2048 no level qualifies (the two runs must then be bitwise equal);
+    netflow4000 with a 64-row LDS limit has fronts narrower than one wide
+    panel."""
+    if case == "pde20":
+        p, opts = workloads.pde_control(20), {}
+    else:
+        p, opts = workloads.network_flow(4000, seed=4, sigma_range=(-2, 2)), {"lds_front_max": 64}
+    print_case("wide_panels", case=case, n=p.n, wide=wide)
+    out = {}
+    for mode in (wide, "100000"):
+        monkeypatch.setenv("CKKT_WIDE_FRONT", mode)
+        s = Solver(p, "lifted", "fp64").bind(DEV)
+        s.factorize(*device_values(p, DEV, "lifted"))
+        assert s.factor_status() == 0
+        b = torch.as_tensor(p.b, device=DEV)
+        x = s.apply_inverse(b)
+        z, info = s.solve(b)
+        torch.cuda.synchronize()
+        om = omega_of(p, "lifted", z.cpu().numpy())
+        print(mode, info, "oracle omega", om)
+        assert om <= 1e-10
+        out[mode] = x.cpu().numpy()
+    a, c = out[wide], out["100000"]
+    if wide == "2048":
+        assert np.array_equal(a, c)
+    else:
+        assert np.all(np.isfinite(a)) and np.abs(a - c).max() <= 1e-6 * np.abs(a).max()
