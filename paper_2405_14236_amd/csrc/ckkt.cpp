@@ -59,6 +59,7 @@ struct Tune {
     int sweep_cutoff = 64;            // sweeps use 256 threads when a level's largest front exceeds this
     int tiled_front = kSweepTiledFront;  // fronts with at least this many rows use the tiled sweeps
     int wide_front = kWideFront;         // FP64 levels with fronts this large use wide panels
+    int lookahead = 0;                   // overlap wide trailing updates with the next panel (opt-in)
 };
 
 struct ckkt_handle {
@@ -177,6 +178,14 @@ struct PhaseTimer {
     }
 };
 
+void destroy_side(SideStream& sd) {
+    if (sd.stream) (void)hipStreamDestroy(sd.stream);
+    if (sd.ahead) (void)hipStreamDestroy(sd.ahead);
+    for (hipEvent_t e : {sd.fork, sd.join, sd.panel_done, sd.rest_done[0], sd.rest_done[1]})
+        if (e) (void)hipEventDestroy(e);
+    sd = SideStream{};
+}
+
 void build_levels(ckkt_handle* h) {
     const Plan& P = h->plan;
     const Tune& T = h->tune;
@@ -219,6 +228,7 @@ void build_levels(ckkt_handle* h) {
         L.sweep_threads = L.all_maxf > T.sweep_cutoff ? 256 : 64;
         L.sweep_tiled_f = T.tiled_front;
         L.wide_front = T.wide_front;
+        L.lookahead = T.lookahead;
     }
 }
 
@@ -414,6 +424,11 @@ ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const Patte
         const int v = std::atoi(wf);
         if (v > 0) h->tune.wide_front = std::max(v, ao.big_front + 1);
     }
+    // CKKT_LOOKAHEAD=1 runs the trailing update of a wide panel beyond the
+    // next wide panel on a second stream (off by default: its first run in a
+    // captured graph ended the process with a host segmentation fault whose
+    // cause is not established)
+    if (const char* la = std::getenv("CKKT_LOOKAHEAD")) h->tune.lookahead = la[0] == '1';
     build_levels(h);
     if (!plan_fits_lds(h)) {
         delete h;
@@ -1061,10 +1076,15 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
         if (hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess) h->capture_stream = nullptr;
     }
     if (!h->side.stream) {
-        if (hipStreamCreateWithFlags(&h->side.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming) != hipSuccess) {
-            h->side = SideStream{};
+        SideStream& sd = h->side;
+        if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess ||
+            hipStreamCreateWithFlags(&sd.ahead, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sd.panel_done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sd.rest_done[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sd.rest_done[1], hipEventDisableTiming) != hipSuccess) {
+            destroy_side(sd);
             (void)hipGetLastError();
         }
     }
@@ -1490,9 +1510,7 @@ void ckkt_destroy(ckkt_handle* h) {
     for (auto& g : h->graphs)
         if (g) (void)hipGraphExecDestroy(g);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
-    if (h->side.stream) (void)hipStreamDestroy(h->side.stream);
-    if (h->side.fork) (void)hipEventDestroy(h->side.fork);
-    if (h->side.join) (void)hipEventDestroy(h->side.join);
+    destroy_side(h->side);
     if (h->host) (void)hipHostFree(h->host);
     delete h;
 }

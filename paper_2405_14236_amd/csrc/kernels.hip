@@ -763,10 +763,10 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
 // operand column touch sixteen consecutive doubles), the next chunk's loads
 // in flight during the current chunk's MFMAs; the tile's old values are
 // loaded first.  The lower-triangle tiles of a front are numbered column by
-// column (only tiles on or below the diagonal are launched).  Grid
-// (tiles, front), 256 threads.
+// column and a launch takes the tiles [lin0, lin1) (a run of whole tile
+// columns).  Grid (lin1 - lin0, front), 256 threads.
 __global__ void __launch_bounds__(256)
-k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb, int nt, int ntri) {
+k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb, int nt, int lin0, int lin1) {
     constexpr int kT = kWideTile, kThreads = 256, kMA = 2, KC = kPanelNB;
     __shared__ double A[KC][kT];
     __shared__ double B[KC][kT];
@@ -777,8 +777,8 @@ k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
     // lower-triangle tiles of a front with nt tile rows, column by column:
     // column tj holds tiles (tj .. nt - 1, tj) and starts at
     // S(tj) = tj nt - tj (tj - 1) / 2
-    const int lin = blockIdx.x;
-    if (lin >= ntri) return;
+    const int lin = lin0 + blockIdx.x;
+    if (lin >= lin1) return;
     auto col_start = [&](int c) { return c * nt - c * (c - 1) / 2; };
     const double q = 2.0 * nt + 1.0;
     int tj = (int)((q - sqrt(q * q - 8.0 * lin)) * 0.5);
@@ -1820,6 +1820,9 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         // panel's end, then one rank-kWideRank update of the trailing part
         const bool wide = sizeof(T) == 8 && L.big_maxf >= L.wide_front;
         const int step = wide ? kWideRank : kPanelNB;
+        const bool ahead = wide && side && side->ahead && L.lookahead;
+        bool pending = false;  // a look-ahead update still to be joined
+        int slot = 0;          // rest_done[slot ^ 1] marks the pending one
         for (int kw = 0; kw < L.big_maxw; kw += step) {
             for (int kb = kw; kb < std::min(kw + step, L.big_maxw); kb += kPanelNB) {
                 const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
@@ -1843,10 +1846,31 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
             if (!wide) continue;
             const int rest = L.big_maxf - kw - step;  // upper bound of trailing rows
             if (rest <= 0) continue;
-            const int t64 = (rest + kWideTile - 1) / kWideTile, ntri = t64 * (t64 + 1) / 2;
-            hipLaunchKernelGGL(k_big_update_wide, dim3(ntri, L.big_count), dim3(256), 0, sb, P,
-                               reinterpret_cast<double*>(arena), L.big_begin, kw, t64, ntri);
+            const int nt = (rest + kWideTile - 1) / kWideTile, ntri = nt * (nt + 1) / 2;
+            // tile columns 0 and 1 are the next wide panel's columns
+            const int split = nt > 2 ? 2 * nt - 1 : ntri;
+            if (ahead && split < ntri) {
+                // the rest runs ahead, once this wide panel is factored; the
+                // next panel's columns wait for the rest of the previous step
+                // (it updates them too)
+                (void)hipEventRecord(side->panel_done, sb);
+                (void)hipStreamWaitEvent(side->ahead, side->panel_done, 0);
+                hipLaunchKernelGGL(k_big_update_wide, dim3(ntri - split, L.big_count), dim3(256), 0, side->ahead, P,
+                                   reinterpret_cast<double*>(arena), L.big_begin, kw, nt, split, ntri);
+                (void)hipEventRecord(side->rest_done[slot], side->ahead);
+                if (pending) (void)hipStreamWaitEvent(sb, side->rest_done[slot ^ 1], 0);
+                hipLaunchKernelGGL(k_big_update_wide, dim3(split, L.big_count), dim3(256), 0, sb, P,
+                                   reinterpret_cast<double*>(arena), L.big_begin, kw, nt, 0, split);
+                pending = true;
+                slot ^= 1;
+            } else {
+                if (pending) (void)hipStreamWaitEvent(sb, side->rest_done[slot ^ 1], 0);
+                pending = false;
+                hipLaunchKernelGGL(k_big_update_wide, dim3(ntri, L.big_count), dim3(256), 0, sb, P,
+                                   reinterpret_cast<double*>(arena), L.big_begin, kw, nt, 0, ntri);
+            }
         }
+        if (pending) (void)hipStreamWaitEvent(sb, side->rest_done[slot ^ 1], 0);
     }
     if (L.small_count > 0) {
         // two LDS size classes so that small fronts keep several workgroups
