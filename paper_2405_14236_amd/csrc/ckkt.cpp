@@ -80,6 +80,11 @@ struct ckkt_handle {
         r_instvar, r_insteq, r_kcol, r_cbptr, r_cbsrc, r_cblen, r_cbuoff;
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
     Region r_ctl, r_done;  // dependency-driven sweeps: control words, per-supernode flags
+    Region r_tflag;        // block flags of the tiled fronts (one launch per level)
+    int64_t n_tflags = 0;
+    unsigned* tflag = nullptr;
+    bool tiled_level = true;              // tiled fronts swept in one launch per level
+    unsigned long long wait_ticks = 0;    // wait limit of the flag waits in wall-clock ticks
     Region r_dscr;         // factored diagonal blocks of tiled fronts between launches
     std::vector<Region> r_vn, r_vm, r_veq;  // scratch vectors of length n, m, m_eq
     // learned preconditioner (opt.learned)
@@ -190,6 +195,7 @@ void build_levels(ckkt_handle* h) {
     const Plan& P = h->plan;
     const Tune& T = h->tune;
     h->levels.assign(P.nlev, LevelInfo{});
+    h->n_tflags = 0;
     auto front = [&](int s) { return P.sn_rowptr[s + 1] - P.sn_rowptr[s]; };
     auto width = [&](int s) { return P.sn_start[s + 1] - P.sn_start[s]; };
     for (int l = 0; l < P.nlev; ++l) {
@@ -229,6 +235,9 @@ void build_levels(ckkt_handle* h) {
         L.sweep_tiled_f = T.tiled_front;
         L.wide_front = T.wide_front;
         L.lookahead = T.lookahead;
+        L.tflag_off = h->n_tflags;
+        if (L.big_count > 0 && L.big_maxf >= L.sweep_tiled_f)
+            h->n_tflags += L.big_count * ((L.big_maxw + 63) / 64);
     }
 }
 
@@ -303,6 +312,7 @@ void build_layout(ckkt_handle* h) {
     h->r_vperm = L.add(n * sizeof(double));
     h->r_status = L.add(4 * sizeof(int32_t));
     h->r_ctl = L.add(kSweepCtlWords * sizeof(unsigned));
+    h->r_tflag = L.add(std::max<size_t>((size_t)h->n_tflags * sizeof(unsigned), 8));
     h->r_done = L.add(std::max<size_t>(P.ns, 1) * sizeof(unsigned));
     {
         int maxbig = 1;
@@ -376,6 +386,7 @@ void fill_devplan(ckkt_handle* h) {
     h->vperm = at<double>(h, h->r_vperm);
     h->status = at<int32_t>(h, h->r_status);
     h->ctl = at<unsigned>(h, h->r_ctl);
+    h->tflag = at<unsigned>(h, h->r_tflag);
     h->done = at<unsigned>(h, h->r_done);
     h->dscr = at<double>(h, h->r_dscr);
     h->bits = at<unsigned long long>(h, h->r_bits);
@@ -537,8 +548,19 @@ void sweep_levels(ckkt_handle* h, hipStream_t st) {
         launch_bwd_sched<T>(h->dp, h->sched, arena, h->vperm, h->ctl, h->done, h->status + 2, st);
         return;
     }
-    for (size_t l = 0; l < h->levels.size(); ++l) launch_fwd_level<T>(h->dp, h->levels[l], arena, h->vperm, h->uvec, st);
-    for (size_t l = h->levels.size(); l-- > 0;) launch_bwd_level<T>(h->dp, h->levels[l], arena, h->vperm, st);
+    TiledSync ts;
+    const TiledSync* tsp = nullptr;
+    if (h->tiled_level && h->n_tflags > 0) {
+        launch_sweep_prep(h->ctl, st);  // advances the epoch the flags are compared with
+        ts.ctl = h->ctl;
+        ts.flags = h->tflag;
+        ts.err = h->status + 2;
+        ts.ticks = h->wait_ticks;
+        tsp = &ts;
+    }
+    for (size_t l = 0; l < h->levels.size(); ++l)
+        launch_fwd_level<T>(h->dp, h->levels[l], arena, h->vperm, h->uvec, st, tsp);
+    for (size_t l = h->levels.size(); l-- > 0;) launch_bwd_level<T>(h->dp, h->levels[l], arena, h->vperm, st, tsp);
 }
 
 // Capture a launch sequence once on the private stream; replay it on `st`.
@@ -1100,6 +1122,17 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
     // sweep flags start below every epoch the sweeps will use
     HIP_TRY(hipMemsetAsync(h->ws + h->r_ctl.off, 0, h->r_ctl.bytes, st));
     HIP_TRY(hipMemsetAsync(h->ws + h->r_done.off, 0, h->r_done.bytes, st));
+    HIP_TRY(hipMemsetAsync(h->ws + h->r_tflag.off, 0, h->r_tflag.bytes, st));
+    {
+        // tiled fronts swept in one launch per level (CKKT_TILED_LEVEL=0:
+        // one launch per column block), with flag waits bounded in time
+        int dev = 0, khz = 0;
+        const char* tl = std::getenv("CKKT_TILED_LEVEL");
+        h->tiled_level = !(tl && tl[0] == '0') && hipGetDevice(&dev) == hipSuccess &&
+                         hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0;
+        (void)hipGetLastError();
+        h->wait_ticks = (unsigned long long)std::max(khz, 1) * 1000ull * kSweepWaitSeconds;
+    }
     HIP_TRY(hipMemsetAsync(h->ws + h->r_status.off, 0, h->r_status.bytes, st));
     HIP_TRY(hipStreamSynchronize(st));
     fill_devplan(h);

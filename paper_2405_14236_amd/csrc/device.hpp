@@ -44,6 +44,7 @@ struct LevelInfo {
     int32_t lookahead;          // wide panels overlap the trailing update with the next panel
     int32_t sweep_tiled_f;      // fronts with f >= this are swept by the tiled kernels
     int32_t sweep_small_count;  // fronts of the level swept one workgroup each (f < sweep_tiled_f)
+    int32_t tflag_off;          // first block flag of the level's tiled fronts
 };
 
 constexpr int kBigTile = 64;    // column tile of the tiled front path
@@ -96,12 +97,20 @@ template <typename T>
 bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
                          int32_t* status, const double* scale, hipStream_t st, const SideStream* side,
                          double* dscr);
+// Completion flags of the tiled fronts' blocks when a level's tiled fronts
+// are swept in one launch (null: one launch per column block).
+struct TiledSync {
+    const unsigned* ctl = nullptr;   // ctl[kCtlEpoch]: application counter
+    unsigned* flags = nullptr;       // per level at LevelInfo::tflag_off, big_count x blocks
+    int32_t* err = nullptr;          // set to 1 when a wait times out
+    unsigned long long ticks = 0;    // wait limit in wall-clock ticks
+};
 template <typename T>
 void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* v_perm,
-                      double* uvec, hipStream_t st);
+                      double* uvec, hipStream_t st, const TiledSync* ts);
 template <typename T>
 void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* x_perm,
-                      hipStream_t st);
+                      hipStream_t st, const TiledSync* ts);
 
 // Dependency-driven sweeps: the supernodes lvl_all[0, wave_t1) (whole
 // levels below wave_lvl, every front of order <= 64) are processed by

@@ -1761,6 +1761,156 @@ __global__ void k_axpy_dev(int n, const double* __restrict__ sc, int idx, double
 
 inline int nblk(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 
+// ---------------------------------------------------------------- tiled sweeps in one launch per level
+//
+// The same arithmetic as the block-by-block launches of the tiled fronts
+// (every row and column receives the same updates in the same order, so
+// the results are bitwise equal), in one launch per level: each workgroup
+// owns 64 rows (forward) or 64 columns (backward) of one front and waits,
+// block by block, on per-block flags raised by the workgroups that solved
+// those blocks; the block's panel tile is loaded before the wait.  A
+// workgroup only waits on blocks owned by workgroups dispatched before it
+// (the front index varies fastest in the grid, then the tile), so the
+// launch makes progress whatever the number of resident workgroups.  The
+// flags hold the sweep's epoch (2 e + 1 forward, 2 e + 2 backward, e the
+// application counter), so they are never reset; every wait is bounded
+// (wait_flag) and a timeout is reported in *err.
+
+// Forward: workgroup (front, t) takes rows [64 t, 64 t + 64).  Grid
+// (big list, ceil(maxf / 64)), 256 threads.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fwd_tiled_level(DevPlan P, const T* __restrict__ arena, int list_begin, int min_f, double* __restrict__ v_perm,
+                  double* __restrict__ uvec, const unsigned* ctl, unsigned* flags, int nblk_lvl, int32_t* err,
+                  unsigned long long ticks) {
+    __shared__ double D[kWave * kWave];
+    __shared__ double yb[kWave];
+    __shared__ double red[4][kWave];
+    const int s = P.lvl_big[list_begin + blockIdx.x];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    const int t = blockIdx.y, r0 = t * kWave;
+    if (f < min_f || r0 >= f) return;
+    const int nblk = (w + kWave - 1) / kWave;
+    const unsigned want = 2u * ctl[kCtlEpoch] + 1u;
+    unsigned* fl = flags + (size_t)blockIdx.x * nblk_lvl;
+    const T* L = arena + P.l_off[s];
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, k0 = wid * 16;
+    const int i = r0 + lane;
+    const bool row = i < f;
+    const bool diag = t < nblk;
+    const int nb = diag ? min(kWave, w - r0) : 0;
+    if (diag) stage_diag_block(L + r0 + (int64_t)r0 * f, f, nb, D, kWave);
+    double vi = 0.0;
+    if (wid == 0 && row) vi = (i < w) ? v_perm[c0 + i] : uvec[ro + i];
+    // contribution of solved block j to this workgroup's rows
+    auto apply = [&](int j) {
+        const int pk = j * kWave, pnb = min(kWave, w - pk);
+        const T* Li = L + (row ? i : r0) + (int64_t)(pk + k0) * f;
+        double l[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) l[u] = (row && k0 + u < pnb) ? (double)Li[(int64_t)u * f] : 0.0;
+        if (tid == 0) wait_flag(&fl[j], want, err, ticks);
+        __syncthreads();
+        acquire_device();
+        if (tid < pnb) yb[tid] = v_perm[c0 + pk + tid];
+        __syncthreads();
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = fma(l[u], (k0 + u < pnb) ? yb[k0 + u] : 0.0, acc);
+        red[wid][lane] = acc;
+        __syncthreads();
+        return (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+    };
+    const int J = min(t, nblk);
+    for (int j = 0; j < J; ++j) {
+        const double sub = apply(j);
+        if (wid == 0 && row) vi -= sub;
+    }
+    if (!diag) {
+        if (wid == 0 && row) uvec[ro + i] = vi;
+        return;
+    }
+    __syncthreads();  // D staged
+    if (wid == 0) {
+#pragma unroll 4
+        for (int k = 0; k < nb; ++k) {
+            const double yk = lane_bcast(vi, k) * D[k + k * kWave];
+            if (lane == k) vi = yk;
+            else if (lane > k && lane < nb) vi = fma(-D[lane + k * kWave], yk, vi);
+        }
+        if (lane < nb) v_perm[c0 + i] = vi;
+        release_device();
+        if (lane == 0) flag_store(&fl[t], want);
+    }
+    if (r0 + nb < min(f, r0 + kWave)) {
+        // rows below the own columns in the last diagonal tile take this
+        // block's update too (its flag is already raised, so the wait in
+        // apply returns at once)
+        const double sub = apply(t);
+        if (wid == 0 && row && lane >= nb) uvec[ro + i] = vi - sub;
+    }
+}
+
+// Backward: workgroup (front, y) takes column tile t = nblk - 1 - y (the
+// last blocks first).  Grid (big list, max blocks), 256 threads.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bwd_tiled_level(DevPlan P, const T* __restrict__ arena, int list_begin, int min_f, double* __restrict__ x_perm,
+                  const unsigned* ctl, unsigned* flags, int nblk_lvl, int32_t* err, unsigned long long ticks) {
+    __shared__ double D[kWave * kWave];
+    __shared__ double S[kWave * (kWave + 1)];
+    __shared__ double tb[kWave];
+    const int s = P.lvl_big[list_begin + blockIdx.x];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
+    const int nblk = (w + kWave - 1) / kWave;
+    const int t = nblk - 1 - (int)blockIdx.y;
+    if (f < min_f || t < 0) return;
+    const unsigned want = 2u * ctl[kCtlEpoch] + 2u;
+    unsigned* fl = flags + (size_t)blockIdx.x * nblk_lvl;
+    const T* L = arena + P.l_off[s];
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, k0 = wid * 16;
+    const int ct = t * kWave, tnb = min(kWave, w - ct);
+    stage_diag_block(L + ct + (int64_t)ct * f, f, tnb, D, kWave);
+    double z = (wid == 0 && lane < tnb) ? x_perm[c0 + ct + lane] : 0.0;
+    for (int b = nblk - 1; b > t; --b) {
+        const int q = b * kWave, qnb = min(kWave, w - q);
+        const bool r = lane < qnb;
+        const T* Lr = L + (r ? q + lane : q) + (int64_t)(ct + k0) * f;
+        double l[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) l[u] = (r && k0 + u < tnb) ? (double)Lr[(int64_t)u * f] : 0.0;
+        if (tid == 0) wait_flag(&fl[b], want, err, ticks);
+        __syncthreads();
+        acquire_device();
+        const double xr = r ? x_perm[c0 + q + lane] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) S[(k0 + u) * (kWave + 1) + lane] = l[u] * xr;
+        __syncthreads();
+        const int c = tid >> 2, rq = tid & 3;
+        double sum = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sum += S[c * (kWave + 1) + rq * 16 + u];
+        sum += __shfl_xor(sum, 1, kWave);
+        sum += __shfl_xor(sum, 2, kWave);
+        if (rq == 0) tb[c] = sum;
+        __syncthreads();
+        if (wid == 0 && lane < tnb) z -= tb[lane];
+    }
+    __syncthreads();  // D staged
+    if (wid != 0) return;
+#pragma unroll 4
+    for (int k = tnb - 1; k >= 0; --k) {
+        const double xk = lane_bcast(z, k) * D[k + k * kWave];
+        if (lane == k) z = xk;
+        else if (lane < k) z = fma(-D[k + lane * kWave], xk, z);
+    }
+    if (lane < tnb) x_perm[c0 + ct + lane] = z;
+    release_device();
+    if (lane == 0) flag_store(&fl[t], want);
+}
+
 }  // namespace
 
 // ================================================================ launchers
@@ -1905,7 +2055,7 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
 
 template <typename T>
 void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* v_perm,
-                      double* uvec, hipStream_t st) {
+                      double* uvec, hipStream_t st, const TiledSync* ts) {
     if (L.all_count == 0) return;
     if (L.all_maxf <= kWave) {
         hipLaunchKernelGGL(k_fwd_waves<T>, dim3((L.all_count + 3) / 4), dim3(256), 0, st, P, arena, L.all_begin,
@@ -1926,6 +2076,12 @@ void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
     hipLaunchKernelGGL(k_fwd_tiled_gather, dim3((L.big_maxf + 255) / 256, L.big_count), dim3(256), 0, st, P,
                        L.big_begin, tf, v_perm, uvec);
     const int nblk = (L.big_maxw + kWave - 1) / kWave;
+    if (ts) {
+        hipLaunchKernelGGL(k_fwd_tiled_level<T>, dim3(L.big_count, (L.big_maxf + kWave - 1) / kWave), dim3(256), 0,
+                           st, P, arena, L.big_begin, tf, v_perm, uvec, ts->ctl, ts->flags + L.tflag_off, nblk,
+                           ts->err, ts->ticks);
+        return;
+    }
     for (int j = 0; j <= nblk; ++j) {
         const int rows = L.big_maxf - std::max(0, (j - 1) * kWave);
         hipLaunchKernelGGL(k_fwd_tiled_step<T>, dim3((rows + kWave - 1) / kWave, L.big_count), dim3(256), 0, st,
@@ -1935,7 +2091,7 @@ void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
 
 template <typename T>
 void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, double* x_perm,
-                      hipStream_t st) {
+                      hipStream_t st, const TiledSync* ts) {
     if (L.all_count == 0) return;
     if (L.all_maxf <= kWave) {
         hipLaunchKernelGGL(k_bwd_waves<T>, dim3((L.all_count + 3) / 4), dim3(256), 0, st, P, arena, L.all_begin,
@@ -1956,6 +2112,11 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
     hipLaunchKernelGGL(k_bwd_tiled_rect<T>, dim3((L.big_maxw + 7) / 8, L.big_count), dim3(256), 0, st, P, arena,
                        L.big_begin, tf, x_perm);
     const int nblk = (L.big_maxw + kWave - 1) / kWave;
+    if (ts) {
+        hipLaunchKernelGGL(k_bwd_tiled_level<T>, dim3(L.big_count, nblk), dim3(256), 0, st, P, arena, L.big_begin,
+                           tf, x_perm, ts->ctl, ts->flags + L.tflag_off, nblk, ts->err, ts->ticks);
+        return;
+    }
     for (int b = nblk - 1; b >= 0; --b)
         hipLaunchKernelGGL(k_bwd_tiled_step<T>, dim3(b + 1, L.big_count), dim3(256), 0, st, P, arena, L.big_begin,
                            tf, b, x_perm);
@@ -1966,11 +2127,13 @@ template bool launch_factor_level<double>(const DevPlan&, const LevelInfo&, cons
 template bool launch_factor_level<float>(const DevPlan&, const LevelInfo&, const double*, float*, int32_t*,
                                          const double*, hipStream_t, const SideStream*, double*);
 template void launch_fwd_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, double*,
-                                       hipStream_t);
+                                       hipStream_t, const TiledSync*);
 template void launch_fwd_level<float>(const DevPlan&, const LevelInfo&, const float*, double*, double*,
-                                      hipStream_t);
-template void launch_bwd_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, hipStream_t);
-template void launch_bwd_level<float>(const DevPlan&, const LevelInfo&, const float*, double*, hipStream_t);
+                                      hipStream_t, const TiledSync*);
+template void launch_bwd_level<double>(const DevPlan&, const LevelInfo&, const double*, double*, hipStream_t,
+                                       const TiledSync*);
+template void launch_bwd_level<float>(const DevPlan&, const LevelInfo&, const float*, double*, hipStream_t,
+                                      const TiledSync*);
 
 namespace {
 template <typename T>

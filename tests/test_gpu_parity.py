@@ -381,3 +381,39 @@ def test_lookahead_wide_panels_bitwise(monkeypatch):
     ref = out[("1", "0")]
     for k, v in out.items():
         assert np.array_equal(v, ref), k
+
+
+@pytest.mark.parametrize("case,precision,tiled", [
+    ("pde20", "fp64", "1024"),
+    ("pde20", "fp64", "141"),
+    ("netflow4000_lds64", "fp32_ir", "65"),
+])
+def test_tiled_level_launch_bitwise(monkeypatch, case, precision, tiled):
+    """Tiled fronts swept in one launch per level (workgroups waiting on
+    per-block flags) apply exactly the arithmetic of one launch per column
+    block: bitwise equal results, over several applications (the flags'
+    epoch advances), in a captured graph and with direct launches."""
+    if case == "pde20":
+        p, opts = workloads.pde_control(20), {}
+    else:
+        p, opts = workloads.network_flow(4000, seed=4, sigma_range=(-2, 2)), {"lds_front_max": 64}
+    print_case("tiled_level", case=case, precision=precision, tiled=tiled)
+    monkeypatch.setenv("CKKT_TILED_SWEEP_FRONT", tiled)
+    out = {}
+    for graph in ("0", "1"):
+        monkeypatch.setenv("CKKT_NO_GRAPH", graph)
+        for mode in ("0", "1"):
+            monkeypatch.setenv("CKKT_TILED_LEVEL", mode)
+            s = Solver(p, "lifted", precision, **opts).bind(DEV)
+            s.factorize(*device_values(p, DEV, "lifted"))
+            b = torch.as_tensor(p.b, device=DEV)
+            xs = [s.apply_inverse(b).cpu().numpy() for _ in range(3)]
+            _, info = s.solve(b)
+            assert info["status"] == 0
+            for x in xs[1:]:
+                assert np.array_equal(x, xs[0])
+            out[(graph, mode)] = xs[0]
+    ref = out[("1", "0")]
+    assert np.all(np.isfinite(ref))
+    for k, v in out.items():
+        assert np.array_equal(v, ref), k
