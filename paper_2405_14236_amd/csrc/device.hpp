@@ -60,6 +60,7 @@ constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several w
 constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
 constexpr int kPanelRows = 256; // rows of the panel solved per workgroup
+constexpr int kPanelLd = 64;    // leading dimension of the panel's diagonal block in LDS (one wave's rows)
 // FP64 levels with fronts of at least kWideFront rows update their trailing
 // matrices once per kWideRank columns (rank-kWideRank MFMA updates)
 constexpr int kWideRank = 128;

@@ -549,24 +549,96 @@ k_big_init(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int t
 // l_ij l_kj from its entries k > j, reading l_kj as LDS broadcasts (one
 // address for the whole wave).  The chain per column is a lane read, the
 // pivot's reciprocal square root and a multiply; the updates overlap it.
+// Pivot of the branch-free panel Cholesky: as pivot_root, with the failure
+// (FP64: d not positive; FP32: d below the floor) returned instead of
+// reported, so that the column loop holds no branch.
+template <typename T>
+__device__ __forceinline__ T pivot_select(T d, T& rinv, bool& fail);
+template <>
+__device__ __forceinline__ double pivot_select<double>(double d, double& rinv, bool& fail) {
+    fail = !(d > 0.0);
+    d = fail ? 1.0 : d;
+    double y = __builtin_amdgcn_rsq(d);
+    y = y * fma(-0.5 * d * y, y, 1.5);
+    y = y * fma(-0.5 * d * y, y, 1.5);
+    rinv = y;
+    return d * y;
+}
+template <>
+__device__ __forceinline__ float pivot_select<float>(float d, float& rinv, bool& fail) {
+    const float floor_ = 1e-5f;
+    fail = !(d > floor_);
+    d = fail ? floor_ : d;
+    float y = __builtin_amdgcn_rsqf(d);
+    y = y * fmaf(-0.5f * d * y, y, 1.5f);
+    rinv = y;
+    return d * y;
+}
+
+// Cholesky of a full kPanelNB x kPanelNB block (LDS, leading dimension
+// kPanelLd) by one wave, right-looking with row i in lane i's registers.
+// One basic block: pivots by select (a failed pivot is recorded after the
+// loop exactly as pivot_root records it), every lane stores its column
+// entry (rows >= kPanelNB land in the padding, entries above the diagonal
+// are never read), and a scheduling barrier per column keeps each column's
+// updates in that column (left to the scheduler they sink to the next
+// pivot and put a chain of up to 31 dependent FMAs in front of it).
+template <typename T>
+__device__ __forceinline__ void potrf_reg_full(T* D, int col0, int32_t* status, T* rdiag) {
+    constexpr int NB = kPanelNB;
+    const int lane = threadIdx.x % kWave;
+    T a[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) a[t] = (lane < NB && t <= lane) ? D[lane + t * kPanelLd] : T(0);
+    int first_bad = INT_MAX, n_bad = 0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        T r;
+        bool fail;
+        const T ljj = pivot_select<T>(bcast<T>(a[j], j), r, fail);
+        first_bad = (fail && first_bad == INT_MAX) ? j : first_bad;
+        n_bad += fail ? 1 : 0;
+        const T lij = lane == j ? ljj : a[j] * r;
+        D[lane + j * kPanelLd] = lij;
+        rdiag[j] = r;
+        // the next pivot's column takes its multiplier by a lane read (off
+        // the LDS store/load round trip); the others read LDS
+        if (j + 1 < NB) a[j + 1] = fma(-lij, bcast<T>(lij, j + 1), a[j + 1]);
+#pragma unroll
+        for (int k = j + 2; k < NB; ++k) a[k] = fma(-lij, D[k + j * kPanelLd], a[k]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (status && lane == 0) {
+        if (std::is_same<T, double>::value) {
+            if (first_bad != INT_MAX) atomicMin(status, col0 + first_bad);
+        } else if (n_bad > 0) {
+            atomicAdd(status + 1, n_bad);
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void potrf32_reg(T* D, int nb, int col0, int32_t* status, T* rdiag) {
+    if (sizeof(T) == 8 && nb == kPanelNB) {  // (the FP32 instance of the full form spills)
+        potrf_reg_full<T>(D, col0, status, rdiag);
+        return;
+    }
     const int lane = threadIdx.x % kWave;
     const bool act = lane < nb;
     T a[kPanelNB];
 #pragma unroll
-    for (int t = 0; t < kPanelNB; ++t) a[t] = (act && t <= lane && t < nb) ? D[lane + t * kPanelNB] : T(0);
+    for (int t = 0; t < kPanelNB; ++t) a[t] = (act && t <= lane && t < nb) ? D[lane + t * kPanelLd] : T(0);
 #pragma unroll
     for (int j = 0; j < kPanelNB; ++j) {
         if (j < nb) {
             T r;
             const T ljj = pivot_root<T>(bcast<T>(a[j], j), col0 + j, status, lane == j, r);
             const T lij = lane == j ? ljj : a[j] * r;
-            if (act && lane >= j) D[lane + j * kPanelNB] = lij;
+            if (act && lane >= j) D[lane + j * kPanelLd] = lij;
             if (lane == j) rdiag[j] = r;
 #pragma unroll
             for (int k = j + 1; k < kPanelNB; ++k)
-                if (k < nb) a[k] = fma(-lij, D[k + j * kPanelNB], a[k]);
+                if (k < nb) a[k] = fma(-lij, D[k + j * kPanelLd], a[k]);
         }
     }
 }
@@ -584,7 +656,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status, T* __restrict__ dscr) {
     static_assert(kPanelRows == 256, "one row per thread");
-    __shared__ T D[kPanelNB * kPanelNB];
+    __shared__ T D[kPanelLd * kPanelNB];
     __shared__ T s_rdiag[kPanelNB];
     const int s = P.lvl_big[list_begin + blockIdx.y];
     const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
@@ -612,7 +684,7 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int idx = u * nt + tid;
-        if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelNB] = t4[u];
+        if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelLd] = t4[u];
     }
     __syncthreads();
     if (tid < kWave) potrf32_reg<T>(D, nb, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
@@ -622,17 +694,29 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
         const int64_t ld = gridDim.x == 1 ? f : kPanelNB;
         for (int idx = tid; idx < nb * nb; idx += nt) {
             const int i = idx % nb, j = idx / nb;
-            if (i >= j) dst[i + j * ld] = D[i + j * kPanelNB];
+            if (i >= j) dst[i + j * ld] = D[i + j * kPanelLd];
         }
     }
     if (!row) return;
+    if (sizeof(T) == 8 && nb == kPanelNB) {
+        // one basic block; the barrier keeps each column's updates in that
+        // column (see potrf_reg_full)
 #pragma unroll
-    for (int j = 0; j < kPanelNB; ++j) {
-        if (j < nb) {
+        for (int j = 0; j < kPanelNB; ++j) {
             x[j] *= s_rdiag[j];
 #pragma unroll
-            for (int k = j + 1; k < kPanelNB; ++k)
-                if (k < nb) x[k] = fma(-x[j], D[k + j * kPanelNB], x[k]);
+            for (int k = j + 1; k < kPanelNB; ++k) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kPanelNB; ++j) {
+            if (j < nb) {
+                x[j] *= s_rdiag[j];
+#pragma unroll
+                for (int k = j + 1; k < kPanelNB; ++k)
+                    if (k < nb) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
+            }
         }
     }
 #pragma unroll
