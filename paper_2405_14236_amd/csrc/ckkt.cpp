@@ -84,6 +84,7 @@ struct ckkt_handle {
     int64_t n_tflags = 0;
     unsigned* tflag = nullptr;
     bool tiled_level = true;              // tiled fronts swept in one launch per level
+    bool sched_hybrid = false;            // dependency-driven sweeps above the single-wave levels only
     unsigned long long wait_ticks = 0;    // wait limit of the flag waits in wall-clock ticks
     Region r_dscr;         // factored diagonal blocks of tiled fronts between launches
     std::vector<Region> r_vn, r_vm, r_veq;  // scratch vectors of length n, m, m_eq
@@ -543,9 +544,18 @@ template <typename T>
 void sweep_levels(ckkt_handle* h, hipStream_t st) {
     const T* arena = arena_of<T>(h);
     if (h->sched_ok) {
+        // dependency-driven: every supernode (CKKT_DEP_SWEEPS=1), or only the
+        // levels above the single-wave class, the ones below swept level by
+        // level (CKKT_DEP_SWEEPS=2)
+        const bool waves = !h->sched_hybrid;
+        const int lw = h->sched.wave_lvl;
         launch_sweep_prep(h->ctl, st);
-        launch_fwd_sched<T>(h->dp, h->sched, arena, h->vperm, h->uvec, h->ctl, h->done, h->status + 2, st);
-        launch_bwd_sched<T>(h->dp, h->sched, arena, h->vperm, h->ctl, h->done, h->status + 2, st);
+        if (!waves)
+            for (int l = 0; l < lw; ++l) launch_fwd_level<T>(h->dp, h->levels[l], arena, h->vperm, h->uvec, st, nullptr);
+        launch_fwd_sched<T>(h->dp, h->sched, arena, h->vperm, h->uvec, h->ctl, h->done, h->status + 2, st, waves);
+        launch_bwd_sched<T>(h->dp, h->sched, arena, h->vperm, h->ctl, h->done, h->status + 2, st, waves);
+        if (!waves)
+            for (int l = lw; l-- > 0;) launch_bwd_level<T>(h->dp, h->levels[l], arena, h->vperm, st, nullptr);
         return;
     }
     TiledSync ts;
@@ -1136,12 +1146,20 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
     HIP_TRY(hipMemsetAsync(h->ws + h->r_status.off, 0, h->r_status.bytes, st));
     HIP_TRY(hipStreamSynchronize(st));
     fill_devplan(h);
-    // Level-by-level sweeps are the default: on this chip a device-scope
-    // release per supernode (an L2 write-back on every producer) costs more
-    // than the kernel boundaries it saves.  CKKT_DEP_SWEEPS=1 selects the
-    // dependency-driven schedule.
+    // Sweep schedule.  Default: the levels of single-wave fronts (order <=
+    // 64, thousands of supernodes) level by level, the levels above
+    // dependency-driven (workgroups taking supernodes in level order and
+    // waiting on their children's or parent's flags): on this chip a
+    // device-scope release per supernode (an L2 write-back on every
+    // producer) costs more than a kernel boundary when a level holds
+    // thousands of supernodes, less when it holds a few.  Plans with fronts
+    // for the tiled sweeps stay level by level (a workgroup worker would
+    // sweep such a front alone).  CKKT_DEP_SWEEPS=0: level by level
+    // throughout; 1: dependency-driven throughout; 2: the default form.
     const char* ds = std::getenv("CKKT_DEP_SWEEPS");
-    h->sched_ok = (ds && ds[0] == '1') && build_sweep_sched(h);
+    const char mode = ds ? ds[0] : (h->n_tflags == 0 ? '2' : '0');
+    h->sched_ok = (mode == '1' || mode == '2') && build_sweep_sched(h);
+    h->sched_hybrid = h->sched_ok && mode == '2';
     h->factored = false;
     h->fp64_factored = false;
     return CKKT_OK;

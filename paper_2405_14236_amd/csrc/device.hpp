@@ -129,10 +129,10 @@ constexpr int kSweepCtlWords = 8;     // ticket counters and epoch
 void launch_sweep_prep(unsigned* ctl, hipStream_t st);  // reset the tickets, advance the epoch
 template <typename T>
 void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* v_perm, double* uvec,
-                      unsigned* ctl, unsigned* done, int32_t* err, hipStream_t st);
+                      unsigned* ctl, unsigned* done, int32_t* err, hipStream_t st, bool waves);
 template <typename T>
 void launch_bwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* x_perm, unsigned* ctl,
-                      unsigned* done, int32_t* err, hipStream_t st);
+                      unsigned* done, int32_t* err, hipStream_t st, bool waves);
 // Grid sizes (resident workgroups) and the wait limit for the current device.
 bool sweep_sched_grids(SweepSched& S, int device);
 

@@ -2241,9 +2241,9 @@ void launch_sweep_prep(unsigned* ctl, hipStream_t st) {
 
 template <typename T>
 void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* v_perm, double* uvec,
-                      unsigned* ctl, unsigned* done, int32_t* err, hipStream_t st) {
+                      unsigned* ctl, unsigned* done, int32_t* err, hipStream_t st, bool waves) {
     set_sweep_attrs<T>();
-    if (S.wave_t1 > 0)
+    if (waves && S.wave_t1 > 0)
         hipLaunchKernelGGL(k_fwd_wave<T>, dim3(S.wave_grid), dim3(kWave), 0, st, P, arena, 0, S.wave_t1, v_perm, uvec,
                            ctl, done, err, S.ticks);
     if (S.ns > S.wave_t1)
@@ -2253,12 +2253,12 @@ void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, dou
 
 template <typename T>
 void launch_bwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* x_perm, unsigned* ctl,
-                      unsigned* done, int32_t* err, hipStream_t st) {
+                      unsigned* done, int32_t* err, hipStream_t st, bool waves) {
     set_sweep_attrs<T>();
     if (S.ns > S.wave_t1)
         hipLaunchKernelGGL(k_bwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, S.wave_t1, S.ns,
                            S.ldd, x_perm, ctl, done, err, S.ticks);
-    if (S.wave_t1 > 0)
+    if (waves && S.wave_t1 > 0)
         hipLaunchKernelGGL(k_bwd_wave<T>, dim3(S.wave_grid), dim3(kWave), 0, st, P, arena, 0, S.wave_t1, S.wave_lvl,
                            x_perm, ctl, done, err, S.ticks);
 }
@@ -2293,13 +2293,13 @@ bool sweep_sched_grids(SweepSched& S, int device) {
 }
 
 template void launch_fwd_sched<double>(const DevPlan&, const SweepSched&, const double*, double*, double*, unsigned*,
-                                       unsigned*, int32_t*, hipStream_t);
+                                       unsigned*, int32_t*, hipStream_t, bool);
 template void launch_fwd_sched<float>(const DevPlan&, const SweepSched&, const float*, double*, double*, unsigned*,
-                                      unsigned*, int32_t*, hipStream_t);
+                                      unsigned*, int32_t*, hipStream_t, bool);
 template void launch_bwd_sched<double>(const DevPlan&, const SweepSched&, const double*, double*, unsigned*,
-                                       unsigned*, int32_t*, hipStream_t);
+                                       unsigned*, int32_t*, hipStream_t, bool);
 template void launch_bwd_sched<float>(const DevPlan&, const SweepSched&, const float*, double*, unsigned*, unsigned*,
-                                      int32_t*, hipStream_t);
+                                      int32_t*, hipStream_t, bool);
 
 void launch_gather_perm(const DevPlan& P, const double* in, double* out, const double* scale, hipStream_t st) {
     if (P.n == 0) return;

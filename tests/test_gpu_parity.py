@@ -233,7 +233,7 @@ def test_dependency_driven_sweeps_match_level_sweeps(monkeypatch, precision):
     print_case("sweep_schedules", n=p.n, precision=precision)
     tol = 1e-10 if precision == "fp64" else 1e-8
     out = {}
-    for mode in ("0", "1"):
+    for mode in ("0", "1", "2"):  # level by level; dependency-driven; hybrid (the default)
         monkeypatch.setenv("CKKT_DEP_SWEEPS", mode)
         s = Solver(p, "lifted", precision, tol=tol).bind(DEV)
         s.factorize(*device_values(p, DEV, "lifted"))
@@ -245,8 +245,9 @@ def test_dependency_driven_sweeps_match_level_sweeps(monkeypatch, precision):
         assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
         assert omega_of(p, "lifted", z.cpu().numpy()) <= tol
         out[mode] = x1.cpu().numpy()
-    a, c = out["0"], out["1"]
-    assert np.abs(a - c).max() <= 1e-8 * np.abs(a).max()
+    a = out["0"]
+    for mode in ("1", "2"):
+        assert np.abs(a - out[mode]).max() <= 1e-8 * np.abs(a).max(), mode
 
 
 @pytest.mark.parametrize("case,precision,tiled", [
