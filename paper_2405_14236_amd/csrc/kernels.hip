@@ -171,6 +171,32 @@ __device__ __forceinline__ float pivot_root<float>(float d, int col, int32_t* st
     return d * y;
 }
 
+// Pivot of the branch-free register Cholesky forms: as pivot_root, with the failure
+// (FP64: d not positive; FP32: d below the floor) returned instead of
+// reported, so that the column loop holds no branch.
+template <typename T>
+__device__ __forceinline__ T pivot_select(T d, T& rinv, bool& fail);
+template <>
+__device__ __forceinline__ double pivot_select<double>(double d, double& rinv, bool& fail) {
+    fail = !(d > 0.0);
+    d = fail ? 1.0 : d;
+    double y = __builtin_amdgcn_rsq(d);
+    y = y * fma(-0.5 * d * y, y, 1.5);
+    y = y * fma(-0.5 * d * y, y, 1.5);
+    rinv = y;
+    return d * y;
+}
+template <>
+__device__ __forceinline__ float pivot_select<float>(float d, float& rinv, bool& fail) {
+    const float floor_ = 1e-5f;
+    fail = !(d > floor_);
+    d = fail ? floor_ : d;
+    float y = __builtin_amdgcn_rsqf(d);
+    y = y * fmaf(-0.5f * d * y, y, 1.5f);
+    rinv = y;
+    return d * y;
+}
+
 constexpr int kDiag = 16;  // diagonal block of the blocked front factorization
 constexpr int kMaxChildBatch = 64;  // children whose metadata is staged at once
 
@@ -250,6 +276,67 @@ __device__ void rows_trsm(T* B, int ld, const T* D, int ldd, int nb, int i0, int
     }
 }
 
+// Full kDiag-column diagonal block of an LDS front (leading dimension ld),
+// right-looking with row i in the registers of lane i (lanes 0..kDiag-1
+// call it).  As potrf_reg_full: select pivots (a failure is recorded after
+// the loop as pivot_root records it), the column store writes back the old
+// value above the diagonal (one store per lane, no branch), and a
+// scheduling barrier per column keeps each column's updates in that
+// column instead of letting them sink in front of the next pivot.
+template <typename T>
+__device__ __forceinline__ void potrf_diag_reg(T* A, int ld, int col0, int32_t* status, T* rdiag) {
+    constexpr int NB = kDiag;
+    const int lane = threadIdx.x % kWave;
+    T a[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) a[t] = t <= lane ? A[lane + t * ld] : T(0);
+    int first_bad = INT_MAX, n_bad = 0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const T old = A[lane + j * ld];
+        T r;
+        bool fail;
+        const T ljj = pivot_select<T>(bcast<T>(a[j], j), r, fail);
+        first_bad = (fail && first_bad == INT_MAX) ? j : first_bad;
+        n_bad += fail ? 1 : 0;
+        const T lij = lane == j ? ljj : a[j] * r;
+        A[lane + j * ld] = lane >= j ? lij : old;
+        rdiag[j] = r;
+#pragma unroll
+        for (int k = j + 1; k < NB; ++k) a[k] = fma(-lij, A[k + j * ld], a[k]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (status && lane == 0) {
+        if (std::is_same<T, double>::value) {
+            if (first_bad != INT_MAX) atomicMin(status, col0 + first_bad);
+        } else if (n_bad > 0) {
+            atomicAdd(status + 1, n_bad);
+        }
+    }
+}
+
+// Rows [i0, i1) of B times the inverse transpose of a factored full
+// kDiag-column block D, one row per thread in registers, right-looking.
+template <typename T>
+__device__ __forceinline__ void rows_trsm_diag_reg(T* B, int ld, const T* D, int ldd, int i0, int i1,
+                                                   const T* rdiag) {
+    constexpr int NB = kDiag;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        T x[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) x[t] = B[i + t * ld];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            x[j] *= rdiag[j];
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) x[k] = fma(-x[j], D[k + j * ldd], x[k]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) B[i + t * ld] = x[t];
+    }
+}
+
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Lower-triangular rank-k update on the matrix cores (FP64):
@@ -290,10 +377,14 @@ __device__ __forceinline__ void syrk_mfma(const double* F, int f, int i0, int i1
 
 // Fronts that fit in LDS (f^2 elements <= 160 KiB): one workgroup per front.
 // Assemble (K columns + extend-add of the children's update matrices in
-// child order), blocked partial Cholesky of the first w columns (32-column
-// diagonal blocks in one wave's registers, parallel row solves and panel
-// updates), store the panel, and form the update matrix
-// U = F22 - L21 L21^T in one parallel pass (multifrontal method).
+// child order), blocked partial Cholesky of the first w columns (kDiag-
+// column diagonal blocks factored by one wave, parallel row solves and
+// panel updates), store the panel, and form the update matrix
+// U = F22 - L21 L21^T in one parallel pass (multifrontal method).  REG:
+// the large class (256 threads, one front per CU), whose full FP64 diagonal
+// blocks use the register forms (potrf_diag_reg, rows_trsm_diag_reg); the
+// compact class keeps the left-looking LDS forms (fewer registers, several
+// workgroups per CU).
 template <typename T, bool REG>
 __global__ void __launch_bounds__(256)
 k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int list_begin,
@@ -382,9 +473,15 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
     for (int kb = 0; kb < w; kb += kDiag) {
         const int nb = min(kDiag, w - kb);
         T* Dg = F + kb + kb * f;
-        if (tid < kWave) wave_potrf<T>(Dg, f, nb, c0 + kb, status, s_rdiag);
-        __syncthreads();
-        rows_trsm<T>(F + kb * f, f, Dg, f, nb, kb + nb, f, s_rdiag);
+        if (REG && sizeof(T) == 8 && nb == kDiag) {  // large class, FP64, full block
+            if (tid < kDiag) potrf_diag_reg<T>(Dg, f, c0 + kb, status, s_rdiag);
+            __syncthreads();
+            rows_trsm_diag_reg<T>(F + kb * f, f, Dg, f, kb + nb, f, s_rdiag);
+        } else {
+            if (tid < kWave) wave_potrf<T>(Dg, f, nb, c0 + kb, status, s_rdiag);
+            __syncthreads();
+            rows_trsm<T>(F + kb * f, f, Dg, f, nb, kb + nb, f, s_rdiag);
+        }
         __syncthreads();
         // remaining panel columns [kb+nb, w), rows >= column
         const int j0 = kb + nb, mr = f - j0, mc = w - j0;
@@ -549,32 +646,6 @@ k_big_init(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int t
 // l_ij l_kj from its entries k > j, reading l_kj as LDS broadcasts (one
 // address for the whole wave).  The chain per column is a lane read, the
 // pivot's reciprocal square root and a multiply; the updates overlap it.
-// Pivot of the branch-free panel Cholesky: as pivot_root, with the failure
-// (FP64: d not positive; FP32: d below the floor) returned instead of
-// reported, so that the column loop holds no branch.
-template <typename T>
-__device__ __forceinline__ T pivot_select(T d, T& rinv, bool& fail);
-template <>
-__device__ __forceinline__ double pivot_select<double>(double d, double& rinv, bool& fail) {
-    fail = !(d > 0.0);
-    d = fail ? 1.0 : d;
-    double y = __builtin_amdgcn_rsq(d);
-    y = y * fma(-0.5 * d * y, y, 1.5);
-    y = y * fma(-0.5 * d * y, y, 1.5);
-    rinv = y;
-    return d * y;
-}
-template <>
-__device__ __forceinline__ float pivot_select<float>(float d, float& rinv, bool& fail) {
-    const float floor_ = 1e-5f;
-    fail = !(d > floor_);
-    d = fail ? floor_ : d;
-    float y = __builtin_amdgcn_rsqf(d);
-    y = y * fmaf(-0.5f * d * y, y, 1.5f);
-    rinv = y;
-    return d * y;
-}
-
 // Cholesky of a full kPanelNB x kPanelNB block (LDS, leading dimension
 // kPanelLd) by one wave, right-looking with row i in lane i's registers.
 // One basic block: pivots by select (a failed pivot is recorded after the
