@@ -342,36 +342,57 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // Lower-triangular rank-k update on the matrix cores (FP64):
 //   out(i, j, (P P^T)_ij)  for i in [i0, i1), j in [j0, j1), i >= j,
 // where P holds columns [t0, t1) of the LDS front F (leading dimension f).
-// One 16 x 16 output tile per wave at a time, K in steps of 4 with
-// v_mfma_f64_16x16x4f64: lane l supplies A(l % 16, l / 16) and
-// B(l / 16, l % 16) and receives D(4 r + l / 16, l % 16) in register r.
-// Tiles entirely above the diagonal are skipped (wave-uniform), so every
+// One 32 x 32 output block (2 x 2 tiles of 16 x 16) per wave at a time, K
+// in steps of 4 with v_mfma_f64_16x16x4f64: lane l supplies A(l % 16, l / 16)
+// and B(l / 16, l % 16) and receives D(4 r + l / 16, l % 16) in register r.
+// Blocks entirely above the diagonal are skipped (wave-uniform), so every
 // matrix instruction runs with all lanes active.
 template <typename Out>
 __device__ __forceinline__ void syrk_mfma(const double* F, int f, int i0, int i1, int j0, int j1, int t0, int t1,
                                           Out out) {
+    // 32 x 32 blocks per wave: 2 x 2 MFMA tiles, four independent
+    // accumulators sharing each K step's operand loads
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int li = lane % 16, lk = lane / 16;
-    const int ni = (i1 - i0 + 15) / 16, nj = (j1 - j0 + 15) / 16;
+    const int ni = (i1 - i0 + 31) / 32, nj = (j1 - j0 + 31) / 32;
     for (int q = wid; q < ni * nj; q += nw) {
-        const int ib = i0 + 16 * (q % ni), jb = j0 + 16 * (q / ni);
-        if (ib + 15 < jb) continue;
-        const int ia = ib + li, ja = jb + li;
-        const bool ai = ia < i1, bj = ja < j1;
-        dbl4 c = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+        const int ib = i0 + 32 * (q % ni), jb = j0 + 32 * (q / ni);
+        if (ib + 31 < jb) continue;
+        bool ai[2], bj[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            ai[a] = ib + 16 * a + li < i1;
+            bj[a] = jb + 16 * a + li < j1;
+        }
+        dbl4 c[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) c[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
         for (int t = t0; t < t1; t += 4) {
             const int tk = t + lk;
             const bool kin = tk < t1;
-            const double a = (ai && kin) ? F[ia + tk * f] : 0.0;
-            const double b = (bj && kin) ? F[ja + tk * f] : 0.0;
-            c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                av[a] = (ai[a] && kin) ? F[ib + 16 * a + li + tk * f] : 0.0;
+                bv[a] = (bj[a] && kin) ? F[jb + 16 * a + li + tk * f] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], c[a][b], 0, 0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = ib + 4 * r + lk, j = jb + li;
-            if (i < i1 && j < j1 && i >= j) out(i, j, c[r]);
-        }
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = ib + 16 * a + 4 * r + lk, j = jb + 16 * b + li;
+                    if (i < i1 && j < j1 && i >= j) out(i, j, c[a][b][r]);
+                }
     }
 }
 
