@@ -1109,11 +1109,12 @@ __device__ __forceinline__ void stage_diag_block(const T* __restrict__ src, int 
 // it (one thread per row, loads in batches of 16).  Rows beyond the
 // supernode's own columns end up holding this front's update vector.
 template <typename T>
-__device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double* v, double* D) {
+__device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double* v, double* D,
+                          bool first_staged = false) {
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid % kWave, wid = tid / kWave;
     for (int kb = 0; kb < w; kb += kWave) {
         const int nb = min(kWave, w - kb);
-        stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
+        if (kb > 0 || !first_staged) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
         __syncthreads();
         if (wid == 0) {
             double vi = lane < nb ? v[kb + lane] : 0.0;
@@ -1150,7 +1151,8 @@ __device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double
 // columns at a time with everything solved so far, then one wave
 // back-substitutes the diagonal block.
 template <typename T>
-__device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double* z, double* D, double* tb) {
+__device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double* z, double* D, double* tb,
+                          bool last_staged = false) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nw = nt / kWave, lane = tid % kWave, wid = tid / kWave;
     const int nblk = (w + kWave - 1) / kWave;
@@ -1174,7 +1176,7 @@ __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double
                 if (lane == 0 && k0 + c < nb) tb[k0 + c] = sc;
             }
         }
-        stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
+        if (b < nblk - 1 || !last_staged) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
         __syncthreads();
         if (wid == 0) {
             double ri = lane < nb ? z[kb + lane] - tb[lane] : 0.0;
@@ -1660,20 +1662,40 @@ k_fwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_lo, 
         const int s = P.lvl_all[t];
         const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
         const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+        const T* Ls = arena + P.l_off[s];
+        // work that does not depend on the children, issued before the
+        // wait: the first diagonal block, this thread's first row's own
+        // right-hand side and its first contribution indices
+        stage_diag_block(Ls, f, min(kWave, w), v + ((f + 1) & ~1), ldd);
+        constexpr int kPre = 4;
+        const bool r0 = tid < f;
+        double own = (r0 && tid < w) ? v_perm[c0 + tid] : 0.0;
+        int qa = r0 ? P.cb_ptr[ro + tid] : 0, qb = r0 ? P.cb_ptr[ro + tid + 1] : 0;
+        int src[kPre];
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) src[k] = qa + k < qb ? P.cb_src[qa + k] : -1;
         for (int c = P.child_ptr[s] + tid; c < P.child_ptr[s + 1]; c += nt) {
             const int ch = P.child_list[c];
             if (P.sn_level[ch] >= lvl_lo) wait_flag(&done[ch], want, err, ticks);
         }
         __syncthreads();
         acquire_device();
-        for (int i = tid; i < f; i += nt) {
+        if (r0) {
+            double acc = own;
+#pragma unroll
+            for (int k = 0; k < kPre; ++k)
+                if (src[k] >= 0) acc += uvec[src[k]];
+            for (int q = qa + kPre; q < qb; ++q) acc += uvec[P.cb_src[q]];
+            v[tid] = acc;
+        }
+        for (int i = tid + nt; i < f; i += nt) {
             double acc = (i < w) ? v_perm[c0 + i] : 0.0;
             const int q1 = P.cb_ptr[ro + i + 1];
             for (int q = P.cb_ptr[ro + i]; q < q1; ++q) acc += uvec[P.cb_src[q]];
             v[i] = acc;
         }
         __syncthreads();
-        fwd_front(arena + P.l_off[s], w, f, ldd, v, v + ((f + 1) & ~1));
+        fwd_front(Ls, w, f, ldd, v, v + ((f + 1) & ~1), true);
         for (int i = tid; i < f; i += nt) {
             if (i < w) v_perm[c0 + i] = v[i];
             else uvec[ro + i] = v[i];
@@ -1707,12 +1729,19 @@ k_bwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int ldd, dou
         const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
         const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
         const int par = P.sn_parent[s];
+        const T* Ls = arena + P.l_off[s];
+        // issued before the wait: the last diagonal block (the first one
+        // solved) and this thread's first row index
+        const int nblk = (w + kWave - 1) / kWave, kbl = (nblk - 1) * kWave;
+        stage_diag_block(Ls + kbl + (int64_t)kbl * f, f, w - kbl, z + ((f + 1) & ~1), ldd);
+        const int row0 = tid < f ? P.sn_rows[ro + tid] : 0;
         if (tid == 0 && par >= 0) wait_flag(&done[par], want, err, ticks);
         __syncthreads();
         acquire_device();
-        for (int i = tid; i < f; i += nt) z[i] = x_perm[P.sn_rows[ro + i]];
+        if (tid < f) z[tid] = x_perm[row0];
+        for (int i = tid + nt; i < f; i += nt) z[i] = x_perm[P.sn_rows[ro + i]];
         __syncthreads();
-        bwd_front(arena + P.l_off[s], w, f, ldd, z, z + ((f + 1) & ~1), tb);
+        bwd_front(Ls, w, f, ldd, z, z + ((f + 1) & ~1), tb, true);
         for (int i = tid; i < w; i += nt) x_perm[c0 + i] = z[i];
         release_device();
         __syncthreads();
