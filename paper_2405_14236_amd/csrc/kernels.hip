@@ -1674,6 +1674,16 @@ k_fwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_lo, 
         int src[kPre];
 #pragma unroll
         for (int k = 0; k < kPre; ++k) src[k] = qa + k < qb ? P.cb_src[qa + k] : -1;
+        // a front with one diagonal block and at most one row below per
+        // thread: this thread's panel row below the block, loaded now
+        const bool single = w <= kWave && f - w <= nt;
+        double lrow[kWave];
+        {
+            const bool hr = single && tid < f - w;
+            const T* Li = Ls + (hr ? w + tid : 0);
+#pragma unroll
+            for (int k = 0; k < kWave; ++k) lrow[k] = (hr && k < w) ? (double)Li[(int64_t)k * f] : 0.0;
+        }
         for (int c = P.child_ptr[s] + tid; c < P.child_ptr[s + 1]; c += nt) {
             const int ch = P.child_list[c];
             if (P.sn_level[ch] >= lvl_lo) wait_flag(&done[ch], want, err, ticks);
@@ -1695,7 +1705,34 @@ k_fwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_lo, 
             v[i] = acc;
         }
         __syncthreads();
-        fwd_front(Ls, w, f, ldd, v, v + ((f + 1) & ~1), true);
+        if (single) {
+            // one diagonal block: its solve, then the rows below from the
+            // panel rows loaded before the wait (same order of operations
+            // as fwd_front, so the result is the same)
+            double* D = v + ((f + 1) & ~1);
+            const int lane = tid % kWave;
+            if (tid < kWave) {
+                double vi = lane < w ? v[lane] : 0.0;
+#pragma unroll 4
+                for (int k = 0; k < w; ++k) {
+                    const double yk = lane_bcast(vi, k) * D[k + k * ldd];
+                    if (lane == k) vi = yk;
+                    else if (lane > k && lane < w) vi = fma(-D[lane + k * ldd], yk, vi);
+                }
+                if (lane < w) v[lane] = vi;
+            }
+            __syncthreads();
+            if (tid < f - w) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < kWave; ++k)
+                    if (k < w) acc = fma(lrow[k], v[k], acc);
+                v[w + tid] -= acc;
+            }
+            __syncthreads();
+        } else {
+            fwd_front(Ls, w, f, ldd, v, v + ((f + 1) & ~1), true);
+        }
         for (int i = tid; i < f; i += nt) {
             if (i < w) v_perm[c0 + i] = v[i];
             else uvec[ro + i] = v[i];
