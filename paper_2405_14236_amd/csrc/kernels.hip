@@ -1772,13 +1772,67 @@ k_bwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int ldd, dou
         const int nblk = (w + kWave - 1) / kWave, kbl = (nblk - 1) * kWave;
         stage_diag_block(Ls + kbl + (int64_t)kbl * f, f, w - kbl, z + ((f + 1) & ~1), ldd);
         const int row0 = tid < f ? P.sn_rows[ro + tid] : 0;
+        // a front with one diagonal block and at most 4 x 64 rows below:
+        // the panel entries of the dot products, loaded now (the products
+        // then run in bwd_front's order)
+        const int lane = tid % kWave, wid = tid / kWave;
+        const bool single = w <= kWave && f - w <= 4 * kWave && nt == 4 * kWave;
+        double lp[2][4][8];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int k = wid * 8 + p * 32 + c, i = w + lane + m * kWave;
+                    lp[p][m][c] = (single && k < w && i < f) ? (double)Ls[i + (int64_t)k * f] : 0.0;
+                }
         if (tid == 0 && par >= 0) wait_flag(&done[par], want, err, ticks);
         __syncthreads();
         acquire_device();
         if (tid < f) z[tid] = x_perm[row0];
         for (int i = tid + nt; i < f; i += nt) z[i] = x_perm[P.sn_rows[ro + i]];
         __syncthreads();
-        bwd_front(Ls, w, f, ldd, z, z + ((f + 1) & ~1), tb, true);
+        if (single) {
+            double* D = z + ((f + 1) & ~1);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int k0 = wid * 8 + p * 32;
+                if (k0 < w) {
+                    double part[8];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) part[c] = 0.0;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int i = w + lane + m * kWave;
+                        if (i < f) {
+                            const double zi = z[i];
+#pragma unroll
+                            for (int c = 0; c < 8; ++c) part[c] = fma(lp[p][m][c], zi, part[c]);
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const double sc = wave_sum(part[c]);
+                        if (lane == 0 && k0 + c < w) tb[k0 + c] = sc;
+                    }
+                }
+            }
+            __syncthreads();
+            if (wid == 0) {
+                double ri = lane < w ? z[lane] - tb[lane] : 0.0;
+#pragma unroll 4
+                for (int k = w - 1; k >= 0; --k) {
+                    const double xk = lane_bcast(ri, k) * D[k + k * ldd];
+                    if (lane == k) ri = xk;
+                    else if (lane < k) ri = fma(-D[k + lane * ldd], xk, ri);
+                }
+                if (lane < w) z[lane] = ri;
+            }
+            __syncthreads();
+        } else {
+            bwd_front(Ls, w, f, ldd, z, z + ((f + 1) & ~1), tb, true);
+        }
         for (int i = tid; i < w; i += nt) x_perm[c0 + i] = z[i];
         release_device();
         __syncthreads();
