@@ -1156,9 +1156,13 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
     // for the tiled sweeps stay level by level (a workgroup worker would
     // sweep such a front alone).  CKKT_DEP_SWEEPS=0: level by level
     // throughout; 1: dependency-driven throughout; 2: the default form.
+    // The default takes the hybrid only while few supernodes lie above the
+    // single-wave levels (kHybridMaxTasks): a batch of hundreds of
+    // instances has thousands there and sweeps faster level by level.
     const char* ds = std::getenv("CKKT_DEP_SWEEPS");
     const char mode = ds ? ds[0] : (h->n_tflags == 0 ? '2' : '0');
     h->sched_ok = (mode == '1' || mode == '2') && build_sweep_sched(h);
+    if (h->sched_ok && !ds && h->sched.ns - h->sched.wave_t1 > kHybridMaxTasks) h->sched_ok = false;
     h->sched_hybrid = h->sched_ok && mode == '2';
     h->factored = false;
     h->fp64_factored = false;

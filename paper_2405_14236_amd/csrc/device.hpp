@@ -126,6 +126,9 @@ struct SweepSched {
 constexpr int kSweepWaveFront = 64;   // largest front of the single-wave class
 constexpr int kSweepWaitSeconds = 4;  // a dependency wait longer than this is reported as an error
 constexpr int kSweepCtlWords = 8;     // ticket counters and epoch
+// largest number of supernodes above the single-wave levels for which the
+// hybrid schedule is the default
+constexpr int kHybridMaxTasks = 8192;
 void launch_sweep_prep(unsigned* ctl, hipStream_t st);  // reset the tickets, advance the epoch
 template <typename T>
 void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* v_perm, double* uvec,
