@@ -128,7 +128,10 @@ struct ckkt_handle {
     // [3] sweeps FP32.  They reference only workspace memory.
     hipStream_t capture_stream = nullptr;
     SideStream side;  // second stream of the factorization (tiled fronts)
-    hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
+    // captured launch sequences: factorization (FP64, FP32), factor
+    // application (FP64, FP32), HyKKT CG iteration (FP64, FP32 factor)
+    hipGraphExec_t graphs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const double* cg_gval[2] = {nullptr, nullptr};  // G values a CG-iteration graph was captured with
     bool use_graphs = true;
     bool debug_launch = false;  // CKKT_DEBUG_LAUNCH=1: report the first failing launch per factor level
 
@@ -613,6 +616,17 @@ void apply_inverse_t(ckkt_handle* h, const double* b, double* x, const double* s
     launch_scatter_perm(h->dp, h->vperm, x, scale, st);
 }
 
+// The same launches, for use inside another captured sequence (no timer,
+// no graph of its own).
+void apply_inverse_launches(ckkt_handle* h, const double* b, double* x, bool use64, hipStream_t st) {
+    const bool d = use64 || h->precision == CKKT_FP64;
+    const double* scale = d ? nullptr : h->scale;
+    launch_gather_perm(h->dp, b, h->vperm, scale, st);
+    if (d) sweep_levels<double>(h, st);
+    else sweep_levels<float>(h, st);
+    launch_scatter_perm(h->dp, h->vperm, x, scale, st);
+}
+
 // Uses the FP64 factor when `use64`, else the handle's precision.
 void apply_inverse(ckkt_handle* h, const double* b, double* x, bool use64, hipStream_t st) {
     if (use64 || h->precision == CKKT_FP64) apply_inverse_t<double>(h, b, x, nullptr, st);
@@ -892,7 +906,10 @@ ckkt_status hykkt_inner(ckkt_handle* h, const double* R1, const double* R2, doub
         PhaseTimer tm(h, 3, st);
         launch_g(P, h->vals, dx, R2, r, st);
         launch_fill(me, 0.0, dy, st);
-        launch_copy(me, r, p, st);
+        // p = 0 and beta = 0: the iteration's first step p = r + beta p
+        // then gives p = r
+        launch_fill(me, 0.0, p, st);
+        launch_fill(1, 0.0, h->sc + 4, st);
         launch_dot(me, r, r, h->dotpart, h->sc + 0, st);
     }
     double hs[5];
@@ -903,31 +920,37 @@ ckkt_status hykkt_inner(ckkt_handle* h, const double* R1, const double* R2, doub
     if (!(rr0 > 0.0)) return rr0 == 0.0 ? CKKT_OK : CKKT_ERR_BREAKDOWN;
     const double stop = h->opt.cg_tol * std::sqrt(rr0);
     int maxit = h->opt.cg_maxit > 0 ? h->opt.cg_maxit : std::max(1, std::min(me, 1000));
+    // One CG iteration is one captured sequence (its pointers are the
+    // handle's buffers and the G values of the current system; the graph is
+    // captured again when the caller's G values move).  Phase time counts
+    // as factor application.
+    const int slot = (use64 || h->precision == CKKT_FP64) ? 4 : 5;
+    if (h->graphs[slot] && h->cg_gval[slot - 4] != h->vals.g_val) {
+        (void)hipGraphExecDestroy(h->graphs[slot]);
+        h->graphs[slot] = nullptr;
+    }
+    h->cg_gval[slot - 4] = h->vals.g_val;
     for (int k = 1; k <= maxit; ++k) {
         {
-            PhaseTimer tm(h, 3, st);
-            launch_gt(P, h->vals, nullptr, 1.0, p, t, st);
-        }
-        apply_inverse(h, t, u, use64, st);
-        {
-            PhaseTimer tm(h, 3, st);
-            launch_g(P, h->vals, u, nullptr, q, st);
-            launch_dot(me, p, q, h->dotpart, h->sc + 1, st);
-            launch_cg_alpha(h->sc, st);
-            launch_cg_update(me, h->sc, p, q, dy, r, st);
-            launch_axpy_dev(n, h->sc, 2, -1.0, u, dx, st);
-            launch_dot(me, r, r, h->dotpart, h->sc + 3, st);
+            PhaseTimer tm(h, 2, st);
+            run_captured(h, slot, st, [&](hipStream_t s) {
+                launch_cg_direction(me, h->sc, r, p, s);  // p = r + beta p
+                launch_gt(P, h->vals, nullptr, 1.0, p, t, s);
+                apply_inverse_launches(h, t, u, use64, s);
+                launch_g(P, h->vals, u, nullptr, q, s);
+                launch_dot(me, p, q, h->dotpart, h->sc + 1, s);
+                launch_cg_alpha(h->sc, s);
+                launch_cg_update(me, h->sc, p, q, dy, r, s);
+                launch_axpy_dev(n, h->sc, 2, -1.0, u, dx, s);
+                launch_dot(me, r, r, h->dotpart, h->sc + 3, s);
+                launch_cg_beta(h->sc, s);  // beta = rr_new / rr, rr = rr_new
+            });
         }
         rc = read_scalars(h, hs, 4, st);
         if (rc) return rc;
         cg_iters++;
         if (!(hs[1] > 0.0) || !std::isfinite(hs[1])) return CKKT_ERR_BREAKDOWN;
         if (std::sqrt(hs[3]) <= stop) return CKKT_OK;
-        {
-            PhaseTimer tm(h, 3, st);
-            launch_cg_beta(h->sc, st);
-            launch_cg_direction(me, h->sc, r, p, st);
-        }
     }
     cg_ok = false;
     return CKKT_OK;

@@ -418,3 +418,27 @@ def test_tiled_level_launch_bitwise(monkeypatch, case, precision, tiled):
     assert np.all(np.isfinite(ref))
     for k, v in out.items():
         assert np.array_equal(v, ref), k
+
+
+def test_hykkt_cg_graph_follows_new_value_arrays():
+    """The captured CG iteration reads the G values of the current system:
+    after the caller moves its value arrays (new allocations, old ones freed
+    and overwritten), a solve gives the same result as before."""
+    p = workloads.network_flow(2000, seed=12)
+    print_case("cg_graph_new_arrays", n=p.n)
+    s = Solver(p, "hykkt").bind(DEV)
+    rhs = torch.as_tensor(rhs_of(p, "hykkt"), device=DEV)
+    vals = device_values(p, DEV, "hykkt")
+    s.factorize(*vals, gamma=1e7)
+    z1, _ = s.solve(rhs)
+    z1 = z1.cpu().numpy()
+    del vals
+    torch.cuda.synchronize()
+    junk = [torch.full((p.g_val.size,), float("nan"), dtype=torch.float64, device=DEV) for _ in range(4)]
+    vals2 = device_values(p, DEV, "hykkt")
+    s.factorize(*vals2, gamma=1e7)
+    z2, info = s.solve(rhs)
+    torch.cuda.synchronize()
+    del junk
+    assert info["cg_iters"] > 0
+    assert np.array_equal(z1, z2.cpu().numpy())
