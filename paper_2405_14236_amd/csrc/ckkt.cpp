@@ -636,6 +636,7 @@ void apply_inverse(ckkt_handle* h, const double* b, double* x, bool use64, hipSt
 struct ResidualOut {
     double omega = 0.0;      // max over instances
     double resmax = 0.0;
+    double rhsmax = 0.0;     // max |rhs| left by launch_rhs_max
     std::vector<double> per_inst;
     int32_t status0 = INT_MAX, status1 = 0, status2 = 0;
 };
@@ -669,11 +670,21 @@ ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, cons
         out.omega = std::max(out.omega, out.per_inst[i]);
     }
     out.resmax = bits_to_double(hb[ni]);
+    out.rhsmax = bits_to_double(hb[ni + 1]);
     const int32_t* hs = reinterpret_cast<const int32_t*>(host + (ni + 2) * sizeof(unsigned long long));
     out.status0 = hs[0];
     out.status1 = hs[1];
     out.status2 = hs[2];
     return out.status2 ? CKKT_ERR_TIMEOUT : CKKT_OK;
+}
+
+// max |rhs| into the word after the residual maxima, read back (without
+// a synchronization of its own) by the next residual_sync
+void launch_rhs_max(ckkt_handle* h, const double* a, int na, const double* b, int nb_, hipStream_t st) {
+    unsigned long long* slot = h->bits + h->plan.ninst + 1;
+    launch_zero_u64(slot, 1, st);
+    launch_maxabs(na, a, slot, st);
+    if (b) launch_maxabs(nb_, b, slot, st);
 }
 
 ckkt_status read_rhs_max(ckkt_handle* h, const double* a, int na, const double* b, int nb_, double& out,
@@ -825,9 +836,8 @@ ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_
     const int n = h->plan.n;
     double* res = h->vn[0];
     double* dx = h->vn[1];
-    double bmax = 0.0;
-    ckkt_status rc = read_rhs_max(h, b, n, nullptr, 0, bmax, st);
-    if (rc) return rc;
+    launch_rhs_max(h, b, n, nullptr, 0, st);
+    ckkt_status rc = CKKT_OK;
     bool use64 = h->precision == CKKT_FP64 || h->fp64_factored;
     apply_inverse(h, b, x, use64, st);
     ResidualOut r;
@@ -839,7 +849,7 @@ ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_
         if (rc) return rc;
         if (!check_factor(h, r)) { info->status = CKKT_ERR_NOT_SPD; return CKKT_ERR_NOT_SPD; }
         info->omega = r.omega;
-        info->rho = bmax > 0 ? r.resmax / bmax : r.resmax;
+        info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
         if (r.omega <= h->opt.tol) break;
         if (!use64) {
             // FP32 factor: Richardson while it contracts; when it stagnates,
@@ -851,7 +861,7 @@ ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_
                     info->fallback = 1;
                     if (pcg_fp32(h, b, x, res, r, info, st, rc)) {
                         info->omega = r.omega;
-                        info->rho = bmax > 0 ? r.resmax / bmax : r.resmax;
+                        info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
                         break;
                     }
                     if (rc) return rc;
@@ -966,9 +976,8 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
     double* res2 = h->veq[3];
     double* ddx = h->vn[1];
     double* ddy = h->veq[4];
-    double bmax = 0.0;
-    ckkt_status rc = read_rhs_max(h, r1, n, r2, me, bmax, st);
-    if (rc) return rc;
+    launch_rhs_max(h, r1, n, r2, me, st);
+    ckkt_status rc = CKKT_OK;
     {
         PhaseTimer tm(h, 3, st);
         launch_fill(n + me, 0.0, sol, st);
@@ -983,7 +992,7 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
         if (rc) return rc;
         if (!check_factor(h, r)) { info->status = CKKT_ERR_NOT_SPD; return CKKT_ERR_NOT_SPD; }
         info->omega = r.omega;
-        info->rho = bmax > 0 ? r.resmax / bmax : r.resmax;
+        info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
         if (r.omega <= h->opt.tol && steps > 0) break;
         if (steps > 0 && !use64) {
             if (!(r.omega < 0.5 * prev)) stall++;
