@@ -31,3 +31,23 @@ def omega_kgamma(p, x, b, gamma):
 
 def rhs_of(p, formulation):
     return p.b if formulation == "lifted" else np.concatenate([p.r1bar, p.r2bar])
+
+
+def plant_negative_curvature(p, formulation, theta, gamma=1e7):
+    """Copy of ``p`` whose W diagonal is lowered uniformly so that the smallest
+    eigenvalue of the condensed matrix (K for LiftedKKT, K_gamma for HyKKT)
+    is exactly -theta.  Dense eigenvalues: small problems only."""
+    import dataclasses
+    from oracle import dense as od
+    W, G, H = od.problem_dense(p)
+    if formulation == "lifted":
+        K = od.condensed_matrix(W, p.sigma_x, np.vstack([G, H]), p.sigma_s)
+    else:
+        K = od.k_gamma(W, p.sigma_x, H, p.sigma_s_ineq, G, gamma)
+    shift = np.linalg.eigvalsh(K)[0] + theta
+    w = p.w_val.copy()
+    for i in range(p.n):
+        for k in range(p.w_ptr[i], p.w_ptr[i + 1]):
+            if p.w_idx[k] == i:
+                w[k] -= shift
+    return dataclasses.replace(p, w_val=w, name=f"{p.name}+curv{theta:g}")
