@@ -194,6 +194,62 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
  * failing column is then in ckkt_info.failed_column). */
 ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream);
 
+/* ---- Inertia correction (primal regularization delta_w) ----
+ *
+ * The augmented system K2 (Sec. 2.2, eq:kkt:augmented) is regularized by
+ * delta_w I on its primal and on its slack block whenever its inertia is not
+ * (n + m_i, m_i + m_e, 0); delta_w follows the inertia-controlling rule of
+ * Waechter & Biegler (2006, Sec. 3.1), which the paper adopts (Sec. 2.2,
+ * Remark 1).  By Sylvester's law (eq:ipm:inertia) the inertia is correct
+ * exactly when the condensed matrix is positive definite -- K_tau for
+ * LiftedKKT (Sec. 3.2), K_gamma for HyKKT once gamma exceeds its threshold
+ * (Sec. 3.1) -- so a Cholesky factorization that meets a non-positive pivot
+ * is the signal to try a larger delta_w.  Condensing K2 with delta_w
+ * (delta_c = 0) adds delta_w to sigma_x and to every slack weight sigma_s
+ * (for HyKKT only the inequality rows have slacks).
+ *
+ * Trials: delta_w = 0; then delta_w_0 when delta_w_last == 0, else
+ * max(delta_w_min, kappa_minus * delta_w_last); each failure multiplies by
+ * kappa_plus_bar (delta_w_last == 0) or kappa_plus (delta_w_last > 0); no
+ * trial above delta_w_max.  A success with delta_w > 0 stores it in
+ * delta_w_last.  The zero-eigenvalue branch of the rule (delta_c > 0) is
+ * not taken: a Cholesky factorization cannot tell a zero eigenvalue from a
+ * negative one, and a singular matrix is treated like an indefinite one. */
+typedef struct ckkt_inertia {
+    double  delta_w_min;     /* smallest nonzero trial                 (default 1e-20) */
+    double  delta_w_0;       /* first trial without history           (default 1e-4)  */
+    double  delta_w_max;     /* largest trial                          (default 1e40)  */
+    double  kappa_minus;     /* decrease of delta_w_last, in (0, 1)    (default 1/3)   */
+    double  kappa_plus;      /* growth with history, > 1               (default 8)     */
+    double  kappa_plus_bar;  /* growth without history, > 1            (default 100)   */
+    double  delta_w_last;    /* in/out: last nonzero delta_w accepted; 0 before the first */
+    double  delta_w;         /* out: delta_w of the accepted factor (the last trial on failure) */
+    int32_t attempts;        /* out: factorizations performed (>= 1) */
+    int32_t pad;
+} ckkt_inertia;
+
+/* Fills the parameters with the defaults above, delta_w_last = 0 and the
+ * outputs with zero. */
+void ckkt_default_inertia(ckkt_inertia* ic);
+
+/* Factorizes K (LiftedKKT) or K_gamma (HyKKT) of the system given by the
+ * arguments (same meaning and memory as ckkt_factorize: the UNREGULARIZED
+ * sigma_x and slack weights sigma_s) with the smallest trial delta_w of the
+ * rule above that gives a positive definite matrix.  Each trial is one
+ * ckkt_factorize of the shifted diagonals followed by one synchronization of
+ * `stream`; the shifted diagonals are kept in the workspace, so the
+ * following ckkt_solve calls refine against the regularized system.
+ *   ic : host, in/out (parameters, delta_w_last; delta_w and attempts out).
+ * FP64 handles of one system only (an FP32_IR factor pivots statically and
+ * reveals no definiteness; a batch has no single delta_w): else
+ * CKKT_ERR_ARG, as for parameters out of range.  Returns CKKT_ERR_NOT_SPD
+ * when every trial up to delta_w_max fails (delta_w_last unchanged; the
+ * factor then is that of the last trial and ckkt_solve reports
+ * CKKT_ERR_NOT_SPD), CKKT_ERR_NONFINITE / CKKT_ERR_HIP as ckkt_factorize. */
+ckkt_status ckkt_factorize_inertia(ckkt_handle* h, const double* w_val, const double* g_val,
+                                   const double* h_val, const double* sigma_x, const double* sigma_s,
+                                   double gamma, ckkt_inertia* ic, void* stream);
+
 /* Solve with the current factor (rows a3-a5): triangular sweeps plus FP64
  * iterative refinement with K applied unassembled (Sec. 2.2, "Iterative
  * refinement"); for HyKKT the CG of eq:kkt:schurcomplhykkt inside an outer
@@ -229,6 +285,15 @@ ckkt_status ckkt_export_k(ckkt_handle* h, int32_t* rows, int32_t* cols, double* 
 ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, const double* g_val,
                                   const double* h_val, const double* sigma_x, const double* sigma_s,
                                   double gamma, const double* rhs, double* sol, int32_t* failed_column);
+
+/* ckkt_factorize_inertia run on the host execution of ckkt_host_factor_solve:
+ * the same trials of delta_w, each a sequential host factorization, then
+ * x = K(delta_w)^{-1} rhs with the accepted factor.  All pointers are HOST
+ * memory (ic as in ckkt_factorize_inertia); needs no GPU.  Returns
+ * CKKT_ERR_NOT_SPD when every trial fails. */
+ckkt_status ckkt_host_factor_solve_inertia(const ckkt_handle* h, const double* w_val, const double* g_val,
+                                           const double* h_val, const double* sigma_x, const double* sigma_s,
+                                           double gamma, ckkt_inertia* ic, const double* rhs, double* sol);
 
 /* ---- Learned diagonal preconditioner (PCG around a stale factor) ----
  *

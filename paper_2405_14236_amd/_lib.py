@@ -55,6 +55,12 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class Inertia(ctypes.Structure):
+    _fields_ = [("delta_w_min", c_double), ("delta_w_0", c_double), ("delta_w_max", c_double),
+                ("kappa_minus", c_double), ("kappa_plus", c_double), ("kappa_plus_bar", c_double),
+                ("delta_w_last", c_double), ("delta_w", c_double), ("attempts", c_int32), ("pad", c_int32)]
+
+
 # (name, restype, argtypes): every entry point declared in include/ckkt.h
 SIGNATURES = [
     ("ckkt_default_options", None, [POINTER(Options)]),
@@ -64,11 +70,16 @@ SIGNATURES = [
     ("ckkt_bind_workspace", c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     ("ckkt_factorize", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p]),
     ("ckkt_factor_status", c_int32, [c_void_p, c_void_p]),
+    ("ckkt_default_inertia", None, [POINTER(Inertia)]),
+    ("ckkt_factorize_inertia", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                         POINTER(Inertia), c_void_p]),
     ("ckkt_solve", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(SolveInfo), c_void_p]),
     ("ckkt_apply_inverse", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("ckkt_export_k", c_int32, [c_void_p, P_i32, P_i32, c_void_p, c_void_p]),
     ("ckkt_host_factor_solve", c_int32, [c_void_p, P_f64, P_f64, P_f64, P_f64, P_f64, c_double, P_f64, P_f64,
                                          P_i32]),
+    ("ckkt_host_factor_solve_inertia", c_int32, [c_void_p, P_f64, P_f64, P_f64, P_f64, P_f64, c_double,
+                                                 POINTER(Inertia), P_f64, P_f64]),
     ("ckkt_features", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
                                 c_void_p]),
     ("ckkt_mlp_forward", c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

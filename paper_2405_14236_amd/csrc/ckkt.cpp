@@ -79,6 +79,7 @@ struct ckkt_handle {
         r_tilesn, r_tilecol, r_wfptr, r_wfcol, r_wfvidx, r_jptr, r_jcol, r_jtptr, r_jtrow, r_jtvidx, r_jtgend,
         r_instvar, r_insteq, r_kcol, r_cbptr, r_cbsrc, r_cblen, r_cbuoff;
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
+    Region r_sxreg, r_ssreg;  // diagonals shifted by delta_w (inertia correction)
     Region r_ctl, r_done;  // dependency-driven sweeps: control words, per-supernode flags
     Region r_tflag;        // block flags of the tiled fronts (one launch per level)
     int64_t n_tflags = 0;
@@ -97,6 +98,7 @@ struct ckkt_handle {
     size_t ws_bytes = 0;
     DevPlan dp{};
     double *K = nullptr, *d = nullptr, *scale = nullptr, *uvec = nullptr, *vperm = nullptr;
+    double *sxreg = nullptr, *ssreg = nullptr;
     double* arena64 = nullptr;
     float* arena32 = nullptr;
     int32_t* status = nullptr;  // [0] failing column, [1] FP32 pivot floors, [2] sweep wait failure
@@ -326,6 +328,8 @@ void build_layout(ckkt_handle* h) {
     h->r_bits = L.add((P.ninst + 2) * sizeof(unsigned long long));
     h->r_dotpart = L.add(kDotBlocks * sizeof(double));
     h->r_sc = L.add(16 * sizeof(double));
+    h->r_sxreg = L.add(n * sizeof(double));
+    h->r_ssreg = L.add(m * sizeof(double));
     h->r_vn.clear();
     h->r_vm.clear();
     h->r_veq.clear();
@@ -396,6 +400,8 @@ void fill_devplan(ckkt_handle* h) {
     h->bits = at<unsigned long long>(h, h->r_bits);
     h->dotpart = at<double>(h, h->r_dotpart);
     h->sc = at<double>(h, h->r_sc);
+    h->sxreg = at<double>(h, h->r_sxreg);
+    h->ssreg = at<double>(h, h->r_ssreg);
     h->vn.clear(); h->vm.clear(); h->veq.clear();
     for (auto& r : h->r_vn) h->vn.push_back(at<double>(h, r));
     for (auto& r : h->r_vm) h->vm.push_back(at<double>(h, r));
@@ -1035,6 +1041,42 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
     return CKKT_OK;
 }
 
+static bool inertia_params_ok(const ckkt_inertia* ic) {
+    if (!ic) return false;
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    return pos(ic->delta_w_min) && pos(ic->delta_w_0) && pos(ic->delta_w_max) && pos(ic->kappa_minus) &&
+           ic->kappa_minus < 1.0 && pos(ic->kappa_plus) && ic->kappa_plus > 1.0 && pos(ic->kappa_plus_bar) &&
+           ic->kappa_plus_bar > 1.0 && std::isfinite(ic->delta_w_last) && ic->delta_w_last >= 0.0;
+}
+
+// Inertia-controlling rule of Waechter & Biegler (2006, Sec. 3.1) without
+// its zero-eigenvalue branch: `attempt(delta_w)` factorizes the system
+// regularized by delta_w and returns CKKT_OK (positive definite, hence the
+// inertia of K2 is correct by eq:ipm:inertia), CKKT_ERR_NOT_SPD, or another
+// error that ends the search.  Every trial is larger than the one before by
+// a factor > 1 and all are bounded by delta_w_max, so the loop ends.
+template <class Attempt>
+static ckkt_status inertia_search(ckkt_inertia* ic, Attempt attempt) {
+    const bool history = ic->delta_w_last > 0.0;
+    double delta = 0.0;
+    ic->attempts = 0;
+    for (;;) {
+        ++ic->attempts;
+        ic->delta_w = delta;
+        const ckkt_status rc = attempt(delta);
+        if (rc == CKKT_OK) {
+            if (delta > 0.0) ic->delta_w_last = delta;
+            return CKKT_OK;
+        }
+        if (rc != CKKT_ERR_NOT_SPD) return rc;
+        if (delta == 0.0)
+            delta = history ? std::max(ic->delta_w_min, ic->kappa_minus * ic->delta_w_last) : ic->delta_w_0;
+        else
+            delta *= history ? ic->kappa_plus : ic->kappa_plus_bar;
+        if (!(delta <= ic->delta_w_max)) return CKKT_ERR_NOT_SPD;
+    }
+}
+
 }  // namespace
 
 // ================================================================= C-ABI
@@ -1052,6 +1094,17 @@ void ckkt_default_options(ckkt_options* o) {
     o->relax = 1;
     o->lds_front_max = 0;
     o->learned = 0;
+}
+
+void ckkt_default_inertia(ckkt_inertia* ic) {
+    if (!ic) return;
+    std::memset(ic, 0, sizeof(*ic));
+    ic->delta_w_min = 1e-20;
+    ic->delta_w_0 = 1e-4;
+    ic->delta_w_max = 1e40;
+    ic->kappa_minus = 1.0 / 3.0;
+    ic->kappa_plus = 8.0;
+    ic->kappa_plus_bar = 100.0;
 }
 
 ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
@@ -1260,6 +1313,26 @@ ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream) {
     return CKKT_OK;
 }
 
+ckkt_status ckkt_factorize_inertia(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                                   const double* sigma_x, const double* sigma_s, double gamma, ckkt_inertia* ic,
+                                   void* stream) {
+    if (!h || !inertia_params_ok(ic)) return CKKT_ERR_ARG;
+    if (h->precision != CKKT_FP64 || h->plan.ninst > 1) return CKKT_ERR_ARG;
+    if (!h->ws) return CKKT_ERR_STATE;
+    const Plan& P = h->plan;
+    const int64_t ns_len = h->formulation == CKKT_HYKKT ? P.m_ineq : P.m;
+    if ((P.n > 0 && !sigma_x) || (ns_len > 0 && !sigma_s)) return CKKT_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return inertia_search(ic, [&](double delta) -> ckkt_status {
+        (void)hipGetLastError();  // report only errors of this trial's own launches
+        launch_shift_copy((int)P.n, sigma_x, delta, h->sxreg, st);
+        launch_shift_copy((int)ns_len, sigma_s, delta, h->ssreg, st);
+        if (hipGetLastError() != hipSuccess) return CKKT_ERR_HIP;
+        ckkt_status rc = ckkt_factorize(h, w_val, g_val, h_val, h->sxreg, h->ssreg, gamma, stream);
+        return rc != CKKT_OK ? rc : ckkt_factor_status(h, stream);
+    });
+}
+
 ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol, ckkt_solve_info* info, void* stream) {
     ckkt_solve_info local{};
     if (!info) info = &local;
@@ -1314,6 +1387,23 @@ ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, co
                                rhs, sol);
     if (failed_column) *failed_column = fc;
     return fc >= 0 ? CKKT_ERR_NOT_SPD : CKKT_OK;
+}
+
+ckkt_status ckkt_host_factor_solve_inertia(const ckkt_handle* h, const double* w_val, const double* g_val,
+                                           const double* h_val, const double* sigma_x, const double* sigma_s,
+                                           double gamma, ckkt_inertia* ic, const double* rhs, double* sol) {
+    if (!h || !rhs || !sol || !inertia_params_ok(ic) || h->plan.ninst > 1) return CKKT_ERR_ARG;
+    const Plan& P = h->plan;
+    const bool hy = h->formulation == CKKT_HYKKT;
+    const int64_t ns_len = hy ? P.m_ineq : P.m;
+    if ((P.n > 0 && !sigma_x) || (ns_len > 0 && !sigma_s)) return CKKT_ERR_ARG;
+    std::vector<double> sx(P.n), ss(ns_len);
+    return inertia_search(ic, [&](double delta) -> ckkt_status {
+        for (int64_t i = 0; i < P.n; ++i) sx[i] = sigma_x[i] + delta;
+        for (int64_t r = 0; r < ns_len; ++r) ss[r] = sigma_s[r] + delta;
+        int fc = host_factor_solve(P, hy, w_val, g_val, h_val, sx.data(), ss.data(), gamma, rhs, sol);
+        return fc >= 0 ? CKKT_ERR_NOT_SPD : CKKT_OK;
+    });
 }
 
 static ckkt_status set_new_values(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,

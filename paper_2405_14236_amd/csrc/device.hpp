@@ -158,6 +158,7 @@ void launch_maxabs(int n, const double* x, unsigned long long* bits, hipStream_t
 void launch_axpy(int n, double alpha, const double* x, double* y, hipStream_t st);  // y += a x
 void launch_copy(int n, const double* x, double* y, hipStream_t st);
 void launch_fill(int n, double v, double* y, hipStream_t st);
+void launch_shift_copy(int n, const double* x, double delta, double* y, hipStream_t st);  // y = x + delta
 // out_i = base_i + scale * (G^T y)_i   (base may be null)
 void launch_gt(const DevPlan& P, const SysVals& v, const double* base, double scale, const double* y,
                double* out, hipStream_t st);

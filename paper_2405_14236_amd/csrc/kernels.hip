@@ -1979,6 +1979,11 @@ __global__ void k_fill(int n, double val, double* __restrict__ y) {
     if (i < n) y[i] = val;
 }
 
+__global__ void k_shift_copy(int n, const double* __restrict__ x, double delta, double* __restrict__ y) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] + delta;
+}
+
 // out_i = base_i + scale * sum_{r < m_eq} G_ri y_r
 __global__ void k_gt(DevPlan P, SysVals v, const double* __restrict__ base, double scale,
                      const double* __restrict__ y, double* __restrict__ out) {
@@ -2552,6 +2557,9 @@ void launch_copy(int n, const double* x, double* y, hipStream_t st) {
 }
 void launch_fill(int n, double v, double* y, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, st, n, v, y);
+}
+void launch_shift_copy(int n, const double* x, double delta, double* y, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_shift_copy, dim3(nblk(n)), dim3(256), 0, st, n, x, delta, y);
 }
 void launch_gt(const DevPlan& P, const SysVals& v, const double* base, double scale, const double* y,
                double* out, hipStream_t st) {

@@ -129,6 +129,24 @@ class Solver:
     def factor_status(self):
         return self.lib.ckkt_factor_status(self.h, _stream())
 
+    def factorize_inertia(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma=0.0, delta_w_last=0.0,
+                          raise_on_error=True, **params):
+        """Factorization with inertia correction (ckkt_factorize_inertia).
+
+        sigma_x / sigma_s are the unregularized diagonals; ``params`` override
+        the rule's constants (delta_w_min, delta_w_0, delta_w_max, kappa_minus,
+        kappa_plus, kappa_plus_bar).  Returns (status, dict with delta_w,
+        attempts and delta_w_last)."""
+        if self.workspace is None:
+            self.bind()
+        self._vals = (w_val, g_val, h_val, sigma_x, sigma_s)
+        ic = inertia_params(delta_w_last, **params)
+        st = self.lib.ckkt_factorize_inertia(self.h, _ptr(w_val), _ptr(g_val), _ptr(h_val), _ptr(sigma_x),
+                                             _ptr(sigma_s), float(gamma), ctypes.byref(ic), _stream())
+        if raise_on_error:
+            L.check(st, "ckkt_factorize_inertia")
+        return st, inertia_result(ic)
+
     def solve(self, rhs, out=None, raise_on_error=True):
         import torch
         if out is None:
@@ -217,6 +235,32 @@ class Solver:
                                              float(gamma), keep[5][1], out.ctypes.data_as(L.P_f64),
                                              ctypes.byref(fc))
         return out, st, fc.value
+
+    def host_factor_solve_inertia(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma, rhs, delta_w_last=0.0,
+                                  **params):
+        """Host run of the inertia-corrected factorization, then one solve."""
+        keep = [_f64(a) for a in (w_val, g_val, h_val, sigma_x, sigma_s, rhs)]
+        out = np.empty(len(rhs), np.float64)
+        ic = inertia_params(delta_w_last, **params)
+        st = self.lib.ckkt_host_factor_solve_inertia(self.h, keep[0][1], keep[1][1], keep[2][1], keep[3][1],
+                                                     keep[4][1], float(gamma), ctypes.byref(ic), keep[5][1],
+                                                     out.ctypes.data_as(L.P_f64))
+        return out, st, inertia_result(ic)
+
+
+def inertia_params(delta_w_last=0.0, **params):
+    ic = L.Inertia()
+    L.load().ckkt_default_inertia(ctypes.byref(ic))
+    ic.delta_w_last = float(delta_w_last)
+    for k, v in params.items():
+        if k not in ("delta_w_min", "delta_w_0", "delta_w_max", "kappa_minus", "kappa_plus", "kappa_plus_bar"):
+            raise TypeError(f"unknown inertia parameter {k}")
+        setattr(ic, k, float(v))
+    return ic
+
+
+def inertia_result(ic):
+    return {"delta_w": ic.delta_w, "attempts": ic.attempts, "delta_w_last": ic.delta_w_last}
 
 
 def device_values(prob, device="cuda", formulation="lifted"):
