@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nodes", type=int, default=10_000)
-    ap.add_argument("--forms", default="lifted_fp64,hykkt_fp64")
+    ap.add_argument("--forms", default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -82,13 +82,36 @@ def algorithmic_counts(p, info, formulation):
                 sweep_bytes=sweep_bytes, sweep_flops=4 * nnz_l, resid_bytes=resid_bytes)
 
 
+INERTIA_SHIFT = 1.0
+
+
 def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
-    formulation, precision = form.split("_", 1)
+    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia].  The _inertia forms
+    lower W's diagonal by INERTIA_SHIFT (negative curvature wherever K_jj is
+    below it) and factorize with inertia correction, carrying delta_w_last
+    from one system to the next as an interior-point method does."""
+    formulation, precision, *variant = form.split("_")
     prec = {"fp64": "fp64", "fp32ir": "fp32_ir"}[precision]
+    inertia = variant == ["inertia"]
     dev = "cuda"
     s = Solver(p, formulation, prec).bind(dev)
     info = s.info()
     w, g, h, _, _ = device_values(p, dev, formulation)
+    if inertia:
+        rows = np.repeat(np.arange(p.n), np.diff(p.w_ptr))
+        wv = p.w_val.copy()
+        wv[rows == p.w_idx] -= INERTIA_SHIFT
+        w = torch.as_tensor(wv, device=dev)
+    last, attempts, deltas = [0.0], [], []
+
+    def factorize(k):
+        if not inertia:
+            s.factorize(w, g, h, sx[k], ss[k], gamma)
+            return
+        st, r = s.factorize_inertia(w, g, h, sx[k], ss[k], gamma, delta_w_last=last[0])
+        last[0] = r["delta_w_last"]
+        attempts.append(r["attempts"])
+        deltas.append(r["delta_w"])
     sx = [torch.as_tensor(a, device=dev) for a, _ in sig]
     ss = [torch.as_tensor(b if formulation == "lifted" else b[p.m_eq:], device=dev) for _, b in sig]
     rhs = np.concatenate([p.r1bar, p.r2bar]) if formulation == "hykkt" else p.b
@@ -96,15 +119,17 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     out = torch.empty_like(rhs)
     gamma = 1e7
     for k in range(warmup):
-        s.factorize(w, g, h, sx[k], ss[k], gamma)
+        factorize(k)
         s.solve(rhs, out)
+    attempts.clear()
+    deltas.clear()
     s.set_timing(True)
     s.get_timing()  # reset
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
-        s.factorize(w, g, h, sx[k], ss[k], gamma)
+        factorize(k)
         _, si = s.solve(rhs, out, raise_on_error=False)
         infos.append(si)
     torch.cuda.synchronize()
@@ -112,7 +137,11 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     ms, calls = s.get_timing()
     s.set_timing(False)
     ok = all(si["status"] == 0 and si["omega"] <= 1e-8 for si in infos)
-    return dict(solves_per_s=steps / (t1 - t0), ms_per_solve=1e3 * (t1 - t0) / steps, gate_ok=ok,
+    extra = {}
+    if inertia:
+        extra = dict(w_diag_shift=-INERTIA_SHIFT, attempts_mean=float(np.mean(attempts)),
+                     delta_w=[float(f"{d:.4g}") for d in deltas])
+    return dict(solves_per_s=steps / (t1 - t0), ms_per_solve=1e3 * (t1 - t0) / steps, gate_ok=ok, **extra,
                 omega_max=max(si["omega"] for si in infos), rho_max=max(si["rho"] for si in infos),
                 refine_steps=float(np.mean([si["refine_steps"] for si in infos])),
                 cg_iters=float(np.mean([si["cg_iters"] for si in infos])),
