@@ -83,9 +83,12 @@ def assemble_k_gamma(W, sigma_x, H, sigma_h, G, gamma):
     return (W + sp.diags(sigma_x) + H.T @ sp.diags(sigma_h) @ H + gamma * (G.T @ G)).tocsc()
 
 
-def k1_matrix(K, G):
-    """[[K, G^T], [G, 0]] (Sec. 2.2, K1 with delta_c = 0)."""
-    return sp.bmat([[K, G.T], [G, None]]).tocsc()
+def k1_matrix(K, G, delta_c=0.0):
+    """[[K, G^T], [G, -delta_c I]] (Sec. 2.2, K1; delta_c = 0 on the hot path,
+    delta_c > 0 is the dual regularization of Remark 1)."""
+    if delta_c == 0.0:
+        return sp.bmat([[K, G.T], [G, None]]).tocsc()
+    return sp.bmat([[K, G.T], [G, -delta_c * sp.identity(G.shape[0])]]).tocsc()
 
 
 # ------------------------------------------------------------- residuals ----
@@ -117,26 +120,27 @@ def eta_condensed(W, sigma_x, J, sigma_s, x, b):
     return np.abs(r).max() / (knorm * np.abs(x).max() + np.abs(b).max())
 
 
-def k1_residual(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar):
-    """Residual blocks of K1 (delta_c = 0) with K unassembled."""
+def k1_residual(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar, delta_c=0.0):
+    """Residual blocks of K1 = [[K, G^T], [G, -delta_c I]] with K unassembled."""
     row1 = r1bar - (apply_condensed(W, sigma_x, H, sigma_h, dx) + G.T @ dy)
-    row2 = r2bar - G @ dx
+    row2 = r2bar - (G @ dx - delta_c * dy)
     return row1, row2
 
 
-def omega_k1(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar):
-    """Componentwise relative backward error of (dx, dy) on K1 w.r.t. its data."""
-    row1, row2 = k1_residual(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar)
+def omega_k1(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar, delta_c=0.0):
+    """Componentwise relative backward error of (dx, dy) on K1 w.r.t. its data
+    (delta_c is one more datum of the second block row)."""
+    row1, row2 = k1_residual(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar, delta_c)
     ax, ay = np.abs(dx), np.abs(dy)
     aH, aG = abs(H), abs(G)
     den1 = (abs(W) @ ax + np.abs(sigma_x) * ax + aH.T @ (np.abs(sigma_h) * (aH @ ax))
             + aG.T @ ay + np.abs(r1bar))
-    den2 = aG @ ax + np.abs(r2bar)
+    den2 = aG @ ax + abs(delta_c) * ay + np.abs(r2bar)
     return max(_cw_ratio(row1, den1), _cw_ratio(row2, den2))
 
 
-def rho_k1(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar):
-    row1, row2 = k1_residual(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar)
+def rho_k1(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar, delta_c=0.0):
+    row1, row2 = k1_residual(W, sigma_x, H, sigma_h, G, dx, dy, r1bar, r2bar, delta_c)
     num = max(np.abs(row1).max(), np.abs(row2).max() if row2.size else 0.0)
     den = max(np.abs(r1bar).max(), np.abs(r2bar).max() if r2bar.size else 0.0)
     return num / max(den, 1e-300)
@@ -168,21 +172,22 @@ def solve_lifted(P: Problem, sigma_x, sigma_s, b, tol=1e-15, maxit=5):
     return x, hist
 
 
-def solve_k1(P: Problem, sigma_x, sigma_h, r1bar, r2bar, tol=1e-15, maxit=5):
-    """(d_x, d_y) of K1 directly (Sec. 2.2): SuperLU with pivoting on the
+def solve_k1(P: Problem, sigma_x, sigma_h, r1bar, r2bar, tol=1e-15, maxit=5, delta_c=0.0):
+    """(d_x, d_y) of K1 directly (Sec. 2.2; with -delta_c I in its (2,2)
+    block when delta_c > 0, Remark 1): SuperLU with pivoting on the
     indefinite saddle matrix, refined with the unassembled K1.  Returns
     (d_x, d_y, omega history)."""
     n = P.n
     K = assemble_condensed(P.W, sigma_x, P.H, sigma_h)
-    lu = spla.splu(k1_matrix(K, P.G))
+    lu = spla.splu(k1_matrix(K, P.G, delta_c))
     rhs = np.concatenate([r1bar, r2bar])
     sol = lu.solve(rhs)
     hist = []
     for _ in range(maxit + 1):
         dx, dy = sol[:n], sol[n:]
-        row1, row2 = k1_residual(P.W, sigma_x, P.H, sigma_h, P.G, dx, dy, r1bar, r2bar)
+        row1, row2 = k1_residual(P.W, sigma_x, P.H, sigma_h, P.G, dx, dy, r1bar, r2bar, delta_c)
         res = np.concatenate([row1, row2])
-        hist.append(omega_k1(P.W, sigma_x, P.H, sigma_h, P.G, dx, dy, r1bar, r2bar))
+        hist.append(omega_k1(P.W, sigma_x, P.H, sigma_h, P.G, dx, dy, r1bar, r2bar, delta_c))
         if hist[-1] <= tol:
             break
         sol = sol + lu.solve(res)
