@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nodes", type=int, default=10_000)
-    ap.add_argument("--forms", default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia")
+    ap.add_argument("--forms", default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia,hykkt_fp64_dualreg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -86,13 +86,16 @@ INERTIA_SHIFT = 1.0
 
 
 def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
-    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia].  The _inertia forms
-    lower W's diagonal by INERTIA_SHIFT (negative curvature wherever K_jj is
-    below it) and factorize with inertia correction, carrying delta_w_last
-    from one system to the next as an interior-point method does."""
+    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia|_dualreg].  The _inertia
+    forms lower W's diagonal by INERTIA_SHIFT (negative curvature wherever
+    K_jj is below it) and factorize with inertia correction, carrying
+    delta_w_last from one system to the next as an interior-point method
+    does.  hykkt_*_dualreg solves K1 with dual regularization delta_c = 1/gamma
+    directly through the same K_gamma factor (no CG)."""
     formulation, precision, *variant = form.split("_")
     prec = {"fp64": "fp64", "fp32ir": "fp32_ir"}[precision]
     inertia = variant == ["inertia"]
+    dualreg = variant == ["dualreg"]
     dev = "cuda"
     s = Solver(p, formulation, prec).bind(dev)
     info = s.info()
@@ -105,6 +108,9 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     last, attempts, deltas = [0.0], [], []
 
     def factorize(k):
+        if dualreg:
+            s.factorize_dual_reg(w, g, h, sx[k], ss[k], 1.0 / gamma)
+            return
         if not inertia:
             s.factorize(w, g, h, sx[k], ss[k], gamma)
             return
@@ -137,7 +143,7 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     ms, calls = s.get_timing()
     s.set_timing(False)
     ok = all(si["status"] == 0 and si["omega"] <= 1e-8 for si in infos)
-    extra = {}
+    extra = {"delta_c": 1.0 / gamma} if dualreg else {}
     if inertia:
         extra = dict(w_diag_shift=-INERTIA_SHIFT, attempts_mean=float(np.mean(attempts)),
                      delta_w=[float(f"{d:.4g}") for d in deltas])

@@ -194,6 +194,22 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
  * failing column is then in ckkt_info.failed_column). */
 ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream);
 
+/* HyKKT handles: the numeric phase for a system with dual regularization
+ * delta_c > 0 (Remark 1, eqn:primal).  K1 then carries -delta_c I in its
+ * (2,2) block, and eliminating d_y = (G d_x - rbar2) / delta_c leaves the
+ * primal Schur complement K + G^T G / delta_c, which is K_gamma with
+ * gamma = 1 / delta_c: this call is ckkt_factorize with that gamma (same
+ * arguments, memory and errors).  The following ckkt_solve calls solve
+ * K1(delta_c) (d_x, d_y) = (rbar1, rbar2) directly, without CG:
+ * d_x = K_gamma^{-1}(rbar1 + G^T rbar2 / delta_c), d_y = (G d_x - rbar2) / delta_c,
+ * inside the same FP64 refinement on K1(delta_c), whose backward error
+ * counts delta_c as data of the second block row.  The next ckkt_factorize
+ * returns the handle to delta_c = 0.  CKKT_ERR_ARG for LiftedKKT handles and
+ * unless delta_c and 1/delta_c are both positive and finite. */
+ckkt_status ckkt_factorize_dual_reg(ckkt_handle* h, const double* w_val, const double* g_val,
+                                    const double* h_val, const double* sigma_x, const double* sigma_s,
+                                    double delta_c, void* stream);
+
 /* ---- Inertia correction (primal regularization delta_w) ----
  *
  * The augmented system K2 (Sec. 2.2, eq:kkt:augmented) is regularized by

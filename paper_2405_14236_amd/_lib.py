@@ -70,6 +70,8 @@ SIGNATURES = [
     ("ckkt_bind_workspace", c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     ("ckkt_factorize", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p]),
     ("ckkt_factor_status", c_int32, [c_void_p, c_void_p]),
+    ("ckkt_factorize_dual_reg", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                          c_void_p]),
     ("ckkt_default_inertia", None, [POINTER(Inertia)]),
     ("ckkt_factorize_inertia", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                                          POINTER(Inertia), c_void_p]),

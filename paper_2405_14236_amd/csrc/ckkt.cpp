@@ -899,6 +899,26 @@ ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_
 
 // ------------------------------------------------------------ HyKKT
 
+// One solve of K1 = [[K, G^T], [G, -delta_c I]] (dx, dy) = (R1, R2) for
+// delta_c > 0 by the primal Schur complement of Remark 1 (eqn:primal), whose
+// matrix K + G^T G / delta_c is the factor's K_gamma with gamma = 1/delta_c:
+// dx = K_gamma^{-1}(R1 + gamma G^T R2), dy = gamma (G dx - R2).  No CG.
+void primal_schur_inner(ckkt_handle* h, const double* R1, const double* R2, double* dx, double* dy, bool use64,
+                        hipStream_t st) {
+    const DevPlan& P = h->dp;
+    double* s = h->vn[2];
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_gt(P, h->vals, R1, h->vals.gamma, R2, s, st);
+    }
+    apply_inverse(h, s, dx, use64, st);
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_g(P, h->vals, dx, R2, dy, st);
+        launch_scale(P.m_eq, h->vals.gamma, dy, st);
+    }
+}
+
 // One HyKKT solve of K1 (dx, dy) = (R1, R2) through K_gamma (Sec. 3.1):
 // s = R1 + gamma G^T R2, w = K_gamma^{-1} s, CG on S_gamma dy = G w - R2
 // (eq:kkt:schurcomplhykkt) from dy = 0, then dx = w - sum_k alpha_k u_k with
@@ -1016,7 +1036,10 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
         prev = r.omega;
         int it = 0;
         bool ok = true;
-        rc = hykkt_inner(h, res1, res2, ddx, ddy, use64, it, ok, st);
+        if (h->vals.delta_c > 0.0)
+            primal_schur_inner(h, res1, res2, ddx, ddy, use64, st);
+        else
+            rc = hykkt_inner(h, res1, res2, ddx, ddy, use64, it, ok, st);
         info->cg_iters += it;
         last_cg_ok = ok;
         if (rc == CKKT_ERR_BREAKDOWN && !use64) {
@@ -1294,6 +1317,19 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
     }
     if (hipGetLastError() != hipSuccess) return CKKT_ERR_HIP;
     h->factored = true;
+    return CKKT_OK;
+}
+
+ckkt_status ckkt_factorize_dual_reg(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
+                                    const double* sigma_x, const double* sigma_s, double delta_c, void* stream) {
+    if (!h) return CKKT_ERR_ARG;
+    const double gamma = 1.0 / delta_c;
+    if (h->formulation != CKKT_HYKKT || !(delta_c > 0.0) || !std::isfinite(delta_c) || !std::isfinite(gamma) ||
+        !(gamma > 0.0))
+        return CKKT_ERR_ARG;
+    ckkt_status rc = ckkt_factorize(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, stream);
+    if (rc != CKKT_OK) return rc;
+    h->vals.delta_c = delta_c;  // ckkt_factorize leaves it 0; ckkt_solve now takes the direct path
     return CKKT_OK;
 }
 

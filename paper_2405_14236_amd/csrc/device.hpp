@@ -28,6 +28,7 @@ struct DevPlan {
 struct SysVals {
     const double *w_val, *g_val, *h_val, *sigma_x, *sigma_s;
     double gamma;
+    double delta_c = 0.0;  // HyKKT: K1 carries -delta_c I in its (2,2) block (Remark 1)
 };
 
 // Per-level launch geometry, computed on the host from the plan.
@@ -159,6 +160,7 @@ void launch_axpy(int n, double alpha, const double* x, double* y, hipStream_t st
 void launch_copy(int n, const double* x, double* y, hipStream_t st);
 void launch_fill(int n, double v, double* y, hipStream_t st);
 void launch_shift_copy(int n, const double* x, double delta, double* y, hipStream_t st);  // y = x + delta
+void launch_scale(int n, double alpha, double* y, hipStream_t st);                     // y = alpha y
 // out_i = base_i + scale * (G^T y)_i   (base may be null)
 void launch_gt(const DevPlan& P, const SysVals& v, const double* base, double scale, const double* y,
                double* out, hipStream_t st);

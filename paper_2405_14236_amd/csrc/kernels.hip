@@ -1860,12 +1860,13 @@ __global__ void k_scatter_perm(DevPlan P, const double* __restrict__ in, double*
 
 // Residual, pass 1 (one thread per constraint row): for rows weighted by d
 // (LiftedKKT all rows; HyKKT rows of H) t = d (J x) and ta = |d| (|J||x|);
-// for HyKKT rows of G the K1 second-block residual rhs2 - G x and its
-// componentwise ratio.
+// for HyKKT rows of G the K1 second-block residual rhs2 - (G x - delta_c y)
+// and its componentwise ratio.
 __global__ void __launch_bounds__(256)
 k_resid_rows(DevPlan P, SysVals v, const double* __restrict__ d, const double* __restrict__ x,
-             const double* __restrict__ rhs2, double* __restrict__ res2, double* __restrict__ t,
-             double* __restrict__ ta, unsigned long long* omega_bits, unsigned long long* resmax_bits) {
+             const double* __restrict__ y, const double* __restrict__ rhs2, double* __restrict__ res2,
+             double* __restrict__ t, double* __restrict__ ta, unsigned long long* omega_bits,
+             unsigned long long* resmax_bits) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = r < P.m;
     double acc = 0.0, mag = 0.0;
@@ -1880,6 +1881,11 @@ k_resid_rows(DevPlan P, SysVals v, const double* __restrict__ d, const double* _
     double ratio = 0.0, num = 0.0;
     int inst = -1;
     if (eq) {
+        if (v.delta_c != 0.0) {
+            const double q = v.delta_c * y[r];
+            acc -= q;
+            mag += fabs(q);
+        }
         double res = rhs2[r] - acc;
         res2[r] = res;
         num = fabs(res);
@@ -1982,6 +1988,11 @@ __global__ void k_fill(int n, double val, double* __restrict__ y) {
 __global__ void k_shift_copy(int n, const double* __restrict__ x, double delta, double* __restrict__ y) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = x[i] + delta;
+}
+
+__global__ void k_scale(int n, double alpha, double* __restrict__ y) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] *= alpha;
 }
 
 // out_i = base_i + scale * sum_{r < m_eq} G_ri y_r
@@ -2538,8 +2549,8 @@ void launch_residual(const DevPlan& P, const SysVals& v, const double* d, const 
                      double* res2, double* tbuf, double* tabuf, unsigned long long* omega_bits,
                      unsigned long long* resmax_bits, hipStream_t st) {
     if (P.m > 0)
-        hipLaunchKernelGGL(k_resid_rows, dim3(nblk(P.m)), dim3(256), 0, st, P, v, d, x, rhs2, res2, tbuf, tabuf,
-                           omega_bits, resmax_bits);
+        hipLaunchKernelGGL(k_resid_rows, dim3(nblk(P.m)), dim3(256), 0, st, P, v, d, x, y, rhs2, res2, tbuf,
+                           tabuf, omega_bits, resmax_bits);
     if (P.n > 0)
         hipLaunchKernelGGL(k_resid_vars, dim3(nblk(P.n)), dim3(256), 0, st, P, v, x, y, rhs1, tbuf, tabuf, res1,
                            omega_bits, resmax_bits);
@@ -2560,6 +2571,9 @@ void launch_fill(int n, double v, double* y, hipStream_t st) {
 }
 void launch_shift_copy(int n, const double* x, double delta, double* y, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_shift_copy, dim3(nblk(n)), dim3(256), 0, st, n, x, delta, y);
+}
+void launch_scale(int n, double alpha, double* y, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(256), 0, st, n, alpha, y);
 }
 void launch_gt(const DevPlan& P, const SysVals& v, const double* base, double scale, const double* y,
                double* out, hipStream_t st) {

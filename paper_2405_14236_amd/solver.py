@@ -129,6 +129,16 @@ class Solver:
     def factor_status(self):
         return self.lib.ckkt_factor_status(self.h, _stream())
 
+    def factorize_dual_reg(self, w_val, g_val, h_val, sigma_x, sigma_s, delta_c):
+        """HyKKT with dual regularization delta_c > 0 (ckkt_factorize_dual_reg):
+        the following solves are direct, without CG."""
+        if self.workspace is None:
+            self.bind()
+        self._vals = (w_val, g_val, h_val, sigma_x, sigma_s)
+        L.check(self.lib.ckkt_factorize_dual_reg(self.h, _ptr(w_val), _ptr(g_val), _ptr(h_val), _ptr(sigma_x),
+                                                 _ptr(sigma_s), float(delta_c), _stream()),
+                "ckkt_factorize_dual_reg")
+
     def factorize_inertia(self, w_val, g_val, h_val, sigma_x, sigma_s, gamma=0.0, delta_w_last=0.0,
                           raise_on_error=True, **params):
         """Factorization with inertia correction (ckkt_factorize_inertia).

@@ -207,3 +207,16 @@ def test_batch_analysis_is_block_diagonal():
         xi = x[off:off + q.n]
         assert osp.omega_condensed(P.W, q.sigma_x, P.J, q.sigma_s, xi, q.b) < 1e-10
         off += q.n
+
+
+def test_dual_reg_arguments_rejected_without_gpu():
+    """ckkt_factorize_dual_reg: HyKKT handles and 0 < delta_c with finite 1/delta_c only."""
+    p = workloads.tiny_grid(0, nx=3, ny=3)
+    lib = _lib.load()
+    lifted = Solver(p, "lifted")
+    assert lib.ckkt_factorize_dual_reg(lifted.h, None, None, None, None, None, 1e-4, None) == -1
+    hy = Solver(p, "hykkt")
+    for dc in (0.0, -1.0, float("nan"), float("inf"), 1e-320):
+        assert lib.ckkt_factorize_dual_reg(hy.h, None, None, None, None, None, dc, None) == -1, dc
+    assert lib.ckkt_factorize_dual_reg(hy.h, None, None, None, None, None, 1e-4, None) == -6  # no workspace
+    assert lib.ckkt_factorize_dual_reg(None, None, None, None, None, None, 1e-4, None) == -1
