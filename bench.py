@@ -32,7 +32,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nodes", type=int, default=10_000)
-    ap.add_argument("--forms", default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia,hykkt_fp64_dualreg")
+    ap.add_argument("--forms",
+                    default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia,hykkt_fp64_dualreg,lifted_fp64_k2,hykkt_fp64_k2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -86,16 +87,19 @@ INERTIA_SHIFT = 1.0
 
 
 def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
-    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia|_dualreg].  The _inertia
+    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia|_dualreg|_k2].  The _inertia
     forms lower W's diagonal by INERTIA_SHIFT (negative curvature wherever
     K_jj is below it) and factorize with inertia correction, carrying
     delta_w_last from one system to the next as an interior-point method
     does.  hykkt_*_dualreg solves K1 with dual regularization delta_c = 1/gamma
-    directly through the same K_gamma factor (no CG)."""
+    directly through the same K_gamma factor (no CG).  The _k2 forms take the
+    full Newton step of the augmented system K2 (ckkt_solve_augmented) for
+    seeded r1..r4 instead of the condensed solve."""
     formulation, precision, *variant = form.split("_")
     prec = {"fp64": "fp64", "fp32ir": "fp32_ir"}[precision]
     inertia = variant == ["inertia"]
     dualreg = variant == ["dualreg"]
+    k2 = variant == ["k2"]
     dev = "cuda"
     s = Solver(p, formulation, prec).bind(dev)
     info = s.info()
@@ -123,10 +127,22 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     rhs = np.concatenate([p.r1bar, p.r2bar]) if formulation == "hykkt" else p.b
     rhs = torch.as_tensor(rhs, device=dev)
     out = torch.empty_like(rhs)
+    if k2:
+        rng = np.random.default_rng(5)
+        ms = p.m if formulation == "lifted" else p.m_ineq
+        me = 0 if formulation == "lifted" else p.m_eq
+        rk2 = [torch.as_tensor(rng.standard_normal(c), device=dev) for c in (p.n, ms, me, ms)]
+        if formulation == "lifted":
+            rk2[2] = None
+
+    def solve(raise_on_error=True):
+        if k2:
+            return s.solve_augmented(*rk2, raise_on_error=raise_on_error)[-1]
+        return s.solve(rhs, out, raise_on_error=raise_on_error)[1]
     gamma = 1e7
     for k in range(warmup):
         factorize(k)
-        s.solve(rhs, out)
+        solve()
     attempts.clear()
     deltas.clear()
     s.set_timing(True)
@@ -136,7 +152,7 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
         factorize(k)
-        _, si = s.solve(rhs, out, raise_on_error=False)
+        si = solve(raise_on_error=False)
         infos.append(si)
     torch.cuda.synchronize()
     t1 = time.perf_counter()

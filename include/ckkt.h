@@ -280,6 +280,41 @@ ckkt_status ckkt_factorize_inertia(ckkt_handle* h, const double* w_val, const do
 ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol,
                        ckkt_solve_info* info, void* stream);
 
+/* Newton step of the augmented system K2 (Sec. 2.2, eq:kkt:augmented,
+ * delta_c = 0) around the condensed factor:
+ *   [ W + Sx  0   G^T  H^T ] [dx]     [r1]
+ *   [ 0       E   0    I   ] [ds]     [r2]
+ *   [ G       0   0    0   ] [dy] = - [r3]
+ *   [ H       I   0    0   ] [dz]     [r4]
+ * with Sx = sigma_x and E = D_s + delta_w I the slack diagonal, which is the
+ * factor's slack weight sigma_s (D_H = E when delta_c = 0).  Slack rows:
+ * LiftedKKT every constraint row (its equalities are relaxed inequalities,
+ * Sec. 3.2; rows of G first, then H), HyKKT the rows of H; the equality
+ * block (r3, dy) exists for HyKKT only.  The condensed right-hand side
+ * rbar1 = -(r1 + H^T (E r4 - r2)), rbar2 = -r3 is solved with the current
+ * factor (LiftedKKT: one application; HyKKT: its CG on S_gamma), the slacks
+ * are recovered (dz = -r2 + E (H dx + r4), ds = -(r2 + dz) / E), and FP64
+ * Richardson iterations on K2 (K2 applied blockwise, unassembled) repeat the
+ * same steps on the residual until the componentwise relative backward error
+ * of K2 w.r.t. its data is <= opt.tol (info->omega; refine_steps counts the
+ * corrections after the first).
+ *   r1, dx : n device doubles;  r2, r4, ds, dz : slack-row count (LiftedKKT
+ *   m_eq + m_ineq, HyKKT m_ineq);  r3, dy : m_eq (HyKKT; ignored, may be
+ *   NULL, for LiftedKKT).  Outputs are overwritten.  Blocks until done.
+ * Errors: CKKT_ERR_ARG (batch handle, missing pointer), CKKT_ERR_STATE (not
+ * factorized, or factorized with ckkt_factorize_dual_reg), CKKT_ERR_NOT_SPD,
+ * CKKT_ERR_NO_CONVERGENCE, CKKT_ERR_BREAKDOWN, CKKT_ERR_HIP. */
+ckkt_status ckkt_solve_augmented(ckkt_handle* h, const double* r1, const double* r2, const double* r3,
+                                 const double* r4, double* dx, double* ds, double* dy, double* dz,
+                                 ckkt_solve_info* info, void* stream);
+
+/* Bound-multiplier step of the unreduced system K3 (eq:kkt:unreduced, last
+ * block row V ds + S dv = -(S v - mu e); Sec. 2.2):
+ * dv = -S^{-1} (V ds - mu e) - v, elementwise over `count` slacks.  s, v, ds,
+ * dv are device doubles (s > 0); enqueued on stream, does not wait. */
+ckkt_status ckkt_recover_bound_dual(int64_t count, const double* s, const double* v, double mu,
+                                   const double* ds, double* dv, void* stream);
+
 /* One application of the factor, x = (L L^T)^{-1} b (forward and backward
  * sweeps only, no refinement), for LiftedKKT and HyKKT (K_gamma).
  * rhs, sol: n device doubles; enqueued on stream, does not wait. */

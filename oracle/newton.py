@@ -91,8 +91,8 @@ def omega_k2(W, sigma_x, G, H, E, r1, r2, r3, r4, dx, ds, dy, dz):
     max_i |res_i| / (|K2| |d| + |r|)_i with |K2| taken block by block."""
     R1, R2, R3, R4 = k2_residual(W, sigma_x, G, H, E, r1, r2, r3, r4, dx, ds, dy, dz)
     ax, asl, ay, az = np.abs(dx), np.abs(ds), np.abs(dy), np.abs(dz)
-    aG, aH = np.abs(G), np.abs(H)
-    d1 = np.abs(W) @ ax + np.abs(sigma_x) * ax + aG.T @ ay + aH.T @ az + np.abs(r1)
+    aG, aH = abs(G), abs(H)  # abs(): dense arrays or scipy.sparse matrices
+    d1 = abs(W) @ ax + np.abs(sigma_x) * ax + aG.T @ ay + aH.T @ az + np.abs(r1)
     d2 = np.abs(E) * asl + az + np.abs(r2)
     d3 = aG @ ax + np.abs(r3)
     d4 = aH @ ax + asl + np.abs(r4)

@@ -76,6 +76,9 @@ SIGNATURES = [
     ("ckkt_factorize_inertia", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                                          POINTER(Inertia), c_void_p]),
     ("ckkt_solve", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(SolveInfo), c_void_p]),
+    ("ckkt_solve_augmented", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, c_void_p, POINTER(SolveInfo), c_void_p]),
+    ("ckkt_recover_bound_dual", c_int32, [c_int64, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     ("ckkt_apply_inverse", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("ckkt_export_k", c_int32, [c_void_p, P_i32, P_i32, c_void_p, c_void_p]),
     ("ckkt_host_factor_solve", c_int32, [c_void_p, P_f64, P_f64, P_f64, P_f64, P_f64, c_double, P_f64, P_f64,

@@ -89,6 +89,7 @@ struct ckkt_handle {
     unsigned long long wait_ticks = 0;    // wait limit of the flag waits in wall-clock ticks
     Region r_dscr;         // factored diagonal blocks of tiled fronts between launches
     std::vector<Region> r_vn, r_vm, r_veq;  // scratch vectors of length n, m, m_eq
+    std::vector<Region> r_vk2;              // augmented-system refinement: 5 vectors of length m
     // learned preconditioner (opt.learned)
     Region r_feat, r_o, r_cache, r_go, r_mlpws, r_grad, r_sxold, r_dold, r_kdold, r_kdnew, r_dnew;
     std::vector<Region> r_lv;
@@ -109,7 +110,7 @@ struct ckkt_handle {
     bool sched_ok = false;
     unsigned long long* bits = nullptr;  // [ninst omega][resmax][bmax]
     double *dotpart = nullptr, *sc = nullptr;
-    std::vector<double*> vn, vm, veq;
+    std::vector<double*> vn, vm, veq, vk2;
     float *feat = nullptr, *mo = nullptr, *cache = nullptr, *go = nullptr, *grad = nullptr;
     void* mlpws = nullptr;
     double *sxold = nullptr, *dold = nullptr, *kdold = nullptr, *kdnew = nullptr, *dnew = nullptr;
@@ -133,7 +134,7 @@ struct ckkt_handle {
     // captured launch sequences: factorization (FP64, FP32), factor
     // application (FP64, FP32), HyKKT CG iteration (FP64, FP32 factor)
     hipGraphExec_t graphs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    const double* cg_gval[2] = {nullptr, nullptr};  // G values a CG-iteration graph was captured with
+    const void* cg_key[2][3] = {};  // G values, dx and dy a CG-iteration graph was captured with
     bool use_graphs = true;
     bool debug_launch = false;  // CKKT_DEBUG_LAUNCH=1: report the first failing launch per factor level
 
@@ -336,6 +337,8 @@ void build_layout(ckkt_handle* h) {
     for (int i = 0; i < 8; ++i) h->r_vn.push_back(L.add(n * sizeof(double)));
     for (int i = 0; i < 2; ++i) h->r_vm.push_back(L.add(m * sizeof(double)));
     for (int i = 0; i < 6; ++i) h->r_veq.push_back(L.add(me * sizeof(double)));
+    h->r_vk2.clear();
+    for (int i = 0; i < 5; ++i) h->r_vk2.push_back(L.add(m * sizeof(double)));
     h->r_lv.clear();
     if (h->opt.learned) {
         h->r_feat = L.add(n * kMlpF * sizeof(float));
@@ -406,6 +409,8 @@ void fill_devplan(ckkt_handle* h) {
     for (auto& r : h->r_vn) h->vn.push_back(at<double>(h, r));
     for (auto& r : h->r_vm) h->vm.push_back(at<double>(h, r));
     for (auto& r : h->r_veq) h->veq.push_back(at<double>(h, r));
+    h->vk2.clear();
+    for (auto& r : h->r_vk2) h->vk2.push_back(at<double>(h, r));
     h->lv.clear();
     if (h->opt.learned) {
         h->feat = at<float>(h, h->r_feat);
@@ -957,15 +962,17 @@ ckkt_status hykkt_inner(ckkt_handle* h, const double* R1, const double* R2, doub
     const double stop = h->opt.cg_tol * std::sqrt(rr0);
     int maxit = h->opt.cg_maxit > 0 ? h->opt.cg_maxit : std::max(1, std::min(me, 1000));
     // One CG iteration is one captured sequence (its pointers are the
-    // handle's buffers and the G values of the current system; the graph is
-    // captured again when the caller's G values move).  Phase time counts
-    // as factor application.
+    // handle's buffers, dx, dy and the G values of the current system; the
+    // graph is captured again when any of the last three moves).  Phase time
+    // counts as factor application.
     const int slot = (use64 || h->precision == CKKT_FP64) ? 4 : 5;
-    if (h->graphs[slot] && h->cg_gval[slot - 4] != h->vals.g_val) {
+    const void* key[3] = {h->vals.g_val, dx, dy};
+    const void** held = h->cg_key[slot - 4];
+    if (h->graphs[slot] && (held[0] != key[0] || held[1] != key[1] || held[2] != key[2])) {
         (void)hipGraphExecDestroy(h->graphs[slot]);
         h->graphs[slot] = nullptr;
     }
-    h->cg_gval[slot - 4] = h->vals.g_val;
+    for (int i = 0; i < 3; ++i) held[i] = key[i];
     for (int k = 1; k <= maxit; ++k) {
         {
             PhaseTimer tm(h, 2, st);
@@ -1057,6 +1064,112 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
             PhaseTimer tm(h, 3, st);
             launch_axpy(n, 1.0, ddx, x, st);
             launch_axpy(me, 1.0, ddy, y, st);
+        }
+        steps++;
+    }
+    info->refine_steps = steps - 1;
+    return CKKT_OK;
+}
+
+// ------------------------------------------------ augmented system K2
+
+// Newton step of K2 (Sec. 2.2, delta_c = 0) around the condensed factor:
+// FP64 Richardson on K2 from d = 0, each correction K2 dd = R taken through
+// the condensation (rbar1 = R1 + H^T (E R4 - R2), rbar2 = R3), the handle's
+// condensed solve (LiftedKKT: one factor application; HyKKT: the CG step of
+// hykkt_inner on K1) and the slack recovery (dz = R2 + E (H dx - R4),
+// ds = (R2 - dz) / E).  Stops when the componentwise backward error of K2
+// is <= opt.tol.
+ckkt_status solve_augmented(ckkt_handle* h, const double* r1, const double* r2, const double* r3, const double* r4,
+                            double* dx, double* ds, double* dy, double* dz, ckkt_solve_info* info, hipStream_t st) {
+    const DevPlan& P = h->dp;
+    const bool hy = h->formulation == CKKT_HYKKT;
+    const int n = P.n, me = hy ? P.m_eq : 0, ms = P.m - me;
+    // ddx, ddy: the buffers solve_hykkt gives hykkt_inner, so that the CG
+    // iteration graph is shared by both solves
+    double *R1 = h->vn[5], *rb1 = h->vn[6], *ddx = h->vn[1];
+    double *R3 = h->veq[3], *ddy = h->veq[4];
+    double *u = h->vk2[0], *R2 = h->vk2[1], *R4 = h->vk2[2], *dds = h->vk2[3], *ddz = h->vk2[4];
+    unsigned long long* slot = h->bits + 2;
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_fill(n, 0.0, dx, st);
+        launch_fill(ms, 0.0, ds, st);
+        launch_fill(ms, 0.0, dz, st);
+        launch_fill(me, 0.0, dy, st);
+        launch_zero_u64(slot, 1, st);
+        launch_maxabs(n, r1, slot, st);
+        launch_maxabs(ms, r2, slot, st);
+        launch_maxabs(me, r3, slot, st);
+        launch_maxabs(ms, r4, slot, st);
+    }
+    bool use64 = h->precision == CKKT_FP64 || h->fp64_factored;
+    int steps = 0, stall = 0;
+    double prev = INFINITY;
+    char* host = static_cast<char*>(h->host);
+    for (;;) {
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_zero_u64(h->bits, 2, st);
+            launch_k2_residual(P, h->vals, h->d, r1, r2, r3, r4, dx, ds, dy, dz, R1, R2, R3, R4, h->bits,
+                               h->bits + 1, st);
+        }
+        HIP_TRY(hipMemcpyAsync(host, h->bits, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(host + 3 * sizeof(unsigned long long), h->status, 3 * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const unsigned long long* hb = reinterpret_cast<const unsigned long long*>(host);
+        const int32_t* hs = reinterpret_cast<const int32_t*>(host + 3 * sizeof(unsigned long long));
+        if (hs[2]) return CKKT_ERR_TIMEOUT;
+        ResidualOut r;
+        r.status0 = hs[0];
+        if (!check_factor(h, r)) return CKKT_ERR_NOT_SPD;
+        const double omega = bits_to_double(hb[0]), resmax = bits_to_double(hb[1]), rmax = bits_to_double(hb[2]);
+        info->omega = omega;
+        info->rho = rmax > 0 ? resmax / rmax : resmax;
+        if (omega <= h->opt.tol && steps > 0) break;
+        if (steps > 0 && !use64) {
+            if (!(omega < 0.5 * prev)) stall++;
+            if (stall >= 2 || steps > h->opt.ir_maxit) {
+                refactor_fp64(h, st);
+                use64 = true;
+                info->fallback = 2;
+                stall = 0;
+                prev = INFINITY;
+            }
+        } else if (steps > h->opt.ir_maxit) {
+            info->refine_steps = steps - 1;
+            return CKKT_ERR_NO_CONVERGENCE;
+        }
+        prev = omega;
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_k2_condense(P, h->vals, h->d, R1, R2, R4, u, rb1, st);
+        }
+        if (hy) {
+            int it = 0;
+            bool ok = true;
+            ckkt_status rc = hykkt_inner(h, rb1, R3, ddx, ddy, use64, it, ok, st);
+            info->cg_iters += it;
+            if (rc == CKKT_ERR_BREAKDOWN && !use64) {
+                refactor_fp64(h, st);
+                use64 = true;
+                info->fallback = 2;
+                stall = 0;
+                prev = INFINITY;
+                continue;
+            }
+            if (rc) return rc;
+        } else {
+            apply_inverse(h, rb1, ddx, use64, st);
+        }
+        {
+            PhaseTimer tm(h, 3, st);
+            launch_k2_recover(P, h->vals, h->d, R2, R4, ddx, dds, ddz, st);
+            launch_axpy(n, 1.0, ddx, dx, st);
+            launch_axpy(ms, 1.0, dds, ds, st);
+            launch_axpy(ms, 1.0, ddz, dz, st);
+            launch_axpy(me, 1.0, ddy, dy, st);
         }
         steps++;
     }
@@ -1383,6 +1496,36 @@ ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol, ckkt_solv
     if (rc == CKKT_OK && hipGetLastError() != hipSuccess) rc = CKKT_ERR_HIP;
     info->status = rc;
     return rc;
+}
+
+ckkt_status ckkt_solve_augmented(ckkt_handle* h, const double* r1, const double* r2, const double* r3,
+                                 const double* r4, double* dx, double* ds, double* dy, double* dz,
+                                 ckkt_solve_info* info, void* stream) {
+    ckkt_solve_info local{};
+    if (!info) info = &local;
+    std::memset(info, 0, sizeof(*info));
+    if (!h || h->plan.ninst > 1) return info->status = CKKT_ERR_ARG;
+    if (!h->ws || !h->factored) return info->status = CKKT_ERR_STATE;
+    if (h->vals.delta_c != 0.0) return info->status = CKKT_ERR_STATE;
+    const Plan& P = h->plan;
+    const bool hy = h->formulation == CKKT_HYKKT;
+    const int64_t me = hy ? P.m_eq : 0, ms = P.m - me;
+    if ((P.n > 0 && (!r1 || !dx)) || (ms > 0 && (!r2 || !r4 || !ds || !dz)) || (me > 0 && (!r3 || !dy)))
+        return info->status = CKKT_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
+    ckkt_status rc = solve_augmented(h, r1, r2, r3, r4, dx, ds, dy, dz, info, st);
+    if (rc == CKKT_OK && hipGetLastError() != hipSuccess) rc = CKKT_ERR_HIP;
+    return info->status = rc;
+}
+
+ckkt_status ckkt_recover_bound_dual(int64_t count, const double* s, const double* v, double mu, const double* ds,
+                                   double* dv, void* stream) {
+    if (count < 0 || (count > 0 && (!s || !v || !ds || !dv)) || !std::isfinite(mu)) return CKKT_ERR_ARG;
+    if (count == 0) return CKKT_OK;
+    (void)hipGetLastError();  // report only errors of this call's own launches
+    launch_bound_dual(count, s, v, mu, ds, dv, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
 }
 
 ckkt_status ckkt_apply_inverse(ckkt_handle* h, const double* rhs, double* sol, void* stream) {

@@ -154,6 +154,20 @@ void launch_residual(const DevPlan& P, const SysVals& v, const double* d, const 
                      unsigned long long* resmax_bits, hipStream_t st);
 void launch_zero_u64(unsigned long long* p, int count, hipStream_t st);
 void launch_maxabs(int n, const double* x, unsigned long long* bits, hipStream_t st);  // atomic max of |x|
+// Augmented system K2 (delta_c = 0) over the slack rows of the plan; f is the
+// right-hand side of K2 d = f, split like d into (f1: n, f2: slack rows,
+// f3: equality rows (HyKKT), f4: slack rows).
+void launch_k2_condense(const DevPlan& P, const SysVals& v, const double* d, const double* f1, const double* f2,
+                        const double* f4, double* u, double* rb1, hipStream_t st);  // rb1 = f1 + H^T (E f4 - f2)
+void launch_k2_recover(const DevPlan& P, const SysVals& v, const double* d, const double* f2, const double* f4,
+                       const double* dx, double* ds, double* dz, hipStream_t st);
+// R = -r - K2 d blockwise with the componentwise backward error (atomic max)
+void launch_k2_residual(const DevPlan& P, const SysVals& v, const double* d, const double* r1, const double* r2,
+                        const double* r3, const double* r4, const double* dx, const double* ds, const double* dy,
+                        const double* dz, double* R1, double* R2, double* R3, double* R4,
+                        unsigned long long* omega_bits, unsigned long long* resmax_bits, hipStream_t st);
+void launch_bound_dual(int64_t count, const double* s, const double* v, double mu, const double* ds, double* dv,
+                       hipStream_t st);  // dv = -(v ds - mu) / s - v
 
 // Vector kernels
 void launch_axpy(int n, double alpha, const double* x, double* y, hipStream_t st);  // y += a x

@@ -1951,6 +1951,142 @@ k_resid_vars(DevPlan P, SysVals v, const double* __restrict__ x, const double* _
     block_max_push(in, inst, ratio, num, omega_bits, resmax_bits);
 }
 
+// ------------------------------------------------- augmented system K2
+//
+// K2 (Sec. 2.2, delta_c = 0) with its slack rows: LiftedKKT every constraint
+// row (relaxed equalities), HyKKT the rows of H.  Global row r, slack index
+// q = r - s0 with s0 = m_eq for HyKKT and 0 for LiftedKKT; the slack
+// diagonal E_r = D_s + delta_w is the row weight d[r] of the condensed
+// matrix (D_H = E when delta_c = 0).  The kernels work on K2 d = f.
+
+__device__ __forceinline__ int slack_begin(const DevPlan& P) { return P.hy ? P.m_eq : 0; }
+
+// u_r = E_r f4_q - f2_q on the slack rows (the other entries are not read)
+__global__ void k_k2_u(DevPlan P, const double* __restrict__ d, const double* __restrict__ f2,
+                       const double* __restrict__ f4, double* __restrict__ u) {
+    const int s0 = slack_begin(P);
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P.m - s0) return;
+    const int r = s0 + q;
+    u[r] = d[r] * f4[q] - f2[q];
+}
+
+// rbar1 = f1 + H^T u over the slack rows (the condensed first block)
+__global__ void k_k2_rbar(DevPlan P, SysVals v, const double* __restrict__ f1, const double* __restrict__ u,
+                          double* __restrict__ rb1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    double acc = 0.0;
+    for (int k = P.hy ? P.jt_gend[i] : P.jt_ptr[i]; k < P.jt_ptr[i + 1]; ++k)
+        acc += jval(v, P.nnzg, P.jt_vidx[k]) * u[P.jt_row[k]];
+    rb1[i] = f1[i] + acc;
+}
+
+// slack recovery: dz = f2 + E (H dx - f4), ds = (f2 - dz) / E
+__global__ void k_k2_recover(DevPlan P, SysVals v, const double* __restrict__ d, const double* __restrict__ f2,
+                             const double* __restrict__ f4, const double* __restrict__ dx, double* __restrict__ ds,
+                             double* __restrict__ dz) {
+    const int s0 = slack_begin(P);
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P.m - s0) return;
+    const int r = s0 + q;
+    double hx = 0.0;
+    for (int a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a) hx += jval(v, P.nnzg, a) * dx[P.j_col[a]];
+    const double e = d[r];
+    const double z = f2[q] + e * (hx - f4[q]);
+    dz[q] = z;
+    ds[q] = (f2[q] - z) / e;
+}
+
+__device__ __forceinline__ double cw_ratio(double num, double den) {
+    return den > 0.0 ? num / den : (num == 0.0 ? 0.0 : INFINITY);  // NaN -> INFINITY
+}
+
+// K2 residual, constraint rows: R3 = f3 - G dx (HyKKT equality rows);
+// R2 = f2 - (E ds + dz) and R4 = f4 - (H dx + ds) (slack rows), with the
+// componentwise ratios |R| / (|K2||d| + |f|).  f = -r.
+__global__ void __launch_bounds__(256)
+k_k2_resid_rows(DevPlan P, SysVals v, const double* __restrict__ d, const double* __restrict__ r2,
+                const double* __restrict__ r3, const double* __restrict__ r4, const double* __restrict__ dx,
+                const double* __restrict__ ds, const double* __restrict__ dz, double* __restrict__ R2,
+                double* __restrict__ R3, double* __restrict__ R4, unsigned long long* omega_bits,
+                unsigned long long* resmax_bits) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = r < P.m;
+    const int s0 = slack_begin(P);
+    double ratio = 0.0, num = 0.0;
+    if (in) {
+        double jx = 0.0, mag = 0.0;
+        for (int a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a) {
+            const double t = jval(v, P.nnzg, a) * dx[P.j_col[a]];
+            jx += t;
+            mag += fabs(t);
+        }
+        if (r < s0) {
+            const double res = -r3[r] - jx;
+            R3[r] = res;
+            num = fabs(res);
+            ratio = cw_ratio(num, mag + fabs(r3[r]));
+        } else {
+            const int q = r - s0;
+            const double res4 = -r4[q] - (jx + ds[q]);
+            const double es = d[r] * ds[q];
+            const double res2 = -r2[q] - (es + dz[q]);
+            R2[q] = res2;
+            R4[q] = res4;
+            num = fmax(fabs(res2), fabs(res4));
+            ratio = fmax(cw_ratio(fabs(res4), mag + fabs(ds[q]) + fabs(r4[q])),
+                         cw_ratio(fabs(res2), fabs(es) + fabs(dz[q]) + fabs(r2[q])));
+        }
+    }
+    block_max_push(in, 0, ratio, num, omega_bits, resmax_bits);
+}
+
+// K2 residual, variables: R1 = f1 - ((W + Sx) dx + G^T dy + H^T dz).
+__global__ void __launch_bounds__(256)
+k_k2_resid_vars(DevPlan P, SysVals v, const double* __restrict__ r1, const double* __restrict__ dx,
+                const double* __restrict__ dy, const double* __restrict__ dz, double* __restrict__ R1,
+                unsigned long long* omega_bits, unsigned long long* resmax_bits) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i < P.n;
+    double ratio = 0.0, num = 0.0;
+    if (in) {
+        double acc = 0.0, mag = 0.0;
+        for (int k = P.wf_ptr[i]; k < P.wf_ptr[i + 1]; ++k) {
+            const double t = v.w_val[P.wf_vidx[k]] * dx[P.wf_col[k]];
+            acc += t;
+            mag += fabs(t);
+        }
+        const double px = v.sigma_x[i] * dx[i];
+        acc += px;
+        mag += fabs(px);
+        const int s0 = slack_begin(P);
+        const int gend = P.hy ? P.jt_gend[i] : P.jt_ptr[i];
+        for (int k = P.jt_ptr[i]; k < gend; ++k) {
+            const double t = jval(v, P.nnzg, P.jt_vidx[k]) * dy[P.jt_row[k]];
+            acc += t;
+            mag += fabs(t);
+        }
+        for (int k = gend; k < P.jt_ptr[i + 1]; ++k) {
+            const double t = jval(v, P.nnzg, P.jt_vidx[k]) * dz[P.jt_row[k] - s0];
+            acc += t;
+            mag += fabs(t);
+        }
+        const double res = -r1[i] - acc;
+        R1[i] = res;
+        num = fabs(res);
+        ratio = cw_ratio(num, mag + fabs(r1[i]));
+    }
+    block_max_push(in, 0, ratio, num, omega_bits, resmax_bits);
+}
+
+// last block row of K3: V ds + S dv = -(S v - mu e)
+__global__ void k_bound_dual(int64_t count, const double* __restrict__ s, const double* __restrict__ v, double mu,
+                             const double* __restrict__ ds, double* __restrict__ dv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dv[i] = -(v[i] * ds[i] - mu) / s[i] - v[i];
+}
+
 __global__ void __launch_bounds__(256) k_maxabs(int n, const double* __restrict__ x, unsigned long long* bits) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double a = i < n ? nan_to_inf(fabs(x[i])) : 0.0;
@@ -2556,6 +2692,33 @@ void launch_residual(const DevPlan& P, const SysVals& v, const double* d, const 
                            omega_bits, resmax_bits);
 }
 
+void launch_k2_condense(const DevPlan& P, const SysVals& v, const double* d, const double* f1, const double* f2,
+                        const double* f4, double* u, double* rb1, hipStream_t st) {
+    const int ms = P.m - (P.hy ? P.m_eq : 0);
+    if (ms > 0) hipLaunchKernelGGL(k_k2_u, dim3(nblk(ms)), dim3(256), 0, st, P, d, f2, f4, u);
+    if (P.n > 0) hipLaunchKernelGGL(k_k2_rbar, dim3(nblk(P.n)), dim3(256), 0, st, P, v, f1, u, rb1);
+}
+void launch_k2_recover(const DevPlan& P, const SysVals& v, const double* d, const double* f2, const double* f4,
+                       const double* dx, double* ds, double* dz, hipStream_t st) {
+    const int ms = P.m - (P.hy ? P.m_eq : 0);
+    if (ms > 0) hipLaunchKernelGGL(k_k2_recover, dim3(nblk(ms)), dim3(256), 0, st, P, v, d, f2, f4, dx, ds, dz);
+}
+void launch_k2_residual(const DevPlan& P, const SysVals& v, const double* d, const double* r1, const double* r2,
+                        const double* r3, const double* r4, const double* dx, const double* ds, const double* dy,
+                        const double* dz, double* R1, double* R2, double* R3, double* R4,
+                        unsigned long long* omega_bits, unsigned long long* resmax_bits, hipStream_t st) {
+    if (P.m > 0)
+        hipLaunchKernelGGL(k_k2_resid_rows, dim3(nblk(P.m)), dim3(256), 0, st, P, v, d, r2, r3, r4, dx, ds, dz, R2,
+                           R3, R4, omega_bits, resmax_bits);
+    if (P.n > 0)
+        hipLaunchKernelGGL(k_k2_resid_vars, dim3(nblk(P.n)), dim3(256), 0, st, P, v, r1, dx, dy, dz, R1,
+                           omega_bits, resmax_bits);
+}
+void launch_bound_dual(int64_t count, const double* s, const double* v, double mu, const double* ds, double* dv,
+                       hipStream_t st) {
+    if (count > 0)
+        hipLaunchKernelGGL(k_bound_dual, dim3(nblk(count)), dim3(256), 0, st, count, s, v, mu, ds, dv);
+}
 void launch_maxabs(int n, const double* x, unsigned long long* bits, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_maxabs, dim3(nblk(n)), dim3(256), 0, st, n, x, bits);
 }

@@ -167,6 +167,19 @@ class Solver:
             L.check(st, "ckkt_solve")
         return out, si.as_dict()
 
+    def solve_augmented(self, r1, r2, r3, r4, raise_on_error=True):
+        """Newton step of K2 (ckkt_solve_augmented): returns (dx, ds, dy, dz, info).
+        r3 / dy are used by HyKKT only (pass None for LiftedKKT)."""
+        import torch
+        dx, ds, dz = torch.empty_like(r1), torch.empty_like(r2), torch.empty_like(r4)
+        dy = torch.empty_like(r3) if r3 is not None else None
+        si = L.SolveInfo()
+        st = self.lib.ckkt_solve_augmented(self.h, _ptr(r1), _ptr(r2), _ptr(r3), _ptr(r4), _ptr(dx), _ptr(ds),
+                                           _ptr(dy), _ptr(dz), ctypes.byref(si), _stream())
+        if raise_on_error:
+            L.check(st, "ckkt_solve_augmented")
+        return dx, ds, dy, dz, si.as_dict()
+
     def apply_inverse(self, rhs, out=None):
         import torch
         if out is None:
@@ -256,6 +269,15 @@ class Solver:
                                                      keep[4][1], float(gamma), ctypes.byref(ic), keep[5][1],
                                                      out.ctypes.data_as(L.P_f64))
         return out, st, inertia_result(ic)
+
+
+def recover_bound_dual(s, v, mu, ds):
+    """d_v = -S^-1 (V d_s - mu e) - v on the device (ckkt_recover_bound_dual)."""
+    import torch
+    dv = torch.empty_like(ds)
+    L.check(L.load().ckkt_recover_bound_dual(ds.numel(), _ptr(s), _ptr(v), float(mu), _ptr(ds), _ptr(dv),
+                                             _stream()), "ckkt_recover_bound_dual")
+    return dv
 
 
 def inertia_params(delta_w_last=0.0, **params):

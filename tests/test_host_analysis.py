@@ -220,3 +220,19 @@ def test_dual_reg_arguments_rejected_without_gpu():
         assert lib.ckkt_factorize_dual_reg(hy.h, None, None, None, None, None, dc, None) == -1, dc
     assert lib.ckkt_factorize_dual_reg(hy.h, None, None, None, None, None, 1e-4, None) == -6  # no workspace
     assert lib.ckkt_factorize_dual_reg(None, None, None, None, None, None, 1e-4, None) == -1
+
+
+def test_augmented_step_arguments_rejected_without_gpu():
+    p = workloads.tiny_grid(0, nx=3, ny=3)
+    lib = _lib.load()
+    si = _lib.SolveInfo()
+    s = Solver(p, "hykkt")  # no workspace bound
+    args = [None] * 8
+    assert lib.ckkt_solve_augmented(s.h, *args, ctypes.byref(si), None) == -6
+    sb = Solver(None, "lifted", batch=[p, workloads.tiny_grid(1, nx=3, ny=3)])
+    assert lib.ckkt_solve_augmented(sb.h, *args, ctypes.byref(si), None) == -1
+    assert lib.ckkt_solve_augmented(None, *args, None, None) == -1
+    assert lib.ckkt_recover_bound_dual(-1, None, None, 0.0, None, None, None) == -1
+    assert lib.ckkt_recover_bound_dual(4, None, None, 0.0, None, None, None) == -1
+    assert lib.ckkt_recover_bound_dual(0, None, None, float("nan"), None, None, None) == -1
+    assert lib.ckkt_recover_bound_dual(0, None, None, 0.1, None, None, None) == 0
