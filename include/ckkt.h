@@ -121,9 +121,10 @@ typedef struct {
     int32_t n_big_fronts;     /* fronts factored by the tiled (multi-workgroup) path */
     int64_t workspace_bytes;
     double  analyze_seconds;
-    int32_t failed_column;    /* first column with a non-positive pivot (original
-                                 numbering), -1 if none; valid after a solve or
-                                 ckkt_factor_status */
+    int32_t failed_column;    /* a column with a non-positive pivot (original
+                                 numbering; an FP64 factorization stops after the
+                                 level of fronts that meets the first one), -1 if
+                                 none; valid after a solve or ckkt_factor_status */
     int32_t pad;
 } ckkt_info;
 

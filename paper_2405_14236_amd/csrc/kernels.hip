@@ -416,8 +416,14 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
     const int c0 = P.sn_start[s], c1 = P.sn_start[s + 1], w = c1 - c0;
     const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro, r = f - w;
     const int tid = threadIdx.x, nt = blockDim.x;
+    // An FP64 factorization that has met a non-positive pivot is not
+    // finished: every later front returns at once (the decision is taken
+    // from one read by thread 0, so the whole workgroup leaves together).
+    __shared__ int s_failed;
+    if (sizeof(T) == 8 && tid == 0) s_failed = *reinterpret_cast<volatile const int32_t*>(status) != INT_MAX;
     for (int i = tid; i < f * f; i += nt) F[i] = T(0);
     __syncthreads();
+    if (sizeof(T) == 8 && s_failed) return;
     // K entries of the w columns: one contiguous slot range (four entries
     // per thread in flight)
     {
