@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nodes", type=int, default=10_000)
     ap.add_argument("--forms",
-                    default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia,hykkt_fp64_dualreg,lifted_fp64_k2,hykkt_fp64_k2")
+                    default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia,hykkt_fp64_dualreg,lifted_fp64_k2,hykkt_fp64_k2,"
+                            "lifted_fp64_dense4")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -87,21 +88,31 @@ INERTIA_SHIFT = 1.0
 
 
 def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
-    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia|_dualreg|_k2].  The _inertia
+    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia|_dualreg|_k2|_dense4].  The _inertia
     forms lower W's diagonal by INERTIA_SHIFT (negative curvature wherever
     K_jj is below it) and factorize with inertia correction, carrying
     delta_w_last from one system to the next as an interior-point method
     does.  hykkt_*_dualreg solves K1 with dual regularization delta_c = 1/gamma
     directly through the same K_gamma factor (no CG).  The _k2 forms take the
     full Newton step of the augmented system K2 (ckkt_solve_augmented) for
-    seeded r1..r4 instead of the condensed solve."""
+    seeded r1..r4 instead of the condensed solve.  The _dense4 forms add four
+    inequality rows over half of the variables, kept out of K
+    (opt.dense_row_min) and applied by the Woodbury step."""
     formulation, precision, *variant = form.split("_")
     prec = {"fp64": "fp64", "fp32ir": "fp32_ir"}[precision]
     inertia = variant == ["inertia"]
     dualreg = variant == ["dualreg"]
     k2 = variant == ["k2"]
+    opts = {}
+    if variant == ["dense4"]:
+        # four extra inequality rows over half of the variables, split off K
+        import paper_2405_14236_amd.workloads as wl
+        p = wl.with_dense_rows(p, count=4, frac=0.5, seed=1)
+        rng = np.random.default_rng(11)
+        sig = [(a, np.concatenate([b, wl.log_uniform(rng, 4)])) for a, b in sig]
+        opts = {"dense_row_min": 1000}
     dev = "cuda"
-    s = Solver(p, formulation, prec).bind(dev)
+    s = Solver(p, formulation, prec, **opts).bind(dev)
     info = s.info()
     w, g, h, _, _ = device_values(p, dev, formulation)
     if inertia:
@@ -160,6 +171,8 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     s.set_timing(False)
     ok = all(si["status"] == 0 and si["omega"] <= 1e-8 for si in infos)
     extra = {"delta_c": 1.0 / gamma} if dualreg else {}
+    if opts:
+        extra = {"dense_rows": info["n_dense_rows"], "nnz_k": info["nnz_k"]}
     if inertia:
         extra = dict(w_diag_shift=-INERTIA_SHIFT, attempts_mean=float(np.mean(attempts)),
                      delta_w=[float(f"{d:.4g}") for d in deltas])

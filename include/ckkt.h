@@ -56,7 +56,8 @@ typedef int32_t ckkt_status;
 #define CKKT_OK                  0
 #define CKKT_ERR_ARG            -1  /* bad argument (null pointer, negative size, bad enum) */
 #define CKKT_ERR_PATTERN        -2  /* malformed CSR: unsorted, duplicate, out of range, W upper entry */
-#define CKKT_ERR_NOT_SPD        -3  /* a Cholesky pivot was not positive; see ckkt_info.failed_column */
+#define CKKT_ERR_NOT_SPD        -3  /* a Cholesky pivot was not positive; see ckkt_info.failed_column
+                                       (n: the capacitance matrix of the split dense rows) */
 #define CKKT_ERR_NO_CONVERGENCE -4  /* refinement or CG did not reach the tolerance within its limit */
 #define CKKT_ERR_BREAKDOWN      -5  /* CG breakdown (p^T S p <= 0 or not finite) */
 #define CKKT_ERR_STATE          -6  /* call out of order (solve before factorize, no workspace, ...) */
@@ -106,6 +107,18 @@ typedef struct {
                              holds in FP64 (140), in both precisions. */
     int32_t learned;      /* 1: reserve workspace for the learned preconditioner
                              (features, MLP cache, stale-system references) */
+    int32_t dense_row_min;/* rows of J = [G; H] with at least this many nonzeros
+                             are kept out of the condensed matrix, whose pattern
+                             one dense row would fill (Sec. 1, Sec. 2.2): the factor is
+                             that of K_s = K - J_d^T D_d J_d, and every
+                             application of K^{-1} adds the Woodbury correction
+                             of the k split rows (K_s^{-1} J_d^T and the k x k
+                             capacitance D_d^{-1} + J_d K_s^{-1} J_d^T, formed
+                             on the device by each factorization).  Needs
+                             K_s positive definite (it is when W + sigma_x is).
+                             0 (default) = no split.  FP64 single-system
+                             handles only (else CKKT_ERR_ARG from
+                             ckkt_analyze), at most 64 split rows. */
 } ckkt_options;
 
 typedef struct {
@@ -125,7 +138,7 @@ typedef struct {
                                  numbering; an FP64 factorization stops after the
                                  level of fronts that meets the first one), -1 if
                                  none; valid after a solve or ckkt_factor_status */
-    int32_t pad;
+    int32_t n_dense_rows;     /* rows split off by opt.dense_row_min */
 } ckkt_info;
 
 typedef struct {

@@ -33,7 +33,7 @@ class Pattern(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("ordering", c_int32), ("tol", c_double), ("ir_maxit", c_int32),
                 ("cg_tol", c_double), ("cg_maxit", c_int32), ("relax", c_int32), ("lds_front_max", c_int32),
-                ("learned", c_int32)]
+                ("learned", c_int32), ("dense_row_min", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -41,7 +41,7 @@ class Info(ctypes.Structure):
                 ("nnz_l", c_int64), ("nnz_l_stored", c_int64), ("factor_flops", c_double),
                 ("assembly_products", c_double), ("n_supernodes", c_int32), ("n_levels", c_int32),
                 ("max_front", c_int32), ("n_big_fronts", c_int32), ("workspace_bytes", c_int64),
-                ("analyze_seconds", c_double), ("failed_column", c_int32), ("pad", c_int32)]
+                ("analyze_seconds", c_double), ("failed_column", c_int32), ("n_dense_rows", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}

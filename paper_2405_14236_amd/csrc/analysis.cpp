@@ -72,12 +72,22 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     std::copy(p.g_idx.begin(), p.g_idx.end(), P.j_col.begin());
     std::copy(p.h_idx.begin(), p.h_idx.end(), P.j_col.begin() + P.nnz_g);
 
+    // ---- dense rows: kept out of K (their J^T J block would fill it)
+    std::vector<char> dense(m, 0);
+    P.dense_rows.clear();
+    if (o.dense_row_min > 0)
+        for (int32_t r = 0; r < m; ++r)
+            if (P.j_ptr[r + 1] - P.j_ptr[r] >= o.dense_row_min) {
+                dense[r] = 1;
+                P.dense_rows.push_back(r);
+            }
+
     // ---- unique off-diagonal pairs (i > j), original numbering
     std::vector<uint64_t> keys;
     {
         int64_t est = P.nnz_w;
         for (int32_t r = 0; r < m; ++r) {
-            int64_t q = P.j_ptr[r + 1] - P.j_ptr[r];
+            int64_t q = dense[r] ? 0 : P.j_ptr[r + 1] - P.j_ptr[r];
             est += q * (q - 1) / 2;
         }
         keys.reserve(est);
@@ -85,10 +95,12 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     for (int32_t i = 0; i < n; ++i)
         for (int32_t k = p.w_ptr[i]; k < p.w_ptr[i + 1]; ++k)
             if (p.w_idx[k] != i) keys.push_back(((uint64_t)i << 32) | (uint32_t)p.w_idx[k]);
-    for (int32_t r = 0; r < m; ++r)
+    for (int32_t r = 0; r < m; ++r) {
+        if (dense[r]) continue;
         for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
             for (int32_t b = a + 1; b < P.j_ptr[r + 1]; ++b)
                 keys.push_back(((uint64_t)P.j_col[b] << 32) | (uint32_t)P.j_col[a]);  // cols increasing: b > a
+    }
     std::sort(keys.begin(), keys.end());
     keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
 
@@ -500,7 +512,8 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     {
         struct Pr { int32_t slot, r, a, b; };
         std::vector<Pr> prods;
-        for (int32_t r = 0; r < m; ++r)
+        for (int32_t r = 0; r < m; ++r) {
+            if (dense[r]) continue;
             for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
                 for (int32_t b = a; b < P.j_ptr[r + 1]; ++b) {
                     int32_t I = P.iperm[P.j_col[a]], J = P.iperm[P.j_col[b]];
@@ -508,6 +521,7 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
                     if (sl < 0) return "internal: J product missing from K";
                     prods.push_back({sl, r, a, b});
                 }
+        }
         P.prod_ptr.assign(nnzk + 1, 0);
         for (auto& q : prods) P.prod_ptr[q.slot + 1]++;
         for (int64_t t = 0; t < nnzk; ++t) P.prod_ptr[t + 1] += P.prod_ptr[t];

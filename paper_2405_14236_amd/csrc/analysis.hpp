@@ -42,6 +42,7 @@ struct Plan {
     std::vector<int32_t> k_diag;      // original index of the diagonal (sigma_x) or -1
     std::vector<int32_t> prod_ptr;    // nnz_k + 1
     std::vector<int32_t> prod_r, prod_a, prod_b;  // J row, two J value indices (G values then H values)
+    std::vector<int32_t> dense_rows;  // rows of J kept out of K (AnalyzeOptions::dense_row_min)
 
     // ---- supernodes (new numbering, columns contiguous)
     int32_t ns = 0;
@@ -104,6 +105,7 @@ struct AnalyzeOptions {
     int relax = 1;
     int big_front = 96;    // fronts larger than this go to the tiled path
     int tile = 64;         // column tile of the tiled path
+    int dense_row_min = 0; // rows of J with at least this many entries stay out of K (0: none)
 };
 
 // Returns an empty string on success, else a description of the pattern error.

@@ -80,6 +80,7 @@ struct ckkt_handle {
         r_instvar, r_insteq, r_kcol, r_cbptr, r_cbsrc, r_cblen, r_cbuoff;
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
     Region r_sxreg, r_ssreg;  // diagonals shifted by delta_w (inertia correction)
+    Region r_jd, r_z, r_cap, r_dpart, r_du;  // split dense rows: J_d, K_s^{-1} J_d^T, capacitance, dots
     Region r_ctl, r_done;  // dependency-driven sweeps: control words, per-supernode flags
     Region r_tflag;        // block flags of the tiled fronts (one launch per level)
     int64_t n_tflags = 0;
@@ -100,6 +101,9 @@ struct ckkt_handle {
     DevPlan dp{};
     double *K = nullptr, *d = nullptr, *scale = nullptr, *uvec = nullptr, *vperm = nullptr;
     double *sxreg = nullptr, *ssreg = nullptr;
+    double *jd = nullptr, *zd = nullptr, *cap = nullptr, *dpart = nullptr, *du = nullptr;
+    int32_t* drows = nullptr;  // device copy of plan.dense_rows
+    Region r_drows;
     double* arena64 = nullptr;
     float* arena32 = nullptr;
     int32_t* status = nullptr;  // [0] failing column, [1] FP32 pivot floors, [2] sweep wait failure
@@ -307,6 +311,7 @@ void build_layout(ckkt_handle* h) {
     plan_region(h->r_cbsrc, P.cb_src);
     plan_region(h->r_cblen, P.cb_len);
     plan_region(h->r_cbuoff, P.cb_uoff);
+    plan_region(h->r_drows, P.dense_rows);
 
     const size_t n = std::max<int64_t>(P.n, 1), m = std::max<int64_t>(P.m, 1), me = std::max<int64_t>(P.m_eq, 1);
     h->r_K = L.add(std::max<size_t>(P.kcolptr.back(), 1) * sizeof(double));
@@ -331,6 +336,14 @@ void build_layout(ckkt_handle* h) {
     h->r_sc = L.add(16 * sizeof(double));
     h->r_sxreg = L.add(n * sizeof(double));
     h->r_ssreg = L.add(m * sizeof(double));
+    {
+        const size_t kd = std::max<size_t>(P.dense_rows.size(), 1);
+        h->r_jd = L.add(kd * n * sizeof(double));
+        h->r_z = L.add(kd * n * sizeof(double));
+        h->r_cap = L.add(kd * kd * sizeof(double));
+        h->r_dpart = L.add(kd * kDotBlocks * sizeof(double));
+        h->r_du = L.add(kd * sizeof(double));
+    }
     h->r_vn.clear();
     h->r_vm.clear();
     h->r_veq.clear();
@@ -405,6 +418,12 @@ void fill_devplan(ckkt_handle* h) {
     h->sc = at<double>(h, h->r_sc);
     h->sxreg = at<double>(h, h->r_sxreg);
     h->ssreg = at<double>(h, h->r_ssreg);
+    h->jd = at<double>(h, h->r_jd);
+    h->zd = at<double>(h, h->r_z);
+    h->cap = at<double>(h, h->r_cap);
+    h->dpart = at<double>(h, h->r_dpart);
+    h->du = at<double>(h, h->r_du);
+    h->drows = at<int32_t>(h, h->r_drows);
     h->vn.clear(); h->vm.clear(); h->veq.clear();
     for (auto& r : h->r_vn) h->vn.push_back(at<double>(h, r));
     for (auto& r : h->r_vm) h->vm.push_back(at<double>(h, r));
@@ -435,6 +454,10 @@ ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const Patte
         bool internal = err.rfind("internal", 0) == 0;
         delete h;
         return internal ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
+    }
+    if ((int)h->plan.dense_rows.size() > kMaxDenseRows) {
+        delete h;
+        return CKKT_ERR_ARG;
     }
     // CKKT_TILED_SWEEP_FRONT moves the size from which fronts are swept by
     // the tiled kernels; it stays above the LDS front limit (so that every
@@ -495,6 +518,7 @@ AnalyzeOptions analyze_options(const ckkt_options& o) {
     AnalyzeOptions ao;
     ao.ordering = o.ordering;
     ao.relax = o.relax;
+    ao.dense_row_min = o.dense_row_min;
     // the whole front of a small supernode lives in LDS (f^2 elements <= 160 KiB)
     // the FP64 factor is also built for FP32_IR handles (refactorization
     // fallback), so the FP64 LDS capacity bounds both precisions
@@ -636,12 +660,38 @@ void apply_inverse_launches(ckkt_handle* h, const double* b, double* x, bool use
     if (d) sweep_levels<double>(h, st);
     else sweep_levels<float>(h, st);
     launch_scatter_perm(h->dp, h->vperm, x, scale, st);
+    if (d) launch_dense_correct(h->plan.n, (int)h->plan.dense_rows.size(), h->jd, h->zd, h->cap, h->dpart, h->du,
+                                x, st);
 }
 
-// Uses the FP64 factor when `use64`, else the handle's precision.
+// Uses the FP64 factor when `use64`, else the handle's precision.  With
+// split dense rows (FP64 handles only) the sweeps apply K_s^{-1} and the
+// Woodbury step turns the result into K^{-1} b.
 void apply_inverse(ckkt_handle* h, const double* b, double* x, bool use64, hipStream_t st) {
-    if (use64 || h->precision == CKKT_FP64) apply_inverse_t<double>(h, b, x, nullptr, st);
-    else apply_inverse_t<float>(h, b, x, h->scale, st);
+    if (use64 || h->precision == CKKT_FP64) {
+        apply_inverse_t<double>(h, b, x, nullptr, st);
+        if (!h->plan.dense_rows.empty()) {
+            PhaseTimer tm(h, 2, st);
+            launch_dense_correct(h->plan.n, (int)h->plan.dense_rows.size(), h->jd, h->zd, h->cap, h->dpart, h->du,
+                                 x, st);
+        }
+    } else {
+        apply_inverse_t<float>(h, b, x, h->scale, st);
+    }
+}
+
+// After the FP64 factorization of K_s: J_d, Z = K_s^{-1} J_d^T (k sweep
+// pairs) and the Cholesky factor of C = D_d^{-1} + J_d Z.
+void dense_rows_setup(ckkt_handle* h, hipStream_t st) {
+    const int k = (int)h->plan.dense_rows.size(), n = h->plan.n;
+    if (k == 0) return;
+    {
+        PhaseTimer tm(h, 1, st);
+        launch_dense_setup_gather(h->dp, h->vals, h->drows, k, h->jd, st);
+    }
+    for (int b = 0; b < k; ++b) apply_inverse_t<double>(h, h->jd + (int64_t)b * n, h->zd + (int64_t)b * n, nullptr, st);
+    PhaseTimer tm(h, 1, st);
+    launch_dense_setup_cap(n, k, h->drows, h->d, h->jd, h->zd, h->cap, h->status, st);
 }
 
 struct ResidualOut {
@@ -1253,6 +1303,10 @@ ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_
     else ckkt_default_options(&h->opt);
     if (h->opt.precision != CKKT_FP64 && h->opt.precision != CKKT_FP32_IR) { delete h; return CKKT_ERR_ARG; }
     if (h->opt.ordering != CKKT_ORDER_AMD && h->opt.ordering != CKKT_ORDER_NATURAL) { delete h; return CKKT_ERR_ARG; }
+    if (h->opt.dense_row_min < 0 || (h->opt.dense_row_min > 0 && h->opt.precision != CKKT_FP64)) {
+        delete h;
+        return CKKT_ERR_ARG;
+    }
     h->formulation = pat->formulation;
     h->precision = h->opt.precision;
     PatternIn pin = copy_pattern(pat);
@@ -1270,6 +1324,7 @@ ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ck
     if (!h) return CKKT_ERR_ARG;
     if (opt) h->opt = *opt;
     else ckkt_default_options(&h->opt);
+    if (h->opt.dense_row_min != 0) { delete h; return CKKT_ERR_ARG; }  // no dense-row split in a batch
     h->formulation = pats[0].formulation;
     h->precision = h->opt.precision;
     // block-diagonal union: variables and W blocks in instance order, then
@@ -1428,6 +1483,7 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
             factor_all<float>(h, h->scale, st);
         }
     }
+    if (h->precision == CKKT_FP64) dense_rows_setup(h, st);
     if (hipGetLastError() != hipSuccess) return CKKT_ERR_HIP;
     h->factored = true;
     return CKKT_OK;
@@ -1466,7 +1522,7 @@ ckkt_status ckkt_factorize_inertia(ckkt_handle* h, const double* w_val, const do
                                    const double* sigma_x, const double* sigma_s, double gamma, ckkt_inertia* ic,
                                    void* stream) {
     if (!h || !inertia_params_ok(ic)) return CKKT_ERR_ARG;
-    if (h->precision != CKKT_FP64 || h->plan.ninst > 1) return CKKT_ERR_ARG;
+    if (h->precision != CKKT_FP64 || h->plan.ninst > 1 || !h->plan.dense_rows.empty()) return CKKT_ERR_ARG;
     if (!h->ws) return CKKT_ERR_STATE;
     const Plan& P = h->plan;
     const int64_t ns_len = h->formulation == CKKT_HYKKT ? P.m_ineq : P.m;
@@ -1562,16 +1618,69 @@ ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, co
                                   const double* h_val, const double* sigma_x, const double* sigma_s,
                                   double gamma, const double* rhs, double* sol, int32_t* failed_column) {
     if (!h || !rhs || !sol) return CKKT_ERR_ARG;
-    int fc = host_factor_solve(h->plan, h->formulation == CKKT_HYKKT, w_val, g_val, h_val, sigma_x, sigma_s, gamma,
-                               rhs, sol);
+    const Plan& P = h->plan;
+    const bool hy = h->formulation == CKKT_HYKKT;
+    int fc = host_factor_solve(P, hy, w_val, g_val, h_val, sigma_x, sigma_s, gamma, rhs, sol);
     if (failed_column) *failed_column = fc;
-    return fc >= 0 ? CKKT_ERR_NOT_SPD : CKKT_OK;
+    if (fc >= 0) return CKKT_ERR_NOT_SPD;
+    const int k = (int)P.dense_rows.size(), n = P.n;
+    if (k == 0) return CKKT_OK;
+    // Woodbury around K_s: sol -= Z C^{-1} (J_d sol), Z = K_s^{-1} J_d^T,
+    // C = D_d^{-1} + J_d Z (each column of Z by a host run of its own)
+    auto jv = [&](int32_t a) { return a < P.nnz_g ? g_val[a] : h_val[a - P.nnz_g]; };
+    auto weight = [&](int32_t r) { return hy ? (r < P.m_eq ? gamma : sigma_s[r - P.m_eq]) : sigma_s[r]; };
+    std::vector<double> jd((size_t)k * n, 0.0), z((size_t)k * n), c((size_t)k * k), t(k);
+    for (int b = 0; b < k; ++b) {
+        const int32_t r = P.dense_rows[b];
+        for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a) jd[(size_t)b * n + P.j_col[a]] = jv(a);
+        if (host_factor_solve(P, hy, w_val, g_val, h_val, sigma_x, sigma_s, gamma, &jd[(size_t)b * n],
+                              &z[(size_t)b * n]) >= 0)
+            return CKKT_ERR_NOT_SPD;
+    }
+    for (int a = 0; a < k; ++a)
+        for (int e = 0; e <= a; ++e) {
+            double acc = 0.0;
+            for (int i = 0; i < n; ++i) acc += jd[(size_t)a * n + i] * z[(size_t)e * n + i];
+            c[a * k + e] = acc + (a == e ? 1.0 / weight(P.dense_rows[a]) : 0.0);
+        }
+    for (int j = 0; j < k; ++j) {  // Cholesky, lower
+        double dj = c[j * k + j];
+        for (int l = 0; l < j; ++l) dj -= c[j * k + l] * c[j * k + l];
+        if (!(dj > 0.0)) {
+            if (failed_column) *failed_column = n;
+            return CKKT_ERR_NOT_SPD;
+        }
+        c[j * k + j] = std::sqrt(dj);
+        for (int i = j + 1; i < k; ++i) {
+            double v = c[i * k + j];
+            for (int l = 0; l < j; ++l) v -= c[i * k + l] * c[j * k + l];
+            c[i * k + j] = v / c[j * k + j];
+        }
+    }
+    for (int b = 0; b < k; ++b) {
+        double acc = 0.0;
+        for (int i = 0; i < n; ++i) acc += jd[(size_t)b * n + i] * sol[i];
+        for (int l = 0; l < b; ++l) acc -= c[b * k + l] * t[l];
+        t[b] = acc / c[b * k + b];
+    }
+    for (int b = k - 1; b >= 0; --b) {
+        double v = t[b];
+        for (int l = b + 1; l < k; ++l) v -= c[l * k + b] * t[l];
+        t[b] = v / c[b * k + b];
+    }
+    for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int b = 0; b < k; ++b) acc += z[(size_t)b * n + i] * t[b];
+        sol[i] -= acc;
+    }
+    return CKKT_OK;
 }
 
 ckkt_status ckkt_host_factor_solve_inertia(const ckkt_handle* h, const double* w_val, const double* g_val,
                                            const double* h_val, const double* sigma_x, const double* sigma_s,
                                            double gamma, ckkt_inertia* ic, const double* rhs, double* sol) {
-    if (!h || !rhs || !sol || !inertia_params_ok(ic) || h->plan.ninst > 1) return CKKT_ERR_ARG;
+    if (!h || !rhs || !sol || !inertia_params_ok(ic) || h->plan.ninst > 1 || !h->plan.dense_rows.empty())
+        return CKKT_ERR_ARG;
     const Plan& P = h->plan;
     const bool hy = h->formulation == CKKT_HYKKT;
     const int64_t ns_len = hy ? P.m_ineq : P.m;
@@ -1836,6 +1945,7 @@ ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info) {
     info->workspace_bytes = (int64_t)h->lay.total;
     info->analyze_seconds = P.analyze_seconds;
     info->failed_column = h->failed_column;
+    info->n_dense_rows = (int32_t)h->plan.dense_rows.size();
     return CKKT_OK;
 }
 

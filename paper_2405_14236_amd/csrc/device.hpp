@@ -168,6 +168,15 @@ void launch_k2_residual(const DevPlan& P, const SysVals& v, const double* d, con
                         unsigned long long* omega_bits, unsigned long long* resmax_bits, hipStream_t st);
 void launch_bound_dual(int64_t count, const double* s, const double* v, double mu, const double* ds, double* dv,
                        hipStream_t st);  // dv = -(v ds - mu) / s - v
+// Split dense rows (Woodbury around the factor of K_s): J_d from the J values;
+// the capacitance C = D_d^{-1} + J_d Z and its Cholesky factor (status gets
+// column n on a non-positive pivot); x -= Z C^{-1} (J_d x).
+void launch_dense_setup_gather(const DevPlan& P, const SysVals& v, const int32_t* rows, int k, double* jd,
+                               hipStream_t st);
+void launch_dense_setup_cap(int n, int k, const int32_t* rows, const double* d, const double* jd, const double* z,
+                            double* cap, int32_t* status, hipStream_t st);
+void launch_dense_correct(int n, int k, const double* jd, const double* z, const double* cap, double* part,
+                          double* u, double* x, hipStream_t st);
 
 // Vector kernels
 void launch_axpy(int n, double alpha, const double* x, double* y, hipStream_t st);  // y += a x
@@ -185,6 +194,7 @@ void launch_g(const DevPlan& P, const SysVals& v, const double* x, const double*
 // Deterministic dot product into *result (device); partial buffer of
 // kDotBlocks doubles.
 constexpr int kDotBlocks = 256;
+constexpr int kMaxDenseRows = 64;  // rows of J split off the condensed matrix at most
 void launch_dot(int n, const double* a, const double* b, double* partial, double* result, hipStream_t st);
 
 // CG helpers with device-resident scalars.  sc[0] = rr, sc[1] = pq,

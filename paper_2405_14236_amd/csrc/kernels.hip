@@ -2093,6 +2093,117 @@ __global__ void k_bound_dual(int64_t count, const double* __restrict__ s, const 
     if (i < count) dv[i] = -(v[i] * ds[i] - mu) / s[i] - v[i];
 }
 
+// ------------------------------------------------------ split dense rows
+//
+// Rows of J kept out of K: the factor is that of K_s = K - J_d^T D_d J_d and
+// K^{-1} b = y - Z C^{-1} (J_d y) with y = K_s^{-1} b, Z = K_s^{-1} J_d^T and
+// C = D_d^{-1} + J_d Z (Woodbury).  J_d and Z are k dense rows of length n
+// (row-major), C's Cholesky factor is k x k (lower, row-major), k <= 64.
+
+// row b of J_d from the CSR values (J_d cleared beforehand)
+__global__ void k_dense_scatter(DevPlan P, SysVals v, const int32_t* __restrict__ rows, double* __restrict__ jd) {
+    const int b = blockIdx.x;
+    const int r = rows[b];
+    double* out = jd + (int64_t)b * P.n;
+    for (int a = P.j_ptr[r] + threadIdx.x; a < P.j_ptr[r + 1]; a += blockDim.x) out[P.j_col[a]] = jval(v, P.nnzg, a);
+}
+
+// block sum in a fixed order (256 threads)
+__device__ double block_sum256(double x) {
+    __shared__ double s_p[256 / kWave];
+    x = wave_sum(x);
+    if (threadIdx.x % kWave == 0) s_p[threadIdx.x / kWave] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < 256 / kWave; ++w) t += s_p[w];
+    __syncthreads();
+    return t;
+}
+
+// lower triangle of C = D_d^{-1} + J_d Z: one workgroup per entry (a >= b)
+__global__ void __launch_bounds__(256)
+k_dense_cap(int n, int k, const int32_t* __restrict__ rows, const double* __restrict__ d,
+            const double* __restrict__ jd, const double* __restrict__ z, double* __restrict__ cap) {
+    int e = blockIdx.x, a = 0;
+    while (e > a) { e -= a + 1; ++a; }  // entry (a, e) of the lower triangle, e <= a
+    const double* ja = jd + (int64_t)a * n;
+    const double* zb = z + (int64_t)e * n;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += ja[i] * zb[i];
+    acc = block_sum256(acc);
+    if (threadIdx.x == 0) cap[a * k + e] = acc + (a == e ? 1.0 / d[rows[a]] : 0.0);
+}
+
+// Cholesky factor of C in place (one workgroup of 64 threads, k <= 64); a
+// non-positive pivot reports column n (outside the matrix) through status.
+__global__ void __launch_bounds__(64) k_dense_chol(int n, int k, double* __restrict__ cap, int32_t* status) {
+    __shared__ double A[64 * 64];
+    const int t = threadIdx.x;
+    for (int i = 0; i < k; ++i)
+        if (t <= i) A[i * 64 + t] = cap[i * k + t];
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (t == 0) {
+            const double dj = A[j * 64 + j];
+            if (!(dj > 0.0)) {
+                atomicMin(status, n);
+                A[j * 64 + j] = 1.0;
+            } else {
+                A[j * 64 + j] = sqrt(dj);
+            }
+        }
+        __syncthreads();
+        const double piv = A[j * 64 + j];
+        if (t > j && t < k) A[t * 64 + j] /= piv;
+        __syncthreads();
+        if (t > j && t < k)
+            for (int l = j + 1; l <= t; ++l) A[t * 64 + l] -= A[t * 64 + j] * A[l * 64 + j];
+        __syncthreads();
+    }
+    for (int i = 0; i < k; ++i)
+        if (t <= i) cap[i * k + t] = A[i * 64 + t];
+}
+
+// partial sums of t_b = J_d[b] . x: grid (kDotBlocks, k)
+__global__ void __launch_bounds__(256)
+k_dense_dots(int n, const double* __restrict__ jd, const double* __restrict__ x, double* __restrict__ part) {
+    const int b = blockIdx.y;
+    const double* row = jd + (int64_t)b * n;
+    double acc = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) acc += row[i] * x[i];
+    acc = block_sum256(acc);
+    if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = acc;
+}
+
+// u = C^{-1} t with t summed from the partials in a fixed order (one thread)
+__global__ void k_dense_solve(int k, int nparts, const double* __restrict__ part, const double* __restrict__ cap,
+                              double* __restrict__ u) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double y[64];
+    for (int b = 0; b < k; ++b) {
+        double t = 0.0;
+        for (int q = 0; q < nparts; ++q) t += part[b * nparts + q];
+        for (int l = 0; l < b; ++l) t -= cap[b * k + l] * y[l];
+        y[b] = t / cap[b * k + b];
+    }
+    for (int b = k - 1; b >= 0; --b) {
+        double t = y[b];
+        for (int l = b + 1; l < k; ++l) t -= cap[l * k + b] * y[l];
+        y[b] = t / cap[b * k + b];
+    }
+    for (int b = 0; b < k; ++b) u[b] = y[b];
+}
+
+// x -= Z^T u
+__global__ void k_dense_correct(int n, int k, const double* __restrict__ z, const double* __restrict__ u,
+                                double* __restrict__ x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int b = 0; b < k; ++b) acc += z[(int64_t)b * n + i] * u[b];
+    x[i] -= acc;
+}
+
 __global__ void __launch_bounds__(256) k_maxabs(int n, const double* __restrict__ x, unsigned long long* bits) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double a = i < n ? nan_to_inf(fabs(x[i])) : 0.0;
@@ -2724,6 +2835,25 @@ void launch_bound_dual(int64_t count, const double* s, const double* v, double m
                        hipStream_t st) {
     if (count > 0)
         hipLaunchKernelGGL(k_bound_dual, dim3(nblk(count)), dim3(256), 0, st, count, s, v, mu, ds, dv);
+}
+void launch_dense_setup_gather(const DevPlan& P, const SysVals& v, const int32_t* rows, int k, double* jd,
+                               hipStream_t st) {
+    if (k <= 0 || P.n <= 0) return;
+    launch_fill(k * P.n, 0.0, jd, st);
+    hipLaunchKernelGGL(k_dense_scatter, dim3(k), dim3(256), 0, st, P, v, rows, jd);
+}
+void launch_dense_setup_cap(int n, int k, const int32_t* rows, const double* d, const double* jd, const double* z,
+                            double* cap, int32_t* status, hipStream_t st) {
+    if (k <= 0) return;
+    hipLaunchKernelGGL(k_dense_cap, dim3(k * (k + 1) / 2), dim3(256), 0, st, n, k, rows, d, jd, z, cap);
+    hipLaunchKernelGGL(k_dense_chol, dim3(1), dim3(64), 0, st, n, k, cap, status);
+}
+void launch_dense_correct(int n, int k, const double* jd, const double* z, const double* cap, double* part,
+                          double* u, double* x, hipStream_t st) {
+    if (k <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(k_dense_dots, dim3(kDotBlocks, k), dim3(256), 0, st, n, jd, x, part);
+    hipLaunchKernelGGL(k_dense_solve, dim3(1), dim3(64), 0, st, k, kDotBlocks, part, cap, u);
+    hipLaunchKernelGGL(k_dense_correct, dim3(nblk(n)), dim3(256), 0, st, n, k, z, u, x);
 }
 void launch_maxabs(int n, const double* x, unsigned long long* bits, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_maxabs, dim3(nblk(n)), dim3(256), 0, st, n, x, bits);

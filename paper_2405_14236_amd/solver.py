@@ -38,7 +38,7 @@ def _pattern(prob, formulation):
 
 
 def options(precision="fp64", ordering="amd", tol=1e-10, ir_maxit=10, cg_tol=1e-10, cg_maxit=0, relax=1,
-            lds_front_max=0, learned=0):
+            lds_front_max=0, learned=0, dense_row_min=0):
     lib = L.load()
     o = L.Options()
     lib.ckkt_default_options(ctypes.byref(o))
@@ -47,6 +47,7 @@ def options(precision="fp64", ordering="amd", tol=1e-10, ir_maxit=10, cg_tol=1e-
     o.tol, o.ir_maxit, o.cg_tol, o.cg_maxit, o.relax = tol, ir_maxit, cg_tol, cg_maxit, relax
     o.lds_front_max = lds_front_max
     o.learned = int(learned)
+    o.dense_row_min = int(dense_row_min)
     return o
 
 

@@ -358,6 +358,32 @@ def ipm_sigma_sequence(prob: KKTProblem, num: int, seed: int = 0,
     return out
 
 
+def with_dense_rows(prob: KKTProblem, count: int = 4, frac: float = 0.5, seed: int = 0,
+                    sigma_exp=(-8.0, 8.0)) -> KKTProblem:
+    """``prob`` with ``count`` extra inequality rows appended to H, each over a
+    random fraction ``frac`` of the variables with N(0, 1) coefficients
+    (budget- or resource-style constraints: the dense rows that fill the
+    condensed matrix, Sec. 1 and Sec. 2.2).  Their sigma_s entries are drawn
+    log-uniform like the others."""
+    rng = np.random.default_rng(seed + 104_729)
+    n = prob.n
+    k = max(1, int(round(frac * n)))
+    ptr = [int(x) for x in prob.h_ptr]
+    idx, val = list(prob.h_idx), list(prob.h_val)
+    for _ in range(count):
+        cols = np.sort(rng.choice(n, size=k, replace=False))
+        idx.extend(int(c) for c in cols)
+        val.extend(rng.standard_normal(k))
+        ptr.append(len(idx))
+    extra = log_uniform(rng, count, *sigma_exp)
+    return dataclasses.replace(
+        prob, m_ineq=prob.m_ineq + count,
+        h_ptr=np.asarray(ptr, dtype=np.int32), h_idx=np.asarray(idx, dtype=np.int32),
+        h_val=np.asarray(val, dtype=np.float64),
+        sigma_s=np.concatenate([prob.sigma_s, extra]),
+        name=f"{prob.name}+{count}dense{frac:g}")
+
+
 def batch_network_flow(count: int = 512, seed: int = 0, nmin: int = 500,
                        nmax: int = 2000) -> List[KKTProblem]:
     """Independent network-flow instances of uneven size (node counts U{nmin..nmax})."""
