@@ -81,6 +81,7 @@ struct ckkt_handle {
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
     Region r_sxreg, r_ssreg;  // diagonals shifted by delta_w (inertia correction)
     Region r_jd, r_z, r_cap, r_dpart, r_du;  // split dense rows: J_d, K_s^{-1} J_d^T, capacitance, dots
+    Region r_drowdot;                        // (J x)_r, (|J||x|)_r of the split rows for the row kernels
     Region r_ctl, r_done;  // dependency-driven sweeps: control words, per-supernode flags
     Region r_tflag;        // block flags of the tiled fronts (one launch per level)
     int64_t n_tflags = 0;
@@ -343,6 +344,7 @@ void build_layout(ckkt_handle* h) {
         h->r_cap = L.add(kd * kd * sizeof(double));
         h->r_dpart = L.add(kd * kDotBlocks * sizeof(double));
         h->r_du = L.add(kd * sizeof(double));
+        h->r_drowdot = L.add(2 * kd * sizeof(double));
     }
     h->r_vn.clear();
     h->r_vm.clear();
@@ -400,6 +402,10 @@ void fill_devplan(ckkt_handle* h) {
     D.kcol = at<int32_t>(h, h->r_kcol);
     D.cb_ptr = at<int32_t>(h, h->r_cbptr); D.cb_src = at<int32_t>(h, h->r_cbsrc);
     D.cb_len = at<int32_t>(h, h->r_cblen); D.cb_uoff = at<int64_t>(h, h->r_cbuoff);
+    D.drows = at<int32_t>(h, h->r_drows);
+    D.ndense = (int32_t)P.dense_rows.size();
+    D.dense_min = D.ndense > 0 ? h->opt.dense_row_min : 0;
+    D.drowdot = at<double>(h, h->r_drowdot);
 
     h->K = at<double>(h, h->r_K);
     h->d = at<double>(h, h->r_d);

@@ -22,6 +22,12 @@ struct DevPlan {
     const int32_t *wf_ptr, *wf_col, *wf_vidx;
     const int32_t *j_ptr, *j_col, *jt_ptr, *jt_row, *jt_vidx, *jt_gend;
     const int32_t *inst_of_var, *inst_of_eqrow;
+    // rows of J split off K (dense_min > 0): rows with at least dense_min
+    // entries, listed in drows; drowdot holds (J x)_r and (|J||x|)_r of each,
+    // written by a launch of their own before a row kernel reads them
+    const int32_t* drows;
+    int32_t ndense, dense_min;
+    double* drowdot;
 };
 
 // Values of the current system (device pointers owned by the caller).

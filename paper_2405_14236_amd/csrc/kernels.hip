@@ -1864,6 +1864,29 @@ __global__ void k_scatter_perm(DevPlan P, const double* __restrict__ in, double*
     out[P.perm[k]] = scale ? v * scale[k] : v;
 }
 
+// (J x)_r and (|J||x|)_r.  A row split off K (long) is read from the values
+// k_dense_rowdot left for this x; the others are summed here, in CSR order.
+__device__ __forceinline__ void row_jx(const DevPlan& P, const SysVals& v, int r, const double* __restrict__ x,
+                                       double& acc, double& mag) {
+    const int a0 = P.j_ptr[r], a1 = P.j_ptr[r + 1];
+    if (P.dense_min > 0 && a1 - a0 >= P.dense_min) {
+        int b = 0;
+        while (b < P.ndense && P.drows[b] != r) ++b;
+        if (b < P.ndense) {
+            acc = P.drowdot[2 * b];
+            mag = P.drowdot[2 * b + 1];
+            return;
+        }
+    }
+    acc = 0.0;
+    mag = 0.0;
+    for (int a = a0; a < a1; ++a) {
+        const double p = jval(v, P.nnzg, a) * x[P.j_col[a]];
+        acc += p;
+        mag += fabs(p);
+    }
+}
+
 // Residual, pass 1 (one thread per constraint row): for rows weighted by d
 // (LiftedKKT all rows; HyKKT rows of H) t = d (J x) and ta = |d| (|J||x|);
 // for HyKKT rows of G the K1 second-block residual rhs2 - (G x - delta_c y)
@@ -1876,13 +1899,7 @@ k_resid_rows(DevPlan P, SysVals v, const double* __restrict__ d, const double* _
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = r < P.m;
     double acc = 0.0, mag = 0.0;
-    if (in) {
-        for (int a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a) {
-            double p = jval(v, P.nnzg, a) * x[P.j_col[a]];
-            acc += p;
-            mag += fabs(p);
-        }
-    }
+    if (in) row_jx(P, v, r, x, acc, mag);
     const bool eq = in && P.hy && r < P.m_eq;
     double ratio = 0.0, num = 0.0;
     int inst = -1;
@@ -1996,8 +2013,8 @@ __global__ void k_k2_recover(DevPlan P, SysVals v, const double* __restrict__ d,
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= P.m - s0) return;
     const int r = s0 + q;
-    double hx = 0.0;
-    for (int a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a) hx += jval(v, P.nnzg, a) * dx[P.j_col[a]];
+    double hx, hmag;
+    row_jx(P, v, r, dx, hx, hmag);
     const double e = d[r];
     const double z = f2[q] + e * (hx - f4[q]);
     dz[q] = z;
@@ -2022,12 +2039,8 @@ k_k2_resid_rows(DevPlan P, SysVals v, const double* __restrict__ d, const double
     const int s0 = slack_begin(P);
     double ratio = 0.0, num = 0.0;
     if (in) {
-        double jx = 0.0, mag = 0.0;
-        for (int a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a) {
-            const double t = jval(v, P.nnzg, a) * dx[P.j_col[a]];
-            jx += t;
-            mag += fabs(t);
-        }
+        double jx, mag;
+        row_jx(P, v, r, dx, jx, mag);
         if (r < s0) {
             const double res = -r3[r] - jx;
             R3[r] = res;
@@ -2118,6 +2131,24 @@ __device__ double block_sum256(double x) {
     for (int w = 0; w < 256 / kWave; ++w) t += s_p[w];
     __syncthreads();
     return t;
+}
+
+// (J x)_r and (|J||x|)_r of the split rows for the row kernels (row_jx):
+// one workgroup per row, fixed-order sums
+__global__ void __launch_bounds__(256) k_dense_rowdot(DevPlan P, SysVals v, const double* __restrict__ x) {
+    const int b = blockIdx.x, r = P.drows[b];
+    double acc = 0.0, mag = 0.0;
+    for (int a = P.j_ptr[r] + threadIdx.x; a < P.j_ptr[r + 1]; a += 256) {
+        const double p = jval(v, P.nnzg, a) * x[P.j_col[a]];
+        acc += p;
+        mag += fabs(p);
+    }
+    acc = block_sum256(acc);
+    mag = block_sum256(mag);
+    if (threadIdx.x == 0) {
+        P.drowdot[2 * b] = acc;
+        P.drowdot[2 * b + 1] = mag;
+    }
 }
 
 // lower triangle of C = D_d^{-1} + J_d Z: one workgroup per entry (a >= b)
@@ -2263,8 +2294,8 @@ __global__ void k_g(DevPlan P, SysVals v, const double* __restrict__ x, const do
                     double* __restrict__ out) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= P.m_eq) return;
-    double acc = 0.0;
-    for (int a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a) acc += v.g_val[a] * x[P.j_col[a]];
+    double acc, mag;
+    row_jx(P, v, r, x, acc, mag);
     out[r] = sub ? acc - sub[r] : acc;
 }
 
@@ -2797,10 +2828,14 @@ void launch_zero_u64(unsigned long long* p, int count, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u64, dim3(nblk(count)), dim3(256), 0, st, p, count);
 }
 
+void launch_dense_rowdot(const DevPlan& P, const SysVals& v, const double* x, hipStream_t st) {
+    if (P.ndense > 0) hipLaunchKernelGGL(k_dense_rowdot, dim3(P.ndense), dim3(256), 0, st, P, v, x);
+}
 void launch_residual(const DevPlan& P, const SysVals& v, const double* d, const double* x,
                      const double* y, const double* rhs1, const double* rhs2, double* res1,
                      double* res2, double* tbuf, double* tabuf, unsigned long long* omega_bits,
                      unsigned long long* resmax_bits, hipStream_t st) {
+    if (P.m > 0) launch_dense_rowdot(P, v, x, st);
     if (P.m > 0)
         hipLaunchKernelGGL(k_resid_rows, dim3(nblk(P.m)), dim3(256), 0, st, P, v, d, x, y, rhs2, res2, tbuf,
                            tabuf, omega_bits, resmax_bits);
@@ -2818,12 +2853,14 @@ void launch_k2_condense(const DevPlan& P, const SysVals& v, const double* d, con
 void launch_k2_recover(const DevPlan& P, const SysVals& v, const double* d, const double* f2, const double* f4,
                        const double* dx, double* ds, double* dz, hipStream_t st) {
     const int ms = P.m - (P.hy ? P.m_eq : 0);
+    if (ms > 0) launch_dense_rowdot(P, v, dx, st);
     if (ms > 0) hipLaunchKernelGGL(k_k2_recover, dim3(nblk(ms)), dim3(256), 0, st, P, v, d, f2, f4, dx, ds, dz);
 }
 void launch_k2_residual(const DevPlan& P, const SysVals& v, const double* d, const double* r1, const double* r2,
                         const double* r3, const double* r4, const double* dx, const double* ds, const double* dy,
                         const double* dz, double* R1, double* R2, double* R3, double* R4,
                         unsigned long long* omega_bits, unsigned long long* resmax_bits, hipStream_t st) {
+    if (P.m > 0) launch_dense_rowdot(P, v, dx, st);
     if (P.m > 0)
         hipLaunchKernelGGL(k_k2_resid_rows, dim3(nblk(P.m)), dim3(256), 0, st, P, v, d, r2, r3, r4, dx, ds, dz, R2,
                            R3, R4, omega_bits, resmax_bits);
@@ -2880,6 +2917,7 @@ void launch_gt(const DevPlan& P, const SysVals& v, const double* base, double sc
 }
 void launch_g(const DevPlan& P, const SysVals& v, const double* x, const double* sub, double* out,
               hipStream_t st) {
+    if (P.m_eq > 0) launch_dense_rowdot(P, v, x, st);
     if (P.m_eq > 0) hipLaunchKernelGGL(k_g, dim3(nblk(P.m_eq)), dim3(256), 0, st, P, v, x, sub, out);
 }
 void launch_dot(int n, const double* a, const double* b, double* partial, double* result, hipStream_t st) {
