@@ -330,11 +330,14 @@ ckkt_status ckkt_recover_bound_dual(int64_t count, const double* s, const double
                                    const double* ds, double* dv, void* stream);
 
 /* One application of the factor, x = (L L^T)^{-1} b (forward and backward
- * sweeps only, no refinement), for LiftedKKT and HyKKT (K_gamma).
+ * sweeps only, no refinement; with rows split off by opt.dense_row_min,
+ * the sweeps of K_s followed by the Woodbury step, so x = K^{-1} b), for
+ * LiftedKKT and HyKKT (K_gamma).
  * rhs, sol: n device doubles; enqueued on stream, does not wait. */
 ckkt_status ckkt_apply_inverse(ckkt_handle* h, const double* rhs, double* sol, void* stream);
 
-/* The assembled K (or K_gamma) of the last factorize as coordinates in the
+/* The assembled K (or K_gamma) of the last factorize -- without the rows
+ * split off by opt.dense_row_min, i.e. K_s -- as coordinates in the
  * ORIGINAL numbering (row >= col), one entry per internal slot, nnz_k
  * entries: rows/cols are host arrays filled when non-NULL, values is a
  * device array of nnz_k doubles filled (synchronously) when non-NULL. */
