@@ -359,29 +359,37 @@ def ipm_sigma_sequence(prob: KKTProblem, num: int, seed: int = 0,
 
 
 def with_dense_rows(prob: KKTProblem, count: int = 4, frac: float = 0.5, seed: int = 0,
-                    sigma_exp=(-8.0, 8.0)) -> KKTProblem:
-    """``prob`` with ``count`` extra inequality rows appended to H, each over a
-    random fraction ``frac`` of the variables with N(0, 1) coefficients
-    (budget- or resource-style constraints: the dense rows that fill the
-    condensed matrix, Sec. 1 and Sec. 2.2).  Their sigma_s entries are drawn
-    log-uniform like the others."""
+                    sigma_exp=(-8.0, 8.0), equality: bool = False) -> KKTProblem:
+    """``prob`` with ``count`` extra rows, each over a random fraction ``frac``
+    of the variables with N(0, 1) coefficients (budget- or resource-style
+    constraints: the dense rows that fill the condensed matrix, Sec. 1 and
+    Sec. 2.2).  Inequality rows (appended to H) get sigma_s entries drawn
+    log-uniform like the others; equality rows (``equality``, appended to G)
+    get sigma_s entries too (LiftedKKT relaxes them) and N(0, 1) entries of
+    rbar2."""
     rng = np.random.default_rng(seed + 104_729)
     n = prob.n
     k = max(1, int(round(frac * n)))
-    ptr = [int(x) for x in prob.h_ptr]
-    idx, val = list(prob.h_idx), list(prob.h_val)
+    src_ptr, src_idx, src_val = ((prob.g_ptr, prob.g_idx, prob.g_val) if equality
+                                 else (prob.h_ptr, prob.h_idx, prob.h_val))
+    ptr = [int(x) for x in src_ptr]
+    idx, val = list(src_idx), list(src_val)
     for _ in range(count):
         cols = np.sort(rng.choice(n, size=k, replace=False))
         idx.extend(int(c) for c in cols)
         val.extend(rng.standard_normal(k))
         ptr.append(len(idx))
     extra = log_uniform(rng, count, *sigma_exp)
+    arrays = (np.asarray(ptr, dtype=np.int32), np.asarray(idx, dtype=np.int32), np.asarray(val, dtype=np.float64))
+    name = f"{prob.name}+{count}dense{'eq' if equality else ''}{frac:g}"
+    if equality:
+        return dataclasses.replace(
+            prob, m_eq=prob.m_eq + count, g_ptr=arrays[0], g_idx=arrays[1], g_val=arrays[2],
+            sigma_s=np.concatenate([prob.sigma_s[:prob.m_eq], extra, prob.sigma_s[prob.m_eq:]]),
+            r2bar=np.concatenate([prob.r2bar, rng.standard_normal(count)]), name=name)
     return dataclasses.replace(
-        prob, m_ineq=prob.m_ineq + count,
-        h_ptr=np.asarray(ptr, dtype=np.int32), h_idx=np.asarray(idx, dtype=np.int32),
-        h_val=np.asarray(val, dtype=np.float64),
-        sigma_s=np.concatenate([prob.sigma_s, extra]),
-        name=f"{prob.name}+{count}dense{frac:g}")
+        prob, m_ineq=prob.m_ineq + count, h_ptr=arrays[0], h_idx=arrays[1], h_val=arrays[2],
+        sigma_s=np.concatenate([prob.sigma_s, extra]), name=name)
 
 
 def batch_network_flow(count: int = 512, seed: int = 0, nmin: int = 500,

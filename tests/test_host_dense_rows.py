@@ -66,3 +66,22 @@ def test_dense_row_option_arguments():
     from paper_2405_14236_amd.solver import inertia_params
     ic = inertia_params()
     assert lib.ckkt_factorize_inertia(s.h, None, None, None, None, None, 0.0, ctypes.byref(ic), None) == -1
+
+
+@pytest.mark.parametrize("formulation", ["lifted", "hykkt"])
+def test_host_woodbury_dense_equality_row(formulation):
+    """A dense row of G: split with weight gamma (HyKKT) or its relaxed sigma_s (LiftedKKT)."""
+    p = workloads.with_dense_rows(workloads.tiny_grid(49, sigma_range=(-2, 2)), count=1, frac=0.7, seed=49,
+                                  equality=True)
+    gamma = 1e7
+    s = Solver(p, formulation, dense_row_min=50)
+    assert s.info()["n_dense_rows"] == 1
+    ss = p.sigma_s if formulation == "lifted" else p.sigma_s_ineq
+    x, st, _ = s.host_factor_solve(p.w_val, p.g_val, p.h_val, p.sigma_x, ss, gamma, p.b)
+    assert st == 0
+    if formulation == "lifted":
+        P = osp.Problem(p)
+        om = osp.omega_condensed(P.W, p.sigma_x, P.J, p.sigma_s, x, p.b)
+    else:
+        om = omega_kgamma(p, x, p.b, gamma)
+    assert om < 1e-11, om
