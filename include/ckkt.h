@@ -63,7 +63,9 @@ typedef int32_t ckkt_status;
 #define CKKT_ERR_STATE          -6  /* call out of order (solve before factorize, no workspace, ...) */
 #define CKKT_ERR_HIP            -7  /* a HIP runtime call failed */
 #define CKKT_ERR_WORKSPACE      -8  /* workspace missing, too small or misaligned */
-#define CKKT_ERR_NONFINITE      -9  /* NaN or Inf in the input values or diagonals */
+#define CKKT_ERR_NONFINITE      -9  /* NaN or Inf in an input that reaches the assembled matrix
+                                       (ckkt_factor_status and the solves report it) or in a
+                                       right-hand side (the solves) */
 #define CKKT_ERR_TIMEOUT       -10  /* a dependency wait inside a triangular sweep exceeded its time
                                        limit (seconds); the results of that solve are invalid.  Reported
                                        by the next call that synchronizes (ckkt_solve, ckkt_pcg_solve,

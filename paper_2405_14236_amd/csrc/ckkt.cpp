@@ -705,7 +705,7 @@ struct ResidualOut {
     double resmax = 0.0;
     double rhsmax = 0.0;     // max |rhs| left by launch_rhs_max
     std::vector<double> per_inst;
-    int32_t status0 = INT_MAX, status1 = 0, status2 = 0;
+    int32_t status0 = INT_MAX, status1 = 0, status2 = 0, status3 = 0;
 };
 
 double bits_to_double(unsigned long long b) {
@@ -726,7 +726,7 @@ ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, cons
     }
     char* host = static_cast<char*>(h->host);
     HIP_TRY(hipMemcpyAsync(host, h->bits, (ni + 2) * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(host + (ni + 2) * sizeof(unsigned long long), h->status, 3 * sizeof(int32_t),
+    HIP_TRY(hipMemcpyAsync(host + (ni + 2) * sizeof(unsigned long long), h->status, 4 * sizeof(int32_t),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const unsigned long long* hb = reinterpret_cast<const unsigned long long*>(host);
@@ -742,6 +742,7 @@ ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, cons
     out.status0 = hs[0];
     out.status1 = hs[1];
     out.status2 = hs[2];
+    out.status3 = hs[3];
     return out.status2 ? CKKT_ERR_TIMEOUT : CKKT_OK;
 }
 
@@ -774,20 +775,23 @@ ckkt_status read_scalars(ckkt_handle* h, double* dst, int count, hipStream_t st)
     return CKKT_OK;
 }
 
-bool check_factor(ckkt_handle* h, const ResidualOut& r) {
+// CKKT_ERR_NONFINITE when an assembled entry was not finite, CKKT_ERR_NOT_SPD
+// when the FP64 factor met a non-positive pivot, else CKKT_OK.
+ckkt_status check_factor(ckkt_handle* h, const ResidualOut& r) {
+    if (r.status3) return CKKT_ERR_NONFINITE;
     if (h->precision == CKKT_FP64 || h->fp64_factored) {
         if (r.status0 != INT_MAX) {
             h->failed_column = (r.status0 >= 0 && r.status0 < h->plan.n) ? h->plan.perm[r.status0] : r.status0;
-            return false;
+            return CKKT_ERR_NOT_SPD;
         }
     }
-    return true;
+    return CKKT_OK;
 }
 
 // FP64 factorization of the already assembled K (fallback of FP32_IR).
 void refactor_fp64(ckkt_handle* h, hipStream_t st) {
     PhaseTimer tm(h, 1, st);
-    launch_init_status(h->status, st);
+    launch_init_status(h->status, true, st);
     factor_all<double>(h, nullptr, st);
     h->fp64_factored = true;
 }
@@ -914,7 +918,8 @@ ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_
     for (;;) {
         rc = residual_sync(h, x, nullptr, b, nullptr, res, nullptr, r, st);
         if (rc) return rc;
-        if (!check_factor(h, r)) { info->status = CKKT_ERR_NOT_SPD; return CKKT_ERR_NOT_SPD; }
+        if ((rc = check_factor(h, r)) != CKKT_OK) return info->status = rc;
+        if (steps == 0 && !std::isfinite(r.rhsmax)) return info->status = CKKT_ERR_NONFINITE;
         info->omega = r.omega;
         info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
         if (r.omega <= h->opt.tol) break;
@@ -1079,7 +1084,8 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
     for (;;) {
         rc = residual_sync(h, x, y, r1, r2, res1, res2, r, st);
         if (rc) return rc;
-        if (!check_factor(h, r)) { info->status = CKKT_ERR_NOT_SPD; return CKKT_ERR_NOT_SPD; }
+        if ((rc = check_factor(h, r)) != CKKT_OK) return info->status = rc;
+        if (steps == 0 && !std::isfinite(r.rhsmax)) return info->status = CKKT_ERR_NONFINITE;
         info->omega = r.omega;
         info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
         if (r.omega <= h->opt.tol && steps > 0) break;
@@ -1171,7 +1177,7 @@ ckkt_status solve_augmented(ckkt_handle* h, const double* r1, const double* r2, 
                                h->bits + 1, st);
         }
         HIP_TRY(hipMemcpyAsync(host, h->bits, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(host + 3 * sizeof(unsigned long long), h->status, 3 * sizeof(int32_t),
+        HIP_TRY(hipMemcpyAsync(host + 3 * sizeof(unsigned long long), h->status, 4 * sizeof(int32_t),
                                hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         const unsigned long long* hb = reinterpret_cast<const unsigned long long*>(host);
@@ -1179,8 +1185,10 @@ ckkt_status solve_augmented(ckkt_handle* h, const double* r1, const double* r2, 
         if (hs[2]) return CKKT_ERR_TIMEOUT;
         ResidualOut r;
         r.status0 = hs[0];
-        if (!check_factor(h, r)) return CKKT_ERR_NOT_SPD;
+        r.status3 = hs[3];
+        if (ckkt_status fc = check_factor(h, r)) return fc;
         const double omega = bits_to_double(hb[0]), resmax = bits_to_double(hb[1]), rmax = bits_to_double(hb[2]);
+        if (steps == 0 && !std::isfinite(rmax)) return CKKT_ERR_NONFINITE;
         info->omega = omega;
         info->rho = rmax > 0 ? resmax / rmax : resmax;
         if (omega <= h->opt.tol && steps > 0) break;
@@ -1468,9 +1476,9 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
     h->fp64_factored = false;
     {
         PhaseTimer tm(h, 0, st);
-        launch_init_status(h->status, st);
+        launch_init_status(h->status, false, st);
         launch_row_weights(h->dp, h->vals, h->d, st);
-        launch_assemble(h->dp, h->vals, h->d, h->K, st);
+        launch_assemble(h->dp, h->vals, h->d, h->K, h->status + 3, st);
         if (h->precision == CKKT_FP32_IR) launch_diag_scale(h->dp, h->K, h->scale, st);
         if (h->opt.learned) {
             // the factorized system becomes the stale reference of the learned PCG
@@ -1513,10 +1521,11 @@ ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream) {
     if (!h->factored) return CKKT_ERR_STATE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();  // report only errors of this call's own launches
-    HIP_TRY(hipMemcpyAsync(h->host, h->status, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h->host, h->status, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     int32_t s0 = static_cast<int32_t*>(h->host)[0];
     if (static_cast<int32_t*>(h->host)[2] != 0) return CKKT_ERR_TIMEOUT;
+    if (static_cast<int32_t*>(h->host)[3] != 0) return CKKT_ERR_NONFINITE;
     if (h->fp64_factored && s0 != INT_MAX) {
         h->failed_column = (s0 >= 0 && s0 < h->plan.n) ? h->plan.perm[s0] : s0;
         return CKKT_ERR_NOT_SPD;
@@ -1826,6 +1835,7 @@ ckkt_status ckkt_pcg_solve(ckkt_handle* h, const double* w_val, const double* g_
     double bmax = 0.0;
     rc = read_rhs_max(h, rhs, n, nullptr, 0, bmax, st);
     if (rc) return info->status = rc;
+    if (!std::isfinite(bmax)) return info->status = CKKT_ERR_NONFINITE;
     bool ok = pcg_stale(h, rhs, sol, o, maxit, tol, r, info, st, rc);
     if (rc) return info->status = rc;
     info->omega = r.omega;

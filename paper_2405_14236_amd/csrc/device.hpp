@@ -83,8 +83,9 @@ static_assert(kSweepTiledFront <= kSweepMaxFront, "fronts below the tiled size f
 
 // ---- launchers (kernels.hip)
 void launch_row_weights(const DevPlan& P, const SysVals& v, double* d, hipStream_t st);
-void launch_assemble(const DevPlan& P, const SysVals& v, const double* d, double* K, hipStream_t st);
-void launch_init_status(int32_t* status, hipStream_t st);
+void launch_assemble(const DevPlan& P, const SysVals& v, const double* d, double* K, int32_t* nonfinite,
+                     hipStream_t st);
+void launch_init_status(int32_t* status, bool keep_inputs, hipStream_t st);
 
 // A second stream with its fork/join events (default priority): the
 // tiled path of a level runs there, concurrently with its LDS fronts.

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -102,7 +103,10 @@ __global__ void k_row_weights(DevPlan P, SysVals v, double* __restrict__ d) {
 
 // K[t] = W + [diag] sigma_x + sum_r d_r J_ra J_rb, gathered per slot
 // (Sec. 2.2 K1: K = W + delta_w I + H^T D_H H; Sec. 3.1 K_gamma; Sec. 3.2 K_tau).
-__global__ void k_assemble(DevPlan P, SysVals v, const double* __restrict__ d, double* __restrict__ K) {
+// One K slot per thread; a slot that is not finite (NaN or Inf in an input
+// that reaches it) sets *nonfinite.
+__global__ void k_assemble(DevPlan P, SysVals v, const double* __restrict__ d, double* __restrict__ K,
+                           int32_t* nonfinite) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= P.nnzk) return;
     double acc = 0.0;
@@ -116,10 +120,18 @@ __global__ void k_assemble(DevPlan P, SysVals v, const double* __restrict__ d, d
         acc += d[r] * (jval(v, P.nnzg, P.prod_a[q]) * jval(v, P.nnzg, P.prod_b[q]));
     }
     K[t] = acc;
+    if (!(fabs(acc) <= DBL_MAX)) atomicOr(nonfinite, 1);
 }
 
-__global__ void k_init_status(int32_t* status) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) { status[0] = INT_MAX; status[1] = 0; status[2] = 0; }
+// status: [0] failing column, [1] FP32 pivot floors, [2] sweep wait failure,
+// [3] non-finite assembled entry (kept when `keep_inputs`: same K)
+__global__ void k_init_status(int32_t* status, int keep_inputs) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        status[0] = INT_MAX;
+        status[1] = 0;
+        status[2] = 0;
+        if (!keep_inputs) status[3] = 0;
+    }
 }
 
 __global__ void k_diag_scale(DevPlan P, const double* __restrict__ K, double* __restrict__ scale) {
@@ -2516,13 +2528,14 @@ void launch_row_weights(const DevPlan& P, const SysVals& v, double* d, hipStream
     hipLaunchKernelGGL(k_row_weights, dim3(nblk(P.m)), dim3(256), 0, st, P, v, d);
 }
 
-void launch_assemble(const DevPlan& P, const SysVals& v, const double* d, double* K, hipStream_t st) {
+void launch_assemble(const DevPlan& P, const SysVals& v, const double* d, double* K, int32_t* nonfinite,
+                     hipStream_t st) {
     if (P.nnzk == 0) return;
-    hipLaunchKernelGGL(k_assemble, dim3(nblk(P.nnzk)), dim3(256), 0, st, P, v, d, K);
+    hipLaunchKernelGGL(k_assemble, dim3(nblk(P.nnzk)), dim3(256), 0, st, P, v, d, K, nonfinite);
 }
 
-void launch_init_status(int32_t* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status);
+void launch_init_status(int32_t* status, bool keep_inputs, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status, keep_inputs ? 1 : 0);
 }
 
 void launch_diag_scale(const DevPlan& P, const double* K, double* scale, hipStream_t st) {

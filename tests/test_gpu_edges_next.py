@@ -79,3 +79,66 @@ def test_dense_equality_row_hykkt_cg():
     torch.cuda.synchronize()
     assert info["status"] == 0 and info["cg_iters"] > 0, info
     assert omega_of(p, "hykkt", z.cpu().numpy()) <= 1e-10
+
+
+def _nan_at(a, k=3, val=float("nan")):
+    b = np.array(a, dtype=np.float64, copy=True)
+    b[k] = val
+    return b
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("form", ["lifted", "hykkt"])
+def test_nonfinite_inputs_reported(form, precision):
+    p = workloads.tiny_grid(54)
+    print_case("nonfinite", form=form, precision=precision, n=p.n)
+    s = Solver(p, form, precision).bind(DEV)
+    rhs = torch.as_tensor(rhs_of(p, form), device=DEV)
+    for bad in (dataclasses.replace(p, sigma_x=_nan_at(p.sigma_x)),
+                dataclasses.replace(p, w_val=_nan_at(p.w_val, val=float("inf")))):
+        s.factorize(*device_values(bad, DEV, form), gamma=1e7)
+        assert s.factor_status() == -9
+        _, info = s.solve(rhs, raise_on_error=False)
+        assert info["status"] == -9, info
+    # a clean system afterwards: the flag is cleared; a NaN right-hand side is reported
+    s.factorize(*device_values(p, DEV, form), gamma=1e7)
+    assert s.factor_status() == 0
+    _, info = s.solve(rhs, raise_on_error=False)
+    assert info["status"] == 0
+    bad_rhs = torch.as_tensor(_nan_at(rhs_of(p, form)), device=DEV)
+    _, info = s.solve(bad_rhs, raise_on_error=False)
+    assert info["status"] == -9, info
+
+
+def test_nonfinite_k2_right_hand_side():
+    p = workloads.tiny_grid(55)
+    print_case("nonfinite_k2", n=p.n)
+    s = Solver(p, "lifted").bind(DEV)
+    s.factorize(*device_values(p, DEV, "lifted"))
+    rng = np.random.default_rng(55)
+    r = [torch.as_tensor(_nan_at(rng.standard_normal(k)) if i == 3 else rng.standard_normal(k), device=DEV)
+         for i, k in enumerate((p.n, p.m, 0, p.m))]
+    *_, info = s.solve_augmented(r[0], r[1], None, r[3], raise_on_error=False)
+    assert info["status"] == -9
+
+
+def test_cg_limit_and_refinement_limit():
+    """One CG iteration per outer step: the outer FP64 refinement on K1 still
+    reaches the gate (a stationary iteration around an inexact inner solve);
+    with the refinement also limited to one step it reports
+    CKKT_ERR_NO_CONVERGENCE and leaves its best iterate."""
+    p = workloads.tiny_grid(56)
+    print_case("cg_maxit_1", n=p.n)
+    rhs = torch.as_tensor(rhs_of(p, "hykkt"), device=DEV)
+    s = Solver(p, "hykkt", cg_maxit=1).bind(DEV)
+    s.factorize(*device_values(p, DEV, "hykkt"), gamma=1e7)
+    z, info = s.solve(rhs, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert info["status"] == 0 and info["refine_steps"] > 0 and info["cg_iters"] == info["refine_steps"] + 1, info
+    assert omega_of(p, "hykkt", z.cpu().numpy()) <= 1e-10
+    s1 = Solver(p, "hykkt", cg_maxit=1, ir_maxit=1).bind(DEV)
+    s1.factorize(*device_values(p, DEV, "hykkt"), gamma=1e7)
+    z1, info1 = s1.solve(rhs, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert info1["status"] == -4, info1
+    assert 1e-10 < info1["omega"] < np.inf and np.all(np.isfinite(z1.cpu().numpy()))

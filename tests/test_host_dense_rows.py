@@ -85,3 +85,31 @@ def test_host_woodbury_dense_equality_row(formulation):
     else:
         om = omega_kgamma(p, x, p.b, gamma)
     assert om < 1e-11, om
+
+
+def test_host_gamma_below_threshold_is_not_spd():
+    """Sec. 3.1 / eq:ipm:inertia: with K indefinite but positive definite on
+    Ker(G), K_gamma fails for small gamma and factors above the threshold."""
+    from oracle import dense as od
+    import dataclasses
+    base = workloads.tiny_grid(57, nx=4, ny=3, vpn=3, sigma_range=(-1, 1))
+    W, G, H = od.problem_dense(base)
+    K = od.condensed_matrix(W, base.sigma_x, H, base.sigma_s_ineq)
+    Y, Z, _ = od.null_range_bases(G)
+    lo, hi = np.linalg.eigvalsh(K)[0], np.linalg.eigvalsh(Z.T @ K @ Z)[0]
+    assert hi > lo + 0.1
+    shift = 0.5 * (lo + hi) + 0.5 * (hi - lo) * 0.5  # between the two smallest eigenvalues
+    w = base.w_val.copy()
+    for i in range(base.n):
+        for k in range(base.w_ptr[i], base.w_ptr[i + 1]):
+            if base.w_idx[k] == i:
+                w[k] -= shift
+    p = dataclasses.replace(base, w_val=w)
+    Kp = K - shift * np.eye(base.n)
+    assert np.linalg.eigvalsh(Kp)[0] < 0 < np.linalg.eigvalsh(Z.T @ Kp @ Z)[0]
+    thr = od.gamma_threshold(Kp, G)
+    s = Solver(p, "hykkt")
+    _, st, fc = s.host_factor_solve(p.w_val, p.g_val, p.h_val, p.sigma_x, p.sigma_s_ineq, 1e-6, p.r1bar)
+    assert st == -3 and fc >= 0
+    _, st, fc = s.host_factor_solve(p.w_val, p.g_val, p.h_val, p.sigma_x, p.sigma_s_ineq, 10 * thr, p.r1bar)
+    assert st == 0 and fc == -1
