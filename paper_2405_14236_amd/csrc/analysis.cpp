@@ -50,6 +50,84 @@ std::string validate(const PatternIn& p) {
     return e;
 }
 
+namespace {
+
+// Off-diagonal pairs (i > j) of W + J^T J, sorted and unique; rows of J
+// flagged in `dense` contribute nothing.
+std::vector<uint64_t> pattern_keys(const PatternIn& p, const std::vector<char>& dense) {
+    const int32_t n = (int32_t)p.n, me = (int32_t)p.m_eq, mi = (int32_t)p.m_ineq;
+    auto row = [&](int32_t r, const int32_t*& b, const int32_t*& e) {
+        if (r < me) { b = p.g_idx.data() + p.g_ptr[r]; e = p.g_idx.data() + p.g_ptr[r + 1]; }
+        else { b = p.h_idx.data() + p.h_ptr[r - me]; e = p.h_idx.data() + p.h_ptr[r - me + 1]; }
+    };
+    std::vector<uint64_t> keys;
+    {
+        int64_t est = (int64_t)p.w_idx.size();
+        for (int32_t r = 0; r < me + mi; ++r) {
+            const int32_t *b, *e;
+            row(r, b, e);
+            const int64_t q = dense[r] ? 0 : e - b;
+            est += q * (q - 1) / 2;
+        }
+        keys.reserve(est);
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = p.w_ptr[i]; k < p.w_ptr[i + 1]; ++k)
+            if (p.w_idx[k] != i) keys.push_back(((uint64_t)i << 32) | (uint32_t)p.w_idx[k]);
+    for (int32_t r = 0; r < me + mi; ++r) {
+        if (dense[r]) continue;
+        const int32_t *b, *e;
+        row(r, b, e);
+        for (const int32_t* a = b; a < e; ++a)
+            for (const int32_t* c = a + 1; c < e; ++c)
+                keys.push_back(((uint64_t)*c << 32) | (uint32_t)*a);  // cols increasing: *c > *a
+    }
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    return keys;
+}
+
+Graph graph_of(int32_t n, const std::vector<uint64_t>& keys) {
+    Graph g;
+    g.n = n;
+    g.ptr.assign(n + 1, 0);
+    for (uint64_t k : keys) {
+        g.ptr[(k >> 32) + 1]++;
+        g.ptr[(uint32_t)k + 1]++;
+    }
+    for (int32_t i = 0; i < n; ++i) g.ptr[i + 1] += g.ptr[i];
+    g.adj.resize(g.ptr[n]);
+    std::vector<int32_t> fill(g.ptr.begin(), g.ptr.end() - 1);
+    for (uint64_t k : keys) {
+        int32_t i = (int32_t)(k >> 32), j = (int32_t)(uint32_t)k;
+        g.adj[fill[i]++] = j;
+        g.adj[fill[j]++] = i;
+    }
+    return g;
+}
+
+std::vector<char> dense_mask(const PatternIn& p, int dense_row_min) {
+    const int32_t me = (int32_t)p.m_eq, mi = (int32_t)p.m_ineq;
+    std::vector<char> dense(me + mi, 0);
+    if (dense_row_min > 0) {
+        for (int32_t r = 0; r < me; ++r) dense[r] = p.g_ptr[r + 1] - p.g_ptr[r] >= dense_row_min;
+        for (int32_t r = 0; r < mi; ++r) dense[me + r] = p.h_ptr[r + 1] - p.h_ptr[r] >= dense_row_min;
+    }
+    return dense;
+}
+
+}  // namespace
+
+std::vector<int32_t> order_pattern(const PatternIn& p, int dense_row_min) {
+    const int32_t n = (int32_t)p.n;
+    if (n <= 1) {
+        std::vector<int32_t> id(n);
+        std::iota(id.begin(), id.end(), 0);
+        return id;
+    }
+    return amd_order(graph_of(n, pattern_keys(p, dense_mask(p, dense_row_min))));
+}
+
 std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     auto t0 = std::chrono::steady_clock::now();
     std::string err = validate(p);
@@ -73,59 +151,21 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     std::copy(p.h_idx.begin(), p.h_idx.end(), P.j_col.begin() + P.nnz_g);
 
     // ---- dense rows: kept out of K (their J^T J block would fill it)
-    std::vector<char> dense(m, 0);
+    const std::vector<char> dense = dense_mask(p, o.dense_row_min);
     P.dense_rows.clear();
-    if (o.dense_row_min > 0)
-        for (int32_t r = 0; r < m; ++r)
-            if (P.j_ptr[r + 1] - P.j_ptr[r] >= o.dense_row_min) {
-                dense[r] = 1;
-                P.dense_rows.push_back(r);
-            }
+    for (int32_t r = 0; r < m; ++r)
+        if (dense[r]) P.dense_rows.push_back(r);
 
-    // ---- unique off-diagonal pairs (i > j), original numbering
-    std::vector<uint64_t> keys;
-    {
-        int64_t est = P.nnz_w;
-        for (int32_t r = 0; r < m; ++r) {
-            int64_t q = dense[r] ? 0 : P.j_ptr[r + 1] - P.j_ptr[r];
-            est += q * (q - 1) / 2;
-        }
-        keys.reserve(est);
-    }
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t k = p.w_ptr[i]; k < p.w_ptr[i + 1]; ++k)
-            if (p.w_idx[k] != i) keys.push_back(((uint64_t)i << 32) | (uint32_t)p.w_idx[k]);
-    for (int32_t r = 0; r < m; ++r) {
-        if (dense[r]) continue;
-        for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
-            for (int32_t b = a + 1; b < P.j_ptr[r + 1]; ++b)
-                keys.push_back(((uint64_t)P.j_col[b] << 32) | (uint32_t)P.j_col[a]);  // cols increasing: b > a
-    }
-    std::sort(keys.begin(), keys.end());
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-
-    // ---- symmetric graph for the ordering
-    Graph g;
-    g.n = n;
-    g.ptr.assign(n + 1, 0);
-    for (uint64_t k : keys) {
-        g.ptr[(k >> 32) + 1]++;
-        g.ptr[(uint32_t)k + 1]++;
-    }
-    for (int32_t i = 0; i < n; ++i) g.ptr[i + 1] += g.ptr[i];
-    g.adj.resize(g.ptr[n]);
-    {
-        std::vector<int32_t> fill(g.ptr.begin(), g.ptr.end() - 1);
-        for (uint64_t k : keys) {
-            int32_t i = (int32_t)(k >> 32), j = (int32_t)(uint32_t)k;
-            g.adj[fill[i]++] = j;
-            g.adj[fill[j]++] = i;
-        }
-    }
+    // ---- unique off-diagonal pairs (i > j) of W + J^T J, original numbering,
+    // and the symmetric graph for the ordering
+    const std::vector<uint64_t> keys = pattern_keys(p, dense);
+    Graph g = graph_of(n, keys);
     std::vector<int32_t> perm0;
     if (o.ordering == 1 || n <= 1) {
         perm0.resize(n);
         std::iota(perm0.begin(), perm0.end(), 0);
+    } else if (o.perm) {
+        perm0 = *o.perm;  // checked below like any ordering
     } else {
         perm0 = amd_order(g);
     }

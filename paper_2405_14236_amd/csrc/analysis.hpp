@@ -106,7 +106,12 @@ struct AnalyzeOptions {
     int big_front = 96;    // fronts larger than this go to the tiled path
     int tile = 64;         // column tile of the tiled path
     int dense_row_min = 0; // rows of J with at least this many entries stay out of K (0: none)
+    const std::vector<int32_t>* perm = nullptr;  // fill-reducing ordering given by the caller (AMD mode)
 };
+
+// AMD ordering of one pattern's K = W + J^T J graph (rows of J with at least
+// dense_row_min entries left out when dense_row_min > 0); identity for n <= 1.
+std::vector<int32_t> order_pattern(const PatternIn& p, int dense_row_min);
 
 // Returns an empty string on success, else a description of the pattern error.
 std::string validate(const PatternIn& p);

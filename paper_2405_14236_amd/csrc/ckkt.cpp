@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -13,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -1377,7 +1379,29 @@ ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ck
         P.inst_n[i + 1] = (int32_t)off;
         P.inst_meq[i + 1] = (int32_t)roff;
     }
-    return finish_analyze(h, analyze_options(h->opt), u, out, workspace_bytes);
+    AnalyzeOptions ao = analyze_options(h->opt);
+    // The union graph is block diagonal: order every instance on its own,
+    // instances spread over up to kAnalyzeThreads host threads, and hand the
+    // concatenation to the analysis of the union.
+    std::vector<int32_t> perm;
+    if (h->opt.ordering == CKKT_ORDER_AMD) {
+        std::vector<std::vector<int32_t>> orders(count);
+        std::atomic<int> next{0};
+        auto work = [&]() {
+            for (int i; (i = next.fetch_add(1)) < count;) orders[i] = order_pattern(copy_pattern(&pats[i]), 0);
+        };
+        const int nthreads = std::max(1, std::min<int>({count, kAnalyzeThreads,
+                                                        (int)std::max(1u, std::thread::hardware_concurrency())}));
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+        work();
+        for (auto& t : pool) t.join();
+        perm.reserve(n);
+        for (int i = 0; i < count; ++i)
+            for (int32_t v : orders[i]) perm.push_back(v + P.inst_n[i]);
+        ao.perm = &perm;
+    }
+    return finish_analyze(h, ao, u, out, workspace_bytes);
 }
 
 ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, void* stream) {

@@ -202,6 +202,7 @@ void launch_g(const DevPlan& P, const SysVals& v, const double* x, const double*
 // kDotBlocks doubles.
 constexpr int kDotBlocks = 256;
 constexpr int kMaxDenseRows = 64;  // rows of J split off the condensed matrix at most
+constexpr int kAnalyzeThreads = 16;  // host threads of a batch analysis (orderings of the instances)
 void launch_dot(int n, const double* a, const double* b, double* partial, double* result, hipStream_t st);
 
 // CG helpers with device-resident scalars.  sc[0] = rr, sc[1] = pq,

@@ -192,6 +192,8 @@ def test_batch_analysis_is_block_diagonal():
     singles = [Solver(q, "lifted").info() for q in probs]
     assert inf["n"] == sum(q.n for q in probs)
     assert inf["nnz_k"] == sum(x["nnz_k"] for x in singles)
+    # every block is ordered on its own (the same AMD ordering as the single analysis)
+    assert inf["nnz_l"] == sum(x["nnz_l"] for x in singles)
     # host run of the union equals the union of host runs (certificate per block)
     w = np.concatenate([q.w_val for q in probs])
     g = np.concatenate([q.g_val for q in probs])
