@@ -6,10 +6,12 @@
 // with J = [G; H]; K_gamma adds gamma G^T G, whose pattern is already in
 // J^T J, so one analysis serves both formulations.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdint>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "analysis.hpp"
@@ -159,7 +161,6 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     // ---- unique off-diagonal pairs (i > j) of W + J^T J, original numbering,
     // and the symmetric graph for the ordering
     const std::vector<uint64_t> keys = pattern_keys(p, dense);
-    Graph g = graph_of(n, keys);
     std::vector<int32_t> perm0;
     if (o.ordering == 1 || n <= 1) {
         perm0.resize(n);
@@ -167,7 +168,7 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     } else if (o.perm) {
         perm0 = *o.perm;  // checked below like any ordering
     } else {
-        perm0 = amd_order(g);
+        perm0 = amd_order(graph_of(n, keys));
     }
     if ((int32_t)perm0.size() != n) return "internal: ordering is not a permutation";
     std::vector<int32_t> ip0(n, -1);
@@ -550,30 +551,53 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
             P.k_wsrc[sl] = k;
         }
     {
-        struct Pr { int32_t slot, r, a, b; };
-        std::vector<Pr> prods;
+        // products (a <= b) of every kept row, numbered row by row; their K
+        // slots are looked up on host threads, then a counting sort by slot
+        // keeps rows increasing inside a slot
+        std::vector<int64_t> poff(m + 1, 0);
+        for (int32_t r = 0; r < m; ++r) {
+            const int64_t q = dense[r] ? 0 : P.j_ptr[r + 1] - P.j_ptr[r];
+            poff[r + 1] = poff[r] + q * (q + 1) / 2;
+        }
+        std::vector<int32_t> pslot(poff[m]);
+        std::atomic<bool> missing{false};
+        auto lookup = [&](int32_t r0, int32_t r1) {
+            for (int32_t r = r0; r < r1; ++r) {
+                if (dense[r]) continue;
+                int64_t k = poff[r];
+                for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
+                    for (int32_t b = a; b < P.j_ptr[r + 1]; ++b) {
+                        const int32_t I = P.iperm[P.j_col[a]], J = P.iperm[P.j_col[b]];
+                        const int32_t sl = slot_of(std::max(I, J), std::min(I, J));
+                        if (sl < 0) missing = true;
+                        pslot[k++] = sl;
+                    }
+            }
+        };
+        const int nth = std::max(1, std::min(o.threads, m / 65536 + 1));
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth; ++t)
+            pool.emplace_back(lookup, (int32_t)((int64_t)m * t / nth), (int32_t)((int64_t)m * (t + 1) / nth));
+        lookup(0, (int32_t)((int64_t)m / nth));
+        for (auto& th : pool) th.join();
+        if (missing) return "internal: J product missing from K";
+        P.prod_ptr.assign(nnzk + 1, 0);
+        for (int32_t sl : pslot) P.prod_ptr[sl + 1]++;
+        for (int64_t t = 0; t < nnzk; ++t) P.prod_ptr[t + 1] += P.prod_ptr[t];
+        P.prod_r.resize(pslot.size());
+        P.prod_a.resize(pslot.size());
+        P.prod_b.resize(pslot.size());
+        std::vector<int32_t> fill(P.prod_ptr.begin(), P.prod_ptr.end() - 1);
+        int64_t k = 0;
         for (int32_t r = 0; r < m; ++r) {
             if (dense[r]) continue;
             for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
                 for (int32_t b = a; b < P.j_ptr[r + 1]; ++b) {
-                    int32_t I = P.iperm[P.j_col[a]], J = P.iperm[P.j_col[b]];
-                    int32_t sl = slot_of(std::max(I, J), std::min(I, J));
-                    if (sl < 0) return "internal: J product missing from K";
-                    prods.push_back({sl, r, a, b});
+                    const int32_t at = fill[pslot[k++]]++;
+                    P.prod_r[at] = r;
+                    P.prod_a[at] = a;
+                    P.prod_b[at] = b;
                 }
-        }
-        P.prod_ptr.assign(nnzk + 1, 0);
-        for (auto& q : prods) P.prod_ptr[q.slot + 1]++;
-        for (int64_t t = 0; t < nnzk; ++t) P.prod_ptr[t + 1] += P.prod_ptr[t];
-        P.prod_r.resize(prods.size());
-        P.prod_a.resize(prods.size());
-        P.prod_b.resize(prods.size());
-        std::vector<int32_t> fill(P.prod_ptr.begin(), P.prod_ptr.end() - 1);
-        for (auto& q : prods) {  // stable: rows stay increasing inside a slot
-            int32_t at = fill[q.slot]++;
-            P.prod_r[at] = q.r;
-            P.prod_a[at] = q.a;
-            P.prod_b[at] = q.b;
         }
     }
 

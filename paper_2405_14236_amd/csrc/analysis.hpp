@@ -107,6 +107,7 @@ struct AnalyzeOptions {
     int tile = 64;         // column tile of the tiled path
     int dense_row_min = 0; // rows of J with at least this many entries stay out of K (0: none)
     const std::vector<int32_t>* perm = nullptr;  // fill-reducing ordering given by the caller (AMD mode)
+    int threads = 1;       // host threads for the assembly recipe
 };
 
 // AMD ordering of one pattern's K = W + J^T J graph (rows of J with at least

@@ -527,6 +527,7 @@ AnalyzeOptions analyze_options(const ckkt_options& o) {
     ao.ordering = o.ordering;
     ao.relax = o.relax;
     ao.dense_row_min = o.dense_row_min;
+    ao.threads = std::max(1, std::min<int>(kAnalyzeThreads, (int)std::thread::hardware_concurrency()));
     // the whole front of a small supernode lives in LDS (f^2 elements <= 160 KiB)
     // the FP64 factor is also built for FP32_IR handles (refactorization
     // fallback), so the FP64 LDS capacity bounds both precisions
