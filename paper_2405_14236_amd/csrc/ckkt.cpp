@@ -83,7 +83,7 @@ struct ckkt_handle {
     Region r_K, r_d, r_scale, r_arena64, r_arena32, r_uvec, r_vperm, r_status, r_bits, r_dotpart, r_sc;
     Region r_sxreg, r_ssreg;  // diagonals shifted by delta_w (inertia correction)
     Region r_jd, r_z, r_cap, r_dpart, r_du;  // split dense rows: J_d, K_s^{-1} J_d^T, capacitance, dots
-    Region r_drowdot;                        // (J x)_r, (|J||x|)_r of the split rows for the row kernels
+    Region r_drowdot, r_drowpart, r_cpart;   // (J x)_r, (|J||x|)_r of the split rows; chunk partials
     Region r_ctl, r_done;  // dependency-driven sweeps: control words, per-supernode flags
     Region r_tflag;        // block flags of the tiled fronts (one launch per level)
     int64_t n_tflags = 0;
@@ -347,6 +347,8 @@ void build_layout(ckkt_handle* h) {
         h->r_dpart = L.add(kd * kDotBlocks * sizeof(double));
         h->r_du = L.add(kd * sizeof(double));
         h->r_drowdot = L.add(2 * kd * sizeof(double));
+        h->r_drowpart = L.add(2 * kd * kDenseChunkBuf * sizeof(double));
+        h->r_cpart = L.add(kd * (kd + 1) / 2 * kDenseChunkBuf * sizeof(double));
     }
     h->r_vn.clear();
     h->r_vm.clear();
@@ -408,6 +410,7 @@ void fill_devplan(ckkt_handle* h) {
     D.ndense = (int32_t)P.dense_rows.size();
     D.dense_min = D.ndense > 0 ? h->opt.dense_row_min : 0;
     D.drowdot = at<double>(h, h->r_drowdot);
+    D.drowpart = at<double>(h, h->r_drowpart);
 
     h->K = at<double>(h, h->r_K);
     h->d = at<double>(h, h->r_d);
@@ -700,7 +703,7 @@ void dense_rows_setup(ckkt_handle* h, hipStream_t st) {
     }
     for (int b = 0; b < k; ++b) apply_inverse_t<double>(h, h->jd + (int64_t)b * n, h->zd + (int64_t)b * n, nullptr, st);
     PhaseTimer tm(h, 1, st);
-    launch_dense_setup_cap(n, k, h->drows, h->d, h->jd, h->zd, h->cap, h->status, st);
+    launch_dense_setup_cap(n, k, h->drows, h->d, h->jd, h->zd, at<double>(h, h->r_cpart), h->cap, h->status, st);
 }
 
 struct ResidualOut {

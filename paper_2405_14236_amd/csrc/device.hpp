@@ -28,6 +28,7 @@ struct DevPlan {
     const int32_t* drows;
     int32_t ndense, dense_min;
     double* drowdot;
+    double* drowpart;  // per-chunk partials of drowdot (kDenseChunks per row)
 };
 
 // Values of the current system (device pointers owned by the caller).
@@ -181,7 +182,7 @@ void launch_bound_dual(int64_t count, const double* s, const double* v, double m
 void launch_dense_setup_gather(const DevPlan& P, const SysVals& v, const int32_t* rows, int k, double* jd,
                                hipStream_t st);
 void launch_dense_setup_cap(int n, int k, const int32_t* rows, const double* d, const double* jd, const double* z,
-                            double* cap, int32_t* status, hipStream_t st);
+                            double* cpart, double* cap, int32_t* status, hipStream_t st);
 void launch_dense_correct(int n, int k, const double* jd, const double* z, const double* cap, double* part,
                           double* u, double* x, hipStream_t st);
 
@@ -202,6 +203,7 @@ void launch_g(const DevPlan& P, const SysVals& v, const double* x, const double*
 // kDotBlocks doubles.
 constexpr int kDotBlocks = 256;
 constexpr int kMaxDenseRows = 64;  // rows of J split off the condensed matrix at most
+constexpr int kDenseChunkBuf = 64;  // chunks per split row in the partial-sum buffers (kernels' kDenseChunks)
 constexpr int kAnalyzeThreads = 16;  // host threads of a batch analysis (orderings of the instances)
 void launch_dot(int n, const double* a, const double* b, double* partial, double* result, hipStream_t st);
 

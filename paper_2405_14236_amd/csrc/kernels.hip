@@ -2125,12 +2125,23 @@ __global__ void k_bound_dual(int64_t count, const double* __restrict__ s, const 
 // C = D_d^{-1} + J_d Z (Woodbury).  J_d and Z are k dense rows of length n
 // (row-major), C's Cholesky factor is k x k (lower, row-major), k <= 64.
 
-// row b of J_d from the CSR values (J_d cleared beforehand)
+// Long rows are split into kDenseChunks chunks, one workgroup each; sums of
+// the chunks' partials are taken in chunk order (deterministic).
+constexpr int kDenseChunks = kDenseChunkBuf;
+
+__device__ __forceinline__ void chunk_of(int a0, int a1, int c, int& lo, int& hi) {
+    const int cs = (a1 - a0 + kDenseChunks - 1) / kDenseChunks;
+    lo = min(a1, a0 + c * cs);
+    hi = min(a1, lo + cs);
+}
+
+// row b of J_d from the CSR values (J_d cleared beforehand): grid (k, chunks)
 __global__ void k_dense_scatter(DevPlan P, SysVals v, const int32_t* __restrict__ rows, double* __restrict__ jd) {
-    const int b = blockIdx.x;
-    const int r = rows[b];
+    const int b = blockIdx.x, r = rows[b];
+    int lo, hi;
+    chunk_of(P.j_ptr[r], P.j_ptr[r + 1], blockIdx.y, lo, hi);
     double* out = jd + (int64_t)b * P.n;
-    for (int a = P.j_ptr[r] + threadIdx.x; a < P.j_ptr[r + 1]; a += blockDim.x) out[P.j_col[a]] = jval(v, P.nnzg, a);
+    for (int a = lo + threadIdx.x; a < hi; a += blockDim.x) out[P.j_col[a]] = jval(v, P.nnzg, a);
 }
 
 // block sum in a fixed order (256 threads)
@@ -2146,11 +2157,13 @@ __device__ double block_sum256(double x) {
 }
 
 // (J x)_r and (|J||x|)_r of the split rows for the row kernels (row_jx):
-// one workgroup per row, fixed-order sums
+// chunk partials, grid (k, chunks), then k_dense_rowdot_sum
 __global__ void __launch_bounds__(256) k_dense_rowdot(DevPlan P, SysVals v, const double* __restrict__ x) {
     const int b = blockIdx.x, r = P.drows[b];
+    int lo, hi;
+    chunk_of(P.j_ptr[r], P.j_ptr[r + 1], blockIdx.y, lo, hi);
     double acc = 0.0, mag = 0.0;
-    for (int a = P.j_ptr[r] + threadIdx.x; a < P.j_ptr[r + 1]; a += 256) {
+    for (int a = lo + threadIdx.x; a < hi; a += 256) {
         const double p = jval(v, P.nnzg, a) * x[P.j_col[a]];
         acc += p;
         mag += fabs(p);
@@ -2158,32 +2171,54 @@ __global__ void __launch_bounds__(256) k_dense_rowdot(DevPlan P, SysVals v, cons
     acc = block_sum256(acc);
     mag = block_sum256(mag);
     if (threadIdx.x == 0) {
-        P.drowdot[2 * b] = acc;
-        P.drowdot[2 * b + 1] = mag;
+        double* out = P.drowpart + 2 * ((int64_t)b * kDenseChunks + blockIdx.y);
+        out[0] = acc;
+        out[1] = mag;
     }
 }
 
-// lower triangle of C = D_d^{-1} + J_d Z: one workgroup per entry (a >= b)
+__global__ void k_dense_rowdot_sum(DevPlan P) {
+    const int b = threadIdx.x;
+    if (b >= P.ndense) return;
+    double acc = 0.0, mag = 0.0;
+    for (int c = 0; c < kDenseChunks; ++c) {
+        acc += P.drowpart[2 * (b * kDenseChunks + c)];
+        mag += P.drowpart[2 * (b * kDenseChunks + c) + 1];
+    }
+    P.drowdot[2 * b] = acc;
+    P.drowdot[2 * b + 1] = mag;
+}
+
+// chunk partials of the lower triangle of J_d Z: grid (k(k+1)/2, chunks)
 __global__ void __launch_bounds__(256)
-k_dense_cap(int n, int k, const int32_t* __restrict__ rows, const double* __restrict__ d,
-            const double* __restrict__ jd, const double* __restrict__ z, double* __restrict__ cap) {
+k_dense_cap(int n, const double* __restrict__ jd, const double* __restrict__ z, double* __restrict__ cpart) {
     int e = blockIdx.x, a = 0;
     while (e > a) { e -= a + 1; ++a; }  // entry (a, e) of the lower triangle, e <= a
+    int lo, hi;
+    chunk_of(0, n, blockIdx.y, lo, hi);
     const double* ja = jd + (int64_t)a * n;
     const double* zb = z + (int64_t)e * n;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) acc += ja[i] * zb[i];
+    for (int i = lo + threadIdx.x; i < hi; i += 256) acc += ja[i] * zb[i];
     acc = block_sum256(acc);
-    if (threadIdx.x == 0) cap[a * k + e] = acc + (a == e ? 1.0 / d[rows[a]] : 0.0);
+    if (threadIdx.x == 0) cpart[(int64_t)blockIdx.x * kDenseChunks + blockIdx.y] = acc;
 }
 
-// Cholesky factor of C in place (one workgroup of 64 threads, k <= 64); a
-// non-positive pivot reports column n (outside the matrix) through status.
-__global__ void __launch_bounds__(64) k_dense_chol(int n, int k, double* __restrict__ cap, int32_t* status) {
+// C = D_d^{-1} + J_d Z from the partials (chunk order), then its Cholesky
+// factor in place (one workgroup of 64 threads, k <= 64); a non-positive
+// pivot reports column n (outside the matrix) through status.
+__global__ void __launch_bounds__(64)
+k_dense_chol(int n, int k, const int32_t* __restrict__ rows, const double* __restrict__ d,
+             const double* __restrict__ cpart, double* __restrict__ cap, int32_t* status) {
     __shared__ double A[64 * 64];
     const int t = threadIdx.x;
     for (int i = 0; i < k; ++i)
-        if (t <= i) A[i * 64 + t] = cap[i * k + t];
+        if (t <= i) {
+            const int64_t e = (int64_t)i * (i + 1) / 2 + t;
+            double acc = 0.0;
+            for (int c = 0; c < kDenseChunks; ++c) acc += cpart[e * kDenseChunks + c];
+            A[i * 64 + t] = acc + (i == t ? 1.0 / d[rows[i]] : 0.0);
+        }
     __syncthreads();
     for (int j = 0; j < k; ++j) {
         if (t == 0) {
@@ -2218,14 +2253,23 @@ k_dense_dots(int n, const double* __restrict__ jd, const double* __restrict__ x,
     if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = acc;
 }
 
-// u = C^{-1} t with t summed from the partials in a fixed order (one thread)
-__global__ void k_dense_solve(int k, int nparts, const double* __restrict__ part, const double* __restrict__ cap,
-                              double* __restrict__ u) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// u = C^{-1} t, t_b summed from the partials by one wave (lane q takes
+// partials q, q + 64, ..., then a fixed butterfly), the solve by lane 0
+__global__ void __launch_bounds__(64)
+k_dense_solve(int k, int nparts, const double* __restrict__ part, const double* __restrict__ cap,
+              double* __restrict__ u) {
+    __shared__ double tb[64];
+    for (int b = 0; b < k; ++b) {
+        double acc = 0.0;
+        for (int q = threadIdx.x; q < nparts; q += kWave) acc += part[b * nparts + q];
+        acc = wave_sum(acc);
+        if (threadIdx.x == 0) tb[b] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     double y[64];
     for (int b = 0; b < k; ++b) {
-        double t = 0.0;
-        for (int q = 0; q < nparts; ++q) t += part[b * nparts + q];
+        double t = tb[b];
         for (int l = 0; l < b; ++l) t -= cap[b * k + l] * y[l];
         y[b] = t / cap[b * k + b];
     }
@@ -2842,7 +2886,9 @@ void launch_zero_u64(unsigned long long* p, int count, hipStream_t st) {
 }
 
 void launch_dense_rowdot(const DevPlan& P, const SysVals& v, const double* x, hipStream_t st) {
-    if (P.ndense > 0) hipLaunchKernelGGL(k_dense_rowdot, dim3(P.ndense), dim3(256), 0, st, P, v, x);
+    if (P.ndense == 0) return;
+    hipLaunchKernelGGL(k_dense_rowdot, dim3(P.ndense, kDenseChunks), dim3(256), 0, st, P, v, x);
+    hipLaunchKernelGGL(k_dense_rowdot_sum, dim3(1), dim3(64), 0, st, P);
 }
 void launch_residual(const DevPlan& P, const SysVals& v, const double* d, const double* x,
                      const double* y, const double* rhs1, const double* rhs2, double* res1,
@@ -2890,13 +2936,13 @@ void launch_dense_setup_gather(const DevPlan& P, const SysVals& v, const int32_t
                                hipStream_t st) {
     if (k <= 0 || P.n <= 0) return;
     launch_fill(k * P.n, 0.0, jd, st);
-    hipLaunchKernelGGL(k_dense_scatter, dim3(k), dim3(256), 0, st, P, v, rows, jd);
+    hipLaunchKernelGGL(k_dense_scatter, dim3(k, kDenseChunks), dim3(256), 0, st, P, v, rows, jd);
 }
 void launch_dense_setup_cap(int n, int k, const int32_t* rows, const double* d, const double* jd, const double* z,
-                            double* cap, int32_t* status, hipStream_t st) {
+                            double* cpart, double* cap, int32_t* status, hipStream_t st) {
     if (k <= 0) return;
-    hipLaunchKernelGGL(k_dense_cap, dim3(k * (k + 1) / 2), dim3(256), 0, st, n, k, rows, d, jd, z, cap);
-    hipLaunchKernelGGL(k_dense_chol, dim3(1), dim3(64), 0, st, n, k, cap, status);
+    hipLaunchKernelGGL(k_dense_cap, dim3(k * (k + 1) / 2, kDenseChunks), dim3(256), 0, st, n, jd, z, cpart);
+    hipLaunchKernelGGL(k_dense_chol, dim3(1), dim3(64), 0, st, n, k, rows, d, cpart, cap, status);
 }
 void launch_dense_correct(int n, int k, const double* jd, const double* z, const double* cap, double* part,
                           double* u, double* x, hipStream_t st) {
