@@ -188,7 +188,7 @@ ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats,
  * Errors: CKKT_ERR_WORKSPACE, CKKT_ERR_HIP. */
 ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, void* stream);
 
-/* Numeric phase for one new system (rows a1 and a2 of the hot path):
+/* Numeric phase for one new system (assembly and factorization):
  * assembles K (LiftedKKT) or K_gamma (HyKKT) in FP64 into the factor's
  * pattern and factorizes it, LL^T, in the handle's precision.  Work is
  * enqueued on `stream` (a hipStream_t, NULL = default stream); the call
@@ -206,8 +206,9 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
                            const double* h_val, const double* sigma_x,
                            const double* sigma_s, double gamma, void* stream);
 
-/* Waits for the factorization and reports CKKT_OK or CKKT_ERR_NOT_SPD (the
- * failing column is then in ckkt_info.failed_column). */
+/* Waits for the factorization and reports CKKT_OK, CKKT_ERR_NOT_SPD (the
+ * failing column is then in ckkt_info.failed_column), CKKT_ERR_NONFINITE (an
+ * assembled entry was NaN or Inf) or CKKT_ERR_TIMEOUT (left by a solve). */
 ckkt_status ckkt_factor_status(ckkt_handle* h, void* stream);
 
 /* HyKKT handles: the numeric phase for a system with dual regularization
@@ -282,7 +283,7 @@ ckkt_status ckkt_factorize_inertia(ckkt_handle* h, const double* w_val, const do
                                    const double* h_val, const double* sigma_x, const double* sigma_s,
                                    double gamma, ckkt_inertia* ic, void* stream);
 
-/* Solve with the current factor (rows a3-a5): triangular sweeps plus FP64
+/* Solve with the current factor: triangular sweeps plus FP64
  * iterative refinement with K applied unassembled (Sec. 2.2, "Iterative
  * refinement"); for HyKKT the CG of eq:kkt:schurcomplhykkt inside an outer
  * FP64 refinement on K1.  Stops when the componentwise relative backward
@@ -291,8 +292,9 @@ ckkt_status ckkt_factorize_inertia(ckkt_handle* h, const double* w_val, const do
  *   sol : same length; receives d_x (LiftedKKT) or (d_x; d_y) (HyKKT)
  *   info: host, may be NULL.
  * Blocks until the result is in `sol`.
- * Errors: CKKT_ERR_STATE, CKKT_ERR_NOT_SPD, CKKT_ERR_NO_CONVERGENCE (sol
- * then holds the best iterate), CKKT_ERR_BREAKDOWN, CKKT_ERR_HIP. */
+ * Errors: CKKT_ERR_STATE, CKKT_ERR_NOT_SPD, CKKT_ERR_NONFINITE (an input of the
+ * factor or the right-hand side), CKKT_ERR_NO_CONVERGENCE (sol then holds the
+ * best iterate), CKKT_ERR_BREAKDOWN, CKKT_ERR_TIMEOUT, CKKT_ERR_HIP. */
 ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol,
                        ckkt_solve_info* info, void* stream);
 
@@ -319,7 +321,8 @@ ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol,
  *   NULL, for LiftedKKT).  Outputs are overwritten.  Blocks until done.
  * Errors: CKKT_ERR_ARG (batch handle, missing pointer), CKKT_ERR_STATE (not
  * factorized, or factorized with ckkt_factorize_dual_reg), CKKT_ERR_NOT_SPD,
- * CKKT_ERR_NO_CONVERGENCE, CKKT_ERR_BREAKDOWN, CKKT_ERR_HIP. */
+ * CKKT_ERR_NONFINITE, CKKT_ERR_NO_CONVERGENCE, CKKT_ERR_BREAKDOWN,
+ * CKKT_ERR_TIMEOUT, CKKT_ERR_HIP. */
 ckkt_status ckkt_solve_augmented(ckkt_handle* h, const double* r1, const double* r2, const double* r3,
                                  const double* r4, double* dx, double* ds, double* dy, double* dz,
                                  ckkt_solve_info* info, void* stream);
