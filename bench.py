@@ -151,12 +151,20 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
             return s.solve_augmented(*rk2, raise_on_error=raise_on_error)[-1]
         return s.solve(rhs, out, raise_on_error=raise_on_error)[1]
     gamma = 1e7
+    names = ["assemble", "factor", "sweeps", "vector"]
+    # all phases are timed over the warm-up to find the dominant one; the
+    # timed region records events for that phase only (fewer event records)
+    s.set_timing(True)
+    s.get_timing()  # reset
     for k in range(warmup):
         factorize(k)
         solve()
+    torch.cuda.synchronize()
+    wms, wcalls = s.get_timing()
+    dom = int(np.argmax(wms)) if warmup > 0 and max(wms) > 0 else None
     attempts.clear()
     deltas.clear()
-    s.set_timing(True)
+    s.set_timing(True, phases=None if dom is None else (dom,))
     s.get_timing()  # reset
     torch.cuda.synchronize()
     infos = []
@@ -181,8 +189,9 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
                 refine_steps=float(np.mean([si["refine_steps"] for si in infos])),
                 cg_iters=float(np.mean([si["cg_iters"] for si in infos])),
                 fallbacks=int(sum(si["fallback"] != 0 for si in infos)),
-                phase_ms=dict(zip(["assemble", "factor", "sweeps", "vector"], ms)),
-                phase_calls=dict(zip(["assemble", "factor", "sweeps", "vector"], calls)),
+                phase_ms=dict(zip(names, ms)), phase_calls=dict(zip(names, calls)),
+                phase_ms_warmup=dict(zip(names, wms)), phase_calls_warmup=dict(zip(names, wcalls)),
+                dominant_phase=names[dom] if dom is not None else max(names, key=lambda q: ms[names.index(q)]),
                 analysis=info)
 
 
@@ -423,7 +432,7 @@ def main():
     # library's stream over the timed region)
     ph_ms, ph_calls = main_form["phase_ms"], main_form["phase_calls"]
     per_call = {k: ph_ms[k] / max(ph_calls[k], 1) for k in ph_ms}
-    dom = max(ph_ms, key=lambda k: ph_ms[k])
+    dom = main_form["dominant_phase"]
     if dom == "factor":
         bound, unit_bytes, flops = "hbm", cnt["factor_bytes"], cnt["factor_flops"]
     elif dom == "sweeps":

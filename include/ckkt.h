@@ -452,8 +452,9 @@ void        ckkt_destroy(ckkt_handle* h);
 /* Per-phase device time, in milliseconds, accumulated with HIP events on
  * the caller's stream since the last reset (0 = assemble, 1 = factor,
  * 2 = sweeps, 3 = residual/refinement/CG vector work) and the number of
- * calls of each phase.  Timing is off unless enabled; enabling it adds
- * event records but no synchronisation. */
+ * calls of each phase.  Timing is off unless enabled; `enable` is a mask of
+ * the phases to time (bit p for phase p; -1 = all, 0 = off).  A timed phase
+ * adds two event records per call but no synchronisation. */
 ckkt_status ckkt_set_timing(ckkt_handle* h, int32_t enable);
 ckkt_status ckkt_get_timing(ckkt_handle* h, double ms[4], int64_t calls[4]);
 

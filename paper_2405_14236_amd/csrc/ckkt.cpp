@@ -146,7 +146,7 @@ struct ckkt_handle {
     bool debug_launch = false;  // CKKT_DEBUG_LAUNCH=1: report the first failing launch per factor level
 
     // timing
-    bool timing = false;
+    int32_t timing = 0;  // bit p: phase p is timed
     double ms[4] = {0, 0, 0, 0};
     int64_t calls[4] = {0, 0, 0, 0};
     struct Pending { int phase; hipEvent_t a, b; };
@@ -181,13 +181,13 @@ struct PhaseTimer {
     hipStream_t st;
     hipEvent_t a = nullptr;
     PhaseTimer(ckkt_handle* h_, int ph, hipStream_t s) : h(h_), phase(ph), st(s) {
-        if (h->timing) {
+        if (h->timing & (1 << phase)) {
             a = take_event(h);
             if (a) (void)hipEventRecord(a, st);
         }
     }
     ~PhaseTimer() {
-        if (h->timing && a) {
+        if (a) {
             hipEvent_t b = take_event(h);
             if (b) {
                 (void)hipEventRecord(b, st);
@@ -2027,7 +2027,7 @@ void ckkt_destroy(ckkt_handle* h) {
 
 ckkt_status ckkt_set_timing(ckkt_handle* h, int32_t enable) {
     if (!h) return CKKT_ERR_ARG;
-    h->timing = enable != 0;
+    h->timing = enable & 0xF;
     return CKKT_OK;
 }
 

@@ -198,8 +198,11 @@ class Solver:
                                        _ptr(vals), _stream()), "ckkt_export_k")
         return rows, cols, vals
 
-    def set_timing(self, on=True):
-        L.check(self.lib.ckkt_set_timing(self.h, int(on)))
+    def set_timing(self, on=True, phases=None):
+        """Per-phase HIP-event timing: all phases, or only the given phase
+        numbers (0 assemble, 1 factor, 2 sweeps, 3 vector work)."""
+        mask = 0 if not on else (-1 if phases is None else sum(1 << int(q) for q in phases))
+        L.check(self.lib.ckkt_set_timing(self.h, mask))
 
     def get_timing(self):
         ms = (ctypes.c_double * 4)()
