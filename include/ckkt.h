@@ -171,6 +171,23 @@ void ckkt_default_options(ckkt_options* opt);
 ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt,
                          ckkt_handle** out, size_t* workspace_bytes);
 
+/* Checkpoint and resume of the symbolic phase (the analysis is done once
+ * per pattern and reused across factorizations, the reuse Sec. 6.1.1 counts
+ * on).  ckkt_plan_size gives the bytes of a serialized plan
+ * of handle h (single system or batch); ckkt_plan_save writes it into a
+ * HOST buffer of at least that size; ckkt_plan_load builds a new handle from
+ * such a buffer without analysing the pattern again (same meaning of opt,
+ * out and workspace_bytes as ckkt_analyze).  The options that shaped the
+ * plan (ordering, relax, LDS front limit, dense_row_min) and the
+ * formulation are taken from the plan; the others (precision, tolerances,
+ * learned) from opt.  The buffer carries a magic word, a format version and
+ * an FNV-1a checksum: a truncated, corrupted or foreign buffer gives
+ * CKKT_ERR_ARG.  A plan is tied to this library's format version. */
+ckkt_status ckkt_plan_size(const ckkt_handle* h, size_t* bytes);
+ckkt_status ckkt_plan_save(const ckkt_handle* h, void* buf, size_t bytes);
+ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* opt, ckkt_handle** out,
+                           size_t* workspace_bytes);
+
 /* Batched analysis: `count` independent systems analysed as one
  * block-diagonal system.  Value arrays passed to ckkt_factorize and
  * ckkt_solve are the per-instance arrays concatenated in instance order

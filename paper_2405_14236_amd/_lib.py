@@ -67,6 +67,9 @@ SIGNATURES = [
     ("ckkt_analyze", c_int32, [POINTER(Pattern), POINTER(Options), POINTER(c_void_p), POINTER(c_size_t)]),
     ("ckkt_batch_analyze", c_int32, [c_int32, POINTER(Pattern), POINTER(Options), POINTER(c_void_p),
                                      POINTER(c_size_t)]),
+    ("ckkt_plan_size", c_int32, [c_void_p, POINTER(c_size_t)]),
+    ("ckkt_plan_save", c_int32, [c_void_p, c_void_p, c_size_t]),
+    ("ckkt_plan_load", c_int32, [c_void_p, c_size_t, POINTER(Options), POINTER(c_void_p), POINTER(c_size_t)]),
     ("ckkt_bind_workspace", c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     ("ckkt_factorize", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p]),
     ("ckkt_factor_status", c_int32, [c_void_p, c_void_p]),

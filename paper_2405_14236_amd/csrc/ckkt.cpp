@@ -458,6 +458,10 @@ void fill_devplan(ckkt_handle* h) {
     }
 }
 
+// Everything after the symbolic analysis: launch geometry and workspace
+// layout (also the path of a plan loaded by ckkt_plan_load).
+ckkt_status finish_plan(ckkt_handle* h, const AnalyzeOptions& ao, ckkt_handle** out, size_t* workspace_bytes);
+
 ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const PatternIn& pin, ckkt_handle** out,
                            size_t* workspace_bytes) {
     std::string err = analyze(pin, ao, h->plan);
@@ -466,6 +470,10 @@ ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const Patte
         delete h;
         return internal ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
     }
+    return finish_plan(h, ao, out, workspace_bytes);
+}
+
+ckkt_status finish_plan(ckkt_handle* h, const AnalyzeOptions& ao, ckkt_handle** out, size_t* workspace_bytes) {
     if ((int)h->plan.dense_rows.size() > kMaxDenseRows) {
         delete h;
         return CKKT_ERR_ARG;
@@ -1283,6 +1291,112 @@ static ckkt_status inertia_search(ckkt_inertia* ic, Attempt attempt) {
     }
 }
 
+// ---------------------------------------------------- plan serialization
+
+// Every field of the plan, in one order for writing and reading.
+template <class A>
+void plan_fields(Plan& P, A& a) {
+    a.pod(P.n); a.pod(P.m_eq); a.pod(P.m_ineq); a.pod(P.m);
+    a.pod(P.nnz_w); a.pod(P.nnz_g); a.pod(P.nnz_h);
+    a.vec(P.perm); a.vec(P.iperm);
+    a.vec(P.kcolptr); a.vec(P.krow); a.vec(P.k_wsrc); a.vec(P.k_diag);
+    a.vec(P.prod_ptr); a.vec(P.prod_r); a.vec(P.prod_a); a.vec(P.prod_b); a.vec(P.dense_rows);
+    a.pod(P.ns);
+    a.vec(P.sn_start); a.vec(P.sn_rowptr); a.vec(P.sn_rows); a.vec(P.sn_parent);
+    a.vec(P.child_ptr); a.vec(P.child_list); a.vec(P.relmap); a.vec(P.kmap); a.vec(P.kcol);
+    a.vec(P.cb_ptr); a.vec(P.cb_src); a.vec(P.cb_len); a.vec(P.cb_uoff);
+    a.vec(P.l_off); a.vec(P.u_off); a.vec(P.u_ld); a.vec(P.big);
+    a.pod(P.arena); a.pod(P.nnz_l); a.pod(P.nnz_l_stored); a.pod(P.flops); a.pod(P.max_front); a.pod(P.n_big);
+    a.pod(P.nlev);
+    a.vec(P.sn_level); a.vec(P.lvl_ptr); a.vec(P.lvl_small); a.vec(P.lvl_small_ptr); a.vec(P.lvl_big);
+    a.vec(P.lvl_big_ptr); a.vec(P.lvl_all); a.vec(P.lvl_all_ptr); a.vec(P.lvl_maxw_big);
+    a.vec(P.big_tiles_ptr); a.vec(P.big_tile_sn); a.vec(P.big_tile_col);
+    a.vec(P.wf_ptr); a.vec(P.wf_col); a.vec(P.wf_vidx);
+    a.vec(P.j_ptr); a.vec(P.j_col);
+    a.vec(P.jt_ptr); a.vec(P.jt_row); a.vec(P.jt_vidx); a.vec(P.jt_gend);
+    a.pod(P.ninst); a.vec(P.inst_n); a.vec(P.inst_meq); a.vec(P.inst_of_var); a.vec(P.inst_of_eqrow);
+    a.pod(P.analyze_seconds);
+}
+
+struct PlanWriter {
+    std::vector<char> buf;
+    template <class T>
+    void pod(const T& v) {
+        const char* p = reinterpret_cast<const char*>(&v);
+        buf.insert(buf.end(), p, p + sizeof(T));
+    }
+    template <class T>
+    void vec(const std::vector<T>& v) {
+        pod((int64_t)v.size());
+        const char* p = reinterpret_cast<const char*>(v.data());
+        buf.insert(buf.end(), p, p + v.size() * sizeof(T));
+    }
+};
+
+struct PlanReader {
+    const char* p;
+    const char* e;
+    bool ok = true;
+    template <class T>
+    void pod(T& v) {
+        if (!ok || (size_t)(e - p) < sizeof(T)) { ok = false; return; }
+        std::memcpy(&v, p, sizeof(T));
+        p += sizeof(T);
+    }
+    template <class T>
+    void vec(std::vector<T>& v) {
+        int64_t n = -1;
+        pod(n);
+        if (!ok || n < 0 || (uint64_t)n > (uint64_t)(e - p) / sizeof(T)) { ok = false; return; }
+        v.resize((size_t)n);
+        if (n > 0) std::memcpy(v.data(), p, (size_t)n * sizeof(T));
+        p += (size_t)n * sizeof(T);
+    }
+};
+
+// FNV-1a, 64 bit
+uint64_t fnv1a(const char* p, size_t n) {
+    uint64_t x = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        x ^= (unsigned char)p[i];
+        x *= 1099511628211ull;
+    }
+    return x;
+}
+
+constexpr char kPlanMagic[8] = {'C', 'K', 'K', 'T', 'P', 'L', 'A', 'N'};
+constexpr int32_t kPlanVersion = 1;
+
+// header: magic, version, formulation, ordering, relax, lds front limit,
+// dense_row_min (int32 each after the magic), payload length (int64);
+// then the payload and its FNV-1a checksum
+struct PlanHeader {
+    char magic[8];
+    int32_t version, formulation, ordering, relax, big_front, dense_row_min;
+    int64_t payload;
+};
+
+std::vector<char> plan_blob(const ckkt_handle* h) {
+    PlanWriter w;
+    plan_fields(const_cast<Plan&>(h->plan), w);
+    PlanHeader hd{};
+    std::memcpy(hd.magic, kPlanMagic, 8);
+    const AnalyzeOptions ao = analyze_options(h->opt);
+    hd.version = kPlanVersion;
+    hd.formulation = h->formulation;
+    hd.ordering = h->opt.ordering;
+    hd.relax = h->opt.relax;
+    hd.big_front = ao.big_front;
+    hd.dense_row_min = h->opt.dense_row_min;
+    hd.payload = (int64_t)w.buf.size();
+    std::vector<char> out(sizeof hd + w.buf.size() + sizeof(uint64_t));
+    std::memcpy(out.data(), &hd, sizeof hd);
+    std::memcpy(out.data() + sizeof hd, w.buf.data(), w.buf.size());
+    const uint64_t sum = fnv1a(w.buf.data(), w.buf.size());
+    std::memcpy(out.data() + sizeof hd + w.buf.size(), &sum, sizeof sum);
+    return out;
+}
+
 }  // namespace
 
 // ================================================================= C-ABI
@@ -1331,6 +1445,64 @@ ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_
     h->precision = h->opt.precision;
     PatternIn pin = copy_pattern(pat);
     return finish_analyze(h, analyze_options(h->opt), pin, out, workspace_bytes);
+}
+
+ckkt_status ckkt_plan_size(const ckkt_handle* h, size_t* bytes) {
+    if (!h || !bytes) return CKKT_ERR_ARG;
+    *bytes = plan_blob(h).size();
+    return CKKT_OK;
+}
+
+ckkt_status ckkt_plan_save(const ckkt_handle* h, void* buf, size_t bytes) {
+    if (!h || !buf) return CKKT_ERR_ARG;
+    const std::vector<char> blob = plan_blob(h);
+    if (bytes < blob.size()) return CKKT_ERR_ARG;
+    std::memcpy(buf, blob.data(), blob.size());
+    return CKKT_OK;
+}
+
+ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* opt, ckkt_handle** out,
+                           size_t* workspace_bytes) {
+    if (!out || !buf || bytes < sizeof(PlanHeader) + sizeof(uint64_t)) return CKKT_ERR_ARG;
+    *out = nullptr;
+    PlanHeader hd;
+    std::memcpy(&hd, buf, sizeof hd);
+    const char* base = static_cast<const char*>(buf);
+    if (std::memcmp(hd.magic, kPlanMagic, 8) != 0 || hd.version != kPlanVersion || hd.payload < 0 ||
+        (uint64_t)hd.payload != bytes - sizeof hd - sizeof(uint64_t))
+        return CKKT_ERR_ARG;
+    uint64_t sum;
+    std::memcpy(&sum, base + sizeof hd + hd.payload, sizeof sum);
+    if (sum != fnv1a(base + sizeof hd, (size_t)hd.payload)) return CKKT_ERR_ARG;
+    if (hd.formulation != CKKT_LIFTED && hd.formulation != CKKT_HYKKT) return CKKT_ERR_ARG;
+    ckkt_handle* h = new (std::nothrow) ckkt_handle();
+    if (!h) return CKKT_ERR_ARG;
+    if (opt) h->opt = *opt;
+    else ckkt_default_options(&h->opt);
+    // the options that shaped the plan are the plan's
+    h->opt.ordering = hd.ordering;
+    h->opt.relax = hd.relax;
+    h->opt.lds_front_max = hd.big_front;
+    h->opt.dense_row_min = hd.dense_row_min;
+    if ((h->opt.precision != CKKT_FP64 && h->opt.precision != CKKT_FP32_IR) ||
+        (h->opt.dense_row_min > 0 && h->opt.precision != CKKT_FP64)) {
+        delete h;
+        return CKKT_ERR_ARG;
+    }
+    h->formulation = hd.formulation;
+    h->precision = h->opt.precision;
+    PlanReader r{base + sizeof hd, base + sizeof hd + hd.payload};
+    plan_fields(h->plan, r);
+    if (!r.ok || r.p != r.e) {
+        delete h;
+        return CKKT_ERR_ARG;
+    }
+    if (h->plan.ninst > 1 && h->opt.dense_row_min != 0) {
+        delete h;
+        return CKKT_ERR_ARG;
+    }
+    AnalyzeOptions ao = analyze_options(h->opt);
+    return finish_plan(h, ao, out, workspace_bytes);
 }
 
 ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt,

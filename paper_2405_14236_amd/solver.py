@@ -99,6 +99,40 @@ class Solver:
         self.workspace = None
         self._vals = None
 
+    # ------------------------------------------------------ plan checkpoint
+    def save_plan(self) -> bytes:
+        """The serialized analysis plan (ckkt_plan_save)."""
+        size = ctypes.c_size_t()
+        L.check(self.lib.ckkt_plan_size(self.h, ctypes.byref(size)), "ckkt_plan_size")
+        buf = ctypes.create_string_buffer(size.value)
+        L.check(self.lib.ckkt_plan_save(self.h, buf, size.value), "ckkt_plan_save")
+        return buf.raw
+
+    @classmethod
+    def from_plan(cls, blob: bytes, precision="fp64", **opts):
+        """A solver built from a saved plan, without analysing the pattern
+        again (ckkt_plan_load); the formulation and the options that shaped
+        the plan come from it."""
+        import struct
+        self = cls.__new__(cls)
+        self.lib = L.load()
+        self.opts = options(precision=precision, **opts)
+        # header: 8-byte magic, int32 version, int32 formulation, ...
+        self.formulation = struct.unpack_from("<i", blob, 12)[0] if len(blob) >= 16 else -1
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        L.check(self.lib.ckkt_plan_load(buf, len(blob), ctypes.byref(self.opts), ctypes.byref(h), ctypes.byref(ws)),
+                "ckkt_plan_load")
+        self.h = h
+        self.workspace_bytes = ws.value
+        self.workspace = None
+        self._vals = None
+        self._keep = []
+        inf = self.info()
+        self.n, self.m_eq, self.m_ineq = inf["n"], inf["m_eq"], inf["m_ineq"]
+        return self
+
     # ---------------------------------------------------------------- info
     def info(self):
         inf = L.Info()

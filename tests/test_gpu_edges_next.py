@@ -142,3 +142,21 @@ def test_cg_limit_and_refinement_limit():
     torch.cuda.synchronize()
     assert info1["status"] == -4, info1
     assert 1e-10 < info1["omega"] < np.inf and np.all(np.isfinite(z1.cpu().numpy()))
+
+
+@pytest.mark.parametrize("form", ["lifted", "hykkt"])
+def test_loaded_plan_solves_bitwise(form):
+    p = workloads.network_flow(2_000, seed=62)
+    print_case("plan_load", form=form, n=p.n)
+    s = Solver(p, form).bind(DEV)
+    t = Solver.from_plan(s.save_plan()).bind(DEV)
+    vals = device_values(p, DEV, form)
+    rhs = torch.as_tensor(rhs_of(p, form), device=DEV)
+    out = []
+    for sv in (s, t):
+        sv.factorize(*vals, gamma=1e7)
+        z, info = sv.solve(rhs)
+        torch.cuda.synchronize()
+        out.append((z.cpu().numpy(), info))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    assert omega_of(p, form, out[1][0]) <= 1e-10
