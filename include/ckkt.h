@@ -182,7 +182,9 @@ ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt,
  * formulation are taken from the plan; the others (precision, tolerances,
  * learned) from opt.  The buffer carries a magic word, a format version and
  * an FNV-1a checksum: a truncated, corrupted or foreign buffer gives
- * CKKT_ERR_ARG.  A plan is tied to this library's format version. */
+ * CKKT_ERR_ARG.  A plan is tied to this library's format version, and its
+ * contents are trusted: load only buffers written by ckkt_plan_save (the
+ * checksum catches corruption, not tampering). */
 ckkt_status ckkt_plan_size(const ckkt_handle* h, size_t* bytes);
 ckkt_status ckkt_plan_save(const ckkt_handle* h, void* buf, size_t bytes);
 ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* opt, ckkt_handle** out,

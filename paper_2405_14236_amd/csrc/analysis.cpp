@@ -576,8 +576,14 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
         };
         const int nth = std::max(1, std::min(o.threads, m / 65536 + 1));
         std::vector<std::thread> pool;
-        for (int t = 1; t < nth; ++t)
-            pool.emplace_back(lookup, (int32_t)((int64_t)m * t / nth), (int32_t)((int64_t)m * (t + 1) / nth));
+        for (int t = 1; t < nth; ++t) {
+            const int32_t lo = (int32_t)((int64_t)m * t / nth), hi = (int32_t)((int64_t)m * (t + 1) / nth);
+            try {
+                pool.emplace_back(lookup, lo, hi);
+            } catch (...) {
+                lookup(lo, hi);  // no thread: this chunk here
+            }
+        }
         lookup(0, (int32_t)((int64_t)m / nth));
         for (auto& th : pool) th.join();
         if (missing) return "internal: J product missing from K";

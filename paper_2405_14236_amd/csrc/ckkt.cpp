@@ -1569,7 +1569,13 @@ ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ck
         const int nthreads = std::max(1, std::min<int>({count, kAnalyzeThreads,
                                                         (int)std::max(1u, std::thread::hardware_concurrency())}));
         std::vector<std::thread> pool;
-        for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+        for (int t = 1; t < nthreads; ++t) {
+            try {
+                pool.emplace_back(work);
+            } catch (...) {
+                break;  // no thread: the ones running (and this one) take all instances
+            }
+        }
         work();
         for (auto& t : pool) t.join();
         perm.reserve(n);
