@@ -70,6 +70,8 @@ typedef int32_t ckkt_status;
                                        limit (seconds); the results of that solve are invalid.  Reported
                                        by the next call that synchronizes (ckkt_solve, ckkt_pcg_solve,
                                        ckkt_factor_status) and cleared by ckkt_factorize. */
+#define CKKT_ERR_HOST_MEMORY   -11  /* host memory or another host resource (a thread) ran out during
+                                       analysis, plan I/O or the host factor-solve */
 
 /* Formulations (Sec. 3). */
 #define CKKT_LIFTED 0

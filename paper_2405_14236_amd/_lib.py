@@ -15,7 +15,7 @@ MLP_F, MLP_H = 8, 64
 MLP_NPARAM = MLP_H * MLP_F + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
 STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_PATTERN", -3: "ERR_NOT_SPD", -4: "ERR_NO_CONVERGENCE",
                 -5: "ERR_BREAKDOWN", -6: "ERR_STATE", -7: "ERR_HIP", -8: "ERR_WORKSPACE", -9: "ERR_NONFINITE",
-                -10: "ERR_TIMEOUT"}
+                -10: "ERR_TIMEOUT", -11: "ERR_HOST_MEMORY"}
 LIFTED, HYKKT = 0, 1
 FP64, FP32_IR = 0, 1
 ORDER_AMD, ORDER_NATURAL = 0, 1

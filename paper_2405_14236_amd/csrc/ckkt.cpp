@@ -1427,8 +1427,9 @@ void ckkt_default_inertia(ckkt_inertia* ic) {
     ic->kappa_plus_bar = 100.0;
 }
 
-ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
+static ckkt_status ckkt_analyze_impl(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
                          size_t* workspace_bytes) {
+
     if (!out || !pattern_args_ok(pat)) return CKKT_ERR_ARG;
     *out = nullptr;
     ckkt_handle* h = new (std::nothrow) ckkt_handle();
@@ -1447,13 +1448,32 @@ ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_
     return finish_analyze(h, analyze_options(h->opt), pin, out, workspace_bytes);
 }
 
-ckkt_status ckkt_plan_size(const ckkt_handle* h, size_t* bytes) {
+ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
+                         size_t* workspace_bytes) {
+    try {
+        return ckkt_analyze_impl(pat, opt, out, workspace_bytes);
+    } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
+}
+
+static ckkt_status ckkt_plan_size_impl(const ckkt_handle* h, size_t* bytes) {
+
     if (!h || !bytes) return CKKT_ERR_ARG;
     *bytes = plan_blob(h).size();
     return CKKT_OK;
 }
 
-ckkt_status ckkt_plan_save(const ckkt_handle* h, void* buf, size_t bytes) {
+ckkt_status ckkt_plan_size(const ckkt_handle* h, size_t* bytes) {
+    try {
+        return ckkt_plan_size_impl(h, bytes);
+    } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
+}
+
+static ckkt_status ckkt_plan_save_impl(const ckkt_handle* h, void* buf, size_t bytes) {
+
     if (!h || !buf) return CKKT_ERR_ARG;
     const std::vector<char> blob = plan_blob(h);
     if (bytes < blob.size()) return CKKT_ERR_ARG;
@@ -1461,8 +1481,17 @@ ckkt_status ckkt_plan_save(const ckkt_handle* h, void* buf, size_t bytes) {
     return CKKT_OK;
 }
 
-ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* opt, ckkt_handle** out,
+ckkt_status ckkt_plan_save(const ckkt_handle* h, void* buf, size_t bytes) {
+    try {
+        return ckkt_plan_save_impl(h, buf, bytes);
+    } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
+}
+
+static ckkt_status ckkt_plan_load_impl(const void* buf, size_t bytes, const ckkt_options* opt, ckkt_handle** out,
                            size_t* workspace_bytes) {
+
     if (!out || !buf || bytes < sizeof(PlanHeader) + sizeof(uint64_t)) return CKKT_ERR_ARG;
     *out = nullptr;
     PlanHeader hd;
@@ -1505,8 +1534,18 @@ ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* op
     return finish_plan(h, ao, out, workspace_bytes);
 }
 
-ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt,
+ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* opt, ckkt_handle** out,
+                           size_t* workspace_bytes) {
+    try {
+        return ckkt_plan_load_impl(buf, bytes, opt, out, workspace_bytes);
+    } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
+}
+
+static ckkt_status ckkt_batch_analyze_impl(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt,
                                ckkt_handle** out, size_t* workspace_bytes) {
+
     if (!out || count <= 0 || !pats) return CKKT_ERR_ARG;
     *out = nullptr;
     for (int i = 0; i < count; ++i) {
@@ -1584,6 +1623,15 @@ ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ck
         ao.perm = &perm;
     }
     return finish_analyze(h, ao, u, out, workspace_bytes);
+}
+
+ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt,
+                               ckkt_handle** out, size_t* workspace_bytes) {
+    try {
+        return ckkt_batch_analyze_impl(count, pats, opt, out, workspace_bytes);
+    } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
 }
 
 ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, void* stream) {
@@ -1835,9 +1883,10 @@ ckkt_status ckkt_export_k(ckkt_handle* h, int32_t* rows, int32_t* cols, double* 
     return CKKT_OK;
 }
 
-ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, const double* g_val,
+static ckkt_status ckkt_host_factor_solve_impl(const ckkt_handle* h, const double* w_val, const double* g_val,
                                   const double* h_val, const double* sigma_x, const double* sigma_s,
                                   double gamma, const double* rhs, double* sol, int32_t* failed_column) {
+
     if (!h || !rhs || !sol) return CKKT_ERR_ARG;
     const Plan& P = h->plan;
     const bool hy = h->formulation == CKKT_HYKKT;
@@ -1897,9 +1946,20 @@ ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, co
     return CKKT_OK;
 }
 
-ckkt_status ckkt_host_factor_solve_inertia(const ckkt_handle* h, const double* w_val, const double* g_val,
+ckkt_status ckkt_host_factor_solve(const ckkt_handle* h, const double* w_val, const double* g_val,
+                                  const double* h_val, const double* sigma_x, const double* sigma_s,
+                                  double gamma, const double* rhs, double* sol, int32_t* failed_column) {
+    try {
+        return ckkt_host_factor_solve_impl(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, rhs, sol, failed_column);
+    } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
+}
+
+static ckkt_status ckkt_host_factor_solve_inertia_impl(const ckkt_handle* h, const double* w_val, const double* g_val,
                                            const double* h_val, const double* sigma_x, const double* sigma_s,
                                            double gamma, ckkt_inertia* ic, const double* rhs, double* sol) {
+
     if (!h || !rhs || !sol || !inertia_params_ok(ic) || h->plan.ninst > 1 || !h->plan.dense_rows.empty())
         return CKKT_ERR_ARG;
     const Plan& P = h->plan;
@@ -1913,6 +1973,16 @@ ckkt_status ckkt_host_factor_solve_inertia(const ckkt_handle* h, const double* w
         int fc = host_factor_solve(P, hy, w_val, g_val, h_val, sx.data(), ss.data(), gamma, rhs, sol);
         return fc >= 0 ? CKKT_ERR_NOT_SPD : CKKT_OK;
     });
+}
+
+ckkt_status ckkt_host_factor_solve_inertia(const ckkt_handle* h, const double* w_val, const double* g_val,
+                                           const double* h_val, const double* sigma_x, const double* sigma_s,
+                                           double gamma, ckkt_inertia* ic, const double* rhs, double* sol) {
+    try {
+        return ckkt_host_factor_solve_inertia_impl(h, w_val, g_val, h_val, sigma_x, sigma_s, gamma, ic, rhs, sol);
+    } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
 }
 
 static ckkt_status set_new_values(ckkt_handle* h, const double* w_val, const double* g_val, const double* h_val,
@@ -2184,6 +2254,7 @@ const char* ckkt_status_string(ckkt_status s) {
         case CKKT_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
         case CKKT_ERR_NONFINITE: return "non-finite input";
         case CKKT_ERR_TIMEOUT: return "dependency wait in a triangular sweep timed out";
+        case CKKT_ERR_HOST_MEMORY: return "host memory or a host thread could not be obtained";
         default: return "unknown status";
     }
 }
