@@ -160,3 +160,47 @@ def test_loaded_plan_solves_bitwise(form):
         out.append((z.cpu().numpy(), info))
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
     assert omega_of(p, form, out[1][0]) <= 1e-10
+
+
+@pytest.mark.parametrize("form", ["lifted", "hykkt"])
+def test_k2_step_fp32_factor(form):
+    """The K2 Newton step on an FP32 + FP64-refinement handle meets the 1e-8
+    gate (refining on K2, falling back to the FP64 factor when it stalls)."""
+    from oracle import newton as on
+    import scipy.sparse as sp
+    p = workloads.tiny_grid(63, nx=12, ny=12)
+    print_case("k2_fp32", form=form, n=p.n)
+    s = Solver(p, form, "fp32_ir", tol=1e-8).bind(DEV)
+    s.factorize(*device_values(p, DEV, form), gamma=1e7)
+    ms = p.m if form == "lifted" else p.m_ineq
+    me = 0 if form == "lifted" else p.m_eq
+    rng = np.random.default_rng(63)
+    r = [rng.standard_normal(k) for k in (p.n, ms, me, ms)]
+    t = [torch.as_tensor(a, device=DEV) for a in r]
+    dx, ds, dy, dz, info = s.solve_augmented(t[0], t[1], t[2] if me else None, t[3])
+    torch.cuda.synchronize()
+    assert info["status"] == 0, info
+    P = osp.Problem(p)
+    if form == "lifted":
+        G, H, E = sp.csr_matrix((0, p.n)), P.J, p.sigma_s
+    else:
+        G, H, E = P.G, P.H, p.sigma_s_ineq
+    yv = dy.cpu().numpy() if dy is not None else np.zeros(0)
+    om = on.omega_k2(P.W, p.sigma_x, G, H, E, *r, dx.cpu().numpy(), ds.cpu().numpy(), yv, dz.cpu().numpy())
+    print("omega", om, info)
+    assert om <= 1e-8
+
+
+def test_dual_reg_fp32_factor():
+    p = workloads.tiny_grid(64, nx=12, ny=12)
+    print_case("dual_reg_fp32", n=p.n)
+    s = Solver(p, "hykkt", "fp32_ir", tol=1e-8).bind(DEV)
+    s.factorize_dual_reg(*device_values(p, DEV, "hykkt"), 1e-6)
+    z, info = s.solve(torch.as_tensor(rhs_of(p, "hykkt"), device=DEV), raise_on_error=False)
+    torch.cuda.synchronize()
+    assert info["status"] == 0 and info["cg_iters"] == 0, info
+    P = osp.Problem(p)
+    zz = z.cpu().numpy()
+    om = osp.omega_k1(P.W, p.sigma_x, P.H, p.sigma_s_ineq, P.G, zz[:p.n], zz[p.n:], p.r1bar, p.r2bar, 1e-6)
+    print("omega", om, info)
+    assert om <= 1e-8
