@@ -54,38 +54,83 @@ std::string validate(const PatternIn& p) {
 
 namespace {
 
-// Off-diagonal pairs (i > j) of W + J^T J, sorted and unique; rows of J
-// flagged in `dense` contribute nothing.
-std::vector<uint64_t> pattern_keys(const PatternIn& p, const std::vector<char>& dense) {
-    const int32_t n = (int32_t)p.n, me = (int32_t)p.m_eq, mi = (int32_t)p.m_ineq;
+// Off-diagonal pairs (i > j) of W + J^T J over the variables [v0, v1), the
+// equality rows [g0, g1) and the inequality rows [h0, h1), sorted and
+// unique; rows of J flagged in `dense` contribute nothing.
+std::vector<uint64_t> pattern_keys_range(const PatternIn& p, const std::vector<char>& dense, int32_t v0, int32_t v1,
+                                         int32_t g0, int32_t g1, int32_t h0, int32_t h1) {
+    const int32_t me = (int32_t)p.m_eq;
     auto row = [&](int32_t r, const int32_t*& b, const int32_t*& e) {
         if (r < me) { b = p.g_idx.data() + p.g_ptr[r]; e = p.g_idx.data() + p.g_ptr[r + 1]; }
         else { b = p.h_idx.data() + p.h_ptr[r - me]; e = p.h_idx.data() + p.h_ptr[r - me + 1]; }
     };
+    auto rows = [&](auto&& fn) {
+        for (int32_t r = g0; r < g1; ++r) fn(r);
+        for (int32_t r = me + h0; r < me + h1; ++r) fn(r);
+    };
     std::vector<uint64_t> keys;
     {
-        int64_t est = (int64_t)p.w_idx.size();
-        for (int32_t r = 0; r < me + mi; ++r) {
+        int64_t est = (int64_t)p.w_ptr[v1] - p.w_ptr[v0];
+        rows([&](int32_t r) {
             const int32_t *b, *e;
             row(r, b, e);
             const int64_t q = dense[r] ? 0 : e - b;
             est += q * (q - 1) / 2;
-        }
+        });
         keys.reserve(est);
     }
-    for (int32_t i = 0; i < n; ++i)
+    for (int32_t i = v0; i < v1; ++i)
         for (int32_t k = p.w_ptr[i]; k < p.w_ptr[i + 1]; ++k)
             if (p.w_idx[k] != i) keys.push_back(((uint64_t)i << 32) | (uint32_t)p.w_idx[k]);
-    for (int32_t r = 0; r < me + mi; ++r) {
-        if (dense[r]) continue;
+    rows([&](int32_t r) {
+        if (dense[r]) return;
         const int32_t *b, *e;
         row(r, b, e);
         for (const int32_t* a = b; a < e; ++a)
             for (const int32_t* c = a + 1; c < e; ++c)
                 keys.push_back(((uint64_t)*c << 32) | (uint32_t)*a);  // cols increasing: *c > *a
-    }
+    });
     std::sort(keys.begin(), keys.end());
     keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    return keys;
+}
+
+std::vector<uint64_t> pattern_keys(const PatternIn& p, const std::vector<char>& dense) {
+    return pattern_keys_range(p, dense, 0, (int32_t)p.n, 0, (int32_t)p.m_eq, 0, (int32_t)p.m_ineq);
+}
+
+// The same for a block-diagonal pattern, block by block on up to `threads`
+// host threads: the blocks' variable ranges increase, so their sorted key
+// lists concatenate into the sorted list of the whole.
+std::vector<uint64_t> block_pattern_keys(const PatternIn& p, const std::vector<char>& dense, const AnalyzeOptions& o) {
+    const std::vector<int32_t>& bn = *o.block_n;
+    const std::vector<int32_t>& bg = *o.block_meq;
+    const std::vector<int32_t>& bh = *o.block_mineq;
+    const int nb = (int)bn.size() - 1;
+    std::vector<std::vector<uint64_t>> part(nb);
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (int i; (i = next.fetch_add(1)) < nb;)
+            part[i] = pattern_keys_range(p, dense, bn[i], bn[i + 1], bg[i], bg[i + 1], bh[i], bh[i + 1]);
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < std::min(o.threads, nb); ++t) {
+        try {
+            pool.emplace_back(work);
+        } catch (...) {
+            break;  // no thread: the others take its blocks
+        }
+    }
+    work();
+    for (auto& th : pool) th.join();
+    size_t total = 0;
+    for (auto& v : part) total += v.size();
+    std::vector<uint64_t> keys;
+    keys.reserve(total);
+    for (auto& v : part) {
+        keys.insert(keys.end(), v.begin(), v.end());
+        std::vector<uint64_t>().swap(v);
+    }
     return keys;
 }
 
@@ -160,7 +205,10 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
 
     // ---- unique off-diagonal pairs (i > j) of W + J^T J, original numbering,
     // and the symmetric graph for the ordering
-    const std::vector<uint64_t> keys = pattern_keys(p, dense);
+    const bool blocks = o.block_n && o.block_meq && o.block_mineq && o.block_n->size() > 1 &&
+                        o.block_meq->size() == o.block_n->size() && o.block_mineq->size() == o.block_n->size() &&
+                        o.block_n->back() == n && o.block_meq->back() == P.m_eq && o.block_mineq->back() == P.m_ineq;
+    const std::vector<uint64_t> keys = blocks ? block_pattern_keys(p, dense, o) : pattern_keys(p, dense);
     std::vector<int32_t> perm0;
     if (o.ordering == 1 || n <= 1) {
         perm0.resize(n);

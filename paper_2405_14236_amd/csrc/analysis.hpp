@@ -107,7 +107,12 @@ struct AnalyzeOptions {
     int tile = 64;         // column tile of the tiled path
     int dense_row_min = 0; // rows of J with at least this many entries stay out of K (0: none)
     const std::vector<int32_t>* perm = nullptr;  // fill-reducing ordering given by the caller (AMD mode)
-    int threads = 1;       // host threads for the assembly recipe
+    int threads = 1;       // host threads (assembly recipe; per-block pair keys)
+    // block-diagonal pattern (a batch): prefix offsets of the blocks' variables,
+    // equality rows and inequality rows; their pair keys are built per block
+    const std::vector<int32_t>* block_n = nullptr;
+    const std::vector<int32_t>* block_meq = nullptr;
+    const std::vector<int32_t>* block_mineq = nullptr;
 };
 
 // AMD ordering of one pattern's K = W + J^T J graph (rows of J with at least

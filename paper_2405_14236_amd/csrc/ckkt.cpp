@@ -1595,6 +1595,11 @@ static ckkt_status ckkt_batch_analyze_impl(int32_t count, const ckkt_pattern* pa
         P.inst_meq[i + 1] = (int32_t)roff;
     }
     AnalyzeOptions ao = analyze_options(h->opt);
+    std::vector<int32_t> bn(P.inst_n), bg(P.inst_meq), bh(count + 1, 0);
+    for (int i = 0; i < count; ++i) bh[i + 1] = bh[i] + (int32_t)pats[i].m_ineq;
+    ao.block_n = &bn;
+    ao.block_meq = &bg;
+    ao.block_mineq = &bh;
     // The union graph is block diagonal: order every instance on its own,
     // instances spread over up to kAnalyzeThreads host threads, and hand the
     // concatenation to the analysis of the union.
