@@ -1,15 +1,32 @@
-"""Benchmark: condensed-KKT solves/s on one MI355X.
+"""Benchmark: condensed-KKT solves/s at a 1e-8 residual on one MI355X.
 
-One step = one new system of the network-flow workload (10,000 nodes,
-13,000 edges: n = 66,000 variables, 20,000 equality and 52,000 inequality
-rows, diagonals drawn log-uniform in [1e-8, 1e8] afresh for every step):
-assemble K, factorize it, and solve with FP64 refinement until the
-componentwise relative backward error is <= 1e-10 (which is below the
-metric's 1e-8).  ``value`` is LiftedKKT FP64 solves/s; the other forms are
-timed the same way and reported under ``forms``.
+Headline (``value``): LiftedKKT FP64 on the large network-flow problem
+(80,000 nodes, 104,000 edges: n = 528,000 variables, 160,000 equality and
+416,000 inequality rows), the stand-in for the paper's 674k-variable OPF
+instance (Sec. 6.1, tab:linsol:time, fig:timebreakdown).  One step = one new
+system (diagonals drawn log-uniform in [1e-8, 1e8] afresh for every step)
+through assembly, factorization and solve with FP64 refinement until the
+componentwise relative backward error is <= 1e-10 (below the metric's 1e-8).
 
-Prints one JSON line.  Inputs (all diagonals of all steps) are resident in
-HBM before the timed region starts.
+The other arms of the metric are timed in the same run and reported under
+``forms``:
+
+* ``netflow80k``: HyKKT FP64 (gamma = 1e7, CG tol 1e-10) on the same systems;
+* ``seq80k``: the 60-system IPM-like sequence on the same pattern (diagonals
+  moving from 1 to 1e+-8), FP64 versus FP32 factor + FP64 refinement, per
+  system, with the systems on which FP32 + refinement wins;
+* ``batch512``: 512 independent network-flow instances of uneven size
+  (500..2000 nodes), FP64 and FP32 + FP64 refinement;
+* ``pde48``: the 48^3 PDE-control problem's 80-system sequence, FP64
+  refactorization of every system versus PCG around a stale factor with
+  D = I and with the learned preconditioner (trained on systems 0..19);
+* ``netflow10k``: the 66,000-variable network flow with the forms built
+  around the path (inertia correction, dual regularization, the K2 Newton
+  step, split dense rows).
+
+Prints one JSON line.  Inputs are resident in HBM before a timed region
+starts; ``--parts`` restricts the run to some of the parts (the headline is
+always measured).
 """
 import argparse
 import json
@@ -24,6 +41,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+METRIC = "condensed-KKT solves/s at 1e-8 rel. residual: FP64 vs FP32+IR/batched/PCG"
+HEADLINE_NODES = 80_000
+PARTS = ("netflow80k", "seq80k", "batch512", "pde48", "netflow10k")
 
 
 def parse():
@@ -31,26 +52,24 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--nodes", type=int, default=10_000)
-    ap.add_argument("--forms",
-                    default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia,hykkt_fp64_dualreg,lifted_fp64_k2,hykkt_fp64_k2,"
-                            "lifted_fp64_dense4")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--parts", default=",".join(PARTS),
+                    help="comma list of " + ", ".join(PARTS) + " (the headline always runs); 'none' for none")
+    ap.add_argument("--forms10k",
+                    default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia,hykkt_fp64_dualreg,lifted_fp64_k2,"
+                            "hykkt_fp64_k2,lifted_fp64_dense4,lifted_fp32ir,hykkt_fp32ir",
+                    help="forms of the netflow10k part")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="netflow",
-                    choices=["netflow", "netflow_seq", "batch", "pde_learned"],
-                    help="netflow: the benchmark line; the others measure the other target forms")
-    ap.add_argument("--systems", type=int, default=None,
-                    help="sequence length (netflow_seq: 60, pde_learned: 80)")
-    ap.add_argument("--instances", type=int, default=512, help="batch size (batch)")
+    ap.add_argument("--systems", type=int, default=None, help="sequence lengths (seq80k: 60, pde48: 80)")
+    ap.add_argument("--instances", type=int, default=512, help="batch size")
     ap.add_argument("--side", type=int, default=48, help="grid side of the PDE workload")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (scale of the HBM byte counters)")
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_factor_netflow10k.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_factor_netflow80k.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2405_14236_amd", "csrc", "kernels.hip")
 
 
@@ -71,46 +90,49 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_factorization"]) if sha == vals["source_sha256"] else None
 
 
-def algorithmic_counts(p, info, formulation):
+def algorithmic_counts(p, info):
     """Algorithmic bytes / flops per unit of work, from the analysis."""
     nnz_w, nnz_g, nnz_h = len(p.w_idx), len(p.g_idx), len(p.h_idx)
     n, m = p.n, p.m_eq + p.m_ineq
     nnz_k, nnz_l = info["nnz_k"], info["nnz_l"]
-    assemble_bytes = 8 * (nnz_w + nnz_g + nnz_h + n + m) + 8 * nnz_k
-    factor_bytes = 8 * nnz_k + 8 * nnz_l
-    sweep_bytes = 2 * 8 * nnz_l + 6 * 8 * n
-    resid_bytes = 8 * (nnz_w + 2 * (nnz_g + nnz_h)) + 5 * 8 * n
-    return dict(assemble_bytes=assemble_bytes, factor_bytes=factor_bytes, factor_flops=info["factor_flops"],
-                sweep_bytes=sweep_bytes, sweep_flops=4 * nnz_l, resid_bytes=resid_bytes)
+    return dict(assemble_bytes=8 * (nnz_w + nnz_g + nnz_h + n + m) + 8 * nnz_k,
+                factor_bytes=8 * nnz_k + 8 * nnz_l, factor_flops=info["factor_flops"],
+                sweep_bytes=2 * 8 * nnz_l + 6 * 8 * n, sweep_flops=4 * nnz_l,
+                resid_bytes=8 * (nnz_w + 2 * (nnz_g + nnz_h)) + 5 * 8 * n)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 INERTIA_SHIFT = 1.0
+GAMMA = 1e7
 
 
 def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
-    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia|_dualreg|_k2|_dense4].  The _inertia
-    forms lower W's diagonal by INERTIA_SHIFT (negative curvature wherever
-    K_jj is below it) and factorize with inertia correction, carrying
-    delta_w_last from one system to the next as an interior-point method
-    does.  hykkt_*_dualreg solves K1 with dual regularization delta_c = 1/gamma
-    directly through the same K_gamma factor (no CG).  The _k2 forms take the
-    full Newton step of the augmented system K2 (ckkt_solve_augmented) for
-    seeded r1..r4 instead of the condensed solve.  The _dense4 forms add four
-    inequality rows over half of the variables, kept out of K
-    (opt.dense_row_min) and applied by the Woodbury step."""
+    """One form: <lifted|hykkt>_<fp64|fp32ir>[_inertia|_dualreg|_k2|_dense4],
+    one new system per step (sig[k] = (sigma_x, sigma_s) of step k).  The
+    _inertia forms lower W's diagonal by INERTIA_SHIFT (negative curvature
+    wherever K_jj is below it) and factorize with inertia correction,
+    carrying delta_w_last from one system to the next as an interior-point
+    method does.  hykkt_*_dualreg solves K1 with dual regularization
+    delta_c = 1/gamma directly through the same K_gamma factor (no CG).  The
+    _k2 forms take the full Newton step of the augmented system K2
+    (ckkt_solve_augmented) for seeded r1..r4 instead of the condensed solve.
+    The _dense4 forms add four inequality rows over half of the variables,
+    kept out of K (opt.dense_row_min) and applied by the Woodbury step."""
     formulation, precision, *variant = form.split("_")
     prec = {"fp64": "fp64", "fp32ir": "fp32_ir"}[precision]
     inertia = variant == ["inertia"]
     dualreg = variant == ["dualreg"]
     k2 = variant == ["k2"]
-    opts = {}
+    opts = {} if prec == "fp64" else {"tol": 1e-8}
     if variant == ["dense4"]:
-        # four extra inequality rows over half of the variables, split off K
         import paper_2405_14236_amd.workloads as wl
         p = wl.with_dense_rows(p, count=4, frac=0.5, seed=1)
         rng = np.random.default_rng(11)
         sig = [(a, np.concatenate([b, wl.log_uniform(rng, 4)])) for a, b in sig]
-        opts = {"dense_row_min": 1000}
+        opts["dense_row_min"] = 1000
     dev = "cuda"
     s = Solver(p, formulation, prec, **opts).bind(dev)
     info = s.info()
@@ -121,20 +143,20 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
         wv[rows == p.w_idx] -= INERTIA_SHIFT
         w = torch.as_tensor(wv, device=dev)
     last, attempts, deltas = [0.0], [], []
+    sx = [torch.as_tensor(a, device=dev) for a, _ in sig]
+    ss = [torch.as_tensor(b if formulation == "lifted" else b[p.m_eq:], device=dev) for _, b in sig]
 
     def factorize(k):
         if dualreg:
-            s.factorize_dual_reg(w, g, h, sx[k], ss[k], 1.0 / gamma)
+            s.factorize_dual_reg(w, g, h, sx[k], ss[k], 1.0 / GAMMA)
             return
         if not inertia:
-            s.factorize(w, g, h, sx[k], ss[k], gamma)
+            s.factorize(w, g, h, sx[k], ss[k], GAMMA)
             return
-        st, r = s.factorize_inertia(w, g, h, sx[k], ss[k], gamma, delta_w_last=last[0])
+        st, r = s.factorize_inertia(w, g, h, sx[k], ss[k], GAMMA, delta_w_last=last[0])
         last[0] = r["delta_w_last"]
         attempts.append(r["attempts"])
         deltas.append(r["delta_w"])
-    sx = [torch.as_tensor(a, device=dev) for a, _ in sig]
-    ss = [torch.as_tensor(b if formulation == "lifted" else b[p.m_eq:], device=dev) for _, b in sig]
     rhs = np.concatenate([p.r1bar, p.r2bar]) if formulation == "hykkt" else p.b
     rhs = torch.as_tensor(rhs, device=dev)
     out = torch.empty_like(rhs)
@@ -150,7 +172,6 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
         if k2:
             return s.solve_augmented(*rk2, raise_on_error=raise_on_error)[-1]
         return s.solve(rhs, out, raise_on_error=raise_on_error)[1]
-    gamma = 1e7
     names = ["assemble", "factor", "sweeps", "vector"]
     # all phases are timed over the warm-up to find the dominant one; the
     # timed region records events for that phase only (fewer event records)
@@ -158,7 +179,7 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     s.get_timing()  # reset
     for k in range(warmup):
         factorize(k)
-        solve()
+        solve(raise_on_error=False)
     torch.cuda.synchronize()
     wms, wcalls = s.get_timing()
     dom = int(np.argmax(wms)) if warmup > 0 and max(wms) > 0 else None
@@ -171,110 +192,126 @@ def time_form(form, p, sig, steps, warmup, torch, Solver, device_values):
     t0 = time.perf_counter()
     for k in range(warmup, warmup + steps):
         factorize(k)
-        si = solve(raise_on_error=False)
-        infos.append(si)
+        infos.append(solve(raise_on_error=False))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms, calls = s.get_timing()
     s.set_timing(False)
     ok = all(si["status"] == 0 and si["omega"] <= 1e-8 for si in infos)
-    extra = {"delta_c": 1.0 / gamma} if dualreg else {}
-    if opts:
+    extra = {"delta_c": 1.0 / GAMMA} if dualreg else {}
+    if variant == ["dense4"]:
         extra = {"dense_rows": info["n_dense_rows"], "nnz_k": info["nnz_k"]}
     if inertia:
         extra = dict(w_diag_shift=-INERTIA_SHIFT, attempts_mean=float(np.mean(attempts)),
                      delta_w=[float(f"{d:.4g}") for d in deltas])
-    return dict(solves_per_s=steps / (t1 - t0), ms_per_solve=1e3 * (t1 - t0) / steps, gate_ok=ok, **extra,
-                omega_max=max(si["omega"] for si in infos), rho_max=max(si["rho"] for si in infos),
-                refine_steps=float(np.mean([si["refine_steps"] for si in infos])),
-                cg_iters=float(np.mean([si["cg_iters"] for si in infos])),
-                fallbacks=int(sum(si["fallback"] != 0 for si in infos)),
-                phase_ms=dict(zip(names, ms)), phase_calls=dict(zip(names, calls)),
-                phase_ms_warmup=dict(zip(names, wms)), phase_calls_warmup=dict(zip(names, wcalls)),
-                dominant_phase=names[dom] if dom is not None else max(names, key=lambda q: ms[names.index(q)]),
-                analysis=info)
+    res = dict(solves_per_s=steps / (t1 - t0), ms_per_solve=1e3 * (t1 - t0) / steps, gate_ok=ok, **extra,
+               omega_max=max(si["omega"] for si in infos), rho_max=max(si["rho"] for si in infos),
+               refine_steps=float(np.mean([si["refine_steps"] for si in infos])),
+               cg_iters=float(np.mean([si["cg_iters"] for si in infos])),
+               fallbacks=int(sum(si["fallback"] != 0 for si in infos)),
+               phase_ms=dict(zip(names, ms)), phase_calls=dict(zip(names, calls)),
+               phase_ms_warmup=dict(zip(names, wms)), phase_calls_warmup=dict(zip(names, wcalls)),
+               dominant_phase=names[dom] if dom is not None else max(names, key=lambda q: ms[names.index(q)]))
+    log(f"[{form}] n={p.n}: {res['solves_per_s']:.1f} solves/s, omega_max {res['omega_max']:.2e}, "
+        f"gate {'ok' if ok else 'FAILED'}")
+    return res, info
+
+
+def host_description():
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(cpu_model=model, nproc=avail, cpu_count=os.cpu_count())
 
 
 def cpu_baseline(p, sig, budget_s):
-    """The oracle (SuperLU factor + FP64 refinement, unassembled residual) on
-    the host cores, on as many of the same systems as fit in the budget."""
+    """The oracle (SuperLU factor + FP64 refinement to omega <= 1e-10,
+    unassembled residual) on one host core, on as many of the timed systems
+    as fit in the budget (at least one)."""
+    from threadpoolctl import threadpool_limits
     from oracle import sparse as osp
     P = osp.Problem(p)
-    t0 = time.perf_counter()
-    done = 0
-    worst = 0.0
-    while done < len(sig):
-        sx, ss = sig[done]
-        x, hist = osp.solve_lifted(P, sx, ss, p.b, tol=1e-10)
-        worst = max(worst, hist[-1])
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    done, worst = 0, 0.0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        while done < len(sig):
+            sx, ss = sig[done]
+            x, hist = osp.solve_lifted(P, sx, ss, p.b, tol=1e-10)
+            worst = max(worst, hist[-1])
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
     return dict(value=done / dt, unit="solves/s", cores=1, kind="oracle",
-                sample=f"{done} LiftedKKT FP64 systems of the same workload (SuperLU + FP64 refinement to "
-                       f"omega<=1e-10, single-threaded), worst omega {worst:.1e}")
+                sample=f"the first {done} of the timed LiftedKKT FP64 systems of the headline workload "
+                       f"(n={p.n}; SuperLU + FP64 refinement to omega<=1e-10, BLAS limited to one thread), "
+                       f"worst omega {worst:.1e}",
+                **host_description())
 
 
-def _line(a, metric_value, ms, config, extra, dtype="f64"):
-    line = {
-        "metric": "condensed-KKT solves/s at 1e-8 rel. residual: FP64 vs FP32+IR/batched/PCG",
-        "value": metric_value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
-        "data": "synthetic", "config": config,
-    }
-    line.update(extra)
-    print(json.dumps(line))
+def part_netflow80k(a, p, sig, torch, Solver, device_values):
+    """HyKKT FP64 on the headline systems."""
+    out = {}
+    res, _ = time_form("hykkt_fp64", p, sig, a.steps, a.warmup, torch, Solver, device_values)
+    out["hykkt_fp64"] = res
+    return out
 
 
-def run_sequence(a, torch, workloads, Solver, device_values):
-    """IPM-like 60-system sequence on the 80k-node network-flow problem:
-    every system is factorized and solved, FP64 versus FP32 + FP64 refinement."""
+def part_seq80k(a, p, torch, workloads, Solver, device_values):
+    """IPM-like sequence on the headline pattern: every system factorized and
+    solved in FP64, then with the FP32 factor + FP64 refinement; per system
+    wall time, the oracle's omega on the first, middle and last system."""
     from oracle import sparse as osp
-    N = a.nodes if a.nodes != 10_000 else 80_000
-    p = workloads.network_flow(N, seed=a.seed)
-    a.systems = a.systems or 60
-    seq = workloads.ipm_sigma_sequence(p, a.systems, seed=a.seed)
+    num = a.systems or 60
+    seq = workloads.ipm_sigma_sequence(p, num, seed=a.seed)
     w, g, h, _, _ = device_values(p, "cuda", "lifted")
     sx = [torch.as_tensor(x, device="cuda") for x, _ in seq]
     ss = [torch.as_tensor(y, device="cuda") for _, y in seq]
     b = torch.as_tensor(p.b, device="cuda")
+    P = osp.Problem(p)
     out = {}
     for prec in ("fp64", "fp32_ir"):
         s = Solver(p, "lifted", prec, tol=1e-10 if prec == "fp64" else 1e-8).bind("cuda")
         x = torch.empty_like(b)
-        s.factorize(w, g, h, sx[0], ss[0]); s.solve(b, x)
+        s.factorize(w, g, h, sx[0], ss[0]); s.solve(b, x, raise_on_error=False)
         torch.cuda.synchronize()
-        per, infos = [], []
-        for k in range(a.systems):
+        per, infos, spot = [], [], {}
+        for k in range(num):
             t0 = time.perf_counter()
             s.factorize(w, g, h, sx[k], ss[k])
             _, si = s.solve(b, x, raise_on_error=False)
             torch.cuda.synchronize()
             per.append(time.perf_counter() - t0)
             infos.append(si)
-            print(f"[{prec}] system {k}: {1e3 * per[-1]:.2f} ms, omega {si['omega']:.2e}, "
-                  f"fallback {si['fallback']}", file=sys.stderr, flush=True)
-            if k in (0, a.systems // 2, a.systems - 1):
-                P = osp.Problem(p)
-                si["oracle_omega"] = osp.omega_condensed(P.W, seq[k][0], P.J, seq[k][1], x.cpu().numpy(), p.b)
+            if k in (0, num // 2, num - 1):
+                spot[k] = float(osp.omega_condensed(P.W, seq[k][0], P.J, seq[k][1], x.cpu().numpy(), p.b))
         out[prec] = dict(solves_per_s=len(per) / sum(per), ms_per_solve=1e3 * float(np.mean(per)),
                          ms_per_system=[round(1e3 * t, 3) for t in per],
                          fallback=[si["fallback"] for si in infos],
                          refine_steps=[si["refine_steps"] for si in infos],
+                         pcg_iters=[si["pcg_iters"] for si in infos],
                          omega_max=max(si["omega"] for si in infos),
                          gate_ok=all(si["status"] == 0 and si["omega"] <= 1e-8 for si in infos),
-                         oracle_spot_omega=[si.get("oracle_omega") for si in infos if "oracle_omega" in si])
-    inf = Solver(p, "lifted").info()
-    _line(a, out["fp32_ir"]["solves_per_s"], out["fp32_ir"]["ms_per_solve"],
-          {"workload": f"network-flow NLP {N} nodes ({p.n} vars), {a.systems}-system IPM-like sigma sequence "
-                       "(1 -> 1e+-8), LiftedKKT", "n": p.n, "nnz_l": inf["nnz_l"], "levels": inf["n_levels"]},
-          {"forms": out}, dtype="f32+f64")
+                         oracle_spot_omega=spot)
+        log(f"[seq80k {prec}] {out[prec]['solves_per_s']:.1f} solves/s, gate {out[prec]['gate_ok']}")
+        del s
+    f64, f32 = out["fp64"]["ms_per_system"], out["fp32_ir"]["ms_per_system"]
+    wins = [k for k in range(num) if f32[k] < f64[k]]
+    out["fp32_ir_faster_on_systems"] = wins
+    out["workload"] = (f"network-flow NLP {HEADLINE_NODES} nodes (n={p.n}), {num}-system IPM-like sigma "
+                       "sequence (1 -> 1e+-8), LiftedKKT")
+    return out
 
 
-def run_batch(a, torch, workloads, Solver):
-    """512 independent network-flow instances of uneven size, analysed as one
-    block-diagonal system, autotuned, FP32 factor + FP64 refinement."""
+def part_batch512(a, torch, workloads, Solver):
+    """512 independent network-flow instances of uneven size analysed as one
+    block-diagonal system, autotuned; FP64 and FP32 + FP64 refinement."""
     probs = workloads.batch_network_flow(a.instances, seed=a.seed)
     rng = np.random.default_rng(a.seed + 5)
     cat = lambda xs: torch.as_tensor(np.concatenate(xs), device="cuda")
@@ -287,15 +324,22 @@ def run_batch(a, torch, workloads, Solver):
         sss = [workloads.log_uniform(rng, q.m) for q in probs]
         sig.append((cat(sxs), cat([x[:q.m_eq] for x, q in zip(sss, probs)] + [x[q.m_eq:] for x, q in zip(sss, probs)])))
     out = {}
-    for prec in ("fp32_ir", "fp64"):
+    blob = None
+    for prec in ("fp64", "fp32_ir"):
         t0 = time.perf_counter()
-        s = Solver(None, "lifted", prec, batch=probs, tol=1e-8 if prec == "fp32_ir" else 1e-10).bind("cuda")
-        t_an = time.perf_counter() - t0
-        print(f"[{prec}] batch analysed in {t_an:.2f} s", file=sys.stderr, flush=True)
+        tol = 1e-8 if prec == "fp32_ir" else 1e-10
+        if blob is None:
+            s = Solver(None, "lifted", prec, batch=probs, tol=tol)
+            blob = s.save_plan()
+            t_an = time.perf_counter() - t0
+        else:
+            s = Solver.from_plan(blob, precision=prec, tol=tol)  # same analysis, reloaded
+        s.bind("cuda")
+        log(f"[batch {prec}] analysed in {t_an:.2f} s")
         chosen, best = s.autotune(w, g, h, sig[0][0], sig[0][1])
         x = torch.empty_like(b)
         for k in range(a.warmup):
-            s.factorize(w, g, h, *sig[k]); s.solve(b, x)
+            s.factorize(w, g, h, *sig[k]); s.solve(b, x, raise_on_error=False)
         torch.cuda.synchronize()
         infos = []
         t0 = time.perf_counter()
@@ -310,21 +354,20 @@ def run_batch(a, torch, workloads, Solver):
                          gate_ok=all(si["status"] == 0 and si["omega"] <= 1e-8 for si in infos),
                          omega_max=max(si["omega"] for si in infos),
                          fallbacks=int(sum(si["fallback"] != 0 for si in infos)))
-    inf = s.info()
-    _line(a, out["fp32_ir"]["solves_per_s"], out["fp32_ir"]["ms_per_batch"],
-          {"workload": f"{a.instances} network-flow instances, nodes uniform in [500, 2000], LiftedKKT, one "
-                       "block-diagonal analysis, graph-captured level launches, autotuned launch shapes",
-           "n_total": inf["n"], "levels": inf["n_levels"]}, {"forms": out}, dtype="f32+f64")
+        log(f"[batch {prec}] {out[prec]['solves_per_s']:.0f} solves/s, gate {out[prec]['gate_ok']}")
+        del s
+    out["workload"] = (f"{a.instances} network-flow instances, nodes uniform in [500, 2000], LiftedKKT, one "
+                       "block-diagonal analysis, graph-captured level launches, autotuned launch shapes")
+    return out
 
 
-def run_pde_learned(a, torch, workloads, Solver, device_values):
+def part_pde48(a, torch, workloads, Solver, device_values):
     """PDE-constrained problem, IPM-like sequence: FP64 refactorization of
-    every system versus PCG around a stale FP32 factor, with and without the
-    learned diagonal (trained on systems 0..19 with the stale factor of
-    system 10, then used around the factor of system 19, refreshed on
+    every system versus PCG around a stale factor, with D = I and with the
+    learned preconditioner (trained on systems 0..19 with the stale factor
+    of system 10, then used around the factor of system 19, refreshed on
     fallback)."""
-    from oracle import mlp as om
-    from oracle import sparse as osp
+    from paper_2405_14236_amd.solver import init_mlp_params
     p = workloads.pde_control(a.side, seed=a.seed)
     num = a.systems or 80
     seq = workloads.ipm_sigma_sequence(p, num, seed=a.seed)
@@ -334,7 +377,6 @@ def run_pde_learned(a, torch, workloads, Solver, device_values):
     T = lambda v: torch.as_tensor(v, device="cuda")
     sx = [T(x) for x, _ in seq]; ss = [T(y) for _, y in seq]
     out = {}
-    # baseline: FP64 factorization of every system
     s64 = Solver(p, "lifted", "fp64").bind("cuda")
     x = torch.empty_like(rhs[0])
     s64.factorize(w, g, h, sx[0], ss[0]); s64.solve(rhs[0], x); torch.cuda.synchronize()
@@ -345,16 +387,13 @@ def run_pde_learned(a, torch, workloads, Solver, device_values):
         _, si = s64.solve(rhs[k], x)
         if k < 20:
             targets.append(x.clone())
-        if k % 10 == 0:
-            torch.cuda.synchronize()
-            print(f"[fp64 refactor] system {k}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     out["fp64_refactor"] = dict(solves_per_s=num / (time.perf_counter() - t0))
+    log(f"[pde{a.side} fp64 refactor] {out['fp64_refactor']['solves_per_s']:.2f} solves/s")
     del s64
-    # training (systems 0..19 generated by the solver above, stale factor of system 10)
     s = Solver(p, "lifted", "fp32_ir", learned=1).bind("cuda")
     s.factorize(w, g, h, sx[10], ss[10])
-    prm = torch.as_tensor(om.init_params(a.seed).astype(np.float32), device="cuda")
+    prm = init_mlp_params(a.seed, device="cuda")
     m = torch.zeros_like(prm); v = torch.zeros_like(prm)
     t0 = time.perf_counter()
     step, losses = 0, []
@@ -364,7 +403,6 @@ def run_pde_learned(a, torch, workloads, Solver, device_values):
                 continue
             step += 1
             losses.append(s.mlp_train_step((w, g, h, sx[k], ss[k]), 0.0, rhs[k], targets[k], prm, m, v, step, 3e-3))
-        print(f"[train] epoch {epoch}: mean loss {np.mean(losses[-19:]):.4f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     for name, params in (("pcg_learned", prm), ("pcg_identity", None)):
@@ -376,73 +414,72 @@ def run_pde_learned(a, torch, workloads, Solver, device_values):
             _, si = s.pcg_solve((w, g, h, sx[k], ss[k]), 0.0, params, rhs[k], maxit=50, tol=1e-8,
                                 allow_refactor=True, raise_on_error=False)
             iters.append(si["pcg_iters"]); fb += si["fallback"] != 0; oms.append(si["omega"])
-            print(f"[{name}] system {k}: {si['pcg_iters']} PCG iterations, fallback {si['fallback']}",
-                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[name] = dict(solves_per_s=(num - 20) / dt, pcg_iters=iters, refactorizations=fb,
                          omega_max=max(oms), gate_ok=max(oms) <= 1e-8)
+        log(f"[pde{a.side} {name}] {out[name]['solves_per_s']:.2f} solves/s, {np.mean(iters):.1f} PCG iterations")
     out["training"] = dict(seconds=train_s, steps=step, loss_first=losses[0], loss_last=losses[-1])
     inf = s.info()
-    _line(a, out["pcg_learned"]["solves_per_s"], 1e3 / out["pcg_learned"]["solves_per_s"],
-          {"workload": f"3-D Poisson control {a.side}^3 states + stride-2 controls (n={p.n}), {num}-system "
-                       "IPM-like sigma sequence, LiftedKKT, PCG around a stale FP32 factor",
-           "n": p.n, "nnz_l": inf["nnz_l"], "factor_flops": inf["factor_flops"], "max_front": inf["max_front"]},
-          {"forms": out}, dtype="f32+f64")
+    out["workload"] = (f"3-D Poisson control {a.side}^3 states + stride-2 controls (n={p.n}, nnz(L)={inf['nnz_l']}, "
+                       f"{inf['factor_flops']:.3g} flops per factor), {num}-system IPM-like sigma sequence, "
+                       "LiftedKKT; PCG around a stale FP32 factor")
+    return out
+
+
+def part_netflow10k(a, torch, workloads, Solver, device_values):
+    p = workloads.network_flow(10_000, seed=a.seed)
+    rng = np.random.default_rng(a.seed + 1)
+    nsys = a.steps + a.warmup
+    sig = [(workloads.log_uniform(rng, p.n), workloads.log_uniform(rng, p.m)) for _ in range(nsys)]
+    out = {}
+    for f in a.forms10k.split(","):
+        out[f], _ = time_form(f, p, sig, a.steps, a.warmup, torch, Solver, device_values)
+    out["workload"] = (f"network-flow NLP 10000 nodes ({p.n} vars, {p.m_eq} eq, {p.m_ineq} ineq), new "
+                       "log-uniform sigma in [1e-8,1e8] per solve")
+    return out
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
-                          "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (one process, one device); "
+                                   "--gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
-    if a.workload != "netflow":
-        from paper_2405_14236_amd import workloads
-        from paper_2405_14236_amd.solver import Solver, device_values
-        if a.workload == "netflow_seq":
-            return run_sequence(a, torch, workloads, Solver, device_values)
-        if a.workload == "batch":
-            return run_batch(a, torch, workloads, Solver)
-        return run_pde_learned(a, torch, workloads, Solver, device_values)
     from paper_2405_14236_amd import workloads
     from paper_2405_14236_amd.solver import Solver, device_values
+    parts = [] if a.parts == "none" else [q for q in a.parts.split(",") if q]
+    for q in parts:
+        if q not in PARTS:
+            raise SystemExit(f"unknown part {q}")
 
     if a.pmc_calibration:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"pmc calibration: one device copy of {src.numel() * 8} bytes read and written", file=sys.stderr)
+        log(f"pmc calibration: one device copy of {src.numel() * 8} bytes read and written")
         del src, dst
-    p = workloads.network_flow(a.nodes, seed=a.seed)
+
+    p = workloads.network_flow(HEADLINE_NODES, seed=a.seed)
     rng = np.random.default_rng(a.seed + 1)
     nsys = a.steps + a.warmup
-    sig = [(workloads.log_uniform(rng, p.n), workloads.log_uniform(rng, p.m_eq + p.m_ineq)) for _ in range(nsys)]
+    sig = [(workloads.log_uniform(rng, p.n), workloads.log_uniform(rng, p.m)) for _ in range(nsys)]
+    head, info = time_form("lifted_fp64", p, sig, a.steps, a.warmup, torch, Solver, device_values)
+    cnt = algorithmic_counts(p, info)
 
-    forms = {}
-    for f in a.forms.split(","):
-        forms[f] = time_form(f, p, sig, a.steps, a.warmup, torch, Solver, device_values)
-    main_form = forms["lifted_fp64"]
-    info = main_form["analysis"]
-    cnt = algorithmic_counts(p, info, "lifted")
-
-    # roofline of the dominant phase of the main form (HIP events on the
-    # library's stream over the timed region)
-    ph_ms, ph_calls = main_form["phase_ms"], main_form["phase_calls"]
+    # roofline of the dominant phase of the headline (HIP events recorded by
+    # the library on its stream over the timed region)
+    ph_ms, ph_calls = head["phase_ms"], head["phase_calls"]
     per_call = {k: ph_ms[k] / max(ph_calls[k], 1) for k in ph_ms}
-    dom = main_form["dominant_phase"]
-    if dom == "factor":
-        bound, unit_bytes, flops = "hbm", cnt["factor_bytes"], cnt["factor_flops"]
-    elif dom == "sweeps":
-        bound, unit_bytes, flops = "hbm", cnt["sweep_bytes"], cnt["sweep_flops"]
-    elif dom == "assemble":
-        bound, unit_bytes, flops = "hbm", cnt["assemble_bytes"], None
-    else:
-        bound, unit_bytes, flops = "hbm", cnt["resid_bytes"], None
+    dom = head["dominant_phase"]
+    unit_bytes, flops = {"factor": (cnt["factor_bytes"], cnt["factor_flops"]),
+                         "sweeps": (cnt["sweep_bytes"], cnt["sweep_flops"]),
+                         "assemble": (cnt["assemble_bytes"], None),
+                         "vector": (cnt["resid_bytes"], None)}[dom]
     achieved = unit_bytes / (per_call[dom] * 1e-3) / 1e9
-    roofline = {"bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic() if dom == "factor" else None,
                 "kernel": dom, "unit_bytes": unit_bytes, "avg_ms": per_call[dom]}
@@ -450,31 +487,38 @@ def main():
         roofline["fp64_tflops"] = flops / (per_call[dom] * 1e-3) / 1e12
         roofline["fp64_frac"] = roofline["fp64_tflops"] / FP64_PEAK_TFLOPS
 
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(p, sig[a.warmup:], a.cpu_seconds)
+    forms = {"netflow80k": {"lifted_fp64": head}}
+    if "netflow80k" in parts:
+        forms["netflow80k"].update(part_netflow80k(a, p, sig, torch, Solver, device_values))
+    if "seq80k" in parts:
+        forms["seq80k"] = part_seq80k(a, p, torch, workloads, Solver, device_values)
+    if "batch512" in parts:
+        forms["batch512"] = part_batch512(a, torch, workloads, Solver)
+    if "pde48" in parts:
+        forms["pde48"] = part_pde48(a, torch, workloads, Solver, device_values)
+    if "netflow10k" in parts:
+        forms["netflow10k"] = part_netflow10k(a, torch, workloads, Solver, device_values)
 
-    for f in forms.values():
-        f.pop("analysis", None)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(p, sig[a.warmup:], a.cpu_seconds)
     line = {
-        "metric": "condensed-KKT solves/s at 1e-8 rel. residual: FP64 vs FP32+IR/batched/PCG",
-        "value": main_form["solves_per_s"],
+        "metric": METRIC,
+        "value": head["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": main_form["ms_per_solve"],
+        "ms_per_step": head["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"network-flow NLP, {a.nodes} nodes / {p.n} vars / {p.m_eq} eq / {p.m_ineq} ineq, "
-                               "LiftedKKT FP64, new log-uniform sigma in [1e-8,1e8] per solve",
+        "config": {"workload": f"network-flow NLP, {HEADLINE_NODES} nodes / {p.n} vars / {p.m_eq} eq / "
+                               f"{p.m_ineq} ineq, LiftedKKT FP64, new log-uniform sigma in [1e-8,1e8] per solve",
                    "n": p.n, "nnz_k": info["nnz_k"], "nnz_l": info["nnz_l"], "supernodes": info["n_supernodes"],
                    "levels": info["n_levels"], "max_front": info["max_front"],
                    "analyze_s": info["analyze_seconds"], "gate_omega": 1e-10},
-        "gate_ok": main_form["gate_ok"],
+        "gate_ok": head["gate_ok"],
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,

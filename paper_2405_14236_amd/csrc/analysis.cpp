@@ -113,16 +113,7 @@ std::vector<uint64_t> block_pattern_keys(const PatternIn& p, const std::vector<c
         for (int i; (i = next.fetch_add(1)) < nb;)
             part[i] = pattern_keys_range(p, dense, bn[i], bn[i + 1], bg[i], bg[i + 1], bh[i], bh[i + 1]);
     };
-    std::vector<std::thread> pool;
-    for (int t = 1; t < std::min(o.threads, nb); ++t) {
-        try {
-            pool.emplace_back(work);
-        } catch (...) {
-            break;  // no thread: the others take its blocks
-        }
-    }
-    work();
-    for (auto& th : pool) th.join();
+    run_threads(std::max(1, std::min(o.threads, nb)), [&](int) { work(); });
     size_t total = 0;
     for (auto& v : part) total += v.size();
     std::vector<uint64_t> keys;
@@ -623,17 +614,9 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
             }
         };
         const int nth = std::max(1, std::min(o.threads, m / 65536 + 1));
-        std::vector<std::thread> pool;
-        for (int t = 1; t < nth; ++t) {
-            const int32_t lo = (int32_t)((int64_t)m * t / nth), hi = (int32_t)((int64_t)m * (t + 1) / nth);
-            try {
-                pool.emplace_back(lookup, lo, hi);
-            } catch (...) {
-                lookup(lo, hi);  // no thread: this chunk here
-            }
-        }
-        lookup(0, (int32_t)((int64_t)m / nth));
-        for (auto& th : pool) th.join();
+        run_threads(nth, [&](int t) {
+            lookup((int32_t)((int64_t)m * t / nth), (int32_t)((int64_t)m * (t + 1) / nth));
+        });
         if (missing) return "internal: J product missing from K";
         P.prod_ptr.assign(nnzk + 1, 0);
         for (int32_t sl : pslot) P.prod_ptr[sl + 1]++;

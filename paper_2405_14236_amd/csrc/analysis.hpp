@@ -8,7 +8,10 @@
 // symbolic factorization (Sec. 6.1, analysis column of tab:linsol:time).
 #pragma once
 #include <cstdint>
+#include <exception>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace ckkt {
@@ -118,6 +121,45 @@ struct AnalyzeOptions {
 // AMD ordering of one pattern's K = W + J^T J graph (rows of J with at least
 // dense_row_min entries left out when dense_row_min > 0); identity for n <= 1.
 std::vector<int32_t> order_pattern(const PatternIn& p, int dense_row_min);
+
+// Runs share(t) for t = 0 .. nthreads-1: share 0 on the calling thread, the
+// others on host threads.  A share whose thread cannot be started runs on
+// the calling thread after share 0.  Every started thread is joined before
+// this returns (also when a share throws), and the first exception thrown
+// by any share is rethrown here, on the calling thread, so that nothing
+// escapes a worker (which would terminate the process).
+template <class F>
+void run_threads(int nthreads, F&& share) {
+    std::exception_ptr first;
+    std::mutex mu;
+    auto guarded = [&](int t) {
+        try {
+            share(t);
+        } catch (...) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (!first) first = std::current_exception();
+        }
+    };
+    struct Joiner {
+        std::vector<std::thread> pool;
+        ~Joiner() {
+            for (auto& th : pool)
+                if (th.joinable()) th.join();
+        }
+    } j;
+    std::vector<int> not_started;
+    for (int t = 1; t < nthreads; ++t) {
+        try {
+            j.pool.emplace_back(guarded, t);
+        } catch (...) {
+            not_started.push_back(t);
+        }
+    }
+    guarded(0);
+    for (int t : not_started) guarded(t);
+    for (auto& th : j.pool) th.join();
+    if (first) std::rethrow_exception(first);
+}
 
 // Returns an empty string on success, else a description of the pattern error.
 std::string validate(const PatternIn& p);

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <thread>
@@ -61,7 +62,6 @@ struct Tune {
     int sweep_cutoff = 64;            // sweeps use 256 threads when a level's largest front exceeds this
     int tiled_front = kSweepTiledFront;  // fronts with at least this many rows use the tiled sweeps
     int wide_front = kWideFront;         // FP64 levels with fronts this large use wide panels
-    int lookahead = 0;                   // overlap wide trailing updates with the next panel (opt-in)
 };
 
 struct ckkt_handle {
@@ -199,8 +199,7 @@ struct PhaseTimer {
 
 void destroy_side(SideStream& sd) {
     if (sd.stream) (void)hipStreamDestroy(sd.stream);
-    if (sd.ahead) (void)hipStreamDestroy(sd.ahead);
-    for (hipEvent_t e : {sd.fork, sd.join, sd.panel_done, sd.rest_done[0], sd.rest_done[1]})
+    for (hipEvent_t e : {sd.fork, sd.join})
         if (e) (void)hipEventDestroy(e);
     sd = SideStream{};
 }
@@ -248,7 +247,6 @@ void build_levels(ckkt_handle* h) {
         L.sweep_threads = L.all_maxf > T.sweep_cutoff ? 256 : 64;
         L.sweep_tiled_f = T.tiled_front;
         L.wide_front = T.wide_front;
-        L.lookahead = T.lookahead;
         L.tflag_off = h->n_tflags;
         if (L.big_count > 0 && L.big_maxf >= L.sweep_tiled_f)
             h->n_tflags += L.big_count * ((L.big_maxw + 63) / 64);
@@ -460,24 +458,21 @@ void fill_devplan(ckkt_handle* h) {
 
 // Everything after the symbolic analysis: launch geometry and workspace
 // layout (also the path of a plan loaded by ckkt_plan_load).
-ckkt_status finish_plan(ckkt_handle* h, const AnalyzeOptions& ao, ckkt_handle** out, size_t* workspace_bytes);
+// The handle is owned by the unique_ptr until it is handed to the caller
+// (*out), so every error return and every exception frees it.
+using HandlePtr = std::unique_ptr<ckkt_handle>;
 
-ckkt_status finish_analyze(ckkt_handle* h, const AnalyzeOptions& ao, const PatternIn& pin, ckkt_handle** out,
+ckkt_status finish_plan(HandlePtr h, const AnalyzeOptions& ao, ckkt_handle** out, size_t* workspace_bytes);
+
+ckkt_status finish_analyze(HandlePtr h, const AnalyzeOptions& ao, const PatternIn& pin, ckkt_handle** out,
                            size_t* workspace_bytes) {
     std::string err = analyze(pin, ao, h->plan);
-    if (!err.empty()) {
-        bool internal = err.rfind("internal", 0) == 0;
-        delete h;
-        return internal ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
-    }
-    return finish_plan(h, ao, out, workspace_bytes);
+    if (!err.empty()) return err.rfind("internal", 0) == 0 ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
+    return finish_plan(std::move(h), ao, out, workspace_bytes);
 }
 
-ckkt_status finish_plan(ckkt_handle* h, const AnalyzeOptions& ao, ckkt_handle** out, size_t* workspace_bytes) {
-    if ((int)h->plan.dense_rows.size() > kMaxDenseRows) {
-        delete h;
-        return CKKT_ERR_ARG;
-    }
+ckkt_status finish_plan(HandlePtr h, const AnalyzeOptions& ao, ckkt_handle** out, size_t* workspace_bytes) {
+    if ((int)h->plan.dense_rows.size() > kMaxDenseRows) return CKKT_ERR_ARG;
     // CKKT_TILED_SWEEP_FRONT moves the size from which fronts are swept by
     // the tiled kernels; it stays above the LDS front limit (so that every
     // such front is in its level's big list) and at most the largest front
@@ -492,20 +487,26 @@ ckkt_status finish_plan(ckkt_handle* h, const AnalyzeOptions& ao, ckkt_handle** 
         const int v = std::atoi(wf);
         if (v > 0) h->tune.wide_front = std::max(v, ao.big_front + 1);
     }
-    // CKKT_LOOKAHEAD=1 runs the trailing update of a wide panel beyond the
-    // next wide panel on a second stream (off by default: its first run in a
-    // captured graph ended the process with a host segmentation fault whose
-    // cause is not established)
-    if (const char* la = std::getenv("CKKT_LOOKAHEAD")) h->tune.lookahead = la[0] == '1';
-    build_levels(h);
-    if (!plan_fits_lds(h)) {
-        delete h;
-        return CKKT_ERR_ARG;  // a small front beyond the LDS of one workgroup
-    }
-    build_layout(h);
-    *out = h;
+    build_levels(h.get());
+    if (!plan_fits_lds(h.get())) return CKKT_ERR_ARG;  // a small front beyond the LDS of one workgroup
+    build_layout(h.get());
     if (workspace_bytes) *workspace_bytes = h->lay.total;
+    *out = h.release();
     return CKKT_OK;
+}
+
+// The row pointer arrays start at 0 and never decrease, so copy_pattern
+// reads index arrays of known, non-negative length (checked before any
+// index array is touched; validate() checks the indices of the copy).
+bool pattern_ptrs_ok(const ckkt_pattern* p) {
+    auto ok = [](const int32_t* ptr, int64_t rows) {
+        if (rows == 0 && !ptr) return true;
+        if (!ptr || ptr[0] != 0) return false;
+        for (int64_t r = 0; r < rows; ++r)
+            if (ptr[r + 1] < ptr[r]) return false;
+        return true;
+    };
+    return ok(p->w_ptr, p->n) && ok(p->g_ptr, p->m_eq) && ok(p->h_ptr, p->m_ineq);
 }
 
 PatternIn copy_pattern(const ckkt_pattern* p) {
@@ -1092,9 +1093,19 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
     }
     bool use64 = h->precision == CKKT_FP64 || h->fp64_factored;
     ResidualOut r;
-    int steps = 0, stall = 0;
+    // steps: outer steps taken (all factors); base: steps taken before the
+    // current factor, so that the FP64 refactorization of the fallback gets
+    // the full ir_maxit budget of its own, as in solve_lifted
+    int steps = 0, base = 0, stall = 0;
     double prev = INFINITY;
-    bool last_cg_ok = true;
+    auto fall_back = [&]() {
+        refactor_fp64(h, st);
+        use64 = true;
+        info->fallback = 2;
+        stall = 0;
+        prev = INFINITY;
+        base = steps;
+    };
     for (;;) {
         rc = residual_sync(h, x, y, r1, r2, res1, res2, r, st);
         if (rc) return rc;
@@ -1103,18 +1114,12 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
         info->omega = r.omega;
         info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
         if (r.omega <= h->opt.tol && steps > 0) break;
-        if (steps > 0 && !use64) {
+        if (steps > base && !use64) {
             if (!(r.omega < 0.5 * prev)) stall++;
-            if (stall >= 2 || steps > h->opt.ir_maxit) {
-                refactor_fp64(h, st);
-                use64 = true;
-                info->fallback = 2;
-                stall = 0;
-                prev = INFINITY;
-            }
-        } else if (steps > h->opt.ir_maxit) {
+            if (stall >= 2 || steps - base > h->opt.ir_maxit) fall_back();
+        } else if (steps - base > h->opt.ir_maxit) {
             info->refine_steps = steps - 1;
-            return last_cg_ok ? CKKT_ERR_NO_CONVERGENCE : CKKT_ERR_NO_CONVERGENCE;
+            return CKKT_ERR_NO_CONVERGENCE;
         }
         prev = r.omega;
         int it = 0;
@@ -1124,15 +1129,10 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
         else
             rc = hykkt_inner(h, res1, res2, ddx, ddy, use64, it, ok, st);
         info->cg_iters += it;
-        last_cg_ok = ok;
         if (rc == CKKT_ERR_BREAKDOWN && !use64) {
             // the FP32 factor of K_gamma is too inexact for CG on S_gamma:
             // refactorize in FP64 and redo this outer step
-            refactor_fp64(h, st);
-            use64 = true;
-            info->fallback = 2;
-            stall = 0;
-            prev = INFINITY;
+            fall_back();
             continue;
         }
         if (rc) return rc;
@@ -1180,8 +1180,18 @@ ckkt_status solve_augmented(ckkt_handle* h, const double* r1, const double* r2, 
         launch_maxabs(ms, r4, slot, st);
     }
     bool use64 = h->precision == CKKT_FP64 || h->fp64_factored;
-    int steps = 0, stall = 0;
+    // base: steps taken before the current factor (the FP64 refactorization
+    // of the fallback gets the full ir_maxit budget of its own)
+    int steps = 0, base = 0, stall = 0;
     double prev = INFINITY;
+    auto fall_back = [&]() {
+        refactor_fp64(h, st);
+        use64 = true;
+        info->fallback = 2;
+        stall = 0;
+        prev = INFINITY;
+        base = steps;
+    };
     char* host = static_cast<char*>(h->host);
     for (;;) {
         {
@@ -1206,16 +1216,10 @@ ckkt_status solve_augmented(ckkt_handle* h, const double* r1, const double* r2, 
         info->omega = omega;
         info->rho = rmax > 0 ? resmax / rmax : resmax;
         if (omega <= h->opt.tol && steps > 0) break;
-        if (steps > 0 && !use64) {
+        if (steps > base && !use64) {
             if (!(omega < 0.5 * prev)) stall++;
-            if (stall >= 2 || steps > h->opt.ir_maxit) {
-                refactor_fp64(h, st);
-                use64 = true;
-                info->fallback = 2;
-                stall = 0;
-                prev = INFINITY;
-            }
-        } else if (steps > h->opt.ir_maxit) {
+            if (stall >= 2 || steps - base > h->opt.ir_maxit) fall_back();
+        } else if (steps - base > h->opt.ir_maxit) {
             info->refine_steps = steps - 1;
             return CKKT_ERR_NO_CONVERGENCE;
         }
@@ -1230,11 +1234,7 @@ ckkt_status solve_augmented(ckkt_handle* h, const double* r1, const double* r2, 
             ckkt_status rc = hykkt_inner(h, rb1, R3, ddx, ddy, use64, it, ok, st);
             info->cg_iters += it;
             if (rc == CKKT_ERR_BREAKDOWN && !use64) {
-                refactor_fp64(h, st);
-                use64 = true;
-                info->fallback = 2;
-                stall = 0;
-                prev = INFINITY;
+                fall_back();
                 continue;
             }
             if (rc) return rc;
@@ -1432,20 +1432,19 @@ static ckkt_status ckkt_analyze_impl(const ckkt_pattern* pat, const ckkt_options
 
     if (!out || !pattern_args_ok(pat)) return CKKT_ERR_ARG;
     *out = nullptr;
-    ckkt_handle* h = new (std::nothrow) ckkt_handle();
-    if (!h) return CKKT_ERR_ARG;
+    HandlePtr h(new ckkt_handle());
     if (opt) h->opt = *opt;
     else ckkt_default_options(&h->opt);
-    if (h->opt.precision != CKKT_FP64 && h->opt.precision != CKKT_FP32_IR) { delete h; return CKKT_ERR_ARG; }
-    if (h->opt.ordering != CKKT_ORDER_AMD && h->opt.ordering != CKKT_ORDER_NATURAL) { delete h; return CKKT_ERR_ARG; }
-    if (h->opt.dense_row_min < 0 || (h->opt.dense_row_min > 0 && h->opt.precision != CKKT_FP64)) {
-        delete h;
+    if (h->opt.precision != CKKT_FP64 && h->opt.precision != CKKT_FP32_IR) return CKKT_ERR_ARG;
+    if (h->opt.ordering != CKKT_ORDER_AMD && h->opt.ordering != CKKT_ORDER_NATURAL) return CKKT_ERR_ARG;
+    if (h->opt.dense_row_min < 0 || (h->opt.dense_row_min > 0 && h->opt.precision != CKKT_FP64))
         return CKKT_ERR_ARG;
-    }
     h->formulation = pat->formulation;
     h->precision = h->opt.precision;
+    if (!pattern_ptrs_ok(pat)) return CKKT_ERR_PATTERN;
     PatternIn pin = copy_pattern(pat);
-    return finish_analyze(h, analyze_options(h->opt), pin, out, workspace_bytes);
+    const AnalyzeOptions ao = analyze_options(h->opt);
+    return finish_analyze(std::move(h), ao, pin, out, workspace_bytes);
 }
 
 ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
@@ -1504,8 +1503,7 @@ static ckkt_status ckkt_plan_load_impl(const void* buf, size_t bytes, const ckkt
     std::memcpy(&sum, base + sizeof hd + hd.payload, sizeof sum);
     if (sum != fnv1a(base + sizeof hd, (size_t)hd.payload)) return CKKT_ERR_ARG;
     if (hd.formulation != CKKT_LIFTED && hd.formulation != CKKT_HYKKT) return CKKT_ERR_ARG;
-    ckkt_handle* h = new (std::nothrow) ckkt_handle();
-    if (!h) return CKKT_ERR_ARG;
+    HandlePtr h(new ckkt_handle());
     if (opt) h->opt = *opt;
     else ckkt_default_options(&h->opt);
     // the options that shaped the plan are the plan's
@@ -1514,24 +1512,16 @@ static ckkt_status ckkt_plan_load_impl(const void* buf, size_t bytes, const ckkt
     h->opt.lds_front_max = hd.big_front;
     h->opt.dense_row_min = hd.dense_row_min;
     if ((h->opt.precision != CKKT_FP64 && h->opt.precision != CKKT_FP32_IR) ||
-        (h->opt.dense_row_min > 0 && h->opt.precision != CKKT_FP64)) {
-        delete h;
+        (h->opt.dense_row_min > 0 && h->opt.precision != CKKT_FP64))
         return CKKT_ERR_ARG;
-    }
     h->formulation = hd.formulation;
     h->precision = h->opt.precision;
     PlanReader r{base + sizeof hd, base + sizeof hd + hd.payload};
     plan_fields(h->plan, r);
-    if (!r.ok || r.p != r.e) {
-        delete h;
-        return CKKT_ERR_ARG;
-    }
-    if (h->plan.ninst > 1 && h->opt.dense_row_min != 0) {
-        delete h;
-        return CKKT_ERR_ARG;
-    }
-    AnalyzeOptions ao = analyze_options(h->opt);
-    return finish_plan(h, ao, out, workspace_bytes);
+    if (!r.ok || r.p != r.e) return CKKT_ERR_ARG;
+    if (h->plan.ninst > 1 && h->opt.dense_row_min != 0) return CKKT_ERR_ARG;
+    const AnalyzeOptions ao = analyze_options(h->opt);
+    return finish_plan(std::move(h), ao, out, workspace_bytes);
 }
 
 ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* opt, ckkt_handle** out,
@@ -1551,11 +1541,19 @@ static ckkt_status ckkt_batch_analyze_impl(int32_t count, const ckkt_pattern* pa
     for (int i = 0; i < count; ++i) {
         if (!pattern_args_ok(&pats[i]) || pats[i].formulation != pats[0].formulation) return CKKT_ERR_ARG;
     }
-    ckkt_handle* h = new (std::nothrow) ckkt_handle();
-    if (!h) return CKKT_ERR_ARG;
+    HandlePtr h(new ckkt_handle());
     if (opt) h->opt = *opt;
     else ckkt_default_options(&h->opt);
-    if (h->opt.dense_row_min != 0) { delete h; return CKKT_ERR_ARG; }  // no dense-row split in a batch
+    if (h->opt.precision != CKKT_FP64 && h->opt.precision != CKKT_FP32_IR) return CKKT_ERR_ARG;
+    if (h->opt.ordering != CKKT_ORDER_AMD && h->opt.ordering != CKKT_ORDER_NATURAL) return CKKT_ERR_ARG;
+    if (h->opt.dense_row_min != 0) return CKKT_ERR_ARG;  // no dense-row split in a batch
+    // every instance is a valid pattern on its own (indices below its own n)
+    // before anything is built from it: the per-instance orderings and the
+    // block-wise pair keys rely on that
+    for (int i = 0; i < count; ++i) {
+        if (!pattern_ptrs_ok(&pats[i])) return CKKT_ERR_PATTERN;
+        if (!validate(copy_pattern(&pats[i])).empty()) return CKKT_ERR_PATTERN;
+    }
     h->formulation = pats[0].formulation;
     h->precision = h->opt.precision;
     // block-diagonal union: variables and W blocks in instance order, then
@@ -1563,7 +1561,7 @@ static ckkt_status ckkt_batch_analyze_impl(int32_t count, const ckkt_pattern* pa
     PatternIn u;
     int64_t n = 0, me = 0, mi = 0;
     for (int i = 0; i < count; ++i) { n += pats[i].n; me += pats[i].m_eq; mi += pats[i].m_ineq; }
-    if (n > (int64_t)1 << 30) { delete h; return CKKT_ERR_ARG; }
+    if (n > (int64_t)1 << 30) return CKKT_ERR_ARG;
     u.n = n; u.m_eq = me; u.m_ineq = mi;
     u.w_ptr.push_back(0); u.g_ptr.push_back(0); u.h_ptr.push_back(0);
     Plan& P = h->plan;
@@ -1607,27 +1605,17 @@ static ckkt_status ckkt_batch_analyze_impl(int32_t count, const ckkt_pattern* pa
     if (h->opt.ordering == CKKT_ORDER_AMD) {
         std::vector<std::vector<int32_t>> orders(count);
         std::atomic<int> next{0};
-        auto work = [&]() {
-            for (int i; (i = next.fetch_add(1)) < count;) orders[i] = order_pattern(copy_pattern(&pats[i]), 0);
-        };
         const int nthreads = std::max(1, std::min<int>({count, kAnalyzeThreads,
                                                         (int)std::max(1u, std::thread::hardware_concurrency())}));
-        std::vector<std::thread> pool;
-        for (int t = 1; t < nthreads; ++t) {
-            try {
-                pool.emplace_back(work);
-            } catch (...) {
-                break;  // no thread: the ones running (and this one) take all instances
-            }
-        }
-        work();
-        for (auto& t : pool) t.join();
+        run_threads(nthreads, [&](int) {
+            for (int i; (i = next.fetch_add(1)) < count;) orders[i] = order_pattern(copy_pattern(&pats[i]), 0);
+        });
         perm.reserve(n);
         for (int i = 0; i < count; ++i)
             for (int32_t v : orders[i]) perm.push_back(v + P.inst_n[i]);
         ao.perm = &perm;
     }
-    return finish_analyze(h, ao, u, out, workspace_bytes);
+    return finish_analyze(std::move(h), ao, u, out, workspace_bytes);
 }
 
 ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt,
@@ -1660,11 +1648,7 @@ ckkt_status ckkt_bind_workspace(ckkt_handle* h, void* dev_ptr, size_t bytes, voi
         SideStream& sd = h->side;
         if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess ||
-            hipStreamCreateWithFlags(&sd.ahead, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sd.panel_done, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&sd.rest_done[0], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&sd.rest_done[1], hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess) {
             destroy_side(sd);
             (void)hipGetLastError();
         }

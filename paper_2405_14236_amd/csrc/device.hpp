@@ -49,7 +49,6 @@ struct LevelInfo {
     int32_t sweep_threads;     // workgroup size of the sweep kernels on this level
     int32_t tile_begin, tile_count;
     int32_t wide_front;         // FP64 levels whose largest big front reaches this use wide panels
-    int32_t lookahead;          // wide panels overlap the trailing update with the next panel
     int32_t sweep_tiled_f;      // fronts with f >= this are swept by the tiled kernels
     int32_t sweep_small_count;  // fronts of the level swept one workgroup each (f < sweep_tiled_f)
     int32_t tflag_off;          // first block flag of the level's tiled fronts
@@ -93,10 +92,6 @@ void launch_init_status(int32_t* status, bool keep_inputs, hipStream_t st);
 struct SideStream {
     hipStream_t stream = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    // look-ahead of the wide panels: the trailing update beyond the next
-    // wide panel runs on `ahead` while the next panel is factored
-    hipStream_t ahead = nullptr;
-    hipEvent_t panel_done = nullptr, rest_done[2] = {nullptr, nullptr};
 };
 constexpr int kMergeCompactFronts = 512;  // one launch for both LDS classes up to this many compact fronts
 

@@ -2623,9 +2623,6 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         // panel's end, then one rank-kWideRank update of the trailing part
         const bool wide = sizeof(T) == 8 && L.big_maxf >= L.wide_front;
         const int step = wide ? kWideRank : kPanelNB;
-        const bool ahead = wide && side && side->ahead && L.lookahead;
-        bool pending = false;  // a look-ahead update still to be joined
-        int slot = 0;          // rest_done[slot ^ 1] marks the pending one
         for (int kw = 0; kw < L.big_maxw; kw += step) {
             for (int kb = kw; kb < std::min(kw + step, L.big_maxw); kb += kPanelNB) {
                 const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
@@ -2650,30 +2647,9 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
             const int rest = L.big_maxf - kw - step;  // upper bound of trailing rows
             if (rest <= 0) continue;
             const int nt = (rest + kWideTile - 1) / kWideTile, ntri = nt * (nt + 1) / 2;
-            // tile columns 0 and 1 are the next wide panel's columns
-            const int split = nt > 2 ? 2 * nt - 1 : ntri;
-            if (ahead && split < ntri) {
-                // the rest runs ahead, once this wide panel is factored; the
-                // next panel's columns wait for the rest of the previous step
-                // (it updates them too)
-                (void)hipEventRecord(side->panel_done, sb);
-                (void)hipStreamWaitEvent(side->ahead, side->panel_done, 0);
-                hipLaunchKernelGGL(k_big_update_wide, dim3(ntri - split, L.big_count), dim3(256), 0, side->ahead, P,
-                                   reinterpret_cast<double*>(arena), L.big_begin, kw, nt, split, ntri);
-                (void)hipEventRecord(side->rest_done[slot], side->ahead);
-                if (pending) (void)hipStreamWaitEvent(sb, side->rest_done[slot ^ 1], 0);
-                hipLaunchKernelGGL(k_big_update_wide, dim3(split, L.big_count), dim3(256), 0, sb, P,
-                                   reinterpret_cast<double*>(arena), L.big_begin, kw, nt, 0, split);
-                pending = true;
-                slot ^= 1;
-            } else {
-                if (pending) (void)hipStreamWaitEvent(sb, side->rest_done[slot ^ 1], 0);
-                pending = false;
-                hipLaunchKernelGGL(k_big_update_wide, dim3(ntri, L.big_count), dim3(256), 0, sb, P,
-                                   reinterpret_cast<double*>(arena), L.big_begin, kw, nt, 0, ntri);
-            }
+            hipLaunchKernelGGL(k_big_update_wide, dim3(ntri, L.big_count), dim3(256), 0, sb, P,
+                               reinterpret_cast<double*>(arena), L.big_begin, kw, nt, 0, ntri);
         }
-        if (pending) (void)hipStreamWaitEvent(sb, side->rest_done[slot ^ 1], 0);
     }
     if (L.small_count > 0) {
         // two LDS size classes so that small fronts keep several workgroups

@@ -368,3 +368,20 @@ def adam(params, grad, m, v, step, lr):
     lib = L.load()
     L.check(lib.ckkt_adam(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
                           _stream()), "ckkt_adam")
+
+
+def init_mlp_params(seed=0, device="cuda"):
+    """Starting parameters of the learned preconditioner's MLP (layout of
+    CKKT_MLP_NPARAM in include/ckkt.h), as a float32 device tensor: hidden
+    weights drawn N(0, 1/fan_in) (LeCun scaling for the tanh layers), zero
+    biases, and an output layer of small weights so that the network starts
+    near o = 0 (D = I, the plain stale-factor preconditioner)."""
+    import torch
+    rng = np.random.default_rng(seed + 0x5EED)
+    F, H = L.MLP_F, L.MLP_H
+    parts = [rng.normal(0.0, 1.0 / np.sqrt(F), H * F), np.zeros(H),
+             rng.normal(0.0, 1.0 / np.sqrt(H), H * H), np.zeros(H),
+             rng.normal(0.0, 1e-2, H), np.zeros(1)]
+    theta = np.concatenate(parts).astype(np.float32)
+    assert theta.size == L.MLP_NPARAM
+    return torch.as_tensor(theta, device=device)

@@ -211,6 +211,32 @@ def test_batch_analysis_is_block_diagonal():
         off += q.n
 
 
+def _bad_batch(probs):
+    with pytest.raises(_lib.CkktError) as e:
+        Solver(None, "lifted", batch=probs)
+    return e.value.status
+
+
+def test_batch_instance_pattern_errors():
+    """Every instance of a batch is validated on its own before it is
+    ordered: an index at or beyond the instance's own n is a pattern error
+    even when it lies inside the union (it would name another instance's
+    variable), and so are a bad row pointer and an unsorted row."""
+    import dataclasses
+    a, b = workloads.tiny_grid(0, nx=3, ny=3), workloads.tiny_grid(1, nx=4, ny=3)
+    assert b.n > a.n
+    g = a.g_idx.copy(); g[0] = a.n          # in range of the union, not of instance 0
+    assert _bad_batch([dataclasses.replace(a, g_idx=g), b]) == -2
+    h = b.h_idx.copy(); h[-1] = b.n + 7      # beyond the last instance
+    assert _bad_batch([a, dataclasses.replace(b, h_idx=h)]) == -2
+    w = a.w_idx.copy(); w[a.w_ptr[4]] = 6    # above the diagonal of row 4
+    assert _bad_batch([dataclasses.replace(a, w_idx=w), b]) == -2
+    gp = b.g_ptr.copy(); gp[1] = -5          # pointer decreases (and is negative)
+    assert _bad_batch([a, dataclasses.replace(b, g_ptr=gp)]) == -2
+    # the valid batch still analyses
+    assert Solver(None, "lifted", batch=[a, b]).info()["n"] == a.n + b.n
+
+
 def test_dual_reg_arguments_rejected_without_gpu():
     """ckkt_factorize_dual_reg: HyKKT handles and 0 < delta_c with finite 1/delta_c only."""
     p = workloads.tiny_grid(0, nx=3, ny=3)

@@ -7,6 +7,7 @@
 * PCG with M^{-1} = K^{-1} converges in one step (exact preconditioner).
 """
 import numpy as np
+import pytest
 import scipy.sparse as sp
 
 from oracle import mlp
@@ -88,6 +89,66 @@ def test_pcg_exact_preconditioner_one_step():
     x, it, ok = mlp.pcg(lambda v: K @ v, b, lambda r: Kinv @ r, np.zeros(n),
                         lambda x: np.abs(K @ x - b).max() < 1e-10, 10)
     assert ok and it == 1
+
+
+def _pcg_iterate(K, b, Minv, k):
+    """x_k of the oracle's PCG from x0 = 0 (its stopping test is called once
+    on x0 and once per iteration; it stops after the k-th)."""
+    calls = [0]
+
+    def stop(_x):
+        calls[0] += 1
+        return calls[0] > k
+    x, it, ok = mlp.pcg(lambda v: K @ v, b, lambda r: Minv @ r, np.zeros(len(b)), stop, 50)
+    assert it == k and ok
+    return x
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pcg_iterates_are_krylov_projections(seed):
+    """CG optimality (Hestenes & Stiefel 1952): with K SPD and the SPD
+    preconditioner M^{-1}, the k-th iterate from x0 = 0 minimises the K-norm
+    of the error over the Krylov space span{M^{-1}b, (M^{-1}K)M^{-1}b, ...,
+    (M^{-1}K)^{k-1}M^{-1}b}, i.e. x_k = V (V^T K V)^{-1} V^T b for any basis V
+    of that space.  A wrong beta, a wrong direction update p = z + beta p, a
+    residual update with the wrong sign or an unpreconditioned inner product
+    all leave that space or lose the optimality from the second step on."""
+    rng = np.random.default_rng(100 + seed)
+    n = 30
+    A = rng.standard_normal((n, n))
+    K = A @ A.T / n + np.diag(10.0 ** rng.uniform(-1, 1, n))
+    B = rng.standard_normal((n, n))
+    Minv = B @ B.T / n + np.diag(rng.uniform(0.5, 2.0, n))   # SPD, far from K^{-1}
+    b = rng.standard_normal(n)
+    z0 = Minv @ b
+    for k in range(1, 6):
+        cols = [z0]
+        for _ in range(k - 1):
+            cols.append(Minv @ (K @ cols[-1]))
+        V, _ = np.linalg.qr(np.array(cols).T)
+        x_ref = V @ np.linalg.solve(V.T @ K @ V, V.T @ b)
+        x = _pcg_iterate(K, b, Minv, k)
+        assert np.linalg.norm(x - x_ref) <= 1e-9 * np.linalg.norm(x_ref), k
+
+
+def test_pcg_counts_match_eigenvalue_clusters():
+    """Exact arithmetic: CG ends after as many steps as M^{-1}K has distinct
+    eigenvalues; with M^{-1} = K^{-1} times a matrix with 3 distinct
+    eigenvalues the oracle's PCG reaches 1e-12 in exactly 3 steps."""
+    rng = np.random.default_rng(9)
+    n = 24
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    K = Q @ np.diag(rng.uniform(1, 5, n)) @ Q.T
+    C = np.diag(np.repeat([1.0, 3.0, 7.0], n // 3))
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    # M^{-1} K is similar to C: M^{-1} = K^{-1/2} U C U^T K^{-1/2}
+    w, E = np.linalg.eigh(K)
+    Kmh = E @ np.diag(w ** -0.5) @ E.T
+    Minv = Kmh @ U @ C @ U.T @ Kmh
+    b = rng.standard_normal(n)
+    x, it, ok = mlp.pcg(lambda v: K @ v, b, lambda r: Minv @ r, np.zeros(n),
+                        lambda x: np.linalg.norm(K @ x - b) <= 1e-12 * np.linalg.norm(b), 20)
+    assert ok and it == 3
 
 
 def test_features_definition_on_tiny_data():

@@ -308,6 +308,24 @@ def test_gamma_threshold_gives_spd():
     assert np.linalg.eigvalsh(K + 1e-3 * G.T @ G).min() < 0
 
 
+@pytest.mark.parametrize("scale", [1.0, 0.5, 3.0])
+def test_gamma_threshold_closed_form(scale):
+    """eq:kkt:boundgamma evaluated by hand: G = s [I 0] and K = diag(A, B) with
+    A = diag(-2, -3) on range(G^T) and B = diag(1, 4, 5) on ker(G) give
+    ||K|| = 5, lam_min(Z^T K Z) = 1, lam_min(Y^T K Y) = -3, sigma_min(G) = s,
+    so the bound is (25 / 1 + 3) / s^2 = 28 / s^2; any orthogonal change of
+    variables (K -> Q^T K Q, G -> G Q) keeps it.  The exact threshold of
+    this K is 3 / s^2 (K_gamma = diag(A + gamma s^2 I, B)), below the bound."""
+    K = np.diag([-2.0, -3.0, 1.0, 4.0, 5.0])
+    G = scale * np.hstack([np.eye(2), np.zeros((2, 3))])
+    assert np.isclose(od.gamma_threshold(K, G), 28.0 / scale ** 2, rtol=1e-12)
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((5, 5)))
+    assert np.isclose(od.gamma_threshold(Q.T @ K @ Q, G @ Q), 28.0 / scale ** 2, rtol=1e-10)
+    exact = 3.0 / scale ** 2
+    assert np.linalg.eigvalsh(K + 1.01 * exact * G.T @ G).min() > 0
+    assert np.linalg.eigvalsh(K + 0.99 * exact * G.T @ G).min() < 0
+
+
 def test_primal_schur_delta_c():
     """Remark 1 (eqn:primal): for delta_c > 0 the primal Schur complement gives
     the K1 (with -delta_c I) solution."""
