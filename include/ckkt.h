@@ -428,6 +428,22 @@ size_t ckkt_mlp_workspace(int64_t n);
 ckkt_status ckkt_mlp_backward(int64_t n, const float* features, const float* params, const float* cache,
                               const float* g_out, float* grad, void* ws, void* stream);
 
+/* ckkt_mlp_backward for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and result (bitwise), with the scratch in a
+ * static device array of the library instead of a workspace argument, so
+ * the call allocates nothing.  n is at most CKKT_MLP_NOALLOC_MAX_ROWS
+ * (CKKT_ERR_ARG beyond).  The array holds 2 * 64 * N + 4801 * N / 256 + 64
+ * FP32 values, N = CKKT_MLP_NOALLOC_MAX_ROWS (19.2 MB), on every device the
+ * library runs on, until the process ends.  Every call on one device
+ * shares that array and nothing in it has to start at zero: calls
+ * that overlap on one device (other streams, other threads) race, so the
+ * caller serializes them.  Other arguments and errors as
+ * ckkt_mlp_backward. */
+#define CKKT_MLP_NOALLOC_MAX_ROWS 32768
+ckkt_status ckkt_mlp_backward_noalloc(int64_t n, const float* features, const float* params, const float* cache,
+                                      const float* g_out, float* grad, void* stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8); step counts from 1. */
 ckkt_status ckkt_adam(int32_t nparam, float* params, const float* grad, float* m, float* v, int32_t step,
                       float lr, void* stream);

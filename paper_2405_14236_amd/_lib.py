@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(PKG, "libckkt.so")
 CKKT_OK = 0
 MLP_F, MLP_H = 8, 64
 MLP_NPARAM = MLP_H * MLP_F + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
+MLP_NOALLOC_MAX_ROWS = 32768
 STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_PATTERN", -3: "ERR_NOT_SPD", -4: "ERR_NO_CONVERGENCE",
                 -5: "ERR_BREAKDOWN", -6: "ERR_STATE", -7: "ERR_HIP", -8: "ERR_WORKSPACE", -9: "ERR_NONFINITE",
                 -10: "ERR_TIMEOUT", -11: "ERR_HOST_MEMORY"}
@@ -93,6 +94,7 @@ SIGNATURES = [
     ("ckkt_mlp_forward", c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("ckkt_mlp_workspace", c_size_t, [c_int64]),
     ("ckkt_mlp_backward", c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    ("ckkt_mlp_backward_noalloc", c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     ("ckkt_adam", c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p]),
     ("ckkt_mlp_train_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float,

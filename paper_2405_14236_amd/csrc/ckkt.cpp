@@ -2030,6 +2030,19 @@ ckkt_status ckkt_mlp_backward(int64_t n, const float* features, const float* par
     return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
 }
 
+ckkt_status ckkt_mlp_backward_noalloc(int64_t n, const float* features, const float* params, const float* cache,
+                                      const float* g_out, float* grad, void* stream) {
+    static_assert(CKKT_MLP_NOALLOC_MAX_ROWS == kMlpNoAllocRows, "row limit of the static scratch");
+    if (n < 0 || n > CKKT_MLP_NOALLOC_MAX_ROWS) return CKKT_ERR_ARG;
+    if (!params || !grad || (n > 0 && (!features || !cache || !g_out))) return CKKT_ERR_ARG;
+    (void)hipGetLastError();  // report only errors of this call's own launches
+    hipError_t e = hipSuccess;
+    void* ws = mlp_noalloc_scratch(&e);
+    if (!ws) return CKKT_ERR_HIP;
+    launch_mlp_backward(n, features, params, cache, g_out, grad, ws, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? CKKT_OK : CKKT_ERR_HIP;
+}
+
 ckkt_status ckkt_adam(int32_t nparam, float* params, const float* grad, float* m, float* v, int32_t step,
                       float lr, void* stream) {
     if (nparam < 0 || step < 1 || (nparam > 0 && (!params || !grad || !m || !v))) return CKKT_ERR_ARG;

@@ -223,6 +223,11 @@ void launch_features(const DevPlan& P, const double* sx_new, const double* d_new
                      const double* sx_old, const double* d_old, const double* kd_old, float* feat, hipStream_t st);
 void launch_mlp_forward(int64_t n, const float* feat, const float* prm, float* out, float* cache, hipStream_t st);
 size_t mlp_workspace_bytes(int64_t n);
+// rows of the allocation-free backward; its scratch is a static device array
+constexpr int64_t kMlpNoAllocRows = 32768;
+// device address of that array on the current device (looked up once per
+// device); null with *err set when the lookup fails
+void* mlp_noalloc_scratch(hipError_t* err);
 void launch_mlp_backward(int64_t n, const float* feat, const float* prm, const float* cache, const float* g_o,
                          float* grad, void* ws, hipStream_t st);
 void launch_adam(int np, float* prm, const float* g, float* m, float* v, int step, float lr, hipStream_t st);

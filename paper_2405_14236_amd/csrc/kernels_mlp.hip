@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "device.hpp"
 
@@ -244,9 +245,43 @@ void launch_features(const DevPlan& P, const double* sx_new, const double* d_new
 void launch_mlp_forward(int64_t n, const float* feat, const float* prm, float* out, float* cache, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_mlp_fwd, dim3(nb(n)), dim3(256), 0, st, n, feat, prm, out, cache);
 }
-size_t mlp_workspace_bytes(int64_t n) {
-    const int64_t nblocks = (n + kRowsPerBlock - 1) / kRowsPerBlock;
-    return (size_t)(2 * H * n + nblocks * (int64_t)kMlpNParam + 64) * sizeof(float);
+constexpr int64_t mlp_workspace_floats(int64_t n) {
+    return 2 * H * n + (n + kRowsPerBlock - 1) / kRowsPerBlock * (int64_t)kMlpNParam + 64;
+}
+size_t mlp_workspace_bytes(int64_t n) { return (size_t)mlp_workspace_floats(n) * sizeof(float); }
+
+namespace {
+// Scratch of ckkt_mlp_backward_noalloc: the backward's workspace for up to
+// kMlpNoAllocRows rows (activation gradients, one partial gradient per
+// 256-row block) in a file-scope device array, so that the call allocates
+// nothing.  Every kernel writes the scratch it later reads, so nothing has
+// to be cleared between calls.  Each device holds its own copy of the
+// array; host code uses only the address returned for the current device.
+static __device__ __align__(256) float scratch[mlp_workspace_floats(kMlpNoAllocRows)];
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+void* mlp_noalloc_scratch(hipError_t* err) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *err = e != hipSuccess ? e : hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        addr[dev] = p;
+    }
+    *err = hipSuccess;
+    return addr[dev];
 }
 void launch_mlp_backward(int64_t n, const float* feat, const float* prm, const float* cache, const float* g_o,
                          float* grad, void* ws, hipStream_t st) {

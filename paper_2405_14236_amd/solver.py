@@ -364,6 +364,19 @@ def mlp_backward(feat, params, cache, g_out):
     return grad
 
 
+def mlp_backward_noalloc(feat, params, cache, g_out, grad=None):
+    """ckkt_mlp_backward_noalloc: the same gradient with the library's static
+    scratch (no workspace); ``grad`` may be a preallocated output."""
+    import torch
+    n = feat.shape[0]
+    lib = L.load()
+    if grad is None:
+        grad = torch.empty(L.MLP_NPARAM, dtype=torch.float32, device=feat.device)
+    L.check(lib.ckkt_mlp_backward_noalloc(n, _ptr(feat), _ptr(params), _ptr(cache), _ptr(g_out), _ptr(grad),
+                                          _stream()), "ckkt_mlp_backward_noalloc")
+    return grad
+
+
 def adam(params, grad, m, v, step, lr):
     lib = L.load()
     L.check(lib.ckkt_adam(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
