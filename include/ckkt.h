@@ -78,7 +78,15 @@ typedef int32_t ckkt_status;
 #define CKKT_HYKKT  1
 
 /* Precision of the Cholesky factor.  Residuals, refinement updates, CG
- * vectors, dot products and the gamma-scaled terms are FP64 in both. */
+ * vectors, dot products and the gamma-scaled terms are FP64 in both.
+ * CKKT_FP32_IR factors the Jacobi-scaled matrix in FP32 (static pivoting)
+ * and refines in FP64; the solve gives the FP32 factor up for an FP64
+ * refactorization when it cannot reach opt.tol: at once when a pivot was
+ * floored or the first FP32 solve has omega > 0.1 (the FP32 error grows
+ * with the largest diagonal weights, Sec. 4), else after Richardson and PCG
+ * around it stagnate.  After such a system the next 4 factorizations of the
+ * handle are FP64 from the start (8, 16, .. 64 while failures repeat;
+ * info->fallback = 8 on their solves), then FP32 is tried again. */
 #define CKKT_FP64    0
 #define CKKT_FP32_IR 1
 
@@ -143,6 +151,8 @@ typedef struct {
                                  level of fronts that meets the first one), -1 if
                                  none; valid after a solve or ckkt_factor_status */
     int32_t n_dense_rows;     /* rows split off by opt.dense_row_min */
+    int32_t n_instances;      /* instances of a batch (1 for a single pattern) */
+    int32_t pad;
 } ckkt_info;
 
 typedef struct {
@@ -150,7 +160,11 @@ typedef struct {
     int32_t refine_steps;     /* refinement steps taken after the first solve (outer steps for HyKKT) */
     int32_t cg_iters;         /* total CG iterations (HyKKT) */
     int32_t pcg_iters;        /* total PCG iterations (FP32 fallback path) */
-    int32_t fallback;         /* 0 none, 1 PCG around the FP32 factor, 2 FP64 refactorization */
+    int32_t fallback;         /* 0 none, 1 PCG around the FP32 factor, 2 FP64 refactorization,
+                                 8 factorized in FP64 from the start after an earlier FP32
+                                 failure (FP32_IR handles); ckkt_batch_factorize_solve adds 4
+                                 when its device steps did not reach opt.tol and the
+                                 refinement of ckkt_solve took over */
     int32_t pad;
     double  omega;            /* final componentwise relative backward error */
     double  rho;              /* final unscaled ||r||_inf / ||rhs||_inf */
@@ -318,6 +332,40 @@ ckkt_status ckkt_factorize_inertia(ckkt_handle* h, const double* w_val, const do
  * best iterate), CKKT_ERR_BREAKDOWN, CKKT_ERR_TIMEOUT, CKKT_ERR_HIP. */
 ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol,
                        ckkt_solve_info* info, void* stream);
+
+/* Factorization and solve of a whole LiftedKKT system in one call, meant
+ * for a batch analysed by ckkt_batch_analyze (the solver's factorization
+ * and solve phases, Sec. 5 and 6.1, applied to every instance at once; also
+ * accepted for a single pattern).  One captured launch sequence does what
+ * ckkt_factorize and ckkt_solve do: assembly (Sec. 3.2, eq:liftedkkt),
+ * factorization in the handle's precision, x = K^{-1} b, then `refine`
+ * refinement steps (residual with K unassembled in FP64, a factor
+ * application, and the update x += dx applied only to the instances whose
+ * componentwise backward error omega is still above opt.tol, so a
+ * converged instance is left as it is), and the final residual.  Then the
+ * call synchronizes `stream` once and reads every instance's omega.  If an
+ * instance is still above opt.tol, the refinement of ckkt_solve (FP32:
+ * Richardson, PCG around the FP32 factor, FP64 refactorization) continues
+ * from that iterate on the host's control, with its own synchronizations
+ * (the device steps count against opt.ir_maxit), and info->fallback gets
+ * 4 added.
+ *   values, sigma_x, sigma_s : as ckkt_factorize (device, caller-owned)
+ *   rhs, sol    : n doubles each (device); sol receives d_x
+ *   refine      : device refinement steps, 0 .. CKKT_MAX_DEVICE_REFINE
+ *   inst_omega  : host, one double per instance (the instance's omega), or NULL
+ *   info        : host, may be NULL (refine_steps counts the device steps)
+ * The sequence is captured on the first call and replayed while the value,
+ * right-hand side and solution pointers and `refine` stay the same (a
+ * change of any of them captures it again).  The handle stays factorized
+ * for ckkt_solve / ckkt_apply_inverse afterwards; the stale reference of
+ * the learned preconditioner is not updated.  LiftedKKT handles without
+ * split dense rows only (else CKKT_ERR_ARG).  Errors as ckkt_factorize and
+ * ckkt_solve. */
+#define CKKT_MAX_DEVICE_REFINE 8
+ckkt_status ckkt_batch_factorize_solve(ckkt_handle* h, const double* w_val, const double* g_val,
+                                       const double* h_val, const double* sigma_x, const double* sigma_s,
+                                       const double* rhs, double* sol, int32_t refine, double* inst_omega,
+                                       ckkt_solve_info* info, void* stream);
 
 /* Newton step of the augmented system K2 (Sec. 2.2, eq:kkt:augmented,
  * delta_c = 0) around the condensed factor:

@@ -14,6 +14,7 @@ CKKT_OK = 0
 MLP_F, MLP_H = 8, 64
 MLP_NPARAM = MLP_H * MLP_F + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
 MLP_NOALLOC_MAX_ROWS = 32768
+MAX_DEVICE_REFINE = 8
 STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_PATTERN", -3: "ERR_NOT_SPD", -4: "ERR_NO_CONVERGENCE",
                 -5: "ERR_BREAKDOWN", -6: "ERR_STATE", -7: "ERR_HIP", -8: "ERR_WORKSPACE", -9: "ERR_NONFINITE",
                 -10: "ERR_TIMEOUT", -11: "ERR_HOST_MEMORY"}
@@ -42,7 +43,8 @@ class Info(ctypes.Structure):
                 ("nnz_l", c_int64), ("nnz_l_stored", c_int64), ("factor_flops", c_double),
                 ("assembly_products", c_double), ("n_supernodes", c_int32), ("n_levels", c_int32),
                 ("max_front", c_int32), ("n_big_fronts", c_int32), ("workspace_bytes", c_int64),
-                ("analyze_seconds", c_double), ("failed_column", c_int32), ("n_dense_rows", c_int32)]
+                ("analyze_seconds", c_double), ("failed_column", c_int32), ("n_dense_rows", c_int32),
+                ("n_instances", c_int32), ("pad", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -80,6 +82,8 @@ SIGNATURES = [
     ("ckkt_factorize_inertia", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                                          POINTER(Inertia), c_void_p]),
     ("ckkt_solve", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(SolveInfo), c_void_p]),
+    ("ckkt_batch_factorize_solve", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                             c_void_p, c_int32, P_f64, POINTER(SolveInfo), c_void_p]),
     ("ckkt_solve_augmented", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                        c_void_p, c_void_p, POINTER(SolveInfo), c_void_p]),
     ("ckkt_recover_bound_dual", c_int32, [c_int64, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),

@@ -57,7 +57,8 @@ size_t vbytes(const std::vector<V>& v) { return v.size() * sizeof(V); }
 struct Tune {
     int compact64 = kCompactFront64;  // FP64 fronts up to this order form the compact class
     int compact32 = kCompactFront32;  // same for FP32
-    int tiny_threads = 64;            // workgroup size when the compact class holds fronts <= 32
+    int tiny_front = 48;              // compact classes whose fronts are at most this order use tiny_threads
+    int tiny_threads = 64;            // workgroup size of such a compact class
     int compact_threads = 256;        // workgroup size of the compact class otherwise
     int sweep_cutoff = 64;            // sweeps use 256 threads when a level's largest front exceeds this
     int tiled_front = kSweepTiledFront;  // fronts with at least this many rows use the tiled sweeps
@@ -126,6 +127,12 @@ struct ckkt_handle {
 
     bool factored = false;
     bool fp64_factored = false;  // FP64 factor valid (fallback path of FP32_IR)
+    // FP32_IR handles: after a system that needed the FP64 refactorization,
+    // the next fp32_skip factorizations are FP64 from the start (the FP32
+    // attempt would fail the same way on the neighbouring systems of an
+    // interior-point sequence); the skip doubles while failures repeat
+    int32_t fp32_skip = 0, fp32_backoff = 0;
+    bool fp64_by_history = false;  // the current factor is FP64 for that reason
     SysVals vals{};
     int32_t failed_column = -1;
 
@@ -139,9 +146,11 @@ struct ckkt_handle {
     hipStream_t capture_stream = nullptr;
     SideStream side;  // second stream of the factorization (tiled fronts)
     // captured launch sequences: factorization (FP64, FP32), factor
-    // application (FP64, FP32), HyKKT CG iteration (FP64, FP32 factor)
-    hipGraphExec_t graphs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // application (FP64, FP32), HyKKT CG iteration (FP64, FP32 factor),
+    // whole factorize-and-solve calls (FP64, FP32)
+    hipGraphExec_t graphs[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     const void* cg_key[2][3] = {};  // G values, dx and dy a CG-iteration graph was captured with
+    const void* fs_key[2][8] = {};  // pointers and step count a factorize-and-solve graph was captured with
     bool use_graphs = true;
     bool debug_launch = false;  // CKKT_DEBUG_LAUNCH=1: report the first failing launch per factor level
 
@@ -225,7 +234,7 @@ void build_levels(ckkt_handle* h) {
             if (f <= T.compact32) { L.small_split32++; L.small_maxf_a32 = std::max(L.small_maxf_a32, f); }
         }
         const int fa = h->precision == CKKT_FP32_IR ? L.small_maxf_a32 : L.small_maxf_a;
-        L.small_threads_a = fa <= 32 ? T.tiny_threads : T.compact_threads;
+        L.small_threads_a = fa <= T.tiny_front ? T.tiny_threads : T.compact_threads;
         L.big_begin = P.lvl_big_ptr[l];
         L.big_count = P.lvl_big_ptr[l + 1] - L.big_begin;
         L.big_maxw = L.big_maxf = 0;
@@ -330,7 +339,7 @@ void build_layout(ckkt_handle* h) {
     {
         int maxbig = 1;
         for (int l = 0; l < P.nlev; ++l) maxbig = std::max(maxbig, P.lvl_big_ptr[l + 1] - P.lvl_big_ptr[l]);
-        h->r_dscr = L.add((size_t)maxbig * kPanelNB * kPanelNB * sizeof(double));
+        h->r_dscr = L.add((size_t)maxbig * kPanel2 * kPanel2 * sizeof(double));
     }
     h->r_bits = L.add((P.ninst + 2) * sizeof(unsigned long long));
     h->r_dotpart = L.add(kDotBlocks * sizeof(double));
@@ -486,6 +495,12 @@ ckkt_status finish_plan(HandlePtr h, const AnalyzeOptions& ao, ckkt_handle** out
     if (const char* wf = std::getenv("CKKT_WIDE_FRONT")) {
         const int v = std::atoi(wf);
         if (v > 0) h->tune.wide_front = std::max(v, ao.big_front + 1);
+    }
+    // CKKT_TINY_FRONT moves the largest front order of the compact classes
+    // factored by one-wave workgroups (at most the compact class's limit)
+    if (const char* tf = std::getenv("CKKT_TINY_FRONT")) {
+        const int v = std::atoi(tf);
+        if (v > 0) h->tune.tiny_front = std::min(v, kCompactFront64);
     }
     build_levels(h.get());
     if (!plan_fits_lds(h.get())) return CKKT_ERR_ARG;  // a small front beyond the LDS of one workgroup
@@ -729,16 +744,10 @@ double bits_to_double(unsigned long long b) {
     return d;
 }
 
-// Enqueue the residual of the current iterate and read omega back (sync).
-ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, const double* rhs1,
-                          const double* rhs2, double* res1, double* res2, ResidualOut& out, hipStream_t st) {
+// Read back (sync) what the last residual left: omega per instance, max
+// |res|, max |rhs| and the status words.
+ckkt_status read_residual(ckkt_handle* h, ResidualOut& out, hipStream_t st) {
     const int ni = h->plan.ninst;
-    {
-        PhaseTimer tm(h, 3, st);
-        launch_zero_u64(h->bits, ni + 1, st);
-        launch_residual(h->dp, h->vals, h->d, x, y, rhs1, rhs2, res1, res2, h->vm[0], h->vm[1], h->bits,
-                        h->bits + ni, st);
-    }
     char* host = static_cast<char*>(h->host);
     HIP_TRY(hipMemcpyAsync(host, h->bits, (ni + 2) * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(host + (ni + 2) * sizeof(unsigned long long), h->status, 4 * sizeof(int32_t),
@@ -759,6 +768,19 @@ ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, cons
     out.status2 = hs[2];
     out.status3 = hs[3];
     return out.status2 ? CKKT_ERR_TIMEOUT : CKKT_OK;
+}
+
+// Enqueue the residual of the current iterate and read omega back (sync).
+ckkt_status residual_sync(ckkt_handle* h, const double* x, const double* y, const double* rhs1,
+                          const double* rhs2, double* res1, double* res2, ResidualOut& out, hipStream_t st) {
+    const int ni = h->plan.ninst;
+    {
+        PhaseTimer tm(h, 3, st);
+        launch_zero_u64(h->bits, ni + 1, st);
+        launch_residual(h->dp, h->vals, h->d, x, y, rhs1, rhs2, res1, res2, h->vm[0], h->vm[1], h->bits,
+                        h->bits + ni, st);
+    }
+    return read_residual(h, out, st);
 }
 
 // max |rhs| into the word after the residual maxima, read back (without
@@ -918,18 +940,55 @@ bool pcg_stale(ckkt_handle* h, const double* b, double* x, const float* o, int m
     return false;
 }
 
-ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_info* info, hipStream_t st) {
+// After a solve of an FP32_IR handle: a system that needed the FP64
+// refactorization makes the next fp32_skip factorizations FP64 from the
+// start (4, doubling while failures repeat, at most kFp32MaxSkip); a system
+// the FP32 factor solved resets the count.
+constexpr int kFp32FirstSkip = 4, kFp32MaxSkip = 64;
+void note_fp32_outcome(ckkt_handle* h, const ckkt_solve_info* info) {
+    if (h->precision != CKKT_FP32_IR || h->fp64_by_history) return;
+    if (info->fallback == 2) {
+        h->fp32_backoff = h->fp32_backoff ? std::min(2 * h->fp32_backoff, kFp32MaxSkip) : kFp32FirstSkip;
+        h->fp32_skip = h->fp32_backoff;
+    } else {
+        h->fp32_backoff = 0;
+        h->fp32_skip = 0;
+    }
+}
+
+// The FP32 factor is given up at once (no Richardson or PCG steps) when
+// static pivoting floored a pivot (the factor is then that of another
+// matrix) or when the first FP32 solve has a backward error above this:
+// the FP32 error in the small space grows with the largest diagonal
+// weights (Sec. 4, eq:cond:inversecondensederror).
+constexpr double kFp32Hopeless = 0.1;
+
+// start_steps > 0: x already holds the iterate after that many refinement
+// steps of the current factor (the device steps of
+// ckkt_batch_factorize_solve), and the refinement continues from it.
+ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_info* info, hipStream_t st,
+                         int start_steps = 0) {
     const int n = h->plan.n;
     double* res = h->vn[0];
     double* dx = h->vn[1];
     launch_rhs_max(h, b, n, nullptr, 0, st);
     ckkt_status rc = CKKT_OK;
     bool use64 = h->precision == CKKT_FP64 || h->fp64_factored;
-    apply_inverse(h, b, x, use64, st);
+    if (h->fp64_by_history) info->fallback = 8;
+    if (start_steps == 0) apply_inverse(h, b, x, use64, st);
     ResidualOut r;
-    int steps = 0;
+    int steps = start_steps;
     double prev = INFINITY;
     int stall = 0;
+    auto refactor = [&]() {
+        refactor_fp64(h, st);
+        use64 = true;
+        info->fallback = 2;
+        apply_inverse(h, b, x, true, st);
+        steps = 0;
+        prev = INFINITY;
+        stall = 0;
+    };
     for (;;) {
         rc = residual_sync(h, x, nullptr, b, nullptr, res, nullptr, r, st);
         if (rc) return rc;
@@ -939,6 +998,10 @@ ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_
         info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
         if (r.omega <= h->opt.tol) break;
         if (!use64) {
+            if (steps == start_steps && (r.status1 > 0 || !(r.omega <= kFp32Hopeless))) {
+                refactor();
+                continue;
+            }
             // FP32 factor: Richardson while it contracts; when it stagnates,
             // FP64 PCG preconditioned by the same factor; if that fails too,
             // FP64 refactorization of the already assembled matrix.
@@ -953,13 +1016,7 @@ ckkt_status solve_lifted(ckkt_handle* h, const double* b, double* x, ckkt_solve_
                     }
                     if (rc) return rc;
                 }
-                refactor_fp64(h, st);
-                use64 = true;
-                info->fallback = 2;
-                apply_inverse(h, b, x, true, st);
-                steps = 0;
-                prev = INFINITY;
-                stall = 0;
+                refactor();
                 continue;
             }
         } else if (steps >= h->opt.ir_maxit) {
@@ -1092,6 +1149,7 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
         launch_fill(n + me, 0.0, sol, st);
     }
     bool use64 = h->precision == CKKT_FP64 || h->fp64_factored;
+    if (h->fp64_by_history) info->fallback = 8;
     ResidualOut r;
     // steps: outer steps taken (all factors); base: steps taken before the
     // current factor, so that the FP64 refactorization of the fallback gets
@@ -1114,6 +1172,7 @@ ckkt_status solve_hykkt(ckkt_handle* h, const double* rhs, double* sol, ckkt_sol
         info->omega = r.omega;
         info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
         if (r.omega <= h->opt.tol && steps > 0) break;
+        if (steps == 0 && !use64 && r.status1 > 0) fall_back();  // floored pivots: give up the FP32 factor at once
         if (steps > base && !use64) {
             if (!(r.omega < 0.5 * prev)) stall++;
             if (stall >= 2 || steps - base > h->opt.ir_maxit) fall_back();
@@ -1717,12 +1776,16 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
     h->vals = SysVals{w_val, g_val, h_val, sigma_x, sigma_s, gamma};
     h->failed_column = -1;
     h->fp64_factored = false;
+    // FP32_IR: FP64 from the start while an earlier FP32 failure is recent
+    h->fp64_by_history = h->precision == CKKT_FP32_IR && h->fp32_skip > 0;
+    if (h->fp64_by_history) h->fp32_skip--;
+    const bool use32 = h->precision == CKKT_FP32_IR && !h->fp64_by_history;
     {
         PhaseTimer tm(h, 0, st);
         launch_init_status(h->status, false, st);
         launch_row_weights(h->dp, h->vals, h->d, st);
         launch_assemble(h->dp, h->vals, h->d, h->K, h->status + 3, st);
-        if (h->precision == CKKT_FP32_IR) launch_diag_scale(h->dp, h->K, h->scale, st);
+        if (use32) launch_diag_scale(h->dp, h->K, h->scale, st);
         if (h->opt.learned) {
             // the factorized system becomes the stale reference of the learned PCG
             launch_copy(h->plan.n, sigma_x, h->sxold, st);
@@ -1733,14 +1796,14 @@ ckkt_status ckkt_factorize(ckkt_handle* h, const double* w_val, const double* g_
     }
     {
         PhaseTimer tm(h, 1, st);
-        if (h->precision == CKKT_FP64) {
+        if (!use32) {
             factor_all<double>(h, nullptr, st);
             h->fp64_factored = true;
         } else {
             factor_all<float>(h, h->scale, st);
         }
     }
-    if (h->precision == CKKT_FP64) dense_rows_setup(h, st);
+    if (!use32) dense_rows_setup(h, st);
     if (hipGetLastError() != hipSuccess) return CKKT_ERR_HIP;
     h->factored = true;
     return CKKT_OK;
@@ -1808,8 +1871,101 @@ ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol, ckkt_solv
     ckkt_status rc = h->formulation == CKKT_HYKKT ? solve_hykkt(h, rhs, sol, info, st)
                                                    : solve_lifted(h, rhs, sol, info, st);
     if (rc == CKKT_OK && hipGetLastError() != hipSuccess) rc = CKKT_ERR_HIP;
+    if (rc == CKKT_OK) note_fp32_outcome(h, info);
     info->status = rc;
     return rc;
+}
+
+// The launches of ckkt_batch_factorize_solve: assembly, factorization,
+// x = K^{-1} b, `refine` refinement steps whose update is applied only to
+// the instances still above the tolerance, and the residual of the result.
+void factorize_solve_launches(ckkt_handle* h, bool d, int refine, const double* b, double* x, hipStream_t s) {
+    const int ni = h->plan.ninst;
+    double* res = h->vn[0];
+    double* dx = h->vn[1];
+    launch_init_status(h->status, false, s);
+    launch_row_weights(h->dp, h->vals, h->d, s);
+    launch_assemble(h->dp, h->vals, h->d, h->K, h->status + 3, s);
+    if (d) {
+        factor_levels<double>(h, nullptr, s);
+    } else {
+        launch_diag_scale(h->dp, h->K, h->scale, s);
+        factor_levels<float>(h, h->scale, s);
+    }
+    launch_rhs_max(h, b, h->plan.n, nullptr, 0, s);
+    apply_inverse_launches(h, b, x, false, s);
+    for (int k = 0; k <= refine; ++k) {
+        launch_zero_u64(h->bits, ni + 1, s);
+        launch_residual(h->dp, h->vals, h->d, x, nullptr, b, nullptr, res, nullptr, h->vm[0], h->vm[1], h->bits,
+                        h->bits + ni, s);
+        if (k == refine) break;
+        apply_inverse_launches(h, res, dx, false, s);
+        launch_masked_axpy(h->dp, h->bits, h->opt.tol, dx, x, s);
+    }
+}
+
+ckkt_status ckkt_batch_factorize_solve(ckkt_handle* h, const double* w_val, const double* g_val,
+                                       const double* h_val, const double* sigma_x, const double* sigma_s,
+                                       const double* rhs, double* sol, int32_t refine, double* inst_omega,
+                                       ckkt_solve_info* info, void* stream) {
+    ckkt_solve_info local{};
+    if (!info) info = &local;
+    std::memset(info, 0, sizeof(*info));
+    if (!h) return info->status = CKKT_ERR_ARG;
+    if (!h->ws) return info->status = CKKT_ERR_STATE;
+    const Plan& P = h->plan;
+    if (h->formulation != CKKT_LIFTED || !P.dense_rows.empty() || refine < 0 || refine > CKKT_MAX_DEVICE_REFINE)
+        return info->status = CKKT_ERR_ARG;
+    if ((P.nnz_w > 0 && !w_val) || (P.nnz_g > 0 && !g_val) || (P.nnz_h > 0 && !h_val) ||
+        (P.n > 0 && (!sigma_x || !rhs || !sol)) || (P.m > 0 && !sigma_s))
+        return info->status = CKKT_ERR_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();  // report only errors of this call's own launches
+    h->vals = SysVals{w_val, g_val, h_val, sigma_x, sigma_s, 0.0};
+    h->failed_column = -1;
+    h->factored = false;
+    const bool d = h->precision == CKKT_FP64;
+    h->fp64_factored = d;
+    // the captured sequence holds the caller's pointers: captured again
+    // when any of them (or the step count) differs from the last call's
+    const int slot = d ? 6 : 7;
+    const void* key[8] = {w_val, g_val, h_val, sigma_x, sigma_s, rhs, sol,
+                          reinterpret_cast<const void*>(static_cast<intptr_t>(refine))};
+    const void** held = h->fs_key[slot - 6];
+    if (h->graphs[slot] && !std::equal(key, key + 8, held)) {
+        (void)hipGraphExecDestroy(h->graphs[slot]);
+        h->graphs[slot] = nullptr;
+    }
+    std::copy(key, key + 8, held);
+    {
+        PhaseTimer tm(h, 1, st);
+        run_captured(h, slot, st, [&](hipStream_t s) { factorize_solve_launches(h, d, refine, rhs, sol, s); });
+    }
+    if (hipGetLastError() != hipSuccess) return info->status = CKKT_ERR_HIP;
+    h->factored = true;
+    ResidualOut r;
+    ckkt_status rc = read_residual(h, r, st);  // the call's one host synchronization
+    if (rc) return info->status = rc;
+    if ((rc = check_factor(h, r)) != CKKT_OK) return info->status = rc;
+    if (!std::isfinite(r.rhsmax)) return info->status = CKKT_ERR_NONFINITE;
+    info->refine_steps = refine;
+    if (!(r.omega <= h->opt.tol)) {
+        // some instance is still above the tolerance: the refinement of
+        // ckkt_solve (with its fallbacks for an FP32 factor) continues from
+        // the iterate of the device steps
+        ckkt_solve_info more{};
+        rc = solve_lifted(h, rhs, sol, &more, st, refine);
+        info->refine_steps = more.refine_steps;
+        info->pcg_iters = more.pcg_iters;
+        info->fallback = more.fallback | 4;
+        if (rc) return info->status = rc;
+        if ((rc = read_residual(h, r, st)) != CKKT_OK) return info->status = rc;
+    }
+    info->omega = r.omega;
+    info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
+    if (inst_omega) std::copy(r.per_inst.begin(), r.per_inst.end(), inst_omega);
+    if (hipGetLastError() != hipSuccess) rc = CKKT_ERR_HIP;
+    return info->status = rc;
 }
 
 ckkt_status ckkt_solve_augmented(ckkt_handle* h, const double* r1, const double* r2, const double* r3,
@@ -2238,6 +2394,7 @@ ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info) {
     info->n_big_fronts = P.n_big;
     info->workspace_bytes = (int64_t)h->lay.total;
     info->analyze_seconds = P.analyze_seconds;
+    info->n_instances = P.ninst;
     info->failed_column = h->failed_column;
     info->n_dense_rows = (int32_t)h->plan.dense_rows.size();
     return CKKT_OK;

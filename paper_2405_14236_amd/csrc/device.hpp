@@ -55,6 +55,9 @@ struct LevelInfo {
 };
 
 constexpr int kBigTile = 64;    // column tile of the tiled front path
+// fronts of at most this many rows are assembled one column per wave in LDS
+// (four column buffers of this length per workgroup)
+constexpr int kInitColRows = 2048;
 constexpr int kLdsBytes = 160 * 1024;   // LDS per workgroup on gfx950
 constexpr int kFactorStaticLds = 2304;  // upper bound of k_factor_small's static LDS
 constexpr int kSweepStaticLds = 1024;   // upper bound of k_fwd / k_bwd static LDS
@@ -66,6 +69,7 @@ constexpr int kSweepMaxFront = (kLdsBytes - kSweepStaticLds) / 8 - 64 * 64;
 constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several workgroups per CU)
 constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
+constexpr int kPanel2 = 64;     // columns factored per panel launch (two kPanelNB panels)
 constexpr int kPanelRows = 256; // rows of the panel solved per workgroup
 constexpr int kPanelLd = 64;    // leading dimension of the panel's diagonal block in LDS (one wave's rows)
 // FP64 levels with fronts of at least kWideFront rows update their trailing
@@ -96,7 +100,7 @@ struct SideStream {
 constexpr int kMergeCompactFronts = 512;  // one launch for both LDS classes up to this many compact fronts
 
 // Returns false (and launches nothing) if a launch would exceed the LDS limit.
-// dscr: kPanelNB^2 doubles per tiled front of the level (factored diagonal
+// dscr: kPanel2^2 doubles per tiled front of the level (factored diagonal
 // blocks in transit between the panel and update launches).
 template <typename T>
 bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,
@@ -183,6 +187,9 @@ void launch_dense_correct(int n, int k, const double* jd, const double* z, const
 
 // Vector kernels
 void launch_axpy(int n, double alpha, const double* x, double* y, hipStream_t st);  // y += a x
+// y += x on the variables of the instances whose omega_bits entry exceeds tol
+void launch_masked_axpy(const DevPlan& P, const unsigned long long* omega_bits, double tol, const double* x,
+                        double* y, hipStream_t st);
 void launch_copy(int n, const double* x, double* y, hipStream_t st);
 void launch_fill(int n, double v, double* y, hipStream_t st);
 void launch_shift_copy(int n, const double* x, double delta, double* y, hipStream_t st);  // y = x + delta

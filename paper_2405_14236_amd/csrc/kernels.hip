@@ -350,6 +350,32 @@ __device__ __forceinline__ void rows_trsm_diag_reg(T* B, int ld, const T* D, int
 }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// The 16 x 16 x 4 matrix-core step of each factor precision: acc += A B
+// with lane l supplying A(l % 16, l / 16) and B(l / 16, l % 16); the
+// output row of accumulator register r in lane l differs between the two
+// instructions (FP64: 4 r + l / 16; FP32: 4 (l / 16) + r; column l % 16).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef dbl4 acc;
+    static __device__ __forceinline__ acc zero() { return dbl4{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ acc step(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
+};
+template <>
+struct Mfma<float> {
+    typedef flt4 acc;
+    static __device__ __forceinline__ acc zero() { return flt4{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ acc step(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int r, int lk) { return 4 * lk + r; }
+};
 
 // Lower-triangular rank-k update on the matrix cores (FP64):
 //   out(i, j, (P P^T)_ij)  for i in [i0, i1), j in [j0, j1), i >= j,
@@ -359,9 +385,10 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // and B(l / 16, l % 16) and receives D(4 r + l / 16, l % 16) in register r.
 // Blocks entirely above the diagonal are skipped (wave-uniform), so every
 // matrix instruction runs with all lanes active.
-template <typename Out>
-__device__ __forceinline__ void syrk_mfma(const double* F, int f, int i0, int i1, int j0, int j1, int t0, int t1,
+template <typename T, typename Out>
+__device__ __forceinline__ void syrk_mfma(const T* F, int f, int i0, int i1, int j0, int j1, int t0, int t1,
                                           Out out) {
+    using M = Mfma<T>;
     // 32 x 32 blocks per wave: 2 x 2 MFMA tiles, four independent
     // accumulators sharing each K step's operand loads
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
@@ -376,25 +403,25 @@ __device__ __forceinline__ void syrk_mfma(const double* F, int f, int i0, int i1
             ai[a] = ib + 16 * a + li < i1;
             bj[a] = jb + 16 * a + li < j1;
         }
-        dbl4 c[2][2];
+        typename M::acc c[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) c[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < 2; ++b) c[a][b] = M::zero();
 #pragma unroll 2
         for (int t = t0; t < t1; t += 4) {
             const int tk = t + lk;
             const bool kin = tk < t1;
-            double av[2], bv[2];
+            T av[2], bv[2];
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-                av[a] = (ai[a] && kin) ? F[ib + 16 * a + li + tk * f] : 0.0;
-                bv[a] = (bj[a] && kin) ? F[jb + 16 * a + li + tk * f] : 0.0;
+                av[a] = (ai[a] && kin) ? F[ib + 16 * a + li + tk * f] : T(0);
+                bv[a] = (bj[a] && kin) ? F[jb + 16 * a + li + tk * f] : T(0);
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], c[a][b], 0, 0, 0);
+                for (int b = 0; b < 2; ++b) c[a][b] = M::step(av[a], bv[b], c[a][b]);
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -402,7 +429,7 @@ __device__ __forceinline__ void syrk_mfma(const double* F, int f, int i0, int i1
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int i = ib + 16 * a + 4 * r + lk, j = jb + 16 * b + li;
+                    const int i = ib + 16 * a + M::row(r, lk), j = jb + 16 * b + li;
                     if (i < i1 && j < j1 && i >= j) out(i, j, c[a][b][r]);
                 }
     }
@@ -463,13 +490,16 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
     }
     __syncthreads();
     // extend-add, one child after the other (fixed order), each child's
-    // lower update entries in one parallel pass with eight loads per thread
-    // in flight; child metadata prefetched, the child's row map staged in LDS
+    // lower update entries column by column: every wave takes columns
+    // wid, wid + nw, ... kCols at a time, lane l rows b + l, b + 64 + l, ...
+    // (kChunks of them, the rest in a tail loop), so that kCols x kChunks
+    // entries per lane (with their row map entries) are loaded before they
+    // are added; child metadata prefetched
     {
         __shared__ int64_t c_uoff[kMaxChildBatch];
         __shared__ int c_rel[kMaxChildBatch], c_rc[kMaxChildBatch], c_ld[kMaxChildBatch];
-        __shared__ int s_rel[kLdsFront64];
         const int q0 = P.child_ptr[s], nch = P.child_ptr[s + 1] - q0;
+        const int lane = tid % kWave, wid = tid / kWave, nw = nt / kWave;
         for (int base = 0; base < nch; base += kMaxChildBatch) {
             const int nb_ch = min(kMaxChildBatch, nch - base);
             if (tid < nb_ch) {
@@ -486,22 +516,33 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
                 const int rc = c_rc[q], ld = c_ld[q];
                 const int* rel = P.relmap + c_rel[q];
                 const T* U = arena + c_uoff[q];
-                for (int a = tid; a < rc; a += nt) s_rel[a] = rel[a];
-                __syncthreads();
-                const int tot = rc * rc;
-                for (int base = 0; base < tot; base += 8 * nt) {
-                    T u8[8];
+                constexpr int kChunks = REG ? 2 : 1, kCols = 4;
+                for (int b0 = wid; b0 < rc; b0 += kCols * nw) {
+                    T u[kCols][kChunks];
+                    int ra[kCols][kChunks], rb[kCols];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int idx = base + u * nt + tid;
-                        const int a = idx % rc, b = idx / rc;
-                        u8[u] = (idx < tot && a >= b) ? U[a + (int64_t)b * ld] : T(0);
+                    for (int k = 0; k < kCols; ++k) {
+                        const int b = b0 + k * nw;
+                        const bool vb = b < rc;
+                        rb[k] = vb ? rel[b] : 0;
+#pragma unroll
+                        for (int c = 0; c < kChunks; ++c) {
+                            const int a = b + c * kWave + lane;
+                            const bool in = vb && a < rc;
+                            u[k][c] = in ? U[a + (int64_t)b * ld] : T(0);
+                            ra[k][c] = in ? rel[a] : -1;
+                        }
                     }
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int idx = base + u * nt + tid;
-                        const int a = idx % rc, b = idx / rc;
-                        if (idx < tot && a >= b) F[s_rel[a] + s_rel[b] * f] += u8[u];
+                    for (int k = 0; k < kCols; ++k)
+#pragma unroll
+                        for (int c = 0; c < kChunks; ++c)
+                            if (ra[k][c] >= 0) F[ra[k][c] + rb[k] * f] += u[k][c];
+#pragma unroll
+                    for (int k = 0; k < kCols; ++k) {
+                        const int b = b0 + k * nw;
+                        for (int a = b + kChunks * kWave + lane; b < rc && a < rc; a += kWave)
+                            F[rel[a] + rb[k] * f] += U[a + (int64_t)b * ld];
                     }
                 }
                 __syncthreads();
@@ -523,41 +564,16 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
         }
         __syncthreads();
         // remaining panel columns [kb+nb, w), rows >= column
-        const int j0 = kb + nb, mr = f - j0, mc = w - j0;
-        if constexpr (std::is_same<T, double>::value) {
-            if (mc > 0)
-                syrk_mfma(F, f, j0, f, j0, w, kb, kb + nb,
-                          [&](int i, int j, double v) { F[i + j * f] -= v; });
-        } else {
-            for (int idx = tid; idx < mr * mc; idx += nt) {
-                const int i = j0 + idx % mr, j = j0 + idx / mr;
-                if (i >= j) {
-                    T acc = F[i + j * f];
-                    for (int t = 0; t < nb; ++t) acc -= F[i + (kb + t) * f] * F[j + (kb + t) * f];
-                    F[i + j * f] = acc;
-                }
-            }
-        }
+        const int j0 = kb + nb, mc = w - j0;
+        if (mc > 0) syrk_mfma<T>(F, f, j0, f, j0, w, kb, kb + nb, [&](int i, int j, T v) { F[i + j * f] -= v; });
         __syncthreads();
     }
     T* L = arena + P.l_off[s];
     for (int idx = tid; idx < f * w; idx += nt) L[idx] = F[idx];
     T* U = arena + P.u_off[s];
-    if constexpr (std::is_same<T, double>::value) {
-        if (r > 0)
-            syrk_mfma(F, f, w, f, w, f, 0, w, [&](int i, int j, double v) {
-                U[(i - w) + (int64_t)(j - w) * r] = F[i + j * f] - v;
-            });
-    } else {
-        for (int idx = tid; idx < r * r; idx += nt) {
-            const int a = idx % r, b = idx / r;
-            if (a >= b) {
-                T acc = F[(w + a) + (w + b) * f];
-                for (int k = 0; k < w; ++k) acc -= F[(w + a) + k * f] * F[(w + b) + k * f];
-                U[idx] = acc;
-            }
-        }
-    }
+    if (r > 0)
+        syrk_mfma<T>(F, f, w, f, w, f, 0, w,
+                     [&](int i, int j, T v) { U[(i - w) + (int64_t)(j - w) * r] = F[i + j * f] - v; });
 }
 
 // Large fronts, step 1: one workgroup per 64-column tile of a front kept in
@@ -678,6 +694,83 @@ k_big_init(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int t
     }
 }
 
+// Large fronts, step 1, for fronts of at most kInitColRows rows: one wave
+// per front column, assembled in LDS.  The column is zeroed from the
+// diagonal down, the K entries of the supernode's own columns are stored,
+// the children's update columns landing on it are added in child order
+// (the same order, so the same sums, as k_big_init), and the column is
+// written to the arena once.  Every wave works on its own column buffer and
+// a wave's LDS operations complete in issue order, so no barrier is needed;
+// the child metadata of up to kWave contributions is fetched by the lanes
+// at once and broadcast.  Grid (tile, kBigTile / 4), 256 threads: block y
+// takes columns 4 y .. 4 y + 3 of the tile, one per wave.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_big_init_cols(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, int tile_begin,
+                const double* __restrict__ scale, int lds_rows) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    const int tix = tile_begin + blockIdx.x;
+    const int s = P.big_tile_sn[tix];
+    const int j = P.big_tile_col[tix] + 4 * (int)blockIdx.y + wid;  // front column of this wave
+    const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+    if (j >= f) return;  // wave-uniform; no workgroup barrier follows
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    T* col = reinterpret_cast<T*>(smem_raw) + (size_t)wid * lds_rows;
+    // metadata of the contributions to this column (one per lane), issued
+    // with the K entries' loads
+    const int q0 = P.cb_ptr[ro + j], nq = P.cb_ptr[ro + j + 1] - q0;
+    int m_src = 0, m_len = 0;
+    int64_t m_off = 0;
+    if (lane < nq) {
+        m_src = P.cb_src[q0 + lane];
+        m_len = P.cb_len[q0 + lane];
+        m_off = P.cb_uoff[q0 + lane];
+    }
+    for (int i = j + lane; i < f; i += kWave) col[i] = T(0);
+    if (j < w) {
+        const int t0 = P.kcolptr[c0 + j], t1 = P.kcolptr[c0 + j + 1];
+        const double sj = scale ? scale[c0 + j] : 1.0;
+        for (int t = t0 + lane; t < t1; t += kWave) {
+            const int pr = P.kmap[t];
+            double v = K[t];
+            if (scale) v *= sj * scale[P.sn_rows[ro + pr]];
+            col[pr] = (T)v;
+        }
+    }
+    for (int q = 0; q < nq; ++q) {
+        int src, len;
+        int64_t off;
+        if (q < kWave) {
+            src = __builtin_amdgcn_readlane(m_src, q);
+            len = __builtin_amdgcn_readlane(m_len, q);
+            off = ((int64_t)__builtin_amdgcn_readlane((int)(m_off >> 32), q) << 32) |
+                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m_off, q);
+        } else {
+            src = P.cb_src[q0 + q];
+            len = P.cb_len[q0 + q];
+            off = P.cb_uoff[q0 + q];
+        }
+        const T* U = arena + off;
+        const int* rel = P.relmap + src;
+        for (int a0 = 0; a0 < len; a0 += 8 * kWave) {
+            int r[8];
+            T u[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int a = a0 + v * kWave + lane;
+                r[v] = a < len ? rel[a] : -1;
+                u[v] = a < len ? U[a] : T(0);
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v)
+                if (r[v] >= 0) col[r[v]] += u[v];
+        }
+    }
+    T* Fj = arena + P.l_off[s] + (int64_t)j * f;
+    for (int i = j + lane; i < f; i += kWave) Fj[i] = col[i];
+}
+
 // Cholesky of the nb x nb (nb <= 32) lower triangle D (LDS, leading
 // dimension kPanelNB) by one wave, right-looking with the rows in
 // registers: lane i keeps row i; per column j the pivot comes from lane j,
@@ -753,114 +846,165 @@ __device__ __forceinline__ void potrf32_reg(T* D, int nb, int col0, int32_t* sta
     }
 }
 
-// Large fronts, step 2 (per block column kb), grid (row chunk, front):
-// every workgroup stages the 32 x 32 diagonal block, one wave factors it
-// (the same arithmetic in every workgroup) while the workgroup's rows are
-// loaded, and each thread then solves its row of the chunk (kPanelRows
-// rows below the block) in registers, right-looking, with the factored
-// block read as LDS broadcasts.  With one chunk the factored block is
-// written back in place; with several, chunk 0 leaves it in dscr (another
-// chunk may still be reading the original block) and the trailing-update
-// launch copies it into the front.
+// Large fronts, step 2 with two 32-column panels per launch (block column
+// kb of up to kPanel2 columns), grid (row chunk, front): every workgroup
+// stages the diagonal block (up to 64 x 64) and factors it blocked: one
+// wave factors its first 32 columns, the rows below them in the block are
+// solved one per thread, the second diagonal block is updated and then
+// factored by one wave (the same arithmetic in every workgroup).  Each
+// 32-column diagonal block is factored in a buffer of its own (Dd, leading
+// dimension kPanelLd: the register Cholesky stores every lane's row, the
+// rows past the block land in Dd's padding) and copied back.  Each thread
+// then solves its row of the chunk: the first 32 columns in registers,
+// right-looking, each finished entry also applied to the second 32
+// columns, which are then solved the same way.  The factored block goes
+// back in place (one chunk) or, with several chunks, chunk 0 leaves it in
+// dscr (another chunk may still be reading the original) for the
+// trailing-update launch to copy.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status, T* __restrict__ dscr) {
-    static_assert(kPanelRows == 256, "one row per thread");
-    __shared__ T D[kPanelLd * kPanelNB];
-    __shared__ T s_rdiag[kPanelNB];
+k_big_panel2(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status, T* __restrict__ dscr) {
+    static_assert(kPanelRows == 256 && kPanel2 == 2 * kPanelNB && kPanelLd == kPanel2, "layout of the block");
+    constexpr int NB = kPanelNB;
+    __shared__ T D[kPanelLd * kPanel2];
+    __shared__ T Dd[kPanelLd * kPanelNB];
+    __shared__ T s_rdiag[kPanel2];
     const int s = P.lvl_big[list_begin + blockIdx.y];
     const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
     const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
     if (kb >= w) return;
-    const int nb = min(kPanelNB, w - kb);
+    const int nb = min(kPanel2, w - kb);  // columns of this block
+    const int nb1 = min(NB, nb), nb2 = nb - nb1;
     T* F = arena + P.l_off[s];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int r0 = kb + nb + blockIdx.x * kPanelRows;
     if (blockIdx.x > 0 && r0 >= f) return;
     const int nr = r0 < f ? min(kPanelRows, f - r0) : 0;
-    // the diagonal block's loads and this thread's row are issued together
-    T t4[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int idx = u * nt + tid;
+    // the diagonal block's loads and this thread's first 32 entries are issued together
+    for (int idx = tid; idx < nb * nb; idx += nt) {
         const int i = idx % nb, j = idx / nb;
-        t4[u] = (idx < nb * nb && i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
+        if (i >= j) D[i + j * kPanelLd] = F[(kb + i) + (int64_t)(kb + j) * f];
     }
     const bool row = tid < nr;
     T* Fr = F + (row ? r0 + tid : kb) + (int64_t)kb * f;
-    T x[kPanelNB];
+    T x[NB];
 #pragma unroll
-    for (int t = 0; t < kPanelNB; ++t) x[t] = (row && t < nb) ? Fr[(int64_t)t * f] : T(0);
+    for (int t = 0; t < NB; ++t) x[t] = (row && t < nb1) ? Fr[(int64_t)t * f] : T(0);
+    int32_t* st0 = blockIdx.x == 0 ? status : nullptr;
+    // factor the m x m diagonal block at D + o (o = (1 + kPanelLd) * column)
+    auto factor_diag = [&](int o, int m, int col, T* rd) {
+        __syncthreads();
+        for (int idx = tid; idx < m * m; idx += nt) {
+            const int i = idx % m, j = idx / m;
+            if (i >= j) Dd[i + j * kPanelLd] = D[o + i + j * kPanelLd];
+        }
+        __syncthreads();
+        if (tid < kWave) potrf32_reg<T>(Dd, m, col, st0, rd);
+        __syncthreads();
+        for (int idx = tid; idx < m * m; idx += nt) {
+            const int i = idx % m, j = idx / m;
+            if (i >= j) D[o + i + j * kPanelLd] = Dd[i + j * kPanelLd];
+        }
+        __syncthreads();
+    };
+    factor_diag(0, nb1, c0 + kb, s_rdiag);
+    if (nb2 > 0) {
+        // rows nb1 .. nb - 1 of the block against the first diagonal block
+        if (tid < nb2) {
+            T y[NB];
+            const int i = nb1 + tid;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int idx = u * nt + tid;
-        if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelLd] = t4[u];
+            for (int t = 0; t < NB; ++t) y[t] = D[i + t * kPanelLd];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                y[j] *= s_rdiag[j];
+#pragma unroll
+                for (int k = j + 1; k < NB; ++k) y[k] = fma(-y[j], D[k + j * kPanelLd], y[k]);
+            }
+#pragma unroll
+            for (int t = 0; t < NB; ++t) D[i + t * kPanelLd] = y[t];
+        }
+        __syncthreads();
+        // second diagonal block minus its rank-32 update
+        for (int idx = tid; idx < nb2 * nb2; idx += nt) {
+            const int i = nb1 + idx % nb2, j = nb1 + idx / nb2;
+            if (i >= j) {
+                T acc = D[i + j * kPanelLd];
+                for (int t = 0; t < NB; ++t) acc = fma(-D[i + t * kPanelLd], D[j + t * kPanelLd], acc);
+                D[i + j * kPanelLd] = acc;
+            }
+        }
+        factor_diag(nb1 * (1 + kPanelLd), nb2, c0 + kb + nb1, s_rdiag + NB);
     }
-    __syncthreads();
-    if (tid < kWave) potrf32_reg<T>(D, nb, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
-    __syncthreads();
     if (blockIdx.x == 0) {
-        T* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * kPanelNB * kPanelNB;
-        const int64_t ld = gridDim.x == 1 ? f : kPanelNB;
+        T* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * kPanel2 * kPanel2;
+        const int64_t ld = gridDim.x == 1 ? f : kPanel2;
         for (int idx = tid; idx < nb * nb; idx += nt) {
             const int i = idx % nb, j = idx / nb;
             if (i >= j) dst[i + j * ld] = D[i + j * kPanelLd];
         }
     }
     if (!row) return;
-    if (sizeof(T) == 8 && nb == kPanelNB) {
-        // one basic block; the barrier keeps each column's updates in that
-        // column (see potrf_reg_full)
+    // first 32 columns; every finished entry also updates the second 32
+    T y[NB];
 #pragma unroll
-        for (int j = 0; j < kPanelNB; ++j) {
+    for (int t = 0; t < NB; ++t) y[t] = (t < nb2) ? Fr[(int64_t)(NB + t) * f] : T(0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < nb1) {
             x[j] *= s_rdiag[j];
 #pragma unroll
-            for (int k = j + 1; k < kPanelNB; ++k) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {
+            for (int k = j + 1; k < NB; ++k) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
 #pragma unroll
-        for (int j = 0; j < kPanelNB; ++j) {
-            if (j < nb) {
-                x[j] *= s_rdiag[j];
-#pragma unroll
-                for (int k = j + 1; k < kPanelNB; ++k)
-                    if (k < nb) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
-            }
+            for (int k = 0; k < NB; ++k)
+                if (k < nb2) y[k] = fma(-x[j], D[(NB + k) + j * kPanelLd], y[k]);
         }
     }
 #pragma unroll
-    for (int t = 0; t < kPanelNB; ++t)
-        if (t < nb) Fr[(int64_t)t * f] = x[t];
+    for (int t = 0; t < NB; ++t)
+        if (t < nb1) Fr[(int64_t)t * f] = x[t];
+    if (nb2 == 0) return;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < nb2) {
+            y[j] *= s_rdiag[NB + j];
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k)
+                if (k < nb2) y[k] = fma(-y[j], D[(NB + k) + (NB + j) * kPanelLd], y[k]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+        if (t < nb2) Fr[(int64_t)(NB + t) * f] = y[t];
 }
 
 // Large fronts, step 3: trailing update C -= P P^T of the lower triangle
 // below the panel, one 64 x 64 tile per workgroup (grid: tile row, tile
 // column, front); only columns below col_end are updated (the rest of a
 // wide panel when the trailing part gets one wide update later).
-template <typename T>
+template <typename T, int PW>
 __global__ void __launch_bounds__(256)
 k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* __restrict__ dscr, int copy_d,
              int col_end) {
-    __shared__ T A[kPanelNB][64];  // panel column t of the tile's rows in A[t]
-    __shared__ T B[kPanelNB][64];
+    __shared__ T A[PW][64];  // panel column t of the tile's rows in A[t]
+    __shared__ T B[PW][64];
     const int s = P.lvl_big[list_begin + blockIdx.z];
     const int w = P.sn_start[s + 1] - P.sn_start[s];
     const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
     if (kb >= w) return;
     if (copy_d && blockIdx.x == 0 && blockIdx.y == 0) {
         // the factored diagonal block left by a multi-chunk panel launch
-        const int nb = min(kPanelNB, w - kb);
-        const T* src = dscr + (size_t)blockIdx.z * kPanelNB * kPanelNB;
+        const int nb = min(PW, w - kb);
+        const T* src = dscr + (size_t)blockIdx.z * PW * PW;
         T* F = arena + P.l_off[s];
         for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
             const int i = idx % nb, j = idx / nb;
-            if (i >= j) F[(kb + i) + (int64_t)(kb + j) * f] = src[i + j * kPanelNB];
+            if (i >= j) F[(kb + i) + (int64_t)(kb + j) * f] = src[i + j * PW];
         }
     }
     const int ti = blockIdx.x, tj = blockIdx.y;
     if (tj > ti) return;
-    const int nb = min(kPanelNB, w - kb);
+    const int nb = min(PW, w - kb);
     const int base = kb + nb;
     const int i0 = base + ti * 64, j0 = base + tj * 64;
     if (i0 >= f || j0 >= col_end) return;
@@ -868,7 +1012,7 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
     const int tid = threadIdx.x;
     const int cmax = min(f, col_end);
     {
-        constexpr int kPer = 64 * kPanelNB / 256;
+        constexpr int kPer = 64 * PW / 256;
         T ta[kPer], tb[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
@@ -886,19 +1030,20 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
         }
     }
     __syncthreads();
-    if constexpr (std::is_same<T, double>::value) {
+    {
         // four waves, one 32 x 32 quadrant each, 2 x 2 MFMA tiles of 16 x 16
+        using M = Mfma<T>;
         const int lane = tid % kWave, wv = tid / kWave;
         const int qi = wv % 2, qj = wv / 2;
         if (ti == tj && qj > qi) return;  // quadrant above the diagonal (wave-uniform)
         const int li = lane % 16, lk = lane / 16;
-        dbl4 c[2][2];
+        typename M::acc c[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) c[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < 2; ++b) c[a][b] = M::zero();
         for (int t = 0; t < nb; t += 4) {
-            double av[2], bv[2];
+            T av[2], bv[2];
 #pragma unroll
             for (int a = 0; a < 2; ++a) av[a] = A[t + lk][qi * 32 + a * 16 + li];
 #pragma unroll
@@ -906,7 +1051,7 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], c[a][b], 0, 0, 0);
+                for (int b = 0; b < 2; ++b) c[a][b] = M::step(av[a], bv[b], c[a][b]);
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -914,56 +1059,31 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = i0 + qi * 32 + a * 16 + 4 * r + lk, col = j0 + qj * 32 + b * 16 + li;
+                    const int row = i0 + qi * 32 + a * 16 + M::row(r, lk), col = j0 + qj * 32 + b * 16 + li;
                     if (row < f && col < cmax && row >= col) F[row + (int64_t)col * f] -= c[a][b][r];
                 }
-    } else {
-        const int tx = tid % 16, ty = tid / 16;
-        T acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-        for (int t = 0; t < nb; ++t) {
-            T av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = A[t][tx + 16 * a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = B[t][ty + 16 * b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-        }
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int col = j0 + ty + 16 * b;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int row = i0 + tx + 16 * a;
-                if (row < f && col < cmax && row >= col) F[row + (int64_t)col * f] -= acc[a][b];
-            }
-        }
     }
 }
 
-// Large FP64 fronts, wide trailing update: C -= P P^T on the lower triangle
+// Large fronts, wide trailing update: C -= P P^T on the lower triangle
 // of the columns from kb + kWideRank on, P the (up to) kWideRank factored
 // columns from kb (rank-kWideRank instead of rank-kPanelNB updates, so the
 // trailing matrix is read and written a quarter as often).  One 64 x 64
 // tile per workgroup of four waves, each a 32 x 32 quadrant of 16 x 16
-// v_mfma_f64_16x16x4f64 tiles.  P's rows come through LDS in 32-column
+// matrix-core tiles (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).  P's rows come through LDS in 32-column
 // chunks stored column by column (the sixteen lanes that read one MFMA
 // operand column touch sixteen consecutive doubles), the next chunk's loads
 // in flight during the current chunk's MFMAs; the tile's old values are
 // loaded first.  The lower-triangle tiles of a front are numbered column by
 // column and a launch takes the tiles [lin0, lin1) (a run of whole tile
 // columns).  Grid (lin1 - lin0, front), 256 threads.
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb, int nt, int lin0, int lin1) {
+k_big_update_wide(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int nt, int lin0, int lin1) {
+    using M = Mfma<T>;
     constexpr int kT = kWideTile, kThreads = 256, kMA = 2, KC = kPanelNB;
-    __shared__ double A[KC][kT];
-    __shared__ double B[KC][kT];
+    __shared__ T A[KC][kT];
+    __shared__ T B[KC][kT];
     const int s = P.lvl_big[list_begin + blockIdx.y];
     const int w = P.sn_start[s + 1] - P.sn_start[s];
     const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
@@ -983,7 +1103,7 @@ k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
     const int base = kb + kWideRank;
     const int i0 = base + ti * kT, j0 = base + tj * kT;
     if (i0 >= f) return;
-    double* F = arena + P.l_off[s];
+    T* F = arena + P.l_off[s];
     const int rank = min(kWideRank, w - kb);
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int qi = wv % 2, qj = wv / 2;  // rows qi * TILE / 2, columns qj * 32 of the tile
@@ -991,18 +1111,18 @@ k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
     const int li = lane % 16, lk = lane / 16;
     // the tile's old values, loaded first so that their latency overlaps
     // the MFMAs
-    double cv[kMA][2][4];
+    T cv[kMA][2][4];
 #pragma unroll
     for (int a = 0; a < kMA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = i0 + qi * (kT / 2) + a * 16 + 4 * r + lk, col = j0 + qj * 32 + b * 16 + li;
-                cv[a][b][r] = (!idle && row < f && col < f && row >= col) ? F[row + (int64_t)col * f] : 0.0;
+                const int row = i0 + qi * (kT / 2) + a * 16 + M::row(r, lk), col = j0 + qj * 32 + b * 16 + li;
+                cv[a][b][r] = (!idle && row < f && col < f && row >= col) ? F[row + (int64_t)col * f] : T(0);
             }
     constexpr int kPer = kT * KC / kThreads;
-    double ta[kPer], tb[kPer];
+    T ta[kPer], tb[kPer];
     auto load_chunk = [&](int t0) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
@@ -1010,16 +1130,16 @@ k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
             const int ii = idx % kT, t = idx / kT;
             const int gi = i0 + ii, gj = j0 + ii;
             const bool tin = t0 + t < rank;
-            ta[u] = (gi < f && tin) ? F[gi + (int64_t)(kb + t0 + t) * f] : 0.0;
-            tb[u] = (gj < f && tin) ? F[gj + (int64_t)(kb + t0 + t) * f] : 0.0;
+            ta[u] = (gi < f && tin) ? F[gi + (int64_t)(kb + t0 + t) * f] : T(0);
+            tb[u] = (gj < f && tin) ? F[gj + (int64_t)(kb + t0 + t) * f] : T(0);
         }
     };
     load_chunk(0);
-    dbl4 c[kMA][2];
+    typename M::acc c[kMA][2];
 #pragma unroll
     for (int a = 0; a < kMA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) c[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 2; ++b) c[a][b] = M::zero();
     for (int t0 = 0; t0 < rank; t0 += KC) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
@@ -1032,7 +1152,7 @@ k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
         const int kc = min(KC, rank - t0);
         if (!idle) {
             for (int t = 0; t < kc; t += 4) {
-                double av[kMA], bv[2];
+                T av[kMA], bv[2];
 #pragma unroll
                 for (int a = 0; a < kMA; ++a) av[a] = A[t + lk][qi * (kT / 2) + a * 16 + li];
 #pragma unroll
@@ -1041,7 +1161,7 @@ k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
                 for (int a = 0; a < kMA; ++a)
 #pragma unroll
                     for (int b = 0; b < 2; ++b)
-                        c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], c[a][b], 0, 0, 0);
+                        c[a][b] = M::step(av[a], bv[b], c[a][b]);
             }
         }
         __syncthreads();
@@ -1053,7 +1173,7 @@ k_big_update_wide(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = i0 + qi * (kT / 2) + a * 16 + 4 * r + lk, col = j0 + qj * 32 + b * 16 + li;
+                const int row = i0 + qi * (kT / 2) + a * 16 + M::row(r, lk), col = j0 + qj * 32 + b * 16 + li;
                 if (row < f && col < f && row >= col) F[row + (int64_t)col * f] = cv[a][b][r] - c[a][b][r];
             }
 }
@@ -2291,9 +2411,13 @@ __global__ void k_dense_correct(int n, int k, const double* __restrict__ z, cons
     x[i] -= acc;
 }
 
+// max |x| (NaN as +inf) into *bits: a grid-stride pass (few blocks, so
+// that few atomics meet at the one word), one atomic per block
+constexpr int kMaxabsBlocks = 128;
 __global__ void __launch_bounds__(256) k_maxabs(int n, const double* __restrict__ x, unsigned long long* bits) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double a = i < n ? nan_to_inf(fabs(x[i])) : 0.0;
+    double a = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        a = fmax(a, nan_to_inf(fabs(x[i])));
     a = wave_max(a);
     __shared__ double s_a[256 / kWave];
     if (threadIdx.x % kWave == 0) s_a[threadIdx.x / kWave] = a;
@@ -2313,6 +2437,17 @@ __global__ void k_zero_u64(unsigned long long* p, int count) {
 __global__ void k_axpy(int n, double alpha, const double* __restrict__ x, double* __restrict__ y) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] += alpha * x[i];
+}
+
+// y_i += x_i for the variables of the instances whose omega (as uint64 bits
+// of a nonnegative double) is still above tol: refinement steps of a batch
+// that leave converged instances as they are
+__global__ void k_masked_axpy(DevPlan P, const unsigned long long* __restrict__ omega_bits, double tol,
+                              const double* __restrict__ x, double* __restrict__ y) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const double om = __longlong_as_double((long long)omega_bits[P.inst_of_var[i]]);
+    if (!(om <= tol)) y[i] += x[i];
 }
 
 __global__ void k_copy(int n, const double* __restrict__ x, double* __restrict__ y) {
@@ -2600,6 +2735,8 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kFactorStaticLds);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_big_init<T>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_big_init_cols<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 4 * kInitColRows * (int)sizeof(T));
         attr_set = true;
     }
     // fronts above the LDS limit run on the side stream, concurrently with
@@ -2613,21 +2750,27 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         sb = side->stream;
     }
     if (L.big_count > 0) {
-        // assemble the tiles in LDS when a whole tile (64 columns x f rows) fits
-        const size_t tile_bytes = (size_t)kBigTile * L.big_maxf * sizeof(T);
-        const bool lds_tile = tile_bytes + 1024 <= (size_t)kLdsBytes;
-        hipLaunchKernelGGL(k_big_init<T>, dim3(L.tile_count), dim3(256), lds_tile ? tile_bytes : 0, sb, P, K, arena,
-                           L.tile_begin, scale, lds_tile ? L.big_maxf : 0);
-        // FP64 levels with large fronts: panels of kWideRank columns, each
+        if (L.big_maxf <= kInitColRows) {
+            // one wave per front column
+            hipLaunchKernelGGL(k_big_init_cols<T>, dim3(L.tile_count, kBigTile / 4), dim3(256),
+                               (size_t)4 * L.big_maxf * sizeof(T), sb, P, K, arena, L.tile_begin, scale, L.big_maxf);
+        } else {
+            // assemble the tiles in LDS when a whole tile (64 columns x f rows) fits
+            const size_t tile_bytes = (size_t)kBigTile * L.big_maxf * sizeof(T);
+            const bool lds_tile = tile_bytes + 1024 <= (size_t)kLdsBytes;
+            hipLaunchKernelGGL(k_big_init<T>, dim3(L.tile_count), dim3(256), lds_tile ? tile_bytes : 0, sb, P, K,
+                               arena, L.tile_begin, scale, lds_tile ? L.big_maxf : 0);
+        }
+        // levels with large fronts: panels of kWideRank columns, each
         // factored as kPanelNB-column panels whose updates stop at the wide
         // panel's end, then one rank-kWideRank update of the trailing part
-        const bool wide = sizeof(T) == 8 && L.big_maxf >= L.wide_front;
-        const int step = wide ? kWideRank : kPanelNB;
+        const bool wide = L.big_maxf >= L.wide_front;
+        const int step = wide ? kWideRank : kPanel2;
         for (int kw = 0; kw < L.big_maxw; kw += step) {
-            for (int kb = kw; kb < std::min(kw + step, L.big_maxw); kb += kPanelNB) {
+            for (int kb = kw; kb < std::min(kw + step, L.big_maxw); kb += kPanel2) {
                 const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
                 const int chunks = below > 0 ? (below + kPanelRows - 1) / kPanelRows : 1;
-                hipLaunchKernelGGL(k_big_panel<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena,
+                hipLaunchKernelGGL(k_big_panel2<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena,
                                    L.big_begin, kb, status, reinterpret_cast<T*>(dscr));
                 // in a wide panel the update stops at the panel's end (after
                 // its last panel it only reaches fronts whose own columns end
@@ -2636,19 +2779,19 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                 const int rest = L.big_maxf - kb - 1;  // upper bound of trailing rows
                 const int tiles = rest > 0 ? (rest + 63) / 64 : 0;
                 // columns: at most up to col_end (a front whose last panel is
-                // narrower starts its trailing part up to kPanelNB - 1 earlier)
+                // narrower starts its trailing part up to kPanel2 - 1 earlier)
                 const int tcols = wide ? std::min(tiles, (kw + step - kb) / 64 + 1) : tiles;
                 if (tiles > 0)
-                    hipLaunchKernelGGL(k_big_update<T>, dim3(tiles, tcols, L.big_count), dim3(256), 0, sb, P,
-                                       arena, L.big_begin, kb, reinterpret_cast<const T*>(dscr), chunks > 1 ? 1 : 0,
-                                       col_end);
+                    hipLaunchKernelGGL((k_big_update<T, kPanel2>), dim3(tiles, tcols, L.big_count), dim3(256), 0,
+                                       sb, P, arena, L.big_begin, kb, reinterpret_cast<const T*>(dscr),
+                                       chunks > 1 ? 1 : 0, col_end);
             }
             if (!wide) continue;
             const int rest = L.big_maxf - kw - step;  // upper bound of trailing rows
             if (rest <= 0) continue;
             const int nt = (rest + kWideTile - 1) / kWideTile, ntri = nt * (nt + 1) / 2;
-            hipLaunchKernelGGL(k_big_update_wide, dim3(ntri, L.big_count), dim3(256), 0, sb, P,
-                               reinterpret_cast<double*>(arena), L.big_begin, kw, nt, 0, ntri);
+            hipLaunchKernelGGL(k_big_update_wide<T>, dim3(ntri, L.big_count), dim3(256), 0, sb, P, arena, L.big_begin,
+                               kw, nt, 0, ntri);
         }
     }
     if (L.small_count > 0) {
@@ -2928,7 +3071,12 @@ void launch_dense_correct(int n, int k, const double* jd, const double* z, const
     hipLaunchKernelGGL(k_dense_correct, dim3(nblk(n)), dim3(256), 0, st, n, k, z, u, x);
 }
 void launch_maxabs(int n, const double* x, unsigned long long* bits, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(k_maxabs, dim3(nblk(n)), dim3(256), 0, st, n, x, bits);
+    if (n > 0) hipLaunchKernelGGL(k_maxabs, dim3(std::min(nblk(n), kMaxabsBlocks)), dim3(256), 0, st, n, x, bits);
+}
+
+void launch_masked_axpy(const DevPlan& P, const unsigned long long* omega_bits, double tol, const double* x,
+                        double* y, hipStream_t st) {
+    if (P.n > 0) hipLaunchKernelGGL(k_masked_axpy, dim3(nblk(P.n)), dim3(256), 0, st, P, omega_bits, tol, x, y);
 }
 
 void launch_axpy(int n, double alpha, const double* x, double* y, hipStream_t st) {

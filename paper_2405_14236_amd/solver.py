@@ -202,6 +202,26 @@ class Solver:
             L.check(st, "ckkt_solve")
         return out, si.as_dict()
 
+    def factorize_solve(self, w, g, h, sigma_x, sigma_s, rhs, out=None, refine=1, raise_on_error=True):
+        """ckkt_batch_factorize_solve: factorization and solve (LiftedKKT) in one
+        captured call with one host synchronization; returns (sol, info,
+        per-instance omega as a numpy array)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(rhs)
+        ninst = self._ninst()
+        om = np.zeros(max(ninst, 1))
+        si = L.SolveInfo()
+        st = self.lib.ckkt_batch_factorize_solve(self.h, _ptr(w), _ptr(g), _ptr(h), _ptr(sigma_x), _ptr(sigma_s),
+                                                 _ptr(rhs), _ptr(out), int(refine), om.ctypes.data_as(L.P_f64),
+                                                 ctypes.byref(si), _stream())
+        if raise_on_error:
+            L.check(st, "ckkt_batch_factorize_solve")
+        return out, si.as_dict(), om[:ninst]
+
+    def _ninst(self):
+        return self.info()["n_instances"]
+
     def solve_augmented(self, r1, r2, r3, r4, raise_on_error=True):
         """Newton step of K2 (ckkt_solve_augmented): returns (dx, ds, dy, dz, info).
         r3 / dy are used by HyKKT only (pass None for LiftedKKT)."""

@@ -5,6 +5,8 @@ system (every instance of a batch), certified by the CPU oracle on the
 returned solution.  The path each solve took (Richardson on the FP32
 factor, FP64 PCG preconditioned by it, FP64 refactorization) is reported.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -167,3 +169,31 @@ def test_hykkt_fp32_fallback_gets_its_own_refinement_budget():
     om = omega_of(p, "hykkt", z)
     print(info, "oracle omega", om)
     assert info["status"] == 0 and info["fallback"] == 2 and om <= 1e-10
+
+
+def test_fp32_failure_makes_next_systems_fp64_with_backoff():
+    """An FP32_IR handle on diagonals spanning 1e+-8: the first system gives
+    the FP32 factor up without PCG steps (floored pivots or a first backward
+    error above 0.1) and refactorizes in FP64; the next four systems are
+    factorized in FP64 from the start (fallback 8); the sixth tries FP32
+    again, fails again, and the next eight are FP64.  Every system meets the
+    gate by the oracle's certificate."""
+    p = workloads.network_flow(3000, seed=4)
+    print_case("fp32_history", n=p.n)
+    s = Solver(p, "lifted", "fp32_ir", tol=1e-8).bind(DEV)
+    w, g, h, _, _ = device_values(p, DEV, "lifted")
+    rng = np.random.default_rng(12)
+    b = torch.as_tensor(p.b, device=DEV)
+    seen = []
+    for k in range(14):
+        sx, ss = workloads.log_uniform(rng, p.n), workloads.log_uniform(rng, p.m)
+        s.factorize(w, g, h, torch.as_tensor(sx, device=DEV), torch.as_tensor(ss, device=DEV))
+        z, info = s.solve(b)
+        torch.cuda.synchronize()
+        seen.append(info["fallback"])
+        q = dataclasses.replace(p, sigma_x=sx, sigma_s=ss)
+        assert info["status"] == 0 and omega_of(q, "lifted", z.cpu().numpy()) <= 1e-8
+        if k == 0:
+            assert info["pcg_iters"] == 0
+    print(seen)
+    assert seen == [2] + [8] * 4 + [2] + [8] * 8

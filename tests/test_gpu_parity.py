@@ -329,7 +329,6 @@ def test_wide_panels_match_narrow_panels(monkeypatch, case, wide):
     else:
         p, opts = workloads.network_flow(4000, seed=4, sigma_range=(-2, 2)), {"lds_front_max": 64}
     print_case("wide_panels", case=case, n=p.n, wide=wide)
-    monkeypatch.setenv("CKKT_LOOKAHEAD", "0")
     out = {}
     for mode in (wide, "100000"):
         monkeypatch.setenv("CKKT_WIDE_FRONT", mode)
