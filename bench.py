@@ -44,7 +44,8 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 METRIC = "condensed-KKT solves/s at 1e-8 rel. residual: FP64 vs FP32+IR/batched/PCG"
 HEADLINE_NODES = 80_000
-PARTS = ("netflow80k", "seq80k", "batch512", "pde48", "netflow10k")
+PARTS = ("netflow80k", "seq80k", "batch512", "pde48", "netflow10k", "pde48factor")
+DEFAULT_PARTS = PARTS[:5]
 
 
 def parse():
@@ -53,8 +54,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--parts", default=",".join(PARTS),
-                    help="comma list of " + ", ".join(PARTS) + " (the headline always runs); 'none' for none")
+    ap.add_argument("--parts", default=",".join(DEFAULT_PARTS),
+                    help="comma list of " + ", ".join(PARTS) + " (the headline always runs); 'none' for none; "
+                         "pde48factor (not in the default) only factorizes and solves the first --systems systems "
+                         "of the PDE sequence in FP64 (a short run for counter collection)")
     ap.add_argument("--forms10k",
                     default="lifted_fp64,hykkt_fp64,lifted_fp64_inertia,hykkt_fp64_dualreg,lifted_fp64_k2,"
                             "hykkt_fp64_k2,lifted_fp64_dense4,lifted_fp32ir,hykkt_fp32ir",
@@ -382,6 +385,31 @@ def part_batch512(a, torch, workloads, Solver):
     return out
 
 
+def part_pde48factor(a, torch, workloads, Solver, device_values):
+    """FP64 factorization and solve of the first systems of the PDE
+    sequence only (matrix-core counters of the 48^3 factorization)."""
+    p = workloads.pde_control(a.side, seed=a.seed)
+    num = a.systems or 3
+    seq = workloads.ipm_sigma_sequence(p, 80, seed=a.seed)
+    rhs = torch.as_tensor(np.random.default_rng(a.seed + 11).standard_normal(p.n), device="cuda")
+    w, g, h, _, _ = device_values(p, "cuda", "lifted")
+    s = Solver(p, "lifted", "fp64").bind("cuda")
+    x = torch.empty_like(rhs)
+    per = []
+    for k in range(num):
+        sx, ss = (torch.as_tensor(v, device="cuda") for v in seq[k])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.factorize(w, g, h, sx, ss)
+        _, si = s.solve(rhs, x)
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - t0)
+    inf = s.info()
+    out = dict(ms_per_system=[round(1e3 * t, 2) for t in per], factor_flops=inf["factor_flops"], nnz_l=inf["nnz_l"])
+    log(f"[pde{a.side} factor only] {num} systems, {np.mean(per) * 1e3:.1f} ms each")
+    return out
+
+
 def part_pde48(a, torch, workloads, Solver, device_values):
     """PDE-constrained problem, IPM-like sequence: FP64 refactorization of
     every system versus PCG around a stale factor, with D = I and with the
@@ -538,6 +566,8 @@ def main():
         forms["seq80k"] = part_seq80k(a, p, torch, workloads, Solver, device_values)
     if "batch512" in parts:
         forms["batch512"] = part_batch512(a, torch, workloads, Solver)
+    if "pde48factor" in parts:
+        forms["pde48factor"] = part_pde48factor(a, torch, workloads, Solver, device_values)
     if "pde48" in parts:
         forms["pde48"] = part_pde48(a, torch, workloads, Solver, device_values)
     if "netflow10k" in parts:

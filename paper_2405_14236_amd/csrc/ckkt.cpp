@@ -339,7 +339,7 @@ void build_layout(ckkt_handle* h) {
     {
         int maxbig = 1;
         for (int l = 0; l < P.nlev; ++l) maxbig = std::max(maxbig, P.lvl_big_ptr[l + 1] - P.lvl_big_ptr[l]);
-        h->r_dscr = L.add((size_t)maxbig * kPanel2 * kPanel2 * sizeof(double));
+        h->r_dscr = L.add((size_t)maxbig * kPanelNB * kPanelNB * sizeof(double));
     }
     h->r_bits = L.add((P.ninst + 2) * sizeof(unsigned long long));
     h->r_dotpart = L.add(kDotBlocks * sizeof(double));

@@ -69,7 +69,6 @@ constexpr int kSweepMaxFront = (kLdsBytes - kSweepStaticLds) / 8 - 64 * 64;
 constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several workgroups per CU)
 constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
-constexpr int kPanel2 = 64;     // columns factored per panel launch (two kPanelNB panels)
 constexpr int kPanelRows = 256; // rows of the panel solved per workgroup
 constexpr int kPanelLd = 64;    // leading dimension of the panel's diagonal block in LDS (one wave's rows)
 // FP64 levels with fronts of at least kWideFront rows update their trailing
@@ -100,7 +99,7 @@ struct SideStream {
 constexpr int kMergeCompactFronts = 512;  // one launch for both LDS classes up to this many compact fronts
 
 // Returns false (and launches nothing) if a launch would exceed the LDS limit.
-// dscr: kPanel2^2 doubles per tiled front of the level (factored diagonal
+// dscr: kPanelNB^2 doubles per tiled front of the level (factored diagonal
 // blocks in transit between the panel and update launches).
 template <typename T>
 bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, T* arena,

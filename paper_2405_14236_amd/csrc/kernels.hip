@@ -516,7 +516,7 @@ k_factor_small(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, i
                 const int rc = c_rc[q], ld = c_ld[q];
                 const int* rel = P.relmap + c_rel[q];
                 const T* U = arena + c_uoff[q];
-                constexpr int kChunks = REG ? 2 : 1, kCols = 4;
+                constexpr int kChunks = REG ? 2 : 1, kCols = REG ? 8 : 4;
                 for (int b0 = wid; b0 < rc; b0 += kCols * nw) {
                     T u[kCols][kChunks];
                     int ra[kCols][kChunks], rb[kCols];
@@ -846,136 +846,85 @@ __device__ __forceinline__ void potrf32_reg(T* D, int nb, int col0, int32_t* sta
     }
 }
 
-// Large fronts, step 2 with two 32-column panels per launch (block column
-// kb of up to kPanel2 columns), grid (row chunk, front): every workgroup
-// stages the diagonal block (up to 64 x 64) and factors it blocked: one
-// wave factors its first 32 columns, the rows below them in the block are
-// solved one per thread, the second diagonal block is updated and then
-// factored by one wave (the same arithmetic in every workgroup).  Each
-// 32-column diagonal block is factored in a buffer of its own (Dd, leading
-// dimension kPanelLd: the register Cholesky stores every lane's row, the
-// rows past the block land in Dd's padding) and copied back.  Each thread
-// then solves its row of the chunk: the first 32 columns in registers,
-// right-looking, each finished entry also applied to the second 32
-// columns, which are then solved the same way.  The factored block goes
-// back in place (one chunk) or, with several chunks, chunk 0 leaves it in
-// dscr (another chunk may still be reading the original) for the
-// trailing-update launch to copy.
+// Large fronts, step 2 (per block column kb), grid (row chunk, front):
+// every workgroup stages the 32 x 32 diagonal block, one wave factors it
+// (the same arithmetic in every workgroup) while the workgroup's rows are
+// loaded, and each thread then solves its row of the chunk (kPanelRows
+// rows below the block) in registers, right-looking, with the factored
+// block read as LDS broadcasts.  With one chunk the factored block is
+// written back in place; with several, chunk 0 leaves it in dscr (another
+// chunk may still be reading the original block) and the trailing-update
+// launch copies it into the front.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_big_panel2(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status, T* __restrict__ dscr) {
-    static_assert(kPanelRows == 256 && kPanel2 == 2 * kPanelNB && kPanelLd == kPanel2, "layout of the block");
-    constexpr int NB = kPanelNB;
-    __shared__ T D[kPanelLd * kPanel2];
-    __shared__ T Dd[kPanelLd * kPanelNB];
-    __shared__ T s_rdiag[kPanel2];
+k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status, T* __restrict__ dscr) {
+    static_assert(kPanelRows == 256, "one row per thread");
+    __shared__ T D[kPanelLd * kPanelNB];
+    __shared__ T s_rdiag[kPanelNB];
     const int s = P.lvl_big[list_begin + blockIdx.y];
     const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
     const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
     if (kb >= w) return;
-    const int nb = min(kPanel2, w - kb);  // columns of this block
-    const int nb1 = min(NB, nb), nb2 = nb - nb1;
+    const int nb = min(kPanelNB, w - kb);
     T* F = arena + P.l_off[s];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int r0 = kb + nb + blockIdx.x * kPanelRows;
     if (blockIdx.x > 0 && r0 >= f) return;
     const int nr = r0 < f ? min(kPanelRows, f - r0) : 0;
-    // the diagonal block's loads and this thread's first 32 entries are issued together
-    for (int idx = tid; idx < nb * nb; idx += nt) {
+    // the diagonal block's loads and this thread's row are issued together
+    T t4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int idx = u * nt + tid;
         const int i = idx % nb, j = idx / nb;
-        if (i >= j) D[i + j * kPanelLd] = F[(kb + i) + (int64_t)(kb + j) * f];
+        t4[u] = (idx < nb * nb && i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
     }
     const bool row = tid < nr;
     T* Fr = F + (row ? r0 + tid : kb) + (int64_t)kb * f;
-    T x[NB];
+    T x[kPanelNB];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) x[t] = (row && t < nb1) ? Fr[(int64_t)t * f] : T(0);
-    int32_t* st0 = blockIdx.x == 0 ? status : nullptr;
-    // factor the m x m diagonal block at D + o (o = (1 + kPanelLd) * column)
-    auto factor_diag = [&](int o, int m, int col, T* rd) {
-        __syncthreads();
-        for (int idx = tid; idx < m * m; idx += nt) {
-            const int i = idx % m, j = idx / m;
-            if (i >= j) Dd[i + j * kPanelLd] = D[o + i + j * kPanelLd];
-        }
-        __syncthreads();
-        if (tid < kWave) potrf32_reg<T>(Dd, m, col, st0, rd);
-        __syncthreads();
-        for (int idx = tid; idx < m * m; idx += nt) {
-            const int i = idx % m, j = idx / m;
-            if (i >= j) D[o + i + j * kPanelLd] = Dd[i + j * kPanelLd];
-        }
-        __syncthreads();
-    };
-    factor_diag(0, nb1, c0 + kb, s_rdiag);
-    if (nb2 > 0) {
-        // rows nb1 .. nb - 1 of the block against the first diagonal block
-        if (tid < nb2) {
-            T y[NB];
-            const int i = nb1 + tid;
+    for (int t = 0; t < kPanelNB; ++t) x[t] = (row && t < nb) ? Fr[(int64_t)t * f] : T(0);
 #pragma unroll
-            for (int t = 0; t < NB; ++t) y[t] = D[i + t * kPanelLd];
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                y[j] *= s_rdiag[j];
-#pragma unroll
-                for (int k = j + 1; k < NB; ++k) y[k] = fma(-y[j], D[k + j * kPanelLd], y[k]);
-            }
-#pragma unroll
-            for (int t = 0; t < NB; ++t) D[i + t * kPanelLd] = y[t];
-        }
-        __syncthreads();
-        // second diagonal block minus its rank-32 update
-        for (int idx = tid; idx < nb2 * nb2; idx += nt) {
-            const int i = nb1 + idx % nb2, j = nb1 + idx / nb2;
-            if (i >= j) {
-                T acc = D[i + j * kPanelLd];
-                for (int t = 0; t < NB; ++t) acc = fma(-D[i + t * kPanelLd], D[j + t * kPanelLd], acc);
-                D[i + j * kPanelLd] = acc;
-            }
-        }
-        factor_diag(nb1 * (1 + kPanelLd), nb2, c0 + kb + nb1, s_rdiag + NB);
+    for (int u = 0; u < 4; ++u) {
+        const int idx = u * nt + tid;
+        if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelLd] = t4[u];
     }
+    __syncthreads();
+    if (tid < kWave) potrf32_reg<T>(D, nb, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
+    __syncthreads();
     if (blockIdx.x == 0) {
-        T* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * kPanel2 * kPanel2;
-        const int64_t ld = gridDim.x == 1 ? f : kPanel2;
+        T* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * kPanelNB * kPanelNB;
+        const int64_t ld = gridDim.x == 1 ? f : kPanelNB;
         for (int idx = tid; idx < nb * nb; idx += nt) {
             const int i = idx % nb, j = idx / nb;
             if (i >= j) dst[i + j * ld] = D[i + j * kPanelLd];
         }
     }
     if (!row) return;
-    // first 32 columns; every finished entry also updates the second 32
-    T y[NB];
+    if (sizeof(T) == 8 && nb == kPanelNB) {
+        // one basic block; the barrier keeps each column's updates in that
+        // column (see potrf_reg_full)
 #pragma unroll
-    for (int t = 0; t < NB; ++t) y[t] = (t < nb2) ? Fr[(int64_t)(NB + t) * f] : T(0);
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        if (j < nb1) {
+        for (int j = 0; j < kPanelNB; ++j) {
             x[j] *= s_rdiag[j];
 #pragma unroll
-            for (int k = j + 1; k < NB; ++k) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
+            for (int k = j + 1; k < kPanelNB; ++k) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
 #pragma unroll
-            for (int k = 0; k < NB; ++k)
-                if (k < nb2) y[k] = fma(-x[j], D[(NB + k) + j * kPanelLd], y[k]);
+        for (int j = 0; j < kPanelNB; ++j) {
+            if (j < nb) {
+                x[j] *= s_rdiag[j];
+#pragma unroll
+                for (int k = j + 1; k < kPanelNB; ++k)
+                    if (k < nb) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
+            }
         }
     }
 #pragma unroll
-    for (int t = 0; t < NB; ++t)
-        if (t < nb1) Fr[(int64_t)t * f] = x[t];
-    if (nb2 == 0) return;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        if (j < nb2) {
-            y[j] *= s_rdiag[NB + j];
-#pragma unroll
-            for (int k = j + 1; k < NB; ++k)
-                if (k < nb2) y[k] = fma(-y[j], D[(NB + k) + (NB + j) * kPanelLd], y[k]);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < NB; ++t)
-        if (t < nb2) Fr[(int64_t)(NB + t) * f] = y[t];
+    for (int t = 0; t < kPanelNB; ++t)
+        if (t < nb) Fr[(int64_t)t * f] = x[t];
 }
 
 // Large fronts, step 3: trailing update C -= P P^T of the lower triangle
@@ -1269,12 +1218,13 @@ __device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double
             const T* Li = L + i + (int64_t)kb * f;
             double acc = 0.0;
             int k = 0;
-            for (; k + 16 <= nb; k += 16) {
-                double l[16];
+            for (; k + 32 <= nb; k += 32) {
+                // 32 loads in flight, then their products in column order
+                T l[32];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) l[u] = (double)Li[(int64_t)(k + u) * f];
+                for (int u = 0; u < 32; ++u) l[u] = Li[(int64_t)(k + u) * f];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) acc = fma(l[u], v[kb + k + u], acc);
+                for (int u = 0; u < 32; ++u) acc = fma((double)l[u], v[kb + k + u], acc);
             }
             for (; k < nb; ++k) acc = fma((double)Li[(int64_t)k * f], v[kb + k], acc);
             v[i] -= acc;
@@ -1300,13 +1250,27 @@ __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double
             double part[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) part[c] = 0.0;
-            for (int i = r0 + lane; i < f; i += kWave) {
+            // two rows per step (16 loads in flight), summed in row order
+            int i = r0 + lane;
+            for (; i + kWave < f; i += 2 * kWave) {
+                const double z0 = z[i], z1 = z[i + kWave];
+                T l0[8], l1[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const bool cin = k0 + c < nb;
+                    l0[c] = cin ? L[i + (int64_t)(kb + k0 + c) * f] : T(0);
+                    l1[c] = cin ? L[i + kWave + (int64_t)(kb + k0 + c) * f] : T(0);
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) part[c] = fma((double)l0[c], z0, part[c]);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) part[c] = fma((double)l1[c], z1, part[c]);
+            }
+            if (i < f) {
                 const double zi = z[i];
-                double l[8];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) l[c] = (k0 + c < nb) ? (double)L[i + (int64_t)(kb + k0 + c) * f] : 0.0;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) part[c] = fma(l[c], zi, part[c]);
+                for (int c = 0; c < 8; ++c)
+                    part[c] = fma((k0 + c < nb) ? (double)L[i + (int64_t)(kb + k0 + c) * f] : 0.0, zi, part[c]);
             }
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
@@ -2765,12 +2729,12 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         // factored as kPanelNB-column panels whose updates stop at the wide
         // panel's end, then one rank-kWideRank update of the trailing part
         const bool wide = L.big_maxf >= L.wide_front;
-        const int step = wide ? kWideRank : kPanel2;
+        const int step = wide ? kWideRank : kPanelNB;
         for (int kw = 0; kw < L.big_maxw; kw += step) {
-            for (int kb = kw; kb < std::min(kw + step, L.big_maxw); kb += kPanel2) {
+            for (int kb = kw; kb < std::min(kw + step, L.big_maxw); kb += kPanelNB) {
                 const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
                 const int chunks = below > 0 ? (below + kPanelRows - 1) / kPanelRows : 1;
-                hipLaunchKernelGGL(k_big_panel2<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena,
+                hipLaunchKernelGGL(k_big_panel<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena,
                                    L.big_begin, kb, status, reinterpret_cast<T*>(dscr));
                 // in a wide panel the update stops at the panel's end (after
                 // its last panel it only reaches fronts whose own columns end
@@ -2779,10 +2743,10 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                 const int rest = L.big_maxf - kb - 1;  // upper bound of trailing rows
                 const int tiles = rest > 0 ? (rest + 63) / 64 : 0;
                 // columns: at most up to col_end (a front whose last panel is
-                // narrower starts its trailing part up to kPanel2 - 1 earlier)
+                // narrower starts its trailing part up to kPanelNB - 1 earlier)
                 const int tcols = wide ? std::min(tiles, (kw + step - kb) / 64 + 1) : tiles;
                 if (tiles > 0)
-                    hipLaunchKernelGGL((k_big_update<T, kPanel2>), dim3(tiles, tcols, L.big_count), dim3(256), 0,
+                    hipLaunchKernelGGL((k_big_update<T, kPanelNB>), dim3(tiles, tcols, L.big_count), dim3(256), 0,
                                        sb, P, arena, L.big_begin, kb, reinterpret_cast<const T*>(dscr),
                                        chunks > 1 ? 1 : 0, col_end);
             }
