@@ -597,6 +597,12 @@ bool build_sweep_sched(ckkt_handle* h) {
     while (lw < (int)h->levels.size() && h->levels[lw].all_maxf <= kSweepWaveFront) ++lw;
     S.wave_lvl = lw;
     S.wave_t1 = P.ns ? P.lvl_all_ptr[lw] : 0;
+    int lp = lw;
+    while (lp < (int)h->levels.size() && h->levels[lp].all_maxf <= 2 * kSweepWaveFront &&
+           h->levels[lp].all_maxw <= kSweepWaveFront)
+        ++lp;
+    S.pair_lvl = lp;
+    S.pair_t1 = P.ns ? P.lvl_all_ptr[lp] : 0;
     int maxf = 1, maxw = 1;
     for (int l = lw; l < (int)h->levels.size(); ++l) {
         maxf = std::max(maxf, h->levels[l].all_maxf);
@@ -619,10 +625,11 @@ void sweep_levels(ckkt_handle* h, hipStream_t st) {
     const T* arena = arena_of<T>(h);
     if (h->sched_ok) {
         // dependency-driven: every supernode (CKKT_DEP_SWEEPS=1), or only the
-        // levels above the single-wave class, the ones below swept level by
-        // level (CKKT_DEP_SWEEPS=2)
+        // levels above those of fronts with at most 128 rows and 64 columns,
+        // which are swept level by level by waves and wave pairs
+        // (CKKT_DEP_SWEEPS=2)
         const bool waves = !h->sched_hybrid;
-        const int lw = h->sched.wave_lvl;
+        const int lw = h->sched.pair_lvl;
         launch_sweep_prep(h->ctl, st);
         if (!waves)
             for (int l = 0; l < lw; ++l) launch_fwd_level<T>(h->dp, h->levels[l], arena, h->vperm, h->uvec, st, nullptr);
@@ -1893,13 +1900,13 @@ void factorize_solve_launches(ckkt_handle* h, bool d, int refine, const double* 
         factor_levels<float>(h, h->scale, s);
     }
     launch_rhs_max(h, b, h->plan.n, nullptr, 0, s);
-    apply_inverse_launches(h, b, x, false, s);
+    apply_inverse_launches(h, b, x, d, s);
     for (int k = 0; k <= refine; ++k) {
         launch_zero_u64(h->bits, ni + 1, s);
         launch_residual(h->dp, h->vals, h->d, x, nullptr, b, nullptr, res, nullptr, h->vm[0], h->vm[1], h->bits,
                         h->bits + ni, s);
         if (k == refine) break;
-        apply_inverse_launches(h, res, dx, false, s);
+        apply_inverse_launches(h, res, dx, d, s);
         launch_masked_axpy(h->dp, h->bits, h->opt.tol, dx, x, s);
     }
 }
@@ -1924,7 +1931,11 @@ ckkt_status ckkt_batch_factorize_solve(ckkt_handle* h, const double* w_val, cons
     h->vals = SysVals{w_val, g_val, h_val, sigma_x, sigma_s, 0.0};
     h->failed_column = -1;
     h->factored = false;
-    const bool d = h->precision == CKKT_FP64;
+    // FP32_IR: FP64 from the start while an earlier FP32 failure is recent
+    // (the policy of ckkt_factorize)
+    h->fp64_by_history = h->precision == CKKT_FP32_IR && h->fp32_skip > 0;
+    if (h->fp64_by_history) h->fp32_skip--;
+    const bool d = h->precision == CKKT_FP64 || h->fp64_by_history;
     h->fp64_factored = d;
     // the captured sequence holds the caller's pointers: captured again
     // when any of them (or the step count) differs from the last call's
@@ -1959,8 +1970,12 @@ ckkt_status ckkt_batch_factorize_solve(ckkt_handle* h, const double* w_val, cons
         info->pcg_iters = more.pcg_iters;
         info->fallback = more.fallback | 4;
         if (rc) return info->status = rc;
+        note_fp32_outcome(h, &more);
         if ((rc = read_residual(h, r, st)) != CKKT_OK) return info->status = rc;
+    } else {
+        note_fp32_outcome(h, info);  // the FP32 factor met the tolerance
     }
+    if (h->fp64_by_history) info->fallback |= 8;
     info->omega = r.omega;
     info->rho = r.rhsmax > 0 ? r.resmax / r.rhsmax : r.resmax;
     if (inst_omega) std::copy(r.per_inst.begin(), r.per_inst.end(), inst_omega);

@@ -126,6 +126,10 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
 // from ticket counters in level order and wait on per-supernode flags.
 struct SweepSched {
     int32_t wave_t1 = 0, wave_lvl = 0, ns = 0;
+    // hybrid schedule: levels below pair_lvl (fronts of order <= 128 and
+    // width <= 64) swept level by level, the workgroup workers from
+    // lvl_all[pair_t1] on
+    int32_t pair_t1 = 0, pair_lvl = 0;
     int32_t wave_grid = 1, group_grid = 1, ldd = 1;
     size_t group_lds = 0;
     unsigned long long ticks = 0;  // wait limit in wall-clock ticks

@@ -1595,6 +1595,128 @@ __device__ __forceinline__ void bwd_wave_front(const DevPlan& P, const T* __rest
     if (own) x_perm[c0 + lane] = ri;
 }
 
+// Forward step of one supernode with f <= 128 and w <= 64 by two waves
+// (threads 128 p .. 128 p + 127 of the workgroup, pair p): lane l of wave h
+// holds row 64 h + l of the panel in registers and gathers that row of the
+// front; wave 0 solves the diagonal block as fwd_wave_front does (its rows
+// below take their updates in the same pass) and leaves the solution in
+// y (LDS); wave 1 then applies it to rows 64 .. f - 1 in the same column
+// order.  Every thread of the workgroup calls it (valid == false: no work,
+// the barrier only).
+template <typename T>
+__device__ __forceinline__ void fwd_pair_front(const DevPlan& P, const T* __restrict__ arena, int s, bool valid,
+                                               double* __restrict__ v_perm, double* __restrict__ uvec, double* y) {
+    const int lane = threadIdx.x % kWave, h = (threadIdx.x / kWave) & 1;
+    int c0 = 0, w = 0, ro = 0, f = 0;
+    if (valid) {
+        c0 = P.sn_start[s];
+        w = P.sn_start[s + 1] - c0;
+        ro = P.sn_rowptr[s];
+        f = P.sn_rowptr[s + 1] - ro;
+    }
+    const int r = h * kWave + lane;
+    const bool act = r < f;
+    const T* L = arena + (valid ? P.l_off[s] : 0);
+    double lr[kWave];
+#pragma unroll
+    for (int k = 0; k < kWave; ++k) lr[k] = (k < w && act) ? (double)L[r + (int64_t)k * f] : 0.0;
+    const double rd = (h == 0 && lane < w) ? 1.0 / (double)L[lane + (int64_t)lane * f] : 0.0;
+    double vi = 0.0;
+    if (act) {
+        vi = r < w ? v_perm[c0 + r] : 0.0;
+        const int q1 = P.cb_ptr[ro + r + 1];
+        for (int q = P.cb_ptr[ro + r]; q < q1; ++q) vi += uvec[P.cb_src[q]];
+    }
+    if (h == 0) {
+#pragma unroll
+        for (int k = 0; k < kWave; ++k) {
+            if (k < w) {
+                const double yk = lane_bcast(vi, k) * lane_bcast(rd, k);
+                if (lane == k) vi = yk;
+                else if (lane > k) vi = fma(-lr[k], yk, vi);
+            }
+        }
+        if (lane < w) y[lane] = vi;
+    }
+    __syncthreads();
+    if (h == 1) {
+#pragma unroll
+        for (int k = 0; k < kWave; ++k)
+            if (k < w) vi = fma(-lr[k], y[k], vi);
+    }
+    if (r < w) v_perm[c0 + r] = vi;
+    else if (act) uvec[ro + r] = vi;
+}
+
+// Backward step of one supernode with f <= 128 and w <= 64 by two waves:
+// lane j of wave h holds rows 64 h .. 64 h + 63 of panel column j; wave 1
+// forms its part of the product with the solved rows below (rows 64 and
+// on) into part (LDS), wave 0 adds its own part (rows w .. 63) and
+// back-substitutes the diagonal block with lane broadcasts.
+template <typename T>
+__device__ __forceinline__ void bwd_pair_front(const DevPlan& P, const T* __restrict__ arena, int s, bool valid,
+                                               double* __restrict__ x_perm, double* part) {
+    const int lane = threadIdx.x % kWave, h = (threadIdx.x / kWave) & 1;
+    int c0 = 0, w = 0, ro = 0, f = 0;
+    if (valid) {
+        c0 = P.sn_start[s];
+        w = P.sn_start[s + 1] - c0;
+        ro = P.sn_rowptr[s];
+        f = P.sn_rowptr[s + 1] - ro;
+    }
+    const int r0 = h * kWave;
+    const bool own = lane < w;
+    const T* Lc = arena + (valid ? P.l_off[s] : 0) + (int64_t)lane * f + r0;
+    double lc[kWave];
+#pragma unroll
+    for (int k = 0; k < kWave; ++k) lc[k] = (own && r0 + k < f) ? (double)Lc[k] : 0.0;
+    const double rd = (h == 0 && own) ? 1.0 / (double)Lc[lane] : 0.0;
+    const int r = r0 + lane;
+    const double z = r < f ? x_perm[P.sn_rows[ro + r]] : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kWave; ++k)
+        if (r0 + k >= w && r0 + k < f) acc = fma(lc[k], lane_bcast(z, k), acc);
+    if (h == 1) part[lane] = acc;
+    __syncthreads();
+    if (h == 1 || !own) return;
+    if (f > kWave) acc += part[lane];
+    double ri = z - acc;
+#pragma unroll
+    for (int k = kWave - 1; k >= 0; --k) {
+        if (k < w) {
+            const double xk = lane_bcast(ri, k) * lane_bcast(rd, k);
+            if (lane == k) ri = xk;
+            else if (lane < k) ri = fma(-lc[k], xk, ri);
+        }
+    }
+    x_perm[c0 + lane] = ri;
+}
+
+// Level-synchronous sweeps for levels whose fronts have order <= 128 and
+// width <= 64 (the larger ones of the small-front levels): two supernodes
+// per 256-thread workgroup, two waves each.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fwd_pairs(DevPlan P, const T* __restrict__ arena, int list_begin, int count, double* __restrict__ v_perm,
+            double* __restrict__ uvec) {
+    __shared__ double y[2][kWave];
+    const int pr = threadIdx.x / (2 * kWave);
+    const int t = blockIdx.x * 2 + pr;
+    const bool valid = t < count;
+    fwd_pair_front(P, arena, valid ? P.lvl_all[list_begin + t] : 0, valid, v_perm, uvec, y[pr]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bwd_pairs(DevPlan P, const T* __restrict__ arena, int list_begin, int count, double* __restrict__ x_perm) {
+    __shared__ double part[2][kWave];
+    const int pr = threadIdx.x / (2 * kWave);
+    const int t = blockIdx.x * 2 + pr;
+    const bool valid = t < count;
+    bwd_pair_front(P, arena, valid ? P.lvl_all[list_begin + t] : 0, valid, x_perm, part[pr]);
+}
+
 // Level-synchronous sweeps for levels whose fronts all have order <= 64:
 // four supernodes per 256-thread workgroup, one per wave.
 template <typename T>
@@ -2798,6 +2920,11 @@ void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
                            L.all_count, v_perm, uvec);
         return;
     }
+    if (L.all_maxf <= 2 * kWave && L.all_maxw <= kWave) {
+        hipLaunchKernelGGL(k_fwd_pairs<T>, dim3((L.all_count + 1) / 2), dim3(256), 0, st, P, arena, L.all_begin,
+                           L.all_count, v_perm, uvec);
+        return;
+    }
     const int tf = L.sweep_tiled_f;
     const bool tiled = L.big_count > 0 && L.big_maxf >= tf;
     const int skip_f = tiled ? tf : INT_MAX;
@@ -2831,6 +2958,11 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
     if (L.all_count == 0) return;
     if (L.all_maxf <= kWave) {
         hipLaunchKernelGGL(k_bwd_waves<T>, dim3((L.all_count + 3) / 4), dim3(256), 0, st, P, arena, L.all_begin,
+                           L.all_count, x_perm);
+        return;
+    }
+    if (L.all_maxf <= 2 * kWave && L.all_maxw <= kWave) {
+        hipLaunchKernelGGL(k_bwd_pairs<T>, dim3((L.all_count + 1) / 2), dim3(256), 0, st, P, arena, L.all_begin,
                            L.all_count, x_perm);
         return;
     }
@@ -2898,18 +3030,20 @@ void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, dou
     if (waves && S.wave_t1 > 0)
         hipLaunchKernelGGL(k_fwd_wave<T>, dim3(S.wave_grid), dim3(kWave), 0, st, P, arena, 0, S.wave_t1, v_perm, uvec,
                            ctl, done, err, S.ticks);
-    if (S.ns > S.wave_t1)
-        hipLaunchKernelGGL(k_fwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, S.wave_t1, S.ns,
-                           S.wave_lvl, S.ldd, v_perm, uvec, ctl, done, err, S.ticks);
+    const int t0 = waves ? S.wave_t1 : S.pair_t1, lvl0 = waves ? S.wave_lvl : S.pair_lvl;
+    if (S.ns > t0)
+        hipLaunchKernelGGL(k_fwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, t0, S.ns, lvl0,
+                           S.ldd, v_perm, uvec, ctl, done, err, S.ticks);
 }
 
 template <typename T>
 void launch_bwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, double* x_perm, unsigned* ctl,
                       unsigned* done, int32_t* err, hipStream_t st, bool waves) {
     set_sweep_attrs<T>();
-    if (S.ns > S.wave_t1)
-        hipLaunchKernelGGL(k_bwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, S.wave_t1, S.ns,
-                           S.ldd, x_perm, ctl, done, err, S.ticks);
+    const int t0 = waves ? S.wave_t1 : S.pair_t1;
+    if (S.ns > t0)
+        hipLaunchKernelGGL(k_bwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, t0, S.ns, S.ldd,
+                           x_perm, ctl, done, err, S.ticks);
     if (waves && S.wave_t1 > 0)
         hipLaunchKernelGGL(k_bwd_wave<T>, dim3(S.wave_grid), dim3(kWave), 0, st, P, arena, 0, S.wave_t1, S.wave_lvl,
                            x_perm, ctl, done, err, S.ticks);
