@@ -360,8 +360,9 @@ ckkt_status ckkt_solve(ckkt_handle* h, const double* rhs, double* sol,
  * for ckkt_solve / ckkt_apply_inverse afterwards; the stale reference of
  * the learned preconditioner is not updated.  FP32_IR handles follow the
  * precision policy described at CKKT_FP32_IR (an FP64 factorization from
- * the start after a recent FP32 failure: info->fallback has 8 set; a
- * different precision uses its own captured sequence).  LiftedKKT handles without
+ * the start after a recent FP32 failure, with at most one device step:
+ * info->fallback has 8 set; a different precision uses its own captured
+ * sequence).  LiftedKKT handles without
  * split dense rows only (else CKKT_ERR_ARG).  Errors as ckkt_factorize and
  * ckkt_solve. */
 #define CKKT_MAX_DEVICE_REFINE 8

@@ -1937,6 +1937,10 @@ ckkt_status ckkt_batch_factorize_solve(ckkt_handle* h, const double* w_val, cons
     if (h->fp64_by_history) h->fp32_skip--;
     const bool d = h->precision == CKKT_FP64 || h->fp64_by_history;
     h->fp64_factored = d;
+    // an FP64 factor chosen by that policy takes at most one device step
+    // (the tolerance of an FP32_IR handle is the metric's 1e-8); the host
+    // refinement covers the rare rest
+    if (h->fp64_by_history) refine = std::min(refine, 1);
     // the captured sequence holds the caller's pointers: captured again
     // when any of them (or the step count) differs from the last call's
     const int slot = d ? 6 : 7;
