@@ -206,6 +206,26 @@ ckkt_status ckkt_plan_save(const ckkt_handle* h, void* buf, size_t bytes);
 ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* opt, ckkt_handle** out,
                            size_t* workspace_bytes);
 
+/* The same analysis with the symbolic factorization on the GPU (Sec. 1:
+ * the solver orders on the host and factors symbolically on the device).
+ * The host builds the pattern and the AMD ordering; kernels on `stream`
+ * compute the elimination tree (atomic-minimum climb of the pattern's
+ * entries to a fixed point), its postorder (Euler tour ranked by pointer
+ * jumping), the K lower CSC, the column counts of L (row-subtree counting
+ * with nearest common ancestors), the front row lists, the child-to-parent
+ * and K-to-front positions and the K slots of the assembly products; the
+ * host keeps the supernode amalgamation, the arena layout and the level
+ * schedule.  The plan equals ckkt_analyze's element by element.  The call
+ * allocates and frees device memory (about 8 bytes per K entry and per
+ * product, plus 4 * ceil(log2 n) bytes per variable for the ancestor
+ * table) and returns after `stream` is idle.  Same arguments and errors as
+ * ckkt_analyze (ckkt_batch_analyze for the batched form), plus
+ * CKKT_ERR_HIP when a HIP call fails. */
+ckkt_status ckkt_analyze_device(const ckkt_pattern* pat, const ckkt_options* opt, void* stream,
+                                ckkt_handle** out, size_t* workspace_bytes);
+ckkt_status ckkt_batch_analyze_device(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt,
+                                      void* stream, ckkt_handle** out, size_t* workspace_bytes);
+
 /* Batched analysis: `count` independent systems analysed as one
  * block-diagonal system.  Value arrays passed to ckkt_factorize and
  * ckkt_solve are the per-instance arrays concatenated in instance order

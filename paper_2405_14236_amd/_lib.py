@@ -70,6 +70,10 @@ SIGNATURES = [
     ("ckkt_analyze", c_int32, [POINTER(Pattern), POINTER(Options), POINTER(c_void_p), POINTER(c_size_t)]),
     ("ckkt_batch_analyze", c_int32, [c_int32, POINTER(Pattern), POINTER(Options), POINTER(c_void_p),
                                      POINTER(c_size_t)]),
+    ("ckkt_analyze_device", c_int32, [POINTER(Pattern), POINTER(Options), c_void_p, POINTER(c_void_p),
+                                      POINTER(c_size_t)]),
+    ("ckkt_batch_analyze_device", c_int32, [c_int32, POINTER(Pattern), POINTER(Options), c_void_p,
+                                            POINTER(c_void_p), POINTER(c_size_t)]),
     ("ckkt_plan_size", c_int32, [c_void_p, POINTER(c_size_t)]),
     ("ckkt_plan_save", c_int32, [c_void_p, c_void_p, c_size_t]),
     ("ckkt_plan_load", c_int32, [c_void_p, c_size_t, POINTER(Options), POINTER(c_void_p), POINTER(c_size_t)]),

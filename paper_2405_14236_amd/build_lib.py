@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-munsafe-fp-atomics"]
 HOST_ONLY = ["analysis.cpp", "ordering.cpp", "hostref.cpp"]
-HIP_SRCS = ["kernels.hip", "kernels_mlp.hip", "ckkt.cpp"]
+HIP_SRCS = ["kernels.hip", "kernels_mlp.hip", "symbolic.hip", "ckkt.cpp"]
 
 
 def _run(cmd):

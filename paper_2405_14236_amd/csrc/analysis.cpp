@@ -166,56 +166,14 @@ std::vector<int32_t> order_pattern(const PatternIn& p, int dense_row_min) {
     return amd_order(graph_of(n, pattern_keys(p, dense_mask(p, dense_row_min))));
 }
 
-std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
-    auto t0 = std::chrono::steady_clock::now();
-    std::string err = validate(p);
-    if (!err.empty()) return err;
-    const int32_t n = (int32_t)p.n;
-    P.n = n;
-    P.m_eq = (int32_t)p.m_eq;
-    P.m_ineq = (int32_t)p.m_ineq;
-    P.m = P.m_eq + P.m_ineq;
-    P.nnz_w = (int64_t)p.w_idx.size();
-    P.nnz_g = (int64_t)p.g_idx.size();
-    P.nnz_h = (int64_t)p.h_idx.size();
-    const int32_t m = P.m;
+namespace {
 
-    // ---- J = [G; H]; the value index of an entry equals its position
-    P.j_ptr.assign(m + 1, 0);
-    for (int32_t r = 0; r < P.m_eq; ++r) P.j_ptr[r + 1] = p.g_ptr[r + 1];
-    for (int32_t r = 0; r < P.m_ineq; ++r) P.j_ptr[P.m_eq + r + 1] = (int32_t)P.nnz_g + p.h_ptr[r + 1];
-    P.j_col.resize(P.nnz_g + P.nnz_h);
-    std::copy(p.g_idx.begin(), p.g_idx.end(), P.j_col.begin());
-    std::copy(p.h_idx.begin(), p.h_idx.end(), P.j_col.begin() + P.nnz_g);
-
-    // ---- dense rows: kept out of K (their J^T J block would fill it)
-    const std::vector<char> dense = dense_mask(p, o.dense_row_min);
-    P.dense_rows.clear();
-    for (int32_t r = 0; r < m; ++r)
-        if (dense[r]) P.dense_rows.push_back(r);
-
-    // ---- unique off-diagonal pairs (i > j) of W + J^T J, original numbering,
-    // and the symmetric graph for the ordering
-    const bool blocks = o.block_n && o.block_meq && o.block_mineq && o.block_n->size() > 1 &&
-                        o.block_meq->size() == o.block_n->size() && o.block_mineq->size() == o.block_n->size() &&
-                        o.block_n->back() == n && o.block_meq->back() == P.m_eq && o.block_mineq->back() == P.m_ineq;
-    const std::vector<uint64_t> keys = blocks ? block_pattern_keys(p, dense, o) : pattern_keys(p, dense);
-    std::vector<int32_t> perm0;
-    if (o.ordering == 1 || n <= 1) {
-        perm0.resize(n);
-        std::iota(perm0.begin(), perm0.end(), 0);
-    } else if (o.perm) {
-        perm0 = *o.perm;  // checked below like any ordering
-    } else {
-        perm0 = amd_order(graph_of(n, keys));
-    }
-    if ((int32_t)perm0.size() != n) return "internal: ordering is not a permutation";
-    std::vector<int32_t> ip0(n, -1);
-    for (int32_t k = 0; k < n; ++k) {
-        if (perm0[k] < 0 || perm0[k] >= n || ip0[perm0[k]] >= 0) return "internal: ordering is not a permutation";
-        ip0[perm0[k]] = k;
-    }
-
+// Elimination tree of the ordered pattern, its postorder (children in
+// increasing order), the K lower CSC in the postordered numbering and the
+// column counts of L, diagonal included.
+std::string order_host(int32_t n, const std::vector<uint64_t>& keys, const std::vector<int32_t>& perm0,
+                       const std::vector<int32_t>& ip0, Plan& P, std::vector<int32_t>& parent,
+                       std::vector<int64_t>& cnt) {
     // ---- elimination tree of the permuted matrix (Liu, with path compression)
     auto etree_of = [&](const std::vector<int32_t>& ip, std::vector<int32_t>& parent) {
         // lower-row lists in the new numbering: for row I, columns J < I
@@ -281,7 +239,6 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
     for (int32_t k = 0; k < n; ++k) P.perm[k] = perm0[post[k]];
     for (int32_t k = 0; k < n; ++k) P.iperm[P.perm[k]] = k;
 
-    std::vector<int32_t> parent;
     auto rows = etree_of(P.iperm, parent);
     const std::vector<int32_t>& rp = rows.first;   // lower rows: row i -> columns j < i
     const std::vector<int32_t>& rc = rows.second;
@@ -304,7 +261,7 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
 
     // ---- column counts via row subtrees: L(i, j) != 0 iff j on the path from
     //      some k in row i of K (k < i) up to i in the etree
-    std::vector<int64_t> cnt(n, 1);
+    cnt.assign(n, 1);
     {
         std::vector<int32_t> mk(n, -1);
         for (int32_t i = 0; i < n; ++i) {
@@ -320,6 +277,192 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
             }
         }
     }
+    return "";
+}
+
+// Row lists of the fronts (own columns, then the rows below in increasing
+// order; children before parents), the position of every child row inside
+// its parent front and of every K entry inside its own front.  sn_rowptr is
+// set from the column counts beforehand.
+std::string fronts_host(Plan& P, const std::vector<int64_t>& cnt, const std::vector<int32_t>& col2sn) {
+    const int32_t n = P.n, ns = P.ns;
+    const int64_t nnzk = P.kcolptr[n];
+    // ---- front row structures (children before parents)
+    std::vector<std::vector<int32_t>> R(ns);
+    {
+        std::vector<int32_t> stamp(n, -1);
+        for (int32_t s = 0; s < ns; ++s) {
+            int32_t c0 = P.sn_start[s], c1 = P.sn_start[s + 1];
+            auto& Rs = R[s];
+            for (int32_t j = c0; j < c1; ++j)
+                for (int32_t t = P.kcolptr[j]; t < P.kcolptr[j + 1]; ++t) {
+                    int32_t i = P.krow[t];
+                    if (i >= c1 && stamp[i] != s) { stamp[i] = s; Rs.push_back(i); }
+                }
+            for (int32_t q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q)
+                for (int32_t i : R[P.child_list[q]])
+                    if (i >= c1 && stamp[i] != s) { stamp[i] = s; Rs.push_back(i); }
+            std::sort(Rs.begin(), Rs.end());
+            if ((int64_t)Rs.size() != cnt[c1 - 1] - 1) return "internal: supernode structure mismatch";
+        }
+    }
+    P.sn_rows.resize(P.sn_rowptr[ns]);
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t c0 = P.sn_start[s], c1 = P.sn_start[s + 1];
+        int32_t o0 = P.sn_rowptr[s];
+        for (int32_t j = c0; j < c1; ++j) P.sn_rows[o0 + j - c0] = j;
+        std::copy(R[s].begin(), R[s].end(), P.sn_rows.begin() + o0 + (c1 - c0));
+    }
+    auto pos_in = [&](int32_t s, int32_t i) -> int32_t {
+        int32_t c0 = P.sn_start[s], c1 = P.sn_start[s + 1];
+        if (i >= c0 && i < c1) return i - c0;
+        auto it = std::lower_bound(R[s].begin(), R[s].end(), i);
+        if (it == R[s].end() || *it != i) return -1;
+        return (c1 - c0) + (int32_t)(it - R[s].begin());
+    };
+    P.relmap.assign(P.sn_rows.size(), -1);
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t ps = P.sn_parent[s];
+        if (ps < 0) continue;
+        int32_t w = P.sn_start[s + 1] - P.sn_start[s];
+        for (size_t a = 0; a < R[s].size(); ++a) {
+            int32_t q = pos_in(ps, R[s][a]);
+            if (q < 0) return "internal: child row missing from parent front";
+            P.relmap[P.sn_rowptr[s] + w + a] = q;
+        }
+    }
+    P.kmap.resize(nnzk);
+    for (int32_t j = 0; j < n; ++j) {
+        int32_t s = col2sn[j];
+        for (int32_t t = P.kcolptr[j]; t < P.kcolptr[j + 1]; ++t) {
+            int32_t q = pos_in(s, P.krow[t]);
+            if (q < 0) return "internal: K entry outside its front";
+            P.kmap[t] = q;
+        }
+    }
+    return "";
+}
+
+// K slot of every product J_ra J_rb (a <= b) of the kept rows, grouped by
+// slot with the products in row order inside a slot.
+std::string products_host(Plan& P, const std::vector<char>& dense, int threads) {
+    const int32_t n = P.n, m = P.m;
+    const int64_t nnzk = P.kcolptr[n];
+    auto slot_of = [&](int32_t I, int32_t J) -> int32_t {  // I >= J, new numbering
+        auto b = P.krow.begin() + P.kcolptr[J], e = P.krow.begin() + P.kcolptr[J + 1];
+        auto it = std::lower_bound(b, e, I);
+        if (it == e || *it != I) return -1;
+        return (int32_t)(it - P.krow.begin());
+    };
+    {
+        // products (a <= b) of every kept row, numbered row by row; their K
+        // slots are looked up on host threads, then a counting sort by slot
+        // keeps rows increasing inside a slot
+        std::vector<int64_t> poff(m + 1, 0);
+        for (int32_t r = 0; r < m; ++r) {
+            const int64_t q = dense[r] ? 0 : P.j_ptr[r + 1] - P.j_ptr[r];
+            poff[r + 1] = poff[r] + q * (q + 1) / 2;
+        }
+        std::vector<int32_t> pslot(poff[m]);
+        std::atomic<bool> missing{false};
+        auto lookup = [&](int32_t r0, int32_t r1) {
+            for (int32_t r = r0; r < r1; ++r) {
+                if (dense[r]) continue;
+                int64_t k = poff[r];
+                for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
+                    for (int32_t b = a; b < P.j_ptr[r + 1]; ++b) {
+                        const int32_t I = P.iperm[P.j_col[a]], J = P.iperm[P.j_col[b]];
+                        const int32_t sl = slot_of(std::max(I, J), std::min(I, J));
+                        if (sl < 0) missing = true;
+                        pslot[k++] = sl;
+                    }
+            }
+        };
+        const int nth = std::max(1, std::min(threads, m / 65536 + 1));
+        run_threads(nth, [&](int t) {
+            lookup((int32_t)((int64_t)m * t / nth), (int32_t)((int64_t)m * (t + 1) / nth));
+        });
+        if (missing) return "internal: J product missing from K";
+        P.prod_ptr.assign(nnzk + 1, 0);
+        for (int32_t sl : pslot) P.prod_ptr[sl + 1]++;
+        for (int64_t t = 0; t < nnzk; ++t) P.prod_ptr[t + 1] += P.prod_ptr[t];
+        P.prod_r.resize(pslot.size());
+        P.prod_a.resize(pslot.size());
+        P.prod_b.resize(pslot.size());
+        std::vector<int32_t> fill(P.prod_ptr.begin(), P.prod_ptr.end() - 1);
+        int64_t k = 0;
+        for (int32_t r = 0; r < m; ++r) {
+            if (dense[r]) continue;
+            for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
+                for (int32_t b = a; b < P.j_ptr[r + 1]; ++b) {
+                    const int32_t at = fill[pslot[k++]]++;
+                    P.prod_r[at] = r;
+                    P.prod_a[at] = a;
+                    P.prod_b[at] = b;
+                }
+        }
+    }
+    return "";
+}
+
+}  // namespace
+
+std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
+    auto t0 = std::chrono::steady_clock::now();
+    std::string err = validate(p);
+    if (!err.empty()) return err;
+    const int32_t n = (int32_t)p.n;
+    P.n = n;
+    P.m_eq = (int32_t)p.m_eq;
+    P.m_ineq = (int32_t)p.m_ineq;
+    P.m = P.m_eq + P.m_ineq;
+    P.nnz_w = (int64_t)p.w_idx.size();
+    P.nnz_g = (int64_t)p.g_idx.size();
+    P.nnz_h = (int64_t)p.h_idx.size();
+    const int32_t m = P.m;
+
+    // ---- J = [G; H]; the value index of an entry equals its position
+    P.j_ptr.assign(m + 1, 0);
+    for (int32_t r = 0; r < P.m_eq; ++r) P.j_ptr[r + 1] = p.g_ptr[r + 1];
+    for (int32_t r = 0; r < P.m_ineq; ++r) P.j_ptr[P.m_eq + r + 1] = (int32_t)P.nnz_g + p.h_ptr[r + 1];
+    P.j_col.resize(P.nnz_g + P.nnz_h);
+    std::copy(p.g_idx.begin(), p.g_idx.end(), P.j_col.begin());
+    std::copy(p.h_idx.begin(), p.h_idx.end(), P.j_col.begin() + P.nnz_g);
+
+    // ---- dense rows: kept out of K (their J^T J block would fill it)
+    const std::vector<char> dense = dense_mask(p, o.dense_row_min);
+    P.dense_rows.clear();
+    for (int32_t r = 0; r < m; ++r)
+        if (dense[r]) P.dense_rows.push_back(r);
+
+    // ---- unique off-diagonal pairs (i > j) of W + J^T J, original numbering,
+    // and the symmetric graph for the ordering
+    const bool blocks = o.block_n && o.block_meq && o.block_mineq && o.block_n->size() > 1 &&
+                        o.block_meq->size() == o.block_n->size() && o.block_mineq->size() == o.block_n->size() &&
+                        o.block_n->back() == n && o.block_meq->back() == P.m_eq && o.block_mineq->back() == P.m_ineq;
+    const std::vector<uint64_t> keys = blocks ? block_pattern_keys(p, dense, o) : pattern_keys(p, dense);
+    std::vector<int32_t> perm0;
+    if (o.ordering == 1 || n <= 1) {
+        perm0.resize(n);
+        std::iota(perm0.begin(), perm0.end(), 0);
+    } else if (o.perm) {
+        perm0 = *o.perm;  // checked below like any ordering
+    } else {
+        perm0 = amd_order(graph_of(n, keys));
+    }
+    if ((int32_t)perm0.size() != n) return "internal: ordering is not a permutation";
+    std::vector<int32_t> ip0(n, -1);
+    for (int32_t k = 0; k < n; ++k) {
+        if (perm0[k] < 0 || perm0[k] >= n || ip0[perm0[k]] >= 0) return "internal: ordering is not a permutation";
+        ip0[perm0[k]] = k;
+    }
+
+    std::vector<int32_t> parent;
+    std::vector<int64_t> cnt;
+    err = o.device ? o.device->order(n, keys, perm0, ip0, P, parent, cnt)
+                   : order_host(n, keys, perm0, ip0, P, parent, cnt);
+    if (!err.empty()) return err;
+    const int64_t nnzk = P.kcolptr[n];
     P.nnz_l = 0;
     P.flops = 0.0;
     for (int32_t j = 0; j < n; ++j) {
@@ -327,7 +470,6 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
         double eta = (double)(cnt[j] - 1);
         P.flops += eta * eta + 2.0 * eta + 1.0;
     }
-
     // ---- fundamental supernodes
     std::vector<int32_t> nchild(n, 0);
     for (int32_t j = 0; j < n; ++j)
@@ -402,62 +544,14 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
             if (P.sn_parent[s] >= 0) P.child_list[fill[P.sn_parent[s]]++] = s;
     }
 
-    // ---- front row structures (children before parents)
+    // ---- front row structures: sizes from the column counts
     P.sn_rowptr.assign(ns + 1, 0);
-    std::vector<std::vector<int32_t>> R(ns);
-    {
-        std::vector<int32_t> stamp(n, -1);
-        for (int32_t s = 0; s < ns; ++s) {
-            int32_t c0 = P.sn_start[s], c1 = P.sn_start[s + 1];
-            auto& Rs = R[s];
-            for (int32_t j = c0; j < c1; ++j)
-                for (int32_t t = P.kcolptr[j]; t < P.kcolptr[j + 1]; ++t) {
-                    int32_t i = P.krow[t];
-                    if (i >= c1 && stamp[i] != s) { stamp[i] = s; Rs.push_back(i); }
-                }
-            for (int32_t q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q)
-                for (int32_t i : R[P.child_list[q]])
-                    if (i >= c1 && stamp[i] != s) { stamp[i] = s; Rs.push_back(i); }
-            std::sort(Rs.begin(), Rs.end());
-            if ((int64_t)Rs.size() != cnt[c1 - 1] - 1) return "internal: supernode structure mismatch";
-            P.sn_rowptr[s + 1] = P.sn_rowptr[s] + (c1 - c0) + (int32_t)Rs.size();
-        }
-    }
-    P.sn_rows.resize(P.sn_rowptr[ns]);
     for (int32_t s = 0; s < ns; ++s) {
-        int32_t c0 = P.sn_start[s], c1 = P.sn_start[s + 1];
-        int32_t o0 = P.sn_rowptr[s];
-        for (int32_t j = c0; j < c1; ++j) P.sn_rows[o0 + j - c0] = j;
-        std::copy(R[s].begin(), R[s].end(), P.sn_rows.begin() + o0 + (c1 - c0));
+        const int32_t c0 = P.sn_start[s], c1 = P.sn_start[s + 1];
+        P.sn_rowptr[s + 1] = P.sn_rowptr[s] + (c1 - c0) + (int32_t)(cnt[c1 - 1] - 1);
     }
-    auto pos_in = [&](int32_t s, int32_t i) -> int32_t {
-        int32_t c0 = P.sn_start[s], c1 = P.sn_start[s + 1];
-        if (i >= c0 && i < c1) return i - c0;
-        auto it = std::lower_bound(R[s].begin(), R[s].end(), i);
-        if (it == R[s].end() || *it != i) return -1;
-        return (c1 - c0) + (int32_t)(it - R[s].begin());
-    };
-    P.relmap.assign(P.sn_rows.size(), -1);
-    for (int32_t s = 0; s < ns; ++s) {
-        int32_t ps = P.sn_parent[s];
-        if (ps < 0) continue;
-        int32_t w = P.sn_start[s + 1] - P.sn_start[s];
-        for (size_t a = 0; a < R[s].size(); ++a) {
-            int32_t q = pos_in(ps, R[s][a]);
-            if (q < 0) return "internal: child row missing from parent front";
-            P.relmap[P.sn_rowptr[s] + w + a] = q;
-        }
-    }
-    P.kmap.resize(nnzk);
-    for (int32_t j = 0; j < n; ++j) {
-        int32_t s = col2sn[j];
-        for (int32_t t = P.kcolptr[j]; t < P.kcolptr[j + 1]; ++t) {
-            int32_t q = pos_in(s, P.krow[t]);
-            if (q < 0) return "internal: K entry outside its front";
-            P.kmap[t] = q;
-        }
-    }
-
+    err = o.device ? o.device->fronts(P) : fronts_host(P, cnt, col2sn);
+    if (!err.empty()) return err;
     P.kcol.resize(nnzk);
     for (int32_t j = 0; j < n; ++j)
         for (int32_t t = P.kcolptr[j]; t < P.kcolptr[j + 1]; ++t) P.kcol[t] = j;
@@ -589,54 +683,8 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
             if (sl < 0) return "internal: W entry missing from K";
             P.k_wsrc[sl] = k;
         }
-    {
-        // products (a <= b) of every kept row, numbered row by row; their K
-        // slots are looked up on host threads, then a counting sort by slot
-        // keeps rows increasing inside a slot
-        std::vector<int64_t> poff(m + 1, 0);
-        for (int32_t r = 0; r < m; ++r) {
-            const int64_t q = dense[r] ? 0 : P.j_ptr[r + 1] - P.j_ptr[r];
-            poff[r + 1] = poff[r] + q * (q + 1) / 2;
-        }
-        std::vector<int32_t> pslot(poff[m]);
-        std::atomic<bool> missing{false};
-        auto lookup = [&](int32_t r0, int32_t r1) {
-            for (int32_t r = r0; r < r1; ++r) {
-                if (dense[r]) continue;
-                int64_t k = poff[r];
-                for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
-                    for (int32_t b = a; b < P.j_ptr[r + 1]; ++b) {
-                        const int32_t I = P.iperm[P.j_col[a]], J = P.iperm[P.j_col[b]];
-                        const int32_t sl = slot_of(std::max(I, J), std::min(I, J));
-                        if (sl < 0) missing = true;
-                        pslot[k++] = sl;
-                    }
-            }
-        };
-        const int nth = std::max(1, std::min(o.threads, m / 65536 + 1));
-        run_threads(nth, [&](int t) {
-            lookup((int32_t)((int64_t)m * t / nth), (int32_t)((int64_t)m * (t + 1) / nth));
-        });
-        if (missing) return "internal: J product missing from K";
-        P.prod_ptr.assign(nnzk + 1, 0);
-        for (int32_t sl : pslot) P.prod_ptr[sl + 1]++;
-        for (int64_t t = 0; t < nnzk; ++t) P.prod_ptr[t + 1] += P.prod_ptr[t];
-        P.prod_r.resize(pslot.size());
-        P.prod_a.resize(pslot.size());
-        P.prod_b.resize(pslot.size());
-        std::vector<int32_t> fill(P.prod_ptr.begin(), P.prod_ptr.end() - 1);
-        int64_t k = 0;
-        for (int32_t r = 0; r < m; ++r) {
-            if (dense[r]) continue;
-            for (int32_t a = P.j_ptr[r]; a < P.j_ptr[r + 1]; ++a)
-                for (int32_t b = a; b < P.j_ptr[r + 1]; ++b) {
-                    const int32_t at = fill[pslot[k++]]++;
-                    P.prod_r[at] = r;
-                    P.prod_a[at] = a;
-                    P.prod_b[at] = b;
-                }
-        }
-    }
+    err = o.device ? o.device->products(P, dense) : products_host(P, dense, o.threads);
+    if (!err.empty()) return err;
 
     // ---- unassembled operators (original numbering)
     {
@@ -658,9 +706,10 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
                 P.wf_col[fill[i]] = j; P.wf_vidx[fill[i]++] = k;
                 if (j != i) { P.wf_col[fill[j]] = i; P.wf_vidx[fill[j]++] = k; }
             }
+        std::vector<std::pair<int32_t, int32_t>> row;
         for (int32_t i = 0; i < n; ++i) {
             int32_t b = P.wf_ptr[i], e = P.wf_ptr[i + 1];
-            std::vector<std::pair<int32_t, int32_t>> row;
+            row.clear();
             for (int32_t t = b; t < e; ++t) row.push_back({P.wf_col[t], P.wf_vidx[t]});
             std::sort(row.begin(), row.end());
             for (int32_t t = b; t < e; ++t) { P.wf_col[t] = row[t - b].first; P.wf_vidx[t] = row[t - b].second; }

@@ -103,6 +103,30 @@ struct Plan {
     double analyze_seconds = 0.0;
 };
 
+// The symbolic factorization steps that can run on the device once the
+// ordering is fixed (the paper's solver orders on the host and factors
+// symbolically on the GPU, Sec. 1).  With AnalyzeOptions::device set,
+// analyze() hands these steps to it; each must produce exactly what the host
+// steps produce, element by element, so that both give the same plan.
+class SymbolicDevice {
+public:
+    virtual ~SymbolicDevice() = default;
+    // Elimination tree and its postorder (children in increasing order) of
+    // the pattern `keys` (pairs (i << 32) | j, i > j, original numbering)
+    // ordered by perm0 (ip0 its inverse): fills P.perm, P.iperm, P.kcolptr,
+    // P.krow, the etree `parent` (new numbering, -1 at roots) and the column
+    // counts of L with the diagonal.
+    virtual std::string order(int32_t n, const std::vector<uint64_t>& keys, const std::vector<int32_t>& perm0,
+                              const std::vector<int32_t>& ip0, Plan& P, std::vector<int32_t>& parent,
+                              std::vector<int64_t>& cnt) = 0;
+    // Fills P.sn_rows, P.relmap and P.kmap from P.sn_start, P.sn_rowptr and
+    // P.sn_parent (and the arrays order() produced).
+    virtual std::string fronts(Plan& P) = 0;
+    // Fills P.prod_ptr, P.prod_r, P.prod_a, P.prod_b: the K slots of the
+    // products J_ra J_rb (a <= b) of the rows not flagged in `dense`.
+    virtual std::string products(Plan& P, const std::vector<char>& dense) = 0;
+};
+
 struct AnalyzeOptions {
     int ordering = 0;      // 0 AMD, 1 natural
     int relax = 1;
@@ -116,6 +140,8 @@ struct AnalyzeOptions {
     const std::vector<int32_t>* block_n = nullptr;
     const std::vector<int32_t>* block_meq = nullptr;
     const std::vector<int32_t>* block_mineq = nullptr;
+    // symbolic factorization on the device (null: on the host)
+    SymbolicDevice* device = nullptr;
 };
 
 // AMD ordering of one pattern's K = W + J^T J graph (rows of J with at least

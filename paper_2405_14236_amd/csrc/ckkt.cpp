@@ -476,7 +476,10 @@ ckkt_status finish_plan(HandlePtr h, const AnalyzeOptions& ao, ckkt_handle** out
 ckkt_status finish_analyze(HandlePtr h, const AnalyzeOptions& ao, const PatternIn& pin, ckkt_handle** out,
                            size_t* workspace_bytes) {
     std::string err = analyze(pin, ao, h->plan);
-    if (!err.empty()) return err.rfind("internal", 0) == 0 ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
+    if (!err.empty()) {
+        if (err.rfind("device:", 0) == 0) return CKKT_ERR_HIP;  // a HIP call of the device analysis failed
+        return err.rfind("internal", 0) == 0 ? CKKT_ERR_ARG : CKKT_ERR_PATTERN;
+    }
     return finish_plan(std::move(h), ao, out, workspace_bytes);
 }
 
@@ -1494,7 +1497,7 @@ void ckkt_default_inertia(ckkt_inertia* ic) {
 }
 
 static ckkt_status ckkt_analyze_impl(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_handle** out,
-                         size_t* workspace_bytes) {
+                         size_t* workspace_bytes, SymbolicDevice* device = nullptr) {
 
     if (!out || !pattern_args_ok(pat)) return CKKT_ERR_ARG;
     *out = nullptr;
@@ -1509,7 +1512,8 @@ static ckkt_status ckkt_analyze_impl(const ckkt_pattern* pat, const ckkt_options
     h->precision = h->opt.precision;
     if (!pattern_ptrs_ok(pat)) return CKKT_ERR_PATTERN;
     PatternIn pin = copy_pattern(pat);
-    const AnalyzeOptions ao = analyze_options(h->opt);
+    AnalyzeOptions ao = analyze_options(h->opt);
+    ao.device = device;
     return finish_analyze(std::move(h), ao, pin, out, workspace_bytes);
 }
 
@@ -1518,6 +1522,16 @@ ckkt_status ckkt_analyze(const ckkt_pattern* pat, const ckkt_options* opt, ckkt_
     try {
         return ckkt_analyze_impl(pat, opt, out, workspace_bytes);
     } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
+}
+
+ckkt_status ckkt_analyze_device(const ckkt_pattern* pat, const ckkt_options* opt, void* stream, ckkt_handle** out,
+                                size_t* workspace_bytes) {
+    try {
+        std::unique_ptr<SymbolicDevice> dev = make_symbolic_device(static_cast<hipStream_t>(stream));
+        return ckkt_analyze_impl(pat, opt, out, workspace_bytes, dev.get());
+    } catch (...) {
         return CKKT_ERR_HOST_MEMORY;
     }
 }
@@ -1600,7 +1614,7 @@ ckkt_status ckkt_plan_load(const void* buf, size_t bytes, const ckkt_options* op
 }
 
 static ckkt_status ckkt_batch_analyze_impl(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt,
-                               ckkt_handle** out, size_t* workspace_bytes) {
+                               ckkt_handle** out, size_t* workspace_bytes, SymbolicDevice* device = nullptr) {
 
     if (!out || count <= 0 || !pats) return CKKT_ERR_ARG;
     *out = nullptr;
@@ -1681,6 +1695,7 @@ static ckkt_status ckkt_batch_analyze_impl(int32_t count, const ckkt_pattern* pa
             for (int32_t v : orders[i]) perm.push_back(v + P.inst_n[i]);
         ao.perm = &perm;
     }
+    ao.device = device;
     return finish_analyze(std::move(h), ao, u, out, workspace_bytes);
 }
 
@@ -1689,6 +1704,16 @@ ckkt_status ckkt_batch_analyze(int32_t count, const ckkt_pattern* pats, const ck
     try {
         return ckkt_batch_analyze_impl(count, pats, opt, out, workspace_bytes);
     } catch (...) {  // std::bad_alloc, or a host thread that could not be started
+        return CKKT_ERR_HOST_MEMORY;
+    }
+}
+
+ckkt_status ckkt_batch_analyze_device(int32_t count, const ckkt_pattern* pats, const ckkt_options* opt, void* stream,
+                                      ckkt_handle** out, size_t* workspace_bytes) {
+    try {
+        std::unique_ptr<SymbolicDevice> dev = make_symbolic_device(static_cast<hipStream_t>(stream));
+        return ckkt_batch_analyze_impl(count, pats, opt, out, workspace_bytes, dev.get());
+    } catch (...) {
         return CKKT_ERR_HOST_MEMORY;
     }
 }

@@ -3,8 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 
 namespace ckkt {
+
+class SymbolicDevice;
+// The symbolic factorization steps of the analysis run by kernels on
+// `stream` (symbolic.hip).
+std::unique_ptr<SymbolicDevice> make_symbolic_device(hipStream_t stream);
 
 // Plain pointers into the bound workspace; passed to kernels by value.
 struct DevPlan {

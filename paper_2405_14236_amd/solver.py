@@ -67,19 +67,27 @@ class Solver:
 
     ``formulation``: "lifted" (K_tau d_x = b) or "hykkt" (K1 through K_gamma + CG).
     ``precision``: "fp64" or "fp32_ir" (FP32 factor, FP64 refinement).
+    ``analysis``: "host" (ckkt_analyze) or "device" (ckkt_analyze_device: the
+    symbolic factorization runs on the current torch stream).
     """
 
     def __init__(self, prob, formulation="lifted", precision="fp64", *, batch: Optional[Sequence] = None,
-                 **opts):
+                 analysis="host", **opts):
         self.lib = L.load()
+        if analysis not in ("host", "device"):
+            raise ValueError("analysis must be 'host' or 'device'")
         self.formulation = {"lifted": L.LIFTED, "hykkt": L.HYKKT}[formulation]
         self.opts = options(precision=precision, **opts)
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
         if batch is None:
             pat, self._keep = _pattern(prob, self.formulation)
-            L.check(self.lib.ckkt_analyze(ctypes.byref(pat), ctypes.byref(self.opts), ctypes.byref(h),
-                                          ctypes.byref(ws)), "ckkt_analyze")
+            if analysis == "device":
+                L.check(self.lib.ckkt_analyze_device(ctypes.byref(pat), ctypes.byref(self.opts), _stream(),
+                                                     ctypes.byref(h), ctypes.byref(ws)), "ckkt_analyze_device")
+            else:
+                L.check(self.lib.ckkt_analyze(ctypes.byref(pat), ctypes.byref(self.opts), ctypes.byref(h),
+                                              ctypes.byref(ws)), "ckkt_analyze")
             self.n, self.m_eq, self.m_ineq = prob.n, prob.m_eq, prob.m_ineq
         else:
             pats, keep = [], []
@@ -88,8 +96,13 @@ class Solver:
                 pats.append(pat)
                 keep += k
             arr = (L.Pattern * len(pats))(*pats)
-            L.check(self.lib.ckkt_batch_analyze(len(pats), arr, ctypes.byref(self.opts), ctypes.byref(h),
-                                                ctypes.byref(ws)), "ckkt_batch_analyze")
+            if analysis == "device":
+                L.check(self.lib.ckkt_batch_analyze_device(len(pats), arr, ctypes.byref(self.opts), _stream(),
+                                                           ctypes.byref(h), ctypes.byref(ws)),
+                        "ckkt_batch_analyze_device")
+            else:
+                L.check(self.lib.ckkt_batch_analyze(len(pats), arr, ctypes.byref(self.opts), ctypes.byref(h),
+                                                    ctypes.byref(ws)), "ckkt_batch_analyze")
             self._keep = keep
             self.n = sum(p.n for p in batch)
             self.m_eq = sum(p.m_eq for p in batch)
