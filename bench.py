@@ -44,8 +44,8 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 METRIC = "condensed-KKT solves/s at 1e-8 rel. residual: FP64 vs FP32+IR/batched/PCG"
 HEADLINE_NODES = 80_000
-PARTS = ("netflow80k", "seq80k", "batch512", "pde48", "netflow10k", "pde48factor")
-DEFAULT_PARTS = PARTS[:5]
+PARTS = ("netflow80k", "seq80k", "batch512", "pde48", "netflow10k", "analysis", "pde48factor")
+DEFAULT_PARTS = PARTS[:6]
 
 
 def parse():
@@ -385,6 +385,38 @@ def part_batch512(a, torch, workloads, Solver):
     return out
 
 
+def part_analysis(a, p, torch, workloads, Solver):
+    """Analysis time with the symbolic factorization on the host
+    (ckkt_analyze) and on the GPU (ckkt_analyze_device), both after the same
+    host ordering: the 528,000-variable network flow, the 48^3 PDE-control
+    pattern and the 512-instance batch.  The two plans are equal byte for
+    byte (GPU tests); order_s is the host part up to the ordering, symbolic_s
+    the part the GPU takes over."""
+    Solver(workloads.tiny_grid(0), "lifted", analysis="device")  # first device use outside the timing
+    cases = [("netflow80k", lambda mode: Solver(p, "lifted", analysis=mode))]
+    pde = workloads.pde_control(a.side)
+    cases.append((f"pde{a.side}", lambda mode: Solver(pde, "lifted", analysis=mode)))
+    probs = workloads.batch_network_flow(a.instances, seed=a.seed)
+    cases.append((f"batch{a.instances}", lambda mode: Solver(None, "lifted", batch=probs, analysis=mode)))
+    out = {}
+    for name, make in cases:
+        row = {}
+        for mode in ("host", "device"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = make(mode)
+            wall = time.perf_counter() - t0
+            inf = s.info()
+            row[mode] = {"wall_s": wall, "analyze_s": inf["analyze_seconds"], "order_s": inf["order_seconds"],
+                         "symbolic_s": inf["symbolic_seconds"]}
+            del s
+        row["symbolic_speedup"] = row["host"]["symbolic_s"] / max(row["device"]["symbolic_s"], 1e-9)
+        row["analysis_speedup"] = row["host"]["analyze_s"] / max(row["device"]["analyze_s"], 1e-9)
+        out[name] = row
+        print(f"[analysis] {name}: {row}", file=sys.stderr, flush=True)
+    return out
+
+
 def part_pde48factor(a, torch, workloads, Solver, device_values):
     """FP64 factorization and solve of the first systems of the PDE
     sequence only (matrix-core counters of the 48^3 factorization)."""
@@ -572,6 +604,8 @@ def main():
         forms["pde48"] = part_pde48(a, torch, workloads, Solver, device_values)
     if "netflow10k" in parts:
         forms["netflow10k"] = part_netflow10k(a, torch, workloads, Solver, device_values)
+    if "analysis" in parts:
+        forms["analysis"] = part_analysis(a, p, torch, workloads, Solver)
 
     cpu = None if a.no_cpu_baseline else cpu_baseline(p, sig[a.warmup:], a.cpu_seconds)
     line = {

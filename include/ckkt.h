@@ -153,6 +153,9 @@ typedef struct {
     int32_t n_dense_rows;     /* rows split off by opt.dense_row_min */
     int32_t n_instances;      /* instances of a batch (1 for a single pattern) */
     int32_t pad;
+    double  order_seconds;    /* part of analyze_seconds up to the ordering (pattern, AMD) */
+    double  symbolic_seconds; /* part spent in the steps ckkt_analyze_device runs on the GPU
+                                 (0 for a plan from ckkt_plan_load) */
 } ckkt_info;
 
 typedef struct {

@@ -44,7 +44,8 @@ class Info(ctypes.Structure):
                 ("assembly_products", c_double), ("n_supernodes", c_int32), ("n_levels", c_int32),
                 ("max_front", c_int32), ("n_big_fronts", c_int32), ("workspace_bytes", c_int64),
                 ("analyze_seconds", c_double), ("failed_column", c_int32), ("n_dense_rows", c_int32),
-                ("n_instances", c_int32), ("pad", c_int32)]
+                ("n_instances", c_int32), ("pad", c_int32), ("order_seconds", c_double),
+                ("symbolic_seconds", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}

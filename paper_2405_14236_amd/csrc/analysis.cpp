@@ -457,10 +457,17 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
         ip0[perm0[k]] = k;
     }
 
+    auto since = [](std::chrono::steady_clock::time_point a) {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+    };
+    P.order_seconds = since(t0);
+    P.symbolic_seconds = 0.0;
     std::vector<int32_t> parent;
     std::vector<int64_t> cnt;
+    auto ts = std::chrono::steady_clock::now();
     err = o.device ? o.device->order(n, keys, perm0, ip0, P, parent, cnt)
                    : order_host(n, keys, perm0, ip0, P, parent, cnt);
+    P.symbolic_seconds += since(ts);
     if (!err.empty()) return err;
     const int64_t nnzk = P.kcolptr[n];
     P.nnz_l = 0;
@@ -550,7 +557,9 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
         const int32_t c0 = P.sn_start[s], c1 = P.sn_start[s + 1];
         P.sn_rowptr[s + 1] = P.sn_rowptr[s] + (c1 - c0) + (int32_t)(cnt[c1 - 1] - 1);
     }
+    ts = std::chrono::steady_clock::now();
     err = o.device ? o.device->fronts(P) : fronts_host(P, cnt, col2sn);
+    P.symbolic_seconds += since(ts);
     if (!err.empty()) return err;
     P.kcol.resize(nnzk);
     for (int32_t j = 0; j < n; ++j)
@@ -683,7 +692,9 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
             if (sl < 0) return "internal: W entry missing from K";
             P.k_wsrc[sl] = k;
         }
+    ts = std::chrono::steady_clock::now();
     err = o.device ? o.device->products(P, dense) : products_host(P, dense, o.threads);
+    P.symbolic_seconds += since(ts);
     if (!err.empty()) return err;
 
     // ---- unassembled operators (original numbering)

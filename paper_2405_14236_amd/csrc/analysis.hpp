@@ -101,6 +101,10 @@ struct Plan {
     std::vector<int32_t> inst_of_eqrow; // m_eq
 
     double analyze_seconds = 0.0;
+    // not serialized: the part of analyze_seconds spent up to the ordering
+    // (pattern keys and AMD), and in the symbolic factorization steps that
+    // SymbolicDevice can take over (0 for a loaded plan)
+    double order_seconds = 0.0, symbolic_seconds = 0.0;
 };
 
 // The symbolic factorization steps that can run on the device once the

@@ -2438,6 +2438,8 @@ ckkt_status ckkt_get_info(const ckkt_handle* h, ckkt_info* info) {
     info->n_big_fronts = P.n_big;
     info->workspace_bytes = (int64_t)h->lay.total;
     info->analyze_seconds = P.analyze_seconds;
+    info->order_seconds = P.order_seconds;
+    info->symbolic_seconds = P.symbolic_seconds;
     info->n_instances = P.ninst;
     info->failed_column = h->failed_column;
     info->n_dense_rows = (int32_t)h->plan.dense_rows.size();
