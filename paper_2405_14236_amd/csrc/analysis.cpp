@@ -709,22 +709,16 @@ std::string analyze(const PatternIn& p, const AnalyzeOptions& o, Plan& P) {
         P.wf_col.resize(P.wf_ptr[n]);
         P.wf_vidx.resize(P.wf_ptr[n]);
         std::vector<int32_t> fill(P.wf_ptr.begin(), P.wf_ptr.end() - 1);
-        // upper part of row j (entries (i, j), i > j) first come from rows i in
-        // increasing order; write lower then upper and sort each row
+        // Row j of the full W: its own lower entries (columns <= j, strictly
+        // increasing, as validate() checks) are written when row j is
+        // visited, then the entries (i, j) of the rows i > j in increasing i:
+        // every row comes out sorted without a sort.
         for (int32_t i = 0; i < n; ++i)
             for (int32_t k = p.w_ptr[i]; k < p.w_ptr[i + 1]; ++k) {
                 int32_t j = p.w_idx[k];
                 P.wf_col[fill[i]] = j; P.wf_vidx[fill[i]++] = k;
                 if (j != i) { P.wf_col[fill[j]] = i; P.wf_vidx[fill[j]++] = k; }
             }
-        std::vector<std::pair<int32_t, int32_t>> row;
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t b = P.wf_ptr[i], e = P.wf_ptr[i + 1];
-            row.clear();
-            for (int32_t t = b; t < e; ++t) row.push_back({P.wf_col[t], P.wf_vidx[t]});
-            std::sort(row.begin(), row.end());
-            for (int32_t t = b; t < e; ++t) { P.wf_col[t] = row[t - b].first; P.wf_vidx[t] = row[t - b].second; }
-        }
     }
     {
         P.jt_ptr.assign(n + 1, 0);
