@@ -62,6 +62,14 @@ __device__ __forceinline__ float bcast<float>(float x, int k) {
 // Per-block maxima of (ratio, |res|) pushed with one atomic each when the
 // whole block belongs to one instance, else one atomic per element.  The
 // block must be 256 threads and every thread must call it.
+// atomicMax on the bits of a non-negative double, skipped when the word
+// already holds at least v (most blocks find a larger maximum there, so the
+// atomics on one address stay few)
+__device__ __forceinline__ void max_bits(unsigned long long* p, double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) atomicMax(p, b);
+}
+
 __device__ void block_max_push(bool active, int inst, double ratio, double num,
                                unsigned long long* omega_bits, unsigned long long* resmax_bits) {
     __shared__ int s_inst0, s_mixed;
@@ -75,8 +83,8 @@ __device__ void block_max_push(bool active, int inst, double ratio, double num,
     num = nan_to_inf(num);
     if (s_mixed) {
         if (active) {
-            atomicMax(omega_bits + inst, (unsigned long long)__double_as_longlong(ratio));
-            atomicMax(resmax_bits, (unsigned long long)__double_as_longlong(num));
+            max_bits(omega_bits + inst, ratio);
+            max_bits(resmax_bits, num);
         }
         return;
     }
@@ -87,8 +95,8 @@ __device__ void block_max_push(bool active, int inst, double ratio, double num,
     if (threadIdx.x == 0 && s_inst0 >= 0) {
         double r = 0.0, nm = 0.0;
         for (int t = 0; t < (int)(blockDim.x / kWave); ++t) { r = fmax(r, s_r[t]); nm = fmax(nm, s_n[t]); }
-        atomicMax(omega_bits + s_inst0, (unsigned long long)__double_as_longlong(r));
-        atomicMax(resmax_bits, (unsigned long long)__double_as_longlong(nm));
+        max_bits(omega_bits + s_inst0, r);
+        max_bits(resmax_bits, nm);
     }
 }
 
@@ -1533,7 +1541,7 @@ k_bwd_tiled_step(DevPlan P, const T* __restrict__ arena, int list_begin, int min
 // overlap), gathers row i of the front, and one pass over the columns
 // solves the diagonal block and forms the update vector (lane k broadcasts
 // y_k, rows below subtract their multiple).
-template <typename T>
+template <typename T, int MW>
 __device__ __forceinline__ void fwd_wave_front(const DevPlan& P, const T* __restrict__ arena, int s,
                                                double* __restrict__ v_perm, double* __restrict__ uvec) {
     const int lane = threadIdx.x % kWave;
@@ -1541,9 +1549,9 @@ __device__ __forceinline__ void fwd_wave_front(const DevPlan& P, const T* __rest
     const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
     const T* L = arena + P.l_off[s];
     const bool act = lane < f;
-    double lr[kWave];
+    double lr[MW];
 #pragma unroll
-    for (int k = 0; k < kWave; ++k) lr[k] = (k < w && act) ? (double)L[lane + (int64_t)k * f] : 0.0;
+    for (int k = 0; k < MW; ++k) lr[k] = (k < w && act) ? (double)L[lane + (int64_t)k * f] : 0.0;
     const double rd = lane < w ? 1.0 / (double)L[lane + (int64_t)lane * f] : 0.0;
     double vi = 0.0;
     if (act) {
@@ -1552,7 +1560,7 @@ __device__ __forceinline__ void fwd_wave_front(const DevPlan& P, const T* __rest
         for (int q = P.cb_ptr[ro + lane]; q < q1; ++q) vi += uvec[P.cb_src[q]];
     }
 #pragma unroll
-    for (int k = 0; k < kWave; ++k) {
+    for (int k = 0; k < MW; ++k) {
         if (k < w) {
             const double yk = lane_bcast(vi, k) * lane_bcast(rd, k);
             if (lane == k) vi = yk;
@@ -1566,7 +1574,7 @@ __device__ __forceinline__ void fwd_wave_front(const DevPlan& P, const T* __rest
 // Backward step of one supernode with f <= 64 by one wave: lane j holds
 // column j of the panel, forms the product with the solved rows below and
 // back-substitutes the diagonal block with lane broadcasts.
-template <typename T>
+template <typename T, int MF>
 __device__ __forceinline__ void bwd_wave_front(const DevPlan& P, const T* __restrict__ arena, int s,
                                                double* __restrict__ x_perm) {
     const int lane = threadIdx.x % kWave;
@@ -1574,18 +1582,18 @@ __device__ __forceinline__ void bwd_wave_front(const DevPlan& P, const T* __rest
     const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
     const T* Lc = arena + P.l_off[s] + (int64_t)lane * f;
     const bool act = lane < f, own = lane < w;
-    double lc[kWave];
+    double lc[MF];
 #pragma unroll
-    for (int k = 0; k < kWave; ++k) lc[k] = (k < f && own) ? (double)Lc[k] : 0.0;
+    for (int k = 0; k < MF; ++k) lc[k] = (k < f && own) ? (double)Lc[k] : 0.0;
     const double rd = own ? 1.0 / (double)Lc[lane] : 0.0;
     const double z = act ? x_perm[P.sn_rows[ro + lane]] : 0.0;
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < kWave; ++k)
+    for (int k = 0; k < MF; ++k)
         if (k >= w && k < f) acc = fma(lc[k], lane_bcast(z, k), acc);
     double ri = own ? z - acc : 0.0;
 #pragma unroll
-    for (int k = kWave - 1; k >= 0; --k) {
+    for (int k = MF - 1; k >= 0; --k) {
         if (k < w) {
             const double xk = lane_bcast(ri, k) * lane_bcast(rd, k);
             if (lane == k) ri = xk;
@@ -1603,7 +1611,7 @@ __device__ __forceinline__ void bwd_wave_front(const DevPlan& P, const T* __rest
 // y (LDS); wave 1 then applies it to rows 64 .. f - 1 in the same column
 // order.  Every thread of the workgroup calls it (valid == false: no work,
 // the barrier only).
-template <typename T>
+template <typename T, int MW>
 __device__ __forceinline__ void fwd_pair_front(const DevPlan& P, const T* __restrict__ arena, int s, bool valid,
                                                double* __restrict__ v_perm, double* __restrict__ uvec, double* y) {
     const int lane = threadIdx.x % kWave, h = (threadIdx.x / kWave) & 1;
@@ -1617,9 +1625,9 @@ __device__ __forceinline__ void fwd_pair_front(const DevPlan& P, const T* __rest
     const int r = h * kWave + lane;
     const bool act = r < f;
     const T* L = arena + (valid ? P.l_off[s] : 0);
-    double lr[kWave];
+    double lr[MW];
 #pragma unroll
-    for (int k = 0; k < kWave; ++k) lr[k] = (k < w && act) ? (double)L[r + (int64_t)k * f] : 0.0;
+    for (int k = 0; k < MW; ++k) lr[k] = (k < w && act) ? (double)L[r + (int64_t)k * f] : 0.0;
     const double rd = (h == 0 && lane < w) ? 1.0 / (double)L[lane + (int64_t)lane * f] : 0.0;
     double vi = 0.0;
     if (act) {
@@ -1629,7 +1637,7 @@ __device__ __forceinline__ void fwd_pair_front(const DevPlan& P, const T* __rest
     }
     if (h == 0) {
 #pragma unroll
-        for (int k = 0; k < kWave; ++k) {
+        for (int k = 0; k < MW; ++k) {
             if (k < w) {
                 const double yk = lane_bcast(vi, k) * lane_bcast(rd, k);
                 if (lane == k) vi = yk;
@@ -1641,7 +1649,7 @@ __device__ __forceinline__ void fwd_pair_front(const DevPlan& P, const T* __rest
     __syncthreads();
     if (h == 1) {
 #pragma unroll
-        for (int k = 0; k < kWave; ++k)
+        for (int k = 0; k < MW; ++k)
             if (k < w) vi = fma(-lr[k], y[k], vi);
     }
     if (r < w) v_perm[c0 + r] = vi;
@@ -1696,7 +1704,7 @@ __device__ __forceinline__ void bwd_pair_front(const DevPlan& P, const T* __rest
 // Level-synchronous sweeps for levels whose fronts have order <= 128 and
 // width <= 64 (the larger ones of the small-front levels): two supernodes
 // per 256-thread workgroup, two waves each.
-template <typename T>
+template <typename T, int MW>
 __global__ void __launch_bounds__(256)
 k_fwd_pairs(DevPlan P, const T* __restrict__ arena, int list_begin, int count, double* __restrict__ v_perm,
             double* __restrict__ uvec) {
@@ -1704,7 +1712,7 @@ k_fwd_pairs(DevPlan P, const T* __restrict__ arena, int list_begin, int count, d
     const int pr = threadIdx.x / (2 * kWave);
     const int t = blockIdx.x * 2 + pr;
     const bool valid = t < count;
-    fwd_pair_front(P, arena, valid ? P.lvl_all[list_begin + t] : 0, valid, v_perm, uvec, y[pr]);
+    fwd_pair_front<T, MW>(P, arena, valid ? P.lvl_all[list_begin + t] : 0, valid, v_perm, uvec, y[pr]);
 }
 
 template <typename T>
@@ -1719,21 +1727,24 @@ k_bwd_pairs(DevPlan P, const T* __restrict__ arena, int list_begin, int count, d
 
 // Level-synchronous sweeps for levels whose fronts all have order <= 64:
 // four supernodes per 256-thread workgroup, one per wave.
-template <typename T>
+// MW (forward) bounds the level's supernode widths, MF (backward) its
+// front orders: the panel row or column a lane holds is that many
+// registers, so narrow levels keep more waves in flight.
+template <typename T, int MW>
 __global__ void __launch_bounds__(256)
 k_fwd_waves(DevPlan P, const T* __restrict__ arena, int list_begin, int count, double* __restrict__ v_perm,
             double* __restrict__ uvec) {
     const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (t >= count) return;
-    fwd_wave_front(P, arena, P.lvl_all[list_begin + t], v_perm, uvec);
+    fwd_wave_front<T, MW>(P, arena, P.lvl_all[list_begin + t], v_perm, uvec);
 }
 
-template <typename T>
+template <typename T, int MF>
 __global__ void __launch_bounds__(256)
 k_bwd_waves(DevPlan P, const T* __restrict__ arena, int list_begin, int count, double* __restrict__ x_perm) {
     const int t = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (t >= count) return;
-    bwd_wave_front(P, arena, P.lvl_all[list_begin + t], x_perm);
+    bwd_wave_front<T, MF>(P, arena, P.lvl_all[list_begin + t], x_perm);
 }
 
 // Control words of the dependency-driven sweeps (one array per handle):
@@ -2916,13 +2927,26 @@ void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
                       double* uvec, hipStream_t st, const TiledSync* ts) {
     if (L.all_count == 0) return;
     if (L.all_maxf <= kWave) {
-        hipLaunchKernelGGL(k_fwd_waves<T>, dim3((L.all_count + 3) / 4), dim3(256), 0, st, P, arena, L.all_begin,
-                           L.all_count, v_perm, uvec);
+        const dim3 g((L.all_count + 3) / 4);
+        if (L.all_maxw <= 16)
+            hipLaunchKernelGGL((k_fwd_waves<T, 16>), g, dim3(256), 0, st, P, arena, L.all_begin, L.all_count, v_perm,
+                               uvec);
+        else if (L.all_maxw <= 32)
+            hipLaunchKernelGGL((k_fwd_waves<T, 32>), g, dim3(256), 0, st, P, arena, L.all_begin, L.all_count, v_perm,
+                               uvec);
+        else
+            hipLaunchKernelGGL((k_fwd_waves<T, kWave>), g, dim3(256), 0, st, P, arena, L.all_begin, L.all_count,
+                               v_perm, uvec);
         return;
     }
     if (L.all_maxf <= 2 * kWave && L.all_maxw <= kWave) {
-        hipLaunchKernelGGL(k_fwd_pairs<T>, dim3((L.all_count + 1) / 2), dim3(256), 0, st, P, arena, L.all_begin,
-                           L.all_count, v_perm, uvec);
+        const dim3 g((L.all_count + 1) / 2);
+        if (L.all_maxw <= 32)
+            hipLaunchKernelGGL((k_fwd_pairs<T, 32>), g, dim3(256), 0, st, P, arena, L.all_begin, L.all_count, v_perm,
+                               uvec);
+        else
+            hipLaunchKernelGGL((k_fwd_pairs<T, kWave>), g, dim3(256), 0, st, P, arena, L.all_begin, L.all_count,
+                               v_perm, uvec);
         return;
     }
     const int tf = L.sweep_tiled_f;
@@ -2957,8 +2981,12 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
                       hipStream_t st, const TiledSync* ts) {
     if (L.all_count == 0) return;
     if (L.all_maxf <= kWave) {
-        hipLaunchKernelGGL(k_bwd_waves<T>, dim3((L.all_count + 3) / 4), dim3(256), 0, st, P, arena, L.all_begin,
-                           L.all_count, x_perm);
+        const dim3 g((L.all_count + 3) / 4);
+        if (L.all_maxf <= 32)
+            hipLaunchKernelGGL((k_bwd_waves<T, 32>), g, dim3(256), 0, st, P, arena, L.all_begin, L.all_count, x_perm);
+        else
+            hipLaunchKernelGGL((k_bwd_waves<T, kWave>), g, dim3(256), 0, st, P, arena, L.all_begin, L.all_count,
+                               x_perm);
         return;
     }
     if (L.all_maxf <= 2 * kWave && L.all_maxw <= kWave) {
