@@ -802,21 +802,35 @@ __device__ __forceinline__ void potrf_reg_full(T* D, int col0, int32_t* status, 
 #pragma unroll
     for (int t = 0; t < NB; ++t) a[t] = (lane < NB && t <= lane) ? D[lane + t * kPanelLd] : T(0);
     int first_bad = INT_MAX, n_bad = 0;
+    // column j's multipliers reach the entries k >= j + 2 one column late
+    // (loaded from LDS in column j, applied at the start of column j + 1,
+    // still before column j + 1's own update of each entry), so the LDS
+    // round trip overlaps the next pivot instead of preceding it
+    T m[NB];
+    T lprev = T(0);
+#pragma unroll
+    for (int t = 0; t < NB; ++t) m[t] = T(0);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
+        // the pivot first (a[j] is complete), then the late updates
         T r;
         bool fail;
         const T ljj = pivot_select<T>(bcast<T>(a[j], j), r, fail);
+        if (j >= 1) {
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) a[k] = fma(-lprev, m[k], a[k]);
+        }
         first_bad = (fail && first_bad == INT_MAX) ? j : first_bad;
         n_bad += fail ? 1 : 0;
         const T lij = lane == j ? ljj : a[j] * r;
         D[lane + j * kPanelLd] = lij;
         rdiag[j] = r;
         // the next pivot's column takes its multiplier by a lane read (off
-        // the LDS store/load round trip); the others read LDS
+        // the LDS store/load round trip)
         if (j + 1 < NB) a[j + 1] = fma(-lij, bcast<T>(lij, j + 1), a[j + 1]);
 #pragma unroll
-        for (int k = j + 2; k < NB; ++k) a[k] = fma(-lij, D[k + j * kPanelLd], a[k]);
+        for (int k = j + 2; k < NB; ++k) m[k] = D[k + j * kPanelLd];
+        lprev = lij;
         __builtin_amdgcn_sched_barrier(0);
     }
     if (status && lane == 0) {
@@ -892,6 +906,9 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
     T x[kPanelNB];
 #pragma unroll
     for (int t = 0; t < kPanelNB; ++t) x[t] = (row && t < nb) ? Fr[(int64_t)t * f] : T(0);
+    // FP64: a block narrower than kPanelNB is padded with an identity (unit
+    // pivots, zero multipliers) so that the full-width forms factor and
+    // solve it; the padding leaves the real entries' arithmetic unchanged
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int idx = u * nt + tid;
@@ -911,12 +928,26 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
     if (!row) return;
     if (sizeof(T) == 8 && nb == kPanelNB) {
         // one basic block; the barrier keeps each column's updates in that
-        // column (see potrf_reg_full)
+        // column (see potrf_reg_full); the next column's multipliers are
+        // loaded while the current column's are applied
+        T dc[kPanelNB], dn[kPanelNB];
+        T rc = s_rdiag[0];
+#pragma unroll
+        for (int k = 1; k < kPanelNB; ++k) dc[k] = D[k];
 #pragma unroll
         for (int j = 0; j < kPanelNB; ++j) {
-            x[j] *= s_rdiag[j];
+            T rn = T(0);
+            if (j + 1 < kPanelNB) {
+                rn = s_rdiag[j + 1];
 #pragma unroll
-            for (int k = j + 1; k < kPanelNB; ++k) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
+                for (int k = j + 2; k < kPanelNB; ++k) dn[k] = D[k + (j + 1) * kPanelLd];
+            }
+            x[j] *= rc;
+#pragma unroll
+            for (int k = j + 1; k < kPanelNB; ++k) x[k] = fma(-x[j], dc[k], x[k]);
+#pragma unroll
+            for (int k = j + 2; k < kPanelNB; ++k) dc[k] = dn[k];
+            rc = rn;
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
