@@ -894,12 +894,19 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
     if (blockIdx.x > 0 && r0 >= f) return;
     const int nr = r0 < f ? min(kPanelRows, f - r0) : 0;
     // the diagonal block's loads and this thread's row are issued together
+    // FP64 blocks are staged 32 x 32: one narrower than kPanelNB is padded
+    // with an identity (unit pivots, zero multipliers), so that the
+    // full-width Cholesky factors it without touching the real entries'
+    // arithmetic, and the row solve needs no per-entry bounds
+    const int nbs = sizeof(T) == 8 ? kPanelNB : nb;
     T t4[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int idx = u * nt + tid;
-        const int i = idx % nb, j = idx / nb;
-        t4[u] = (idx < nb * nb && i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
+        const int i = idx % nbs, j = idx / nbs;
+        t4[u] = (idx < nbs * nbs && i >= j) ? ((i < nb && j < nb) ? F[(kb + i) + (int64_t)(kb + j) * f]
+                                                                  : (i == j ? T(1) : T(0)))
+                                            : T(0);
     }
     const bool row = tid < nr;
     T* Fr = F + (row ? r0 + tid : kb) + (int64_t)kb * f;
@@ -912,10 +919,10 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int idx = u * nt + tid;
-        if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelLd] = t4[u];
+        if (idx < nbs * nbs) D[idx % nbs + (idx / nbs) * kPanelLd] = t4[u];
     }
     __syncthreads();
-    if (tid < kWave) potrf32_reg<T>(D, nb, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
+    if (tid < kWave) potrf32_reg<T>(D, nbs, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
     __syncthreads();
     if (blockIdx.x == 0) {
         T* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * kPanelNB * kPanelNB;
@@ -949,6 +956,17 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
             for (int k = j + 2; k < kPanelNB; ++k) dc[k] = dn[k];
             rc = rn;
             __builtin_amdgcn_sched_barrier(0);
+        }
+    } else if (sizeof(T) == 8) {
+        // a padded block: the multipliers past nb are zeros, so only the
+        // column loop stops at nb
+#pragma unroll
+        for (int j = 0; j < kPanelNB; ++j) {
+            if (j < nb) {
+                x[j] *= s_rdiag[j];
+#pragma unroll
+                for (int k = j + 1; k < kPanelNB; ++k) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
+            }
         }
     } else {
 #pragma unroll
