@@ -1017,6 +1017,23 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
     T* F = arena + P.l_off[s];
     const int tid = threadIdx.x;
     const int cmax = min(f, col_end);
+    using M = Mfma<T>;
+    const int lane = tid % kWave, wv = tid / kWave;
+    const int qi = wv % 2, qj = wv / 2;
+    const int li = lane % 16, lk = lane / 16;
+    const bool quad = !(ti == tj && qj > qi);  // quadrant on or below the diagonal (wave-uniform)
+    // the tile's old values, loaded first so that their latency overlaps the
+    // panel loads and the matrix-core steps
+    T old[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = i0 + qi * 32 + a * 16 + M::row(r, lk), col = j0 + qj * 32 + b * 16 + li;
+                old[a][b][r] = (quad && row < f && col < cmax && row >= col) ? F[row + (int64_t)col * f] : T(0);
+            }
     {
         constexpr int kPer = 64 * PW / 256;
         T ta[kPer], tb[kPer];
@@ -1038,11 +1055,7 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
     __syncthreads();
     {
         // four waves, one 32 x 32 quadrant each, 2 x 2 MFMA tiles of 16 x 16
-        using M = Mfma<T>;
-        const int lane = tid % kWave, wv = tid / kWave;
-        const int qi = wv % 2, qj = wv / 2;
-        if (ti == tj && qj > qi) return;  // quadrant above the diagonal (wave-uniform)
-        const int li = lane % 16, lk = lane / 16;
+        if (!quad) return;  // quadrant above the diagonal (wave-uniform)
         typename M::acc c[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -1066,7 +1079,7 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = i0 + qi * 32 + a * 16 + M::row(r, lk), col = j0 + qj * 32 + b * 16 + li;
-                    if (row < f && col < cmax && row >= col) F[row + (int64_t)col * f] -= c[a][b][r];
+                    if (row < f && col < cmax && row >= col) F[row + (int64_t)col * f] = old[a][b][r] - c[a][b][r];
                 }
     }
 }
