@@ -311,19 +311,32 @@ __device__ __forceinline__ void potrf_diag_reg(T* A, int ld, int col0, int32_t* 
 #pragma unroll
     for (int t = 0; t < NB; ++t) a[t] = t <= lane ? A[lane + t * ld] : T(0);
     int first_bad = INT_MAX, n_bad = 0;
+    // as potrf_reg_full: the next column's entry takes its multiplier by a
+    // lane read, the others one column late from LDS (loaded while the next
+    // pivot is computed), in the same order of operations
+    T m[NB];
+    T lprev = T(0);
+#pragma unroll
+    for (int t = 0; t < NB; ++t) m[t] = T(0);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const T old = A[lane + j * ld];
         T r;
         bool fail;
         const T ljj = pivot_select<T>(bcast<T>(a[j], j), r, fail);
+        if (j >= 1) {
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) a[k] = fma(-lprev, m[k], a[k]);
+        }
         first_bad = (fail && first_bad == INT_MAX) ? j : first_bad;
         n_bad += fail ? 1 : 0;
         const T lij = lane == j ? ljj : a[j] * r;
         A[lane + j * ld] = lane >= j ? lij : old;
         rdiag[j] = r;
+        if (j + 1 < NB) a[j + 1] = fma(-lij, bcast<T>(lij, j + 1), a[j + 1]);
 #pragma unroll
-        for (int k = j + 1; k < NB; ++k) a[k] = fma(-lij, A[k + j * ld], a[k]);
+        for (int k = j + 2; k < NB; ++k) m[k] = A[k + j * ld];
+        lprev = lij;
         __builtin_amdgcn_sched_barrier(0);
     }
     if (status && lane == 0) {
@@ -345,11 +358,26 @@ __device__ __forceinline__ void rows_trsm_diag_reg(T* B, int ld, const T* D, int
         T x[NB];
 #pragma unroll
         for (int t = 0; t < NB; ++t) x[t] = B[i + t * ld];
+        // the next column's multipliers are loaded while the current
+        // column's are applied
+        T dc[NB], dn[NB];
+        T rc = rdiag[0];
+#pragma unroll
+        for (int k = 1; k < NB; ++k) dc[k] = D[k];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            x[j] *= rdiag[j];
+            T rn = T(0);
+            if (j + 1 < NB) {
+                rn = rdiag[j + 1];
 #pragma unroll
-            for (int k = j + 1; k < NB; ++k) x[k] = fma(-x[j], D[k + j * ldd], x[k]);
+                for (int k = j + 2; k < NB; ++k) dn[k] = D[k + (j + 1) * ldd];
+            }
+            x[j] *= rc;
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) x[k] = fma(-x[j], dc[k], x[k]);
+#pragma unroll
+            for (int k = j + 2; k < NB; ++k) dc[k] = dn[k];
+            rc = rn;
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
