@@ -612,7 +612,8 @@ bool build_sweep_sched(ckkt_handle* h) {
         maxw = std::max(maxw, h->levels[l].all_maxw);
     }
     if (maxf > kSweepMaxFront) return false;  // a workgroup stages its whole front vector
-    S.ldd = std::min(64, maxw);
+    S.ldd = sweep_diag_ld(maxw);
+    S.rows = maxf <= kGroupThreads;
     S.group_lds = (size_t)(((maxf + 1) & ~1) + S.ldd * S.ldd) * sizeof(double);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || !sweep_sched_grids(S, dev)) {

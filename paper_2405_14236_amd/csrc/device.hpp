@@ -70,8 +70,12 @@ constexpr int kSweepStaticLds = 1024;   // upper bound of k_fwd / k_bwd static L
 // largest FP64 front held whole in LDS next to the kernel's static arrays:
 // 140^2 * 8 + 2304 <= 160 KiB
 constexpr int kLdsFront64 = 140;
-// largest front the sweep kernels can stage (front vector + 64 x 64 block)
-constexpr int kSweepMaxFront = (kLdsBytes - kSweepStaticLds) / 8 - 64 * 64;
+// Leading dimension of a sweep's staged diagonal block for panels of at most
+// maxw columns: at least min(64, maxw), odd (a row read across the lanes
+// then falls on distinct LDS banks).
+constexpr int sweep_diag_ld(int maxw) { return (maxw < 64 ? (maxw < 1 ? 1 : maxw) : 64) | 1; }
+// largest front the sweep kernels can stage (front vector + 65 x 65 block)
+constexpr int kSweepMaxFront = (kLdsBytes - kSweepStaticLds) / 8 - 65 * 65;
 constexpr int kCompactFront64 = 64;  // fronts with f^2 * 8 <= 32 KiB (several workgroups per CU)
 constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
@@ -138,9 +142,17 @@ struct SweepSched {
     int32_t pair_t1 = 0, pair_lvl = 0;
     int32_t wave_grid = 1, group_grid = 1, ldd = 1;
     size_t group_lds = 0;
+    // every workgroup-swept front has at most kGroupThreads rows: the
+    // forward workgroup sweep holds fronts one row per thread
+    bool rows = false;
+    int32_t rows_grid = 1;
     unsigned long long ticks = 0;  // wait limit in wall-clock ticks
 };
 constexpr int kSweepWaveFront = 64;   // largest front of the single-wave class
+// workgroup size of the row-held forward workgroup sweep: a front of at
+// most this many rows is held one row per thread (its panel row of the
+// current 64-column block in registers)
+constexpr int kGroupThreads = 768;
 constexpr int kSweepWaitSeconds = 4;  // a dependency wait longer than this is reported as an error
 constexpr int kSweepCtlWords = 8;     // ticket counters and epoch
 // largest number of supernodes above the single-wave levels for which the

@@ -1263,7 +1263,9 @@ __device__ void wait_flag(const unsigned* flag, unsigned want, int32_t* err, uns
 }
 
 // Stage the nb x nb lower triangle of the diagonal block at src (leading
-// dimension f) into D[r + c * ldd] with reciprocal pivots; eight loads per
+// dimension f) into D[r + c * ldd] with reciprocal pivots (ldd odd,
+// sweep_diag_ld: the backward solves read a row of D across the lanes, and
+// an odd stride spreads it over the LDS banks); eight loads per
 // thread are issued before their LDS stores so that their latencies overlap.
 template <typename T>
 __device__ __forceinline__ void stage_diag_block(const T* __restrict__ src, int f, int nb, double* D, int ldd) {
@@ -1287,6 +1289,36 @@ __device__ __forceinline__ void stage_diag_block(const T* __restrict__ src, int 
     }
 }
 
+// Triangular solves of a staged diagonal block by one wave (D: the block's
+// lower triangle with reciprocal pivots, leading dimension ldd; lane r < nb
+// holds entry r).  Lane k's value times its own reciprocal pivot is the
+// k-th unknown, broadcast from a register; the other lanes update with
+// selects (no divergent branches) and their own row (forward) or column
+// (backward) entry of D.  Lanes from nb on read row/column 0 and keep
+// their value.
+__device__ __forceinline__ double wave_fwd_tri(double vi, const double* D, int ldd, int nb) {
+    const int lane = threadIdx.x % kWave, lr = lane < nb ? lane : 0;
+    const double rdl = D[lr + lr * ldd];
+#pragma unroll 8
+    for (int k = 0; k < nb; ++k) {
+        const double yk = lane_bcast(vi * rdl, k);
+        const double u = fma(-D[lr + k * ldd], yk, vi);
+        vi = lane == k ? yk : ((lane > k && lane < nb) ? u : vi);
+    }
+    return vi;
+}
+__device__ __forceinline__ double wave_bwd_tri(double ri, const double* D, int ldd, int nb) {
+    const int lane = threadIdx.x % kWave, lr = lane < nb ? lane : 0;
+    const double rdl = D[lr + lr * ldd];
+#pragma unroll 8
+    for (int k = nb - 1; k >= 0; --k) {
+        const double xk = lane_bcast(ri * rdl, k);
+        const double u = fma(-D[k + lr * ldd], xk, ri);
+        ri = lane == k ? xk : (lane < k ? u : ri);
+    }
+    return ri;
+}
+
 // Forward sweep of one supernode by a workgroup: v (LDS, f entries) holds
 // the gathered right-hand side on entry; per block of 64 columns one wave
 // solves the diagonal block (staged in LDS with reciprocal pivots) with
@@ -1302,13 +1334,7 @@ __device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double
         if (kb > 0 || !first_staged) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
         __syncthreads();
         if (wid == 0) {
-            double vi = lane < nb ? v[kb + lane] : 0.0;
-#pragma unroll 4
-            for (int k = 0; k < nb; ++k) {
-                const double yk = lane_bcast(vi, k) * D[k + k * ldd];
-                if (lane == k) vi = yk;
-                else if (lane > k && lane < nb) vi = fma(-D[lane + k * ldd], yk, vi);
-            }
+            const double vi = wave_fwd_tri(lane < nb ? v[kb + lane] : 0.0, D, ldd, nb);
             if (lane < nb) v[kb + lane] = vi;
         }
         __syncthreads();
@@ -1333,9 +1359,9 @@ __device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double
 
 // Backward sweep of one supernode by a workgroup: z (LDS, f entries) holds
 // y on the own columns and the solved x on the rows below; per block of 64
-// columns (last block first) each wave forms the dot products of eight
-// columns at a time with everything solved so far, then one wave
-// back-substitutes the diagonal block.
+// columns (last block first) each wave forms the dot products of its
+// columns (two groups of eight at a time) with everything solved so far,
+// then one wave back-substitutes the diagonal block.
 template <typename T>
 __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double* z, double* D, double* tb,
                           bool last_staged = false) {
@@ -1344,48 +1370,61 @@ __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double
     const int nblk = (w + kWave - 1) / kWave;
     for (int b = nblk - 1; b >= 0; --b) {
         const int kb = b * kWave, nb = min(kWave, w - kb), r0 = kb + nb;
-        for (int k0 = wid * 8; k0 < nb; k0 += nw * 8) {
-            double part[8];
+        for (int k0 = wid * 8; k0 < nb; k0 += 2 * nw * 8) {
+            // column groups k0 and k1 = k0 + 8 nw (when below nb); each
+            // lane sums its rows r0 + lane + 64 m in row order, four rows of
+            // both groups per step (64 loads in flight)
+            const int k1 = k0 + nw * 8;
+            const bool g1 = k1 < nb;
+            double pa[8], pb[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) part[c] = 0.0;
-            // two rows per step (16 loads in flight), summed in row order
+            for (int c = 0; c < 8; ++c) pa[c] = pb[c] = 0.0;
             int i = r0 + lane;
-            for (; i + kWave < f; i += 2 * kWave) {
-                const double z0 = z[i], z1 = z[i + kWave];
-                T l0[8], l1[8];
+            for (; i + 3 * kWave < f; i += 4 * kWave) {
+                double zm[4];
+                T la[4][8], lb[4][8];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const bool cin = k0 + c < nb;
-                    l0[c] = cin ? L[i + (int64_t)(kb + k0 + c) * f] : T(0);
-                    l1[c] = cin ? L[i + kWave + (int64_t)(kb + k0 + c) * f] : T(0);
+                for (int m = 0; m < 4; ++m) {
+                    zm[m] = z[i + m * kWave];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        la[m][c] = (k0 + c < nb) ? L[i + m * kWave + (int64_t)(kb + k0 + c) * f] : T(0);
+                        lb[m][c] = (g1 && k1 + c < nb) ? L[i + m * kWave + (int64_t)(kb + k1 + c) * f] : T(0);
+                    }
                 }
 #pragma unroll
-                for (int c = 0; c < 8; ++c) part[c] = fma((double)l0[c], z0, part[c]);
+                for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int c = 0; c < 8; ++c) part[c] = fma((double)l1[c], z1, part[c]);
+                    for (int c = 0; c < 8; ++c) {
+                        pa[c] = fma((double)la[m][c], zm[m], pa[c]);
+                        pb[c] = fma((double)lb[m][c], zm[m], pb[c]);
+                    }
             }
-            if (i < f) {
+            for (; i < f; i += kWave) {
                 const double zi = z[i];
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    part[c] = fma((k0 + c < nb) ? (double)L[i + (int64_t)(kb + k0 + c) * f] : 0.0, zi, part[c]);
+                for (int c = 0; c < 8; ++c) {
+                    pa[c] = fma((k0 + c < nb) ? (double)L[i + (int64_t)(kb + k0 + c) * f] : 0.0, zi, pa[c]);
+                    pb[c] = fma((g1 && k1 + c < nb) ? (double)L[i + (int64_t)(kb + k1 + c) * f] : 0.0, zi, pb[c]);
+                }
             }
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                const double sc = wave_sum(part[c]);
-                if (lane == 0 && k0 + c < nb) tb[k0 + c] = sc;
+                const double sa = wave_sum(pa[c]);
+                if (lane == 0 && k0 + c < nb) tb[k0 + c] = sa;
+            }
+            if (g1) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const double sb = wave_sum(pb[c]);
+                    if (lane == 0 && k1 + c < nb) tb[k1 + c] = sb;
+                }
             }
         }
         if (b < nblk - 1 || !last_staged) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
         __syncthreads();
         if (wid == 0) {
-            double ri = lane < nb ? z[kb + lane] - tb[lane] : 0.0;
-#pragma unroll 4
-            for (int k = nb - 1; k >= 0; --k) {
-                const double xk = lane_bcast(ri, k) * D[k + k * ldd];
-                if (lane == k) ri = xk;
-                else if (lane < k) ri = fma(-D[k + lane * ldd], xk, ri);
-            }
+            const double ri = wave_bwd_tri(lane < nb ? z[kb + lane] - tb[lane] : 0.0, D, ldd, nb);
             if (lane < nb) z[kb + lane] = ri;
         }
         __syncthreads();
@@ -1964,6 +2003,161 @@ k_bwd_wave(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_hi, d
     }
 }
 
+// x, opaque to the optimizer: lane comparisons made from it inside a loop
+// are not hoisted out of it (64 lane masks kept across a loop would not fit
+// in scalar registers).  Emits no instruction.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+// Completes the load that produced x here (the empty asm reads x, so the
+// wait for it is placed before it), and leaves x as a value that is no
+// longer a pending load: later uses inside loops then wait for nothing,
+// in particular not for younger loads still in flight.
+__device__ __forceinline__ double settle(double x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Row r of columns c .. c + 63 of a column-major panel with leading
+// dimension f: l[k] = L[r + (c + k) f] for k < n when ok.  A wave none of
+// whose lanes has ok loads nothing (l = 0); otherwise, in groups of eight
+// columns, loads stop after the group holding column n - 1, columns from n
+// on inside that group re-read column c + n - 1 and a lane with ok false
+// reads L[0], so every load is from inside the panel; callers use only
+// k < n of rows with ok.  The offset is a per-thread 32-bit value that
+// advances by f per column.
+template <typename T>
+__device__ __forceinline__ void load_panel_row(T (&l)[kWave], const T* __restrict__ L, int r, int c, int f, int n,
+                                               bool ok) {
+    if (__ballot(ok) == 0) {
+#pragma unroll
+        for (int k = 0; k < kWave; ++k) l[k] = T(0);
+        return;
+    }
+    int off = ok ? r + c * f : 0;
+    const int step = ok ? f : 0;
+#pragma unroll
+    for (int k0 = 0; k0 < kWave; k0 += 8) {
+        if (k0 < n) {
+#pragma unroll
+            for (int k = k0; k < k0 + 8; ++k) {
+                l[k] = L[off];
+                off += (k + 1 < n) ? step : 0;
+            }
+        } else {
+#pragma unroll
+            for (int k = k0; k < k0 + 8; ++k) l[k] = T(0);
+        }
+    }
+}
+
+// Forward sweep of one supernode with f <= blockDim.x, one row per thread:
+// thread i holds v_i (vi), the reciprocal of its pivot when i < w (rd) and
+// its row of the panel in the current 64-column block (l; the caller loads
+// block 0).  Per block the wave that holds the block's rows solves it with
+// lane broadcasts from registers and leaves y in LDS (two buffers, so one
+// barrier per block suffices); every row below then subtracts its products
+// in column order and loads its row of the next block.  The arithmetic and
+// its order are fwd_front's.
+template <typename T>
+__device__ __forceinline__ void fwd_rows(const T* __restrict__ L, int w, int f, double& vi, T (&l)[kWave],
+                                         double rd, double* ybuf) {
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int nblk = (w + kWave - 1) / kWave;
+    for (int b = 0; b < nblk; ++b) {
+        const int kb = b * kWave, nb = min(kWave, w - kb);
+        double* y = ybuf + (b & 1) * kWave;
+        if (wv == b) {
+            // lane k's v_k times its reciprocal pivot is y_k
+            const int ln = opaque(lane);
+#pragma unroll
+            for (int k = 0; k < kWave; ++k) {
+                if (k < nb) {
+                    const double yk = lane_bcast(vi * rd, k);
+                    const double u = fma(-(double)l[k], yk, vi);
+                    vi = ln == k ? yk : ((ln > k && ln < nb) ? u : vi);
+                }
+                if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+            if (lane < nb) y[lane] = vi;
+        }
+        __syncthreads();
+        if (tid >= kb + nb && tid < f) {
+            // y read from LDS 8 entries at a time (bounded register use)
+            double acc = 0.0;
+#pragma unroll
+            for (int k0 = 0; k0 < kWave; k0 += 8) {
+#pragma unroll
+                for (int k = k0; k < k0 + 8; ++k)
+                    if (k < nb) acc = fma((double)l[k], y[k], acc);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            vi -= acc;
+        }
+        if (b + 1 < nblk) {
+            const int kn = kb + kWave;
+            load_panel_row(l, L, tid, kn, f, min(kWave, w - kn), tid >= kn && tid < f);
+        }
+    }
+}
+
+// Dependency-driven forward sweep by workgroups of kGroupThreads threads
+// when every front of lvl_all[t0, t1) has at most that many rows: each
+// front is held one row per thread (fwd_rows), its first block row loaded
+// before the wait on the children; otherwise as k_fwd_group.
+template <typename T>
+__global__ void __launch_bounds__(kGroupThreads)
+k_fwd_group_rows(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_lo, double* __restrict__ v_perm,
+                 double* __restrict__ uvec, unsigned* ctl, unsigned* done, int32_t* err, unsigned long long ticks) {
+    __shared__ double ybuf[2 * kWave];
+    __shared__ int s_ticket[2];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const unsigned want = 2u * ctl[kCtlEpoch];
+    if (tid == 0) s_ticket[0] = (int)atomicAdd(&ctl[kCtlFwdGroup], 1u);
+    __syncthreads();
+    for (int it = 0;; ++it) {
+        const int t = s_ticket[it & 1] + t0;
+        if (t >= t1) break;
+        if (tid == 0) s_ticket[(it + 1) & 1] = (int)atomicAdd(&ctl[kCtlFwdGroup], 1u);
+        const int s = P.lvl_all[t];
+        const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+        const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
+        const T* Ls = arena + P.l_off[s];
+        // work that does not depend on the children, issued before the
+        // wait: this thread's row of the first column block and its pivot,
+        // its own right-hand side entry and its first contribution indices
+        T l[kWave];
+        const bool r0 = tid < f;
+        load_panel_row(l, Ls, tid, 0, f, min(kWave, w), r0);
+        double rd = tid < w ? 1.0 / (double)Ls[tid + (int64_t)tid * f] : 0.0;
+        constexpr int kPre = 4;
+        double vi = (r0 && tid < w) ? v_perm[c0 + tid] : 0.0;
+        const int qa = r0 ? P.cb_ptr[ro + tid] : 0, qb = r0 ? P.cb_ptr[ro + tid + 1] : 0;
+        int src[kPre];
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) src[k] = qa + k < qb ? P.cb_src[qa + k] : -1;
+        for (int c = P.child_ptr[s] + tid; c < P.child_ptr[s + 1]; c += nt) {
+            const int ch = P.child_list[c];
+            if (P.sn_level[ch] >= lvl_lo) wait_flag(&done[ch], want, err, ticks);
+        }
+        __syncthreads();
+        acquire_device();
+#pragma unroll
+        for (int k = 0; k < kPre; ++k)
+            if (src[k] >= 0) vi += uvec[src[k]];
+        for (int q = qa + kPre; q < qb; ++q) vi += uvec[P.cb_src[q]];
+        vi = settle(vi);
+        rd = settle(rd);
+        fwd_rows(Ls, w, f, vi, l, rd, ybuf);
+        if (tid < w) v_perm[c0 + tid] = vi;
+        else if (r0) uvec[ro + tid] = vi;
+        release_device();
+        __syncthreads();
+        if (tid == 0) flag_store(&done[s], want);
+    }
+}
+
 // Dependency-driven forward sweep by workgroups over lvl_all[t0, t1)
 // (levels from lvl_lo up); children below lvl_lo were finished by an
 // earlier launch.  The next ticket is fetched while the current supernode
@@ -2037,13 +2231,7 @@ k_fwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_lo, 
             double* D = v + ((f + 1) & ~1);
             const int lane = tid % kWave;
             if (tid < kWave) {
-                double vi = lane < w ? v[lane] : 0.0;
-#pragma unroll 4
-                for (int k = 0; k < w; ++k) {
-                    const double yk = lane_bcast(vi, k) * D[k + k * ldd];
-                    if (lane == k) vi = yk;
-                    else if (lane > k && lane < w) vi = fma(-D[lane + k * ldd], yk, vi);
-                }
+                const double vi = wave_fwd_tri(lane < w ? v[lane] : 0.0, D, ldd, w);
                 if (lane < w) v[lane] = vi;
             }
             __syncthreads();
@@ -2145,13 +2333,7 @@ k_bwd_group(DevPlan P, const T* __restrict__ arena, int t0, int t1, int ldd, dou
             }
             __syncthreads();
             if (wid == 0) {
-                double ri = lane < w ? z[lane] - tb[lane] : 0.0;
-#pragma unroll 4
-                for (int k = w - 1; k >= 0; --k) {
-                    const double xk = lane_bcast(ri, k) * D[k + k * ldd];
-                    if (lane == k) ri = xk;
-                    else if (lane < k) ri = fma(-D[k + lane * ldd], xk, ri);
-                }
+                const double ri = wave_bwd_tri(lane < w ? z[lane] - tb[lane] : 0.0, D, ldd, w);
                 if (lane < w) z[lane] = ri;
             }
             __syncthreads();
@@ -3044,7 +3226,7 @@ void launch_fwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
     const int skip_f = tiled ? tf : INT_MAX;
     const int maxf = tiled ? std::min(L.all_maxf, tf - 1) : L.all_maxf;
     const int threads = L.sweep_threads;
-    const int ldd = std::min(kWave, std::max(L.all_maxw, 1));
+    const int ldd = sweep_diag_ld(L.all_maxw);
     size_t lds = (size_t)(((maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
     if (!tiled || L.sweep_small_count > 0)
         hipLaunchKernelGGL(k_fwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, skip_f,
@@ -3089,7 +3271,7 @@ void launch_bwd_level(const DevPlan& P, const LevelInfo& L, const T* arena, doub
     const int skip_f = tiled ? tf : INT_MAX;
     const int maxf = tiled ? std::min(L.all_maxf, tf - 1) : L.all_maxf;
     const int threads = L.sweep_threads;
-    const int ldd = std::min(kWave, std::max(L.all_maxw, 1));
+    const int ldd = sweep_diag_ld(L.all_maxw);
     size_t lds = (size_t)(((maxf + 1) & ~1) + ldd * ldd) * sizeof(double);
     if (!tiled || L.sweep_small_count > 0)
         hipLaunchKernelGGL(k_bwd<T>, dim3(L.all_count), dim3(threads), lds, st, P, arena, L.all_begin, ldd, skip_f,
@@ -3149,9 +3331,14 @@ void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, dou
         hipLaunchKernelGGL(k_fwd_wave<T>, dim3(S.wave_grid), dim3(kWave), 0, st, P, arena, 0, S.wave_t1, v_perm, uvec,
                            ctl, done, err, S.ticks);
     const int t0 = waves ? S.wave_t1 : S.pair_t1, lvl0 = waves ? S.wave_lvl : S.pair_lvl;
-    if (S.ns > t0)
-        hipLaunchKernelGGL(k_fwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, t0, S.ns, lvl0,
-                           S.ldd, v_perm, uvec, ctl, done, err, S.ticks);
+    if (S.ns > t0) {
+        if (S.rows)
+            hipLaunchKernelGGL(k_fwd_group_rows<T>, dim3(S.rows_grid), dim3(kGroupThreads), 0, st, P, arena, t0, S.ns,
+                               lvl0, v_perm, uvec, ctl, done, err, S.ticks);
+        else
+            hipLaunchKernelGGL(k_fwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, t0, S.ns,
+                               lvl0, S.ldd, v_perm, uvec, ctl, done, err, S.ticks);
+    }
 }
 
 template <typename T>
@@ -3188,11 +3375,15 @@ bool sweep_sched_grids(SweepSched& S, int device) {
                        occ(reinterpret_cast<const void*>(&k_bwd_group<double>), 256, S.group_lds),
                        occ(reinterpret_cast<const void*>(&k_fwd_group<float>), 256, S.group_lds),
                        occ(reinterpret_cast<const void*>(&k_bwd_group<float>), 256, S.group_lds)});
+    int orow = std::min(occ(reinterpret_cast<const void*>(&k_fwd_group_rows<double>), kGroupThreads, 0),
+                        occ(reinterpret_cast<const void*>(&k_fwd_group_rows<float>), kGroupThreads, 0));
     (void)hipGetLastError();
     ow = std::max(ow, 1);
     og = std::max(og, 1);
+    orow = std::max(orow, 1);
     S.wave_grid = std::max(1, std::min(ow * cus, S.wave_t1));
     S.group_grid = std::max(1, std::min(og * cus, S.ns - S.wave_t1));
+    S.rows_grid = std::max(1, std::min(orow * cus, S.ns - S.wave_t1));
     return true;
 }
 
