@@ -1263,7 +1263,7 @@ __device__ void wait_flag(const unsigned* flag, unsigned want, int32_t* err, uns
 }
 
 // Stage the nb x nb lower triangle of the diagonal block at src (leading
-// dimension f) into D[r + c * ldd] with reciprocal pivots (ldd odd,
+// dimension f) into D[r + c * ldd] (ldd odd,
 // sweep_diag_ld: the backward solves read a row of D across the lanes, and
 // an odd stride spreads it over the LDS banks); eight loads per
 // thread are issued before their LDS stores so that their latencies overlap.
@@ -1283,39 +1283,56 @@ __device__ __forceinline__ void stage_diag_block(const T* __restrict__ src, int 
             const int idx = base + u * nt + tid;
             if (idx < tot) {
                 const int i = idx % nb, k = idx / nb;
-                D[i + k * ldd] = (i == k) ? 1.0 / t[u] : t[u];
+                D[i + k * ldd] = t[u];
             }
         }
     }
 }
 
 // Triangular solves of a staged diagonal block by one wave (D: the block's
-// lower triangle with reciprocal pivots, leading dimension ldd; lane r < nb
-// holds entry r).  Lane k's value times its own reciprocal pivot is the
-// k-th unknown, broadcast from a register; the other lanes update with
-// selects (no divergent branches) and their own row (forward) or column
-// (backward) entry of D.  Lanes from nb on read row/column 0 and keep
-// their value.
+// lower triangle, leading dimension ldd, raw pivots on the diagonal; lane
+// r < nb holds entry r).  Each lane forms the reciprocal of its pivot; lane
+// k's value times it is the k-th unknown, broadcast from a register; the
+// other lanes update with selects (no divergent branches) and their own
+// row (forward) or column (backward) entry of D, read eight steps at a time
+// ahead of their use.  Lanes from nb on read row/column 0 and keep their
+// value.
+__device__ __forceinline__ void fwd_tri_step(double& vi, double rdl, double dk, int lane, int k, int nb) {
+    const double yk = lane_bcast(vi * rdl, k);
+    const double u = fma(-dk, yk, vi);
+    vi = lane == k ? yk : ((lane > k && lane < nb) ? u : vi);
+}
+__device__ __forceinline__ void bwd_tri_step(double& ri, double rdl, double dk, int lane, int k) {
+    const double xk = lane_bcast(ri * rdl, k);
+    const double u = fma(-dk, xk, ri);
+    ri = lane == k ? xk : (lane < k ? u : ri);
+}
 __device__ __forceinline__ double wave_fwd_tri(double vi, const double* D, int ldd, int nb) {
     const int lane = threadIdx.x % kWave, lr = lane < nb ? lane : 0;
-    const double rdl = D[lr + lr * ldd];
-#pragma unroll 8
-    for (int k = 0; k < nb; ++k) {
-        const double yk = lane_bcast(vi * rdl, k);
-        const double u = fma(-D[lr + k * ldd], yk, vi);
-        vi = lane == k ? yk : ((lane > k && lane < nb) ? u : vi);
+    const double rdl = 1.0 / D[lr + lr * ldd];
+    int k = 0;
+    for (; k + 8 <= nb; k += 8) {
+        double dk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dk[u] = D[lr + (k + u) * ldd];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) fwd_tri_step(vi, rdl, dk[u], lane, k + u, nb);
     }
+    for (; k < nb; ++k) fwd_tri_step(vi, rdl, D[lr + k * ldd], lane, k, nb);
     return vi;
 }
 __device__ __forceinline__ double wave_bwd_tri(double ri, const double* D, int ldd, int nb) {
     const int lane = threadIdx.x % kWave, lr = lane < nb ? lane : 0;
-    const double rdl = D[lr + lr * ldd];
-#pragma unroll 8
-    for (int k = nb - 1; k >= 0; --k) {
-        const double xk = lane_bcast(ri * rdl, k);
-        const double u = fma(-D[k + lr * ldd], xk, ri);
-        ri = lane == k ? xk : (lane < k ? u : ri);
+    const double rdl = 1.0 / D[lr + lr * ldd];
+    int k = nb - 1;
+    for (; k >= 7; k -= 8) {
+        double dk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dk[u] = D[(k - u) + lr * ldd];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bwd_tri_step(ri, rdl, dk[u], lane, k - u);
     }
+    for (; k >= 0; --k) bwd_tri_step(ri, rdl, D[k + lr * ldd], lane, k);
     return ri;
 }
 
@@ -1357,19 +1374,56 @@ __device__ void fwd_front(const T* __restrict__ L, int w, int f, int ldd, double
     }
 }
 
+// The nb x nb lower triangle of the diagonal block at src (leading
+// dimension f) in registers: entry idx = tid + u nt (row idx % nb, column
+// idx / nb) for u < kDiagRegs; store_diag_regs writes them to
+// D[r + c * ldd] and stages any entries beyond
+// kDiagRegs * nt directly (fewer than 256 threads).  Together they are
+// stage_diag_block with the loads issued earlier.
+constexpr int kDiagRegs = 16;
+template <typename T>
+__device__ __forceinline__ void load_diag_regs(T (&d)[kDiagRegs], const T* __restrict__ src, int f, int nb) {
+    const int tid = threadIdx.x, nt = blockDim.x, tot = nb * nb;
+#pragma unroll
+    for (int u = 0; u < kDiagRegs; ++u) {
+        const int idx = u * nt + tid, i = idx % nb, k = idx / nb;
+        d[u] = (idx < tot && i >= k) ? src[i + (int64_t)k * f] : T(0);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_diag_regs(const T (&d)[kDiagRegs], const T* __restrict__ src, int f, int nb,
+                                                double* D, int ldd) {
+    const int tid = threadIdx.x, nt = blockDim.x, tot = nb * nb;
+#pragma unroll
+    for (int u = 0; u < kDiagRegs; ++u) {
+        const int idx = u * nt + tid, i = idx % nb, k = idx / nb;
+        if (idx < tot) D[i + k * ldd] = (double)d[u];
+    }
+    for (int idx = kDiagRegs * nt + tid; idx < tot; idx += nt) {
+        const int i = idx % nb, k = idx / nb;
+        D[i + k * ldd] = i >= k ? (double)src[i + (int64_t)k * f] : 0.0;
+    }
+}
+
 // Backward sweep of one supernode by a workgroup: z (LDS, f entries) holds
 // y on the own columns and the solved x on the rows below; per block of 64
-// columns (last block first) each wave forms the dot products of its
-// columns (two groups of eight at a time) with everything solved so far,
-// then one wave back-substitutes the diagonal block.
+// columns (last block first) the entries of the diagonal block are loaded
+// into registers (unless the caller staged the last block in D:
+// last_staged), each wave forms the dot products of its columns (two
+// groups of eight at a time) with everything solved so far, the block is
+// stored to D and one wave back-substitutes it.
 template <typename T>
 __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double* z, double* D, double* tb,
                           bool last_staged = false) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nw = nt / kWave, lane = tid % kWave, wid = tid / kWave;
     const int nblk = (w + kWave - 1) / kWave;
+    T dreg[kDiagRegs];
     for (int b = nblk - 1; b >= 0; --b) {
         const int kb = b * kWave, nb = min(kWave, w - kb), r0 = kb + nb;
+        const T* Lb = L + kb + (int64_t)kb * f;
+        const bool staged = b == nblk - 1 && last_staged;
+        if (!staged) load_diag_regs(dreg, Lb, f, nb);
         for (int k0 = wid * 8; k0 < nb; k0 += 2 * nw * 8) {
             // column groups k0 and k1 = k0 + 8 nw (when below nb); each
             // lane sums its rows r0 + lane + 64 m in row order, four rows of
@@ -1421,7 +1475,7 @@ __device__ void bwd_front(const T* __restrict__ L, int w, int f, int ldd, double
                 }
             }
         }
-        if (b < nblk - 1 || !last_staged) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, ldd);
+        if (!staged) store_diag_regs(dreg, Lb, f, nb, D, ldd);
         __syncthreads();
         if (wid == 0) {
             const double ri = wave_bwd_tri(lane < nb ? z[kb + lane] - tb[lane] : 0.0, D, ldd, nb);
@@ -1546,14 +1600,7 @@ k_fwd_tiled_step(DevPlan P, const T* __restrict__ arena, int list_begin, int min
     if (wid != 0) return;
     double vi = 0.0;
     if (row) vi = ((i < w) ? v_perm[c0 + i] : uvec[ro + i]) - (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
-    if (solve) {
-#pragma unroll 4
-        for (int k = 0; k < nb; ++k) {
-            const double yk = lane_bcast(vi, k) * D[k + k * kWave];
-            if (lane == k) vi = yk;
-            else if (lane > k && lane < nb) vi = fma(-D[lane + k * kWave], yk, vi);
-        }
-    }
+    if (solve) vi = wave_fwd_tri(vi, D, kWave, nb);
     if (row) {
         if (i < w) v_perm[c0 + i] = vi;
         else uvec[ro + i] = vi;
@@ -1613,7 +1660,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_bwd_tiled_step(DevPlan P, const T* __restrict__ arena, int list_begin, int min_f, int b,
                  double* __restrict__ x_perm) {
-    __shared__ double D[kWave * kWave];
+    __shared__ double D[kWave * (kWave + 1)];
     __shared__ double S[kWave * (kWave + 1)];
     __shared__ double tb[kWave];
     const int s = P.lvl_big[list_begin + blockIdx.y];
@@ -1629,7 +1676,7 @@ k_bwd_tiled_step(DevPlan P, const T* __restrict__ arena, int list_begin, int min
     const int kb = b * kWave, nb = min(kWave, w - kb);
     const int ct = t * kWave, tnb = min(kWave, w - ct);
     const int q = kb + kWave, qnb = b + 1 < nblk ? min(kWave, w - q) : 0;
-    if (solve) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, kWave);
+    if (solve) stage_diag_block(L + kb + (int64_t)kb * f, f, nb, D, kWave + 1);
     if (qnb > 0) {
         const bool r = lane < qnb;
         const double xr = r ? x_perm[c0 + q + lane] : 0.0;
@@ -1654,14 +1701,7 @@ k_bwd_tiled_step(DevPlan P, const T* __restrict__ arena, int list_begin, int min
     __syncthreads();
     if (wid != 0) return;
     double ri = lane < tnb ? x_perm[c0 + ct + lane] - tb[lane] : 0.0;
-    if (solve) {
-#pragma unroll 4
-        for (int k = nb - 1; k >= 0; --k) {
-            const double xk = lane_bcast(ri, k) * D[k + k * kWave];
-            if (lane == k) ri = xk;
-            else if (lane < k) ri = fma(-D[k + lane * kWave], xk, ri);
-        }
-    }
+    if (solve) ri = wave_bwd_tri(ri, D, kWave + 1, nb);
     if (lane < tnb) x_perm[c0 + ct + lane] = ri;
 }
 
@@ -2989,12 +3029,7 @@ k_fwd_tiled_level(DevPlan P, const T* __restrict__ arena, int list_begin, int mi
     }
     __syncthreads();  // D staged
     if (wid == 0) {
-#pragma unroll 4
-        for (int k = 0; k < nb; ++k) {
-            const double yk = lane_bcast(vi, k) * D[k + k * kWave];
-            if (lane == k) vi = yk;
-            else if (lane > k && lane < nb) vi = fma(-D[lane + k * kWave], yk, vi);
-        }
+        vi = wave_fwd_tri(vi, D, kWave, nb);
         if (lane < nb) v_perm[c0 + i] = vi;
         release_device();
         if (lane == 0) flag_store(&fl[t], want);
@@ -3014,7 +3049,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_bwd_tiled_level(DevPlan P, const T* __restrict__ arena, int list_begin, int min_f, double* __restrict__ x_perm,
                   const unsigned* ctl, unsigned* flags, int nblk_lvl, int32_t* err, unsigned long long ticks) {
-    __shared__ double D[kWave * kWave];
+    __shared__ double D[kWave * (kWave + 1)];
     __shared__ double S[kWave * (kWave + 1)];
     __shared__ double tb[kWave];
     const int s = P.lvl_big[list_begin + blockIdx.x];
@@ -3028,7 +3063,7 @@ k_bwd_tiled_level(DevPlan P, const T* __restrict__ arena, int list_begin, int mi
     const T* L = arena + P.l_off[s];
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, k0 = wid * 16;
     const int ct = t * kWave, tnb = min(kWave, w - ct);
-    stage_diag_block(L + ct + (int64_t)ct * f, f, tnb, D, kWave);
+    stage_diag_block(L + ct + (int64_t)ct * f, f, tnb, D, kWave + 1);
     double z = (wid == 0 && lane < tnb) ? x_perm[c0 + ct + lane] : 0.0;
     for (int b = nblk - 1; b > t; --b) {
         const int q = b * kWave, qnb = min(kWave, w - q);
@@ -3056,12 +3091,7 @@ k_bwd_tiled_level(DevPlan P, const T* __restrict__ arena, int list_begin, int mi
     }
     __syncthreads();  // D staged
     if (wid != 0) return;
-#pragma unroll 4
-    for (int k = tnb - 1; k >= 0; --k) {
-        const double xk = lane_bcast(z, k) * D[k + k * kWave];
-        if (lane == k) z = xk;
-        else if (lane < k) z = fma(-D[k + lane * kWave], xk, z);
-    }
+    z = wave_bwd_tri(z, D, kWave + 1, tnb);
     if (lane < tnb) x_perm[c0 + ct + lane] = z;
     release_device();
     if (lane == 0) flag_store(&fl[t], want);
