@@ -614,6 +614,12 @@ bool build_sweep_sched(ckkt_handle* h) {
     if (maxf > kSweepMaxFront) return false;  // a workgroup stages its whole front vector
     S.ldd = sweep_diag_ld(maxw);
     S.rows = maxf <= kGroupThreads;
+    // levels from rows_lvl on (fronts above kRowsMinFront rows) go to the
+    // row-held forward kernel, the levels below it to the LDS one
+    int lr = lp;
+    while (lr < (int)h->levels.size() && h->levels[lr].all_maxf <= kRowsMinFront) ++lr;
+    S.rows_lvl = S.rows ? lr : (int)h->levels.size();
+    S.rows_t0 = P.ns ? P.lvl_all_ptr[S.rows_lvl] : 0;
     S.group_lds = (size_t)(((maxf + 1) & ~1) + S.ldd * S.ldd) * sizeof(double);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || !sweep_sched_grids(S, dev)) {

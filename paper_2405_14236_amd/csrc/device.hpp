@@ -143,9 +143,10 @@ struct SweepSched {
     int32_t wave_grid = 1, group_grid = 1, ldd = 1;
     size_t group_lds = 0;
     // every workgroup-swept front has at most kGroupThreads rows: the
-    // forward workgroup sweep holds fronts one row per thread
+    // forward workgroup sweep holds the fronts of levels rows_lvl and above
+    // (lvl_all[rows_t0] on) one row per thread, in a launch of its own
     bool rows = false;
-    int32_t rows_grid = 1;
+    int32_t rows_grid = 1, rows_lvl = 0, rows_t0 = 0;
     unsigned long long ticks = 0;  // wait limit in wall-clock ticks
 };
 constexpr int kSweepWaveFront = 64;   // largest front of the single-wave class
@@ -153,6 +154,10 @@ constexpr int kSweepWaveFront = 64;   // largest front of the single-wave class
 // most this many rows is held one row per thread (its panel row of the
 // current 64-column block in registers)
 constexpr int kGroupThreads = 768;
+// levels whose fronts all have at most this many rows stay on the LDS
+// forward workgroup sweep (256 threads)
+constexpr int kRowsMinFront = 256;
+constexpr int kRowsMaxGrid = 48;  // workgroups of the row-held forward launch
 constexpr int kSweepWaitSeconds = 4;  // a dependency wait longer than this is reported as an error
 constexpr int kSweepCtlWords = 8;     // ticket counters and epoch
 // largest number of supernodes above the single-wave levels for which the

@@ -1919,11 +1919,11 @@ k_bwd_waves(DevPlan P, const T* __restrict__ arena, int list_begin, int count, d
 // Control words of the dependency-driven sweeps (one array per handle):
 // four ticket counters and the sweep epoch.  A supernode's flag holds
 // 2*epoch after its forward step and 2*epoch+1 after its backward step.
-enum { kCtlFwdWave = 0, kCtlFwdGroup = 1, kCtlBwdGroup = 2, kCtlBwdWave = 3, kCtlEpoch = 4 };
+enum { kCtlFwdWave = 0, kCtlFwdGroup = 1, kCtlBwdGroup = 2, kCtlBwdWave = 3, kCtlEpoch = 4, kCtlFwdRows = 5 };
 
 __global__ void k_sweep_prep(unsigned* ctl) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctl[kCtlFwdWave] = ctl[kCtlFwdGroup] = ctl[kCtlBwdGroup] = ctl[kCtlBwdWave] = 0u;
+        ctl[kCtlFwdWave] = ctl[kCtlFwdGroup] = ctl[kCtlBwdGroup] = ctl[kCtlBwdWave] = ctl[kCtlFwdRows] = 0u;
         ctl[kCtlEpoch] = ctl[kCtlEpoch] + 1u;
     }
 }
@@ -2154,12 +2154,12 @@ k_fwd_group_rows(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl
     __shared__ int s_ticket[2];
     const int tid = threadIdx.x, nt = blockDim.x;
     const unsigned want = 2u * ctl[kCtlEpoch];
-    if (tid == 0) s_ticket[0] = (int)atomicAdd(&ctl[kCtlFwdGroup], 1u);
+    if (tid == 0) s_ticket[0] = (int)atomicAdd(&ctl[kCtlFwdRows], 1u);
     __syncthreads();
     for (int it = 0;; ++it) {
         const int t = s_ticket[it & 1] + t0;
         if (t >= t1) break;
-        if (tid == 0) s_ticket[(it + 1) & 1] = (int)atomicAdd(&ctl[kCtlFwdGroup], 1u);
+        if (tid == 0) s_ticket[(it + 1) & 1] = (int)atomicAdd(&ctl[kCtlFwdRows], 1u);
         const int s = P.lvl_all[t];
         const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
         const int ro = P.sn_rowptr[s], f = P.sn_rowptr[s + 1] - ro;
@@ -3361,14 +3361,15 @@ void launch_fwd_sched(const DevPlan& P, const SweepSched& S, const T* arena, dou
         hipLaunchKernelGGL(k_fwd_wave<T>, dim3(S.wave_grid), dim3(kWave), 0, st, P, arena, 0, S.wave_t1, v_perm, uvec,
                            ctl, done, err, S.ticks);
     const int t0 = waves ? S.wave_t1 : S.pair_t1, lvl0 = waves ? S.wave_lvl : S.pair_lvl;
-    if (S.ns > t0) {
-        if (S.rows)
-            hipLaunchKernelGGL(k_fwd_group_rows<T>, dim3(S.rows_grid), dim3(kGroupThreads), 0, st, P, arena, t0, S.ns,
-                               lvl0, v_perm, uvec, ctl, done, err, S.ticks);
-        else
-            hipLaunchKernelGGL(k_fwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, t0, S.ns,
-                               lvl0, S.ldd, v_perm, uvec, ctl, done, err, S.ticks);
-    }
+    // levels below rows_lvl on the LDS kernel, the rest row-held (their
+    // children below rows_lvl are finished by the first launch)
+    const int ts = S.rows ? std::max(t0, (int)S.rows_t0) : S.ns;
+    if (ts > t0)
+        hipLaunchKernelGGL(k_fwd_group<T>, dim3(S.group_grid), dim3(256), S.group_lds, st, P, arena, t0, ts, lvl0,
+                           S.ldd, v_perm, uvec, ctl, done, err, S.ticks);
+    if (S.ns > ts)
+        hipLaunchKernelGGL(k_fwd_group_rows<T>, dim3(S.rows_grid), dim3(kGroupThreads), 0, st, P, arena, ts, S.ns,
+                           std::max(lvl0, (int)S.rows_lvl), v_perm, uvec, ctl, done, err, S.ticks);
 }
 
 template <typename T>
@@ -3413,7 +3414,9 @@ bool sweep_sched_grids(SweepSched& S, int device) {
     orow = std::max(orow, 1);
     S.wave_grid = std::max(1, std::min(ow * cus, S.wave_t1));
     S.group_grid = std::max(1, std::min(og * cus, S.ns - S.wave_t1));
-    S.rows_grid = std::max(1, std::min(orow * cus, S.ns - S.wave_t1));
+    // the row-held launch covers the upper levels (few fronts per level):
+    // fewer workgroups, each taking several supernodes, run its code warm
+    S.rows_grid = std::max(1, std::min({orow * cus, kRowsMaxGrid, S.ns - std::max(S.wave_t1, S.rows_t0)}));
     return true;
 }
 
