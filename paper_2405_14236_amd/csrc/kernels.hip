@@ -1291,49 +1291,55 @@ __device__ __forceinline__ void stage_diag_block(const T* __restrict__ src, int 
 
 // Triangular solves of a staged diagonal block by one wave (D: the block's
 // lower triangle, leading dimension ldd, raw pivots on the diagonal; lane
-// r < nb holds entry r).  Each lane forms the reciprocal of its pivot; lane
-// k's value times it is the k-th unknown, broadcast from a register; the
-// other lanes update with selects (no divergent branches) and their own
-// row (forward) or column (backward) entry of D, read eight steps at a time
-// ahead of their use.  Lanes from nb on read row/column 0 and keep their
-// value.
-__device__ __forceinline__ void fwd_tri_step(double& vi, double rdl, double dk, int lane, int k, int nb) {
-    const double yk = lane_bcast(vi * rdl, k);
-    const double u = fma(-dk, yk, vi);
-    vi = lane == k ? yk : ((lane > k && lane < nb) ? u : vi);
-}
-__device__ __forceinline__ void bwd_tri_step(double& ri, double rdl, double dk, int lane, int k) {
-    const double xk = lane_bcast(ri * rdl, k);
-    const double u = fma(-dk, xk, ri);
-    ri = lane == k ? xk : (lane < k ? u : ri);
-}
+// r < nb holds entry r, lanes from nb on keep their value).  Each lane of
+// the block carries its value scaled by its reciprocal pivot, so that lane
+// k's value is the k-th unknown once the earlier steps are applied, and
+// takes step k as s -= (d / pivot) x_k with its multiplier zero unless it
+// is updated by step k: one broadcast and one fma per step on the
+// dependency chain.  The entries of D are read eight steps ahead.
 __device__ __forceinline__ double wave_fwd_tri(double vi, const double* D, int ldd, int nb) {
     const int lane = threadIdx.x % kWave, lr = lane < nb ? lane : 0;
+    const bool own = lane < nb;
     const double rdl = 1.0 / D[lr + lr * ldd];
+    double sv = own ? vi * rdl : vi;
     int k = 0;
     for (; k + 8 <= nb; k += 8) {
         double dk[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) dk[u] = D[lr + (k + u) * ldd];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) fwd_tri_step(vi, rdl, dk[u], lane, k + u, nb);
+        for (int u = 0; u < 8; ++u) {
+            const double m = (own && lane > k + u) ? dk[u] * rdl : 0.0;
+            sv = fma(-m, lane_bcast(sv, k + u), sv);
+        }
     }
-    for (; k < nb; ++k) fwd_tri_step(vi, rdl, D[lr + k * ldd], lane, k, nb);
-    return vi;
+    for (; k < nb; ++k) {
+        const double m = (own && lane > k) ? D[lr + k * ldd] * rdl : 0.0;
+        sv = fma(-m, lane_bcast(sv, k), sv);
+    }
+    return sv;
 }
 __device__ __forceinline__ double wave_bwd_tri(double ri, const double* D, int ldd, int nb) {
     const int lane = threadIdx.x % kWave, lr = lane < nb ? lane : 0;
+    const bool own = lane < nb;
     const double rdl = 1.0 / D[lr + lr * ldd];
+    double sv = own ? ri * rdl : ri;
     int k = nb - 1;
     for (; k >= 7; k -= 8) {
         double dk[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) dk[u] = D[(k - u) + lr * ldd];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) bwd_tri_step(ri, rdl, dk[u], lane, k - u);
+        for (int u = 0; u < 8; ++u) {
+            const double m = (own && lane < k - u) ? dk[u] * rdl : 0.0;
+            sv = fma(-m, lane_bcast(sv, k - u), sv);
+        }
     }
-    for (; k >= 0; --k) bwd_tri_step(ri, rdl, D[k + lr * ldd], lane, k);
-    return ri;
+    for (; k >= 0; --k) {
+        const double m = (own && lane < k) ? D[k + lr * ldd] * rdl : 0.0;
+        sv = fma(-m, lane_bcast(sv, k), sv);
+    }
+    return sv;
 }
 
 // Forward sweep of one supernode by a workgroup: v (LDS, f entries) holds
@@ -2096,10 +2102,10 @@ __device__ __forceinline__ void load_panel_row(T (&l)[kWave], const T* __restric
 // thread i holds v_i (vi), the reciprocal of its pivot when i < w (rd) and
 // its row of the panel in the current 64-column block (l; the caller loads
 // block 0).  Per block the wave that holds the block's rows solves it with
-// lane broadcasts from registers and leaves y in LDS (two buffers, so one
-// barrier per block suffices); every row below then subtracts its products
-// in column order and loads its row of the next block.  The arithmetic and
-// its order are fwd_front's.
+// lane broadcasts from registers (rows scaled by their reciprocal pivots)
+// and leaves y in LDS (two buffers, so one barrier per block suffices);
+// every row below then subtracts its products in column order (as
+// fwd_front does) and loads its row of the next block.
 template <typename T>
 __device__ __forceinline__ void fwd_rows(const T* __restrict__ L, int w, int f, double& vi, T (&l)[kWave],
                                          double rd, double* ybuf) {
@@ -2109,28 +2115,43 @@ __device__ __forceinline__ void fwd_rows(const T* __restrict__ L, int w, int f, 
         const int kb = b * kWave, nb = min(kWave, w - kb);
         double* y = ybuf + (b & 1) * kWave;
         if (wv == b) {
-            // lane k's v_k times its reciprocal pivot is y_k
+            // each row of the block carries s = v / pivot (s_k = y_k once
+            // the rows above are applied) and takes the update of row k as
+            // s -= (l_k / pivot) y_k, its multiplier zero unless the row is
+            // below k in the block: one broadcast and one fma per step on
+            // the dependency chain.  Steps in groups of eight (one branch
+            // per group); rows below the block (lanes >= nb) keep v.
             const int ln = opaque(lane);
+            const bool own = ln < nb;
+            double sv = own ? vi * rd : vi;
 #pragma unroll
-            for (int k = 0; k < kWave; ++k) {
-                if (k < nb) {
-                    const double yk = lane_bcast(vi * rd, k);
-                    const double u = fma(-(double)l[k], yk, vi);
-                    vi = ln == k ? yk : ((ln > k && ln < nb) ? u : vi);
+            for (int k0 = 0; k0 < kWave; k0 += 8) {
+                if (k0 < nb) {
+#pragma unroll
+                    for (int k = k0; k < k0 + 8; ++k) {
+                        const double m = (own && ln > k) ? (double)l[k] * rd : 0.0;
+                        sv = fma(-m, lane_bcast(sv, k), sv);
+                    }
                 }
-                if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            if (lane < nb) y[lane] = vi;
+            vi = sv;
+            if (own) y[lane] = vi;
         }
         __syncthreads();
         if (tid >= kb + nb && tid < f) {
-            // y read from LDS 8 entries at a time (bounded register use)
+            // y read from LDS 8 entries at a time (bounded register use);
+            // products of columns k >= nb are not added
             double acc = 0.0;
 #pragma unroll
             for (int k0 = 0; k0 < kWave; k0 += 8) {
+                if (k0 < nb) {
 #pragma unroll
-                for (int k = k0; k < k0 + 8; ++k)
-                    if (k < nb) acc = fma((double)l[k], y[k], acc);
+                    for (int k = k0; k < k0 + 8; ++k) {
+                        const double a = fma((double)l[k], y[k], acc);
+                        acc = k < nb ? a : acc;
+                    }
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
             vi -= acc;
