@@ -81,6 +81,10 @@ constexpr int kCompactFront32 = 90;  // fronts with f^2 * 4 <= 32 KiB
 constexpr int kPanelNB = 32;    // panel width of the tiled front path
 constexpr int kPanelRows = 256; // rows of the panel solved per workgroup
 constexpr int kPanelLd = 64;    // leading dimension of the panel's diagonal block in LDS (one wave's rows)
+// FP64 panel launch: rows below the block per workgroup (32 per wave), and
+// its LDS (one kPanelLd x kPanelNB column exchange per wave)
+constexpr int kFusedPanelRows = 128;
+constexpr int kFusedPanelLds = 4 * kPanelLd * kPanelNB * 8;
 // FP64 levels with fronts of at least kWideFront rows update their trailing
 // matrices once per kWideRank columns (rank-kWideRank MFMA updates)
 constexpr int kWideRank = 128;

@@ -58,6 +58,21 @@ __device__ __forceinline__ float bcast<float>(float x, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
 }
 
+// x, opaque to the optimizer: lane comparisons made from it inside a loop
+// are not hoisted out of it (64 lane masks kept across a loop would not fit
+// in scalar registers).  Emits no instruction.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+// Completes the load that produced x here (the empty asm reads x, so the
+// wait for it is placed before it), and leaves x as a value that is no
+// longer a pending load: later uses inside loops then wait for nothing,
+// in particular not for younger loads still in flight.
+__device__ __forceinline__ double settle(double x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
 
 // Per-block maxima of (ratio, |res|) pushed with one atomic each when the
 // whole block belongs to one instance, else one atomic per element.  The
@@ -298,7 +313,7 @@ __device__ void rows_trsm(T* B, int ld, const T* D, int ldd, int nb, int i0, int
 
 // Full kDiag-column diagonal block of an LDS front (leading dimension ld),
 // right-looking with row i in the registers of lane i (lanes 0..kDiag-1
-// call it).  As potrf_reg_full: select pivots (a failure is recorded after
+// call it).  As k_big_panel_fused: select pivots (a failure is recorded after
 // the loop as pivot_root records it), the column store writes back the old
 // value above the diagonal (one store per lane, no branch), and a
 // scheduling barrier per column keeps each column's updates in that
@@ -311,7 +326,7 @@ __device__ __forceinline__ void potrf_diag_reg(T* A, int ld, int col0, int32_t* 
 #pragma unroll
     for (int t = 0; t < NB; ++t) a[t] = t <= lane ? A[lane + t * ld] : T(0);
     int first_bad = INT_MAX, n_bad = 0;
-    // as potrf_reg_full: the next column's entry takes its multiplier by a
+    // as k_big_panel_fused: the next column's entry takes its multiplier by a
     // lane read, the others one column late from LDS (loaded while the next
     // pivot is computed), in the same order of operations
     T m[NB];
@@ -808,74 +823,13 @@ k_big_init_cols(DevPlan P, const double* __restrict__ K, T* __restrict__ arena, 
 }
 
 // Cholesky of the nb x nb (nb <= 32) lower triangle D (LDS, leading
-// dimension kPanelNB) by one wave, right-looking with the rows in
-// registers: lane i keeps row i; per column j the pivot comes from lane j,
-// the column is scaled and written back to LDS, and every lane subtracts
-// l_ij l_kj from its entries k > j, reading l_kj as LDS broadcasts (one
-// address for the whole wave).  The chain per column is a lane read, the
-// pivot's reciprocal square root and a multiply; the updates overlap it.
-// Cholesky of a full kPanelNB x kPanelNB block (LDS, leading dimension
-// kPanelLd) by one wave, right-looking with row i in lane i's registers.
-// One basic block: pivots by select (a failed pivot is recorded after the
-// loop exactly as pivot_root records it), every lane stores its column
-// entry (rows >= kPanelNB land in the padding, entries above the diagonal
-// are never read), and a scheduling barrier per column keeps each column's
-// updates in that column (left to the scheduler they sink to the next
-// pivot and put a chain of up to 31 dependent FMAs in front of it).
-template <typename T>
-__device__ __forceinline__ void potrf_reg_full(T* D, int col0, int32_t* status, T* rdiag) {
-    constexpr int NB = kPanelNB;
-    const int lane = threadIdx.x % kWave;
-    T a[NB];
-#pragma unroll
-    for (int t = 0; t < NB; ++t) a[t] = (lane < NB && t <= lane) ? D[lane + t * kPanelLd] : T(0);
-    int first_bad = INT_MAX, n_bad = 0;
-    // column j's multipliers reach the entries k >= j + 2 one column late
-    // (loaded from LDS in column j, applied at the start of column j + 1,
-    // still before column j + 1's own update of each entry), so the LDS
-    // round trip overlaps the next pivot instead of preceding it
-    T m[NB];
-    T lprev = T(0);
-#pragma unroll
-    for (int t = 0; t < NB; ++t) m[t] = T(0);
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        // the pivot first (a[j] is complete), then the late updates
-        T r;
-        bool fail;
-        const T ljj = pivot_select<T>(bcast<T>(a[j], j), r, fail);
-        if (j >= 1) {
-#pragma unroll
-            for (int k = j + 1; k < NB; ++k) a[k] = fma(-lprev, m[k], a[k]);
-        }
-        first_bad = (fail && first_bad == INT_MAX) ? j : first_bad;
-        n_bad += fail ? 1 : 0;
-        const T lij = lane == j ? ljj : a[j] * r;
-        D[lane + j * kPanelLd] = lij;
-        rdiag[j] = r;
-        // the next pivot's column takes its multiplier by a lane read (off
-        // the LDS store/load round trip)
-        if (j + 1 < NB) a[j + 1] = fma(-lij, bcast<T>(lij, j + 1), a[j + 1]);
-#pragma unroll
-        for (int k = j + 2; k < NB; ++k) m[k] = D[k + j * kPanelLd];
-        lprev = lij;
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    if (status && lane == 0) {
-        if (std::is_same<T, double>::value) {
-            if (first_bad != INT_MAX) atomicMin(status, col0 + first_bad);
-        } else if (n_bad > 0) {
-            atomicAdd(status + 1, n_bad);
-        }
-    }
-}
-
+// dimension kPanelLd) by one wave (the FP32 panels), right-looking with the
+// rows in registers: lane i keeps row i; per column j the pivot comes from
+// lane j, the column is scaled and written back to LDS, and every lane
+// subtracts l_ij l_kj from its entries k > j, reading l_kj as LDS
+// broadcasts (one address for the whole wave).
 template <typename T>
 __device__ __forceinline__ void potrf32_reg(T* D, int nb, int col0, int32_t* status, T* rdiag) {
-    if (sizeof(T) == 8 && nb == kPanelNB) {  // (the FP32 instance of the full form spills)
-        potrf_reg_full<T>(D, col0, status, rdiag);
-        return;
-    }
     const int lane = threadIdx.x % kWave;
     const bool act = lane < nb;
     T a[kPanelNB];
@@ -896,19 +850,21 @@ __device__ __forceinline__ void potrf32_reg(T* D, int nb, int col0, int32_t* sta
     }
 }
 
-// Large fronts, step 2 (per block column kb), grid (row chunk, front):
-// every workgroup stages the 32 x 32 diagonal block, one wave factors it
-// (the same arithmetic in every workgroup) while the workgroup's rows are
-// loaded, and each thread then solves its row of the chunk (kPanelRows
-// rows below the block) in registers, right-looking, with the factored
-// block read as LDS broadcasts.  With one chunk the factored block is
-// written back in place; with several, chunk 0 leaves it in dscr (another
-// chunk may still be reading the original block) and the trailing-update
-// launch copies it into the front.
+// Large fronts, step 2 in FP32 (per block column kb), grid (row chunk,
+// front): every workgroup stages the diagonal block (nb x nb, nb <= 32), one
+// wave factors it (the same arithmetic in every workgroup) while the
+// workgroup's rows are loaded, and each thread then solves its row of the
+// chunk (kPanelRows rows below the block) in registers, right-looking, with
+// the factored block read as LDS broadcasts.  With one chunk the factored
+// block is written back in place; with several, chunk 0 leaves it in dscr
+// (another chunk may still be reading the original block) and the
+// trailing-update launch copies it into the front.  (FP64 panels:
+// k_big_panel_fused.)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* status, T* __restrict__ dscr) {
     static_assert(kPanelRows == 256, "one row per thread");
+    static_assert(sizeof(T) == 4, "the FP32 panel");
     __shared__ T D[kPanelLd * kPanelNB];
     __shared__ T s_rdiag[kPanelNB];
     const int s = P.lvl_big[list_begin + blockIdx.y];
@@ -922,35 +878,25 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
     if (blockIdx.x > 0 && r0 >= f) return;
     const int nr = r0 < f ? min(kPanelRows, f - r0) : 0;
     // the diagonal block's loads and this thread's row are issued together
-    // FP64 blocks are staged 32 x 32: one narrower than kPanelNB is padded
-    // with an identity (unit pivots, zero multipliers), so that the
-    // full-width Cholesky factors it without touching the real entries'
-    // arithmetic, and the row solve needs no per-entry bounds
-    const int nbs = sizeof(T) == 8 ? kPanelNB : nb;
     T t4[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int idx = u * nt + tid;
-        const int i = idx % nbs, j = idx / nbs;
-        t4[u] = (idx < nbs * nbs && i >= j) ? ((i < nb && j < nb) ? F[(kb + i) + (int64_t)(kb + j) * f]
-                                                                  : (i == j ? T(1) : T(0)))
-                                            : T(0);
+        const int i = idx % nb, j = idx / nb;
+        t4[u] = (idx < nb * nb && i >= j) ? F[(kb + i) + (int64_t)(kb + j) * f] : T(0);
     }
     const bool row = tid < nr;
     T* Fr = F + (row ? r0 + tid : kb) + (int64_t)kb * f;
     T x[kPanelNB];
 #pragma unroll
     for (int t = 0; t < kPanelNB; ++t) x[t] = (row && t < nb) ? Fr[(int64_t)t * f] : T(0);
-    // FP64: a block narrower than kPanelNB is padded with an identity (unit
-    // pivots, zero multipliers) so that the full-width forms factor and
-    // solve it; the padding leaves the real entries' arithmetic unchanged
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int idx = u * nt + tid;
-        if (idx < nbs * nbs) D[idx % nbs + (idx / nbs) * kPanelLd] = t4[u];
+        if (idx < nb * nb) D[idx % nb + (idx / nb) * kPanelLd] = t4[u];
     }
     __syncthreads();
-    if (tid < kWave) potrf32_reg<T>(D, nbs, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
+    if (tid < kWave) potrf32_reg<T>(D, nb, c0 + kb, blockIdx.x == 0 ? status : nullptr, s_rdiag);
     __syncthreads();
     if (blockIdx.x == 0) {
         T* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * kPanelNB * kPanelNB;
@@ -961,55 +907,125 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
         }
     }
     if (!row) return;
-    if (sizeof(T) == 8 && nb == kPanelNB) {
-        // one basic block; the barrier keeps each column's updates in that
-        // column (see potrf_reg_full); the next column's multipliers are
-        // loaded while the current column's are applied
-        T dc[kPanelNB], dn[kPanelNB];
-        T rc = s_rdiag[0];
 #pragma unroll
-        for (int k = 1; k < kPanelNB; ++k) dc[k] = D[k];
+    for (int j = 0; j < kPanelNB; ++j) {
+        if (j < nb) {
+            x[j] *= s_rdiag[j];
 #pragma unroll
-        for (int j = 0; j < kPanelNB; ++j) {
-            T rn = T(0);
-            if (j + 1 < kPanelNB) {
-                rn = s_rdiag[j + 1];
-#pragma unroll
-                for (int k = j + 2; k < kPanelNB; ++k) dn[k] = D[k + (j + 1) * kPanelLd];
-            }
-            x[j] *= rc;
-#pragma unroll
-            for (int k = j + 1; k < kPanelNB; ++k) x[k] = fma(-x[j], dc[k], x[k]);
-#pragma unroll
-            for (int k = j + 2; k < kPanelNB; ++k) dc[k] = dn[k];
-            rc = rn;
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else if (sizeof(T) == 8) {
-        // a padded block: the multipliers past nb are zeros, so only the
-        // column loop stops at nb
-#pragma unroll
-        for (int j = 0; j < kPanelNB; ++j) {
-            if (j < nb) {
-                x[j] *= s_rdiag[j];
-#pragma unroll
-                for (int k = j + 1; k < kPanelNB; ++k) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < kPanelNB; ++j) {
-            if (j < nb) {
-                x[j] *= s_rdiag[j];
-#pragma unroll
-                for (int k = j + 1; k < kPanelNB; ++k)
-                    if (k < nb) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
-            }
+            for (int k = j + 1; k < kPanelNB; ++k)
+                if (k < nb) x[k] = fma(-x[j], D[k + j * kPanelLd], x[k]);
         }
     }
 #pragma unroll
     for (int t = 0; t < kPanelNB; ++t)
         if (t < nb) Fr[(int64_t)t * f] = x[t];
+}
+
+// Large fronts, step 2 in FP64: the diagonal Cholesky and the row solves
+// in one right-looking pass.  In every wave, lanes 0..31 hold the rows of
+// the 32 x 32 diagonal block (padded with an identity when narrower: unit
+// pivots, zero multipliers) and lanes 32..63 hold 32 rows below it; per
+// column j the pivot comes from lane j and every lane scales its entry j by
+// the pivot's reciprocal and subtracts l_ij l_kj from its entries k > j, so
+// that a row below the block is solved by exactly the steps that factor the
+// block's own rows.  Each wave factors the block itself (no LDS staging, no
+// barrier before the solves).  The columns are one basic block: pivots by
+// select (a failed pivot is recorded after the loop exactly as pivot_root
+// records it), every lane stores its column entry to the wave's LDS slice
+// (kPanelLd x kPanelNB doubles; lanes 32..63 land in the padding), the next
+// column's entry takes its multiplier by a lane read and the others take
+// theirs one column late from LDS (loaded while the next pivot is
+// computed), and a scheduling barrier per column keeps each column's
+// updates in that column (left to the scheduler they sink to the next
+// pivot and put a chain of up to 31 dependent FMAs in front of it).  Every
+// entry sees the operations of a column-by-column Cholesky of the block and
+// a forward substitution of each row against it, in the same order.  Grid
+// (row chunk of kFusedPanelRows rows, front), 256 threads.  With one chunk
+// the factored block is written back in place (after a barrier: every wave
+// has read it); with several, chunk 0 leaves it in dscr and the
+// trailing-update launch copies it into the front.
+__global__ void __launch_bounds__(256)
+k_big_panel_fused(DevPlan P, double* __restrict__ arena, int list_begin, int kb, int32_t* status,
+                  double* __restrict__ dscr) {
+    constexpr int NB = kPanelNB;
+    static_assert(2 * NB == kWave && kFusedPanelRows == 4 * NB, "block rows and chunk rows share each wave");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int s = P.lvl_big[list_begin + blockIdx.y];
+    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+    const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
+    if (kb >= w) return;  // workgroup-uniform
+    const int nb = min(NB, w - kb);
+    double* F = arena + P.l_off[s];
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    const int r0 = kb + nb + blockIdx.x * kFusedPanelRows;
+    if (blockIdx.x > 0 && r0 >= f) return;  // workgroup-uniform
+    const bool blk = lane < NB;              // a row of the diagonal block
+    const int rr = r0 + wid * NB + (lane - NB);  // (lanes 32..63) row of the front
+    const bool row = !blk && rr < f;
+    // the lane's row, from clamped addresses (every load in bounds, no
+    // branches between the loads).  The block's padding is selected to an
+    // exact identity (its pivots are reported); a row's entries past nb,
+    // and the entries of lanes without a row, keep whatever they loaded:
+    // they only ever reach entries that are not stored.
+    const int ri = blk ? kb + (lane < nb ? lane : 0) : (row ? rr : kb);
+    double* Fl = F + ri + (int64_t)kb * f;
+    double a[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        const int tc = (t < nb && (!blk || t <= lane)) ? t : 0;
+        a[t] = Fl[(int64_t)tc * f];
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+        if (blk) a[t] = (lane < nb && t <= lane) ? a[t] : (lane == t ? 1.0 : 0.0);
+    double* Dx = reinterpret_cast<double*>(smem_raw) + wid * (kPanelLd * NB);
+    double m[NB];
+    double lprev = 0.0;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) m[t] = 0.0;
+    int first_bad = INT_MAX;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        double r;
+        bool fail;
+        const double ljj = pivot_select<double>(bcast<double>(a[j], j), r, fail);
+        if (j >= 1) {
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) a[k] = fma(-lprev, m[k], a[k]);
+        }
+        first_bad = (fail && first_bad == INT_MAX) ? j : first_bad;
+        const double lij = lane == j ? ljj : a[j] * r;
+        Dx[lane + j * kPanelLd] = lij;  // (lanes 32..63 land in the slice's padding)
+        a[j] = lij;
+        if (j + 1 < NB) a[j + 1] = fma(-lij, bcast<double>(lij, j + 1), a[j + 1]);
+#pragma unroll
+        for (int k = j + 2; k < NB; ++k) m[k] = Dx[k + j * kPanelLd];
+        lprev = lij;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // every wave has consumed its loads of the block before it is
+    // overwritten in place
+    __syncthreads();
+    const int tn = opaque(nb);  // (kept out of the column loop's registers)
+    if (blk) {
+        if (blockIdx.x != 0 || wid != 0) return;
+        if (status && lane == 0 && first_bad != INT_MAX) atomicMin(status, c0 + kb + first_bad);
+        double* dst = gridDim.x == 1 ? F + kb + (int64_t)kb * f : dscr + (size_t)blockIdx.y * NB * NB;
+        const int64_t ld = gridDim.x == 1 ? f : NB;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j < tn && j <= lane && lane < tn) dst[lane + j * ld] = a[j];
+        return;
+    }
+    if (!row) return;
+    if (nb == NB) {
+#pragma unroll
+        for (int t = 0; t < NB; ++t) Fl[(int64_t)t * f] = a[t];
+    } else {
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+            if (t < tn) Fl[(int64_t)t * f] = a[t];
+    }
 }
 
 // Large fronts, step 3: trailing update C -= P P^T of the lower triangle
@@ -2047,22 +2063,6 @@ k_bwd_wave(DevPlan P, const T* __restrict__ arena, int t0, int t1, int lvl_hi, d
         __syncthreads();
         if (lane == 0) flag_store(&done[s], want);
     }
-}
-
-// x, opaque to the optimizer: lane comparisons made from it inside a loop
-// are not hoisted out of it (64 lane masks kept across a loop would not fit
-// in scalar registers).  Emits no instruction.
-__device__ __forceinline__ int opaque(int x) {
-    asm volatile("" : "+v"(x));
-    return x;
-}
-// Completes the load that produced x here (the empty asm reads x, so the
-// wait for it is placed before it), and leaves x as a value that is no
-// longer a pending load: later uses inside loops then wait for nothing,
-// in particular not for younger loads still in flight.
-__device__ __forceinline__ double settle(double x) {
-    asm volatile("" : "+v"(x));
-    return x;
 }
 
 // Row r of columns c .. c + 63 of a column-major panel with leading
@@ -3157,6 +3157,8 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - 1024);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_big_init_cols<T>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 4 * kInitColRows * (int)sizeof(T));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_big_panel_fused),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kFusedPanelLds);
         attr_set = true;
     }
     // fronts above the LDS limit run on the side stream, concurrently with
@@ -3189,9 +3191,15 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
         for (int kw = 0; kw < L.big_maxw; kw += step) {
             for (int kb = kw; kb < std::min(kw + step, L.big_maxw); kb += kPanelNB) {
                 const int below = L.big_maxf - kb - 1;  // upper bound of rows below the block, any front
-                const int chunks = below > 0 ? (below + kPanelRows - 1) / kPanelRows : 1;
-                hipLaunchKernelGGL(k_big_panel<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena,
-                                   L.big_begin, kb, status, reinterpret_cast<T*>(dscr));
+                const int crows = sizeof(T) == 8 ? kFusedPanelRows : kPanelRows;
+                const int chunks = below > 0 ? (below + crows - 1) / crows : 1;
+                if constexpr (sizeof(T) == 8) {
+                    hipLaunchKernelGGL(k_big_panel_fused, dim3(chunks, L.big_count), dim3(256), kFusedPanelLds,
+                                       sb, P, arena, L.big_begin, kb, status, dscr);
+                } else {
+                    hipLaunchKernelGGL(k_big_panel<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena,
+                                       L.big_begin, kb, status, reinterpret_cast<T*>(dscr));
+                }
                 // in a wide panel the update stops at the panel's end (after
                 // its last panel it only reaches fronts whose own columns end
                 // inside the wide panel, for their columns up to its end)
