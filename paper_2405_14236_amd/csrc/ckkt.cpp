@@ -242,6 +242,11 @@ void build_levels(ckkt_handle* h) {
             L.big_maxw = std::max(L.big_maxw, width(P.lvl_big[t]));
             L.big_maxf = std::max(L.big_maxf, front(P.lvl_big[t]));
         }
+        L.big_one = BigOne{0, 0, 0, -1};
+        if (L.big_count == 1) {
+            const int sb = P.lvl_big[L.big_begin];
+            L.big_one = BigOne{P.sn_start[sb], width(sb), front(sb), P.l_off[sb]};
+        }
         L.all_begin = P.lvl_all_ptr[l];
         L.all_count = P.lvl_all_ptr[l + 1] - L.all_begin;
         L.all_maxf = L.all_maxw = 0;

@@ -45,6 +45,14 @@ struct SysVals {
 };
 
 // Per-level launch geometry, computed on the host from the plan.
+// The only large front of a level (loff < 0: the level has several), given
+// to its panel and trailing-update launches as arguments: their workgroups
+// then skip two rounds of dependent metadata loads.
+struct BigOne {
+    int32_t c0, w, f;
+    int64_t loff;
+};
+
 struct LevelInfo {
     int32_t small_begin, small_count, small_maxf;
     int32_t small_split, small_split32;  // fronts [begin, begin+split) have f <= kCompactFront64 / 32
@@ -58,6 +66,7 @@ struct LevelInfo {
     int32_t sweep_tiled_f;      // fronts with f >= this are swept by the tiled kernels
     int32_t sweep_small_count;  // fronts of the level swept one workgroup each (f < sweep_tiled_f)
     int32_t tflag_off;          // first block flag of the level's tiled fronts
+    BigOne big_one;             // its only large front (loff < 0 if not one)
 };
 
 constexpr int kBigTile = 64;    // column tile of the tiled front path

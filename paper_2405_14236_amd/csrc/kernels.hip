@@ -945,17 +945,23 @@ k_big_panel(DevPlan P, T* __restrict__ arena, int list_begin, int kb, int32_t* s
 // has read it); with several, chunk 0 leaves it in dscr and the
 // trailing-update launch copies it into the front.
 __global__ void __launch_bounds__(256)
-k_big_panel_fused(DevPlan P, double* __restrict__ arena, int list_begin, int kb, int32_t* status,
+k_big_panel_fused(DevPlan P, BigOne one, double* __restrict__ arena, int list_begin, int kb, int32_t* status,
                   double* __restrict__ dscr) {
     constexpr int NB = kPanelNB;
     static_assert(2 * NB == kWave && kFusedPanelRows == 4 * NB, "block rows and chunk rows share each wave");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int s = P.lvl_big[list_begin + blockIdx.y];
-    const int c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
-    const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
+    int c0, w, f;
+    int64_t loff;
+    if (one.loff >= 0) {
+        c0 = one.c0, w = one.w, f = one.f, loff = one.loff;
+    } else {
+        const int s = P.lvl_big[list_begin + blockIdx.y];
+        c0 = P.sn_start[s], w = P.sn_start[s + 1] - c0;
+        f = P.sn_rowptr[s + 1] - P.sn_rowptr[s], loff = P.l_off[s];
+    }
     if (kb >= w) return;  // workgroup-uniform
     const int nb = min(NB, w - kb);
-    double* F = arena + P.l_off[s];
+    double* F = arena + loff;
     const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     const int r0 = kb + nb + blockIdx.x * kFusedPanelRows;
     if (blockIdx.x > 0 && r0 >= f) return;  // workgroup-uniform
@@ -980,7 +986,7 @@ k_big_panel_fused(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
         if (blk) a[t] = (lane < nb && t <= lane) ? a[t] : (lane == t ? 1.0 : 0.0);
     double* Dx = reinterpret_cast<double*>(smem_raw) + wid * (kPanelLd * NB);
     double m[NB];
-    double lprev = 0.0;
+    double lprev = 0.0, dn = 0.0;
 #pragma unroll
     for (int t = 0; t < NB; ++t) m[t] = 0.0;
     int first_bad = INT_MAX;
@@ -988,7 +994,7 @@ k_big_panel_fused(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
     for (int j = 0; j < NB; ++j) {
         double r;
         bool fail;
-        const double ljj = pivot_select<double>(bcast<double>(a[j], j), r, fail);
+        const double ljj = pivot_select<double>(bcast<double>(j == 0 ? a[0] : dn, j), r, fail);
         if (j >= 1) {
 #pragma unroll
             for (int k = j + 1; k < NB; ++k) a[k] = fma(-lprev, m[k], a[k]);
@@ -997,7 +1003,13 @@ k_big_panel_fused(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
         const double lij = lane == j ? ljj : a[j] * r;
         Dx[lane + j * kPanelLd] = lij;  // (lanes 32..63 land in the slice's padding)
         a[j] = lij;
-        if (j + 1 < NB) a[j + 1] = fma(-lij, bcast<double>(lij, j + 1), a[j + 1]);
+        if (j + 1 < NB) {
+            // the next pivot's entry, formed in its own lane (its multiplier
+            // is its own l_ij: the same value as the broadcast, one lane
+            // read shorter on the pivot chain)
+            dn = fma(-lij, lij, a[j + 1]);
+            a[j + 1] = fma(-lij, bcast<double>(lij, j + 1), a[j + 1]);
+        }
 #pragma unroll
         for (int k = j + 2; k < NB; ++k) m[k] = Dx[k + j * kPanelLd];
         lprev = lij;
@@ -1034,19 +1046,24 @@ k_big_panel_fused(DevPlan P, double* __restrict__ arena, int list_begin, int kb,
 // wide panel when the trailing part gets one wide update later).
 template <typename T, int PW>
 __global__ void __launch_bounds__(256)
-k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* __restrict__ dscr, int copy_d,
-             int col_end) {
+k_big_update(DevPlan P, BigOne one, T* __restrict__ arena, int list_begin, int kb, const T* __restrict__ dscr,
+             int copy_d, int col_end) {
     __shared__ T A[PW][64];  // panel column t of the tile's rows in A[t]
     __shared__ T B[PW][64];
-    const int s = P.lvl_big[list_begin + blockIdx.z];
-    const int w = P.sn_start[s + 1] - P.sn_start[s];
-    const int f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
+    int w, f;
+    int64_t loff;
+    if (one.loff >= 0) {
+        w = one.w, f = one.f, loff = one.loff;
+    } else {
+        const int s = P.lvl_big[list_begin + blockIdx.z];
+        w = P.sn_start[s + 1] - P.sn_start[s], f = P.sn_rowptr[s + 1] - P.sn_rowptr[s], loff = P.l_off[s];
+    }
     if (kb >= w) return;
     if (copy_d && blockIdx.x == 0 && blockIdx.y == 0) {
         // the factored diagonal block left by a multi-chunk panel launch
         const int nb = min(PW, w - kb);
         const T* src = dscr + (size_t)blockIdx.z * PW * PW;
-        T* F = arena + P.l_off[s];
+        T* F = arena + loff;
         for (int idx = threadIdx.x; idx < nb * nb; idx += blockDim.x) {
             const int i = idx % nb, j = idx / nb;
             if (i >= j) F[(kb + i) + (int64_t)(kb + j) * f] = src[i + j * PW];
@@ -1058,7 +1075,7 @@ k_big_update(DevPlan P, T* __restrict__ arena, int list_begin, int kb, const T* 
     const int base = kb + nb;
     const int i0 = base + ti * 64, j0 = base + tj * 64;
     if (i0 >= f || j0 >= col_end) return;
-    T* F = arena + P.l_off[s];
+    T* F = arena + loff;
     const int tid = threadIdx.x;
     const int cmax = min(f, col_end);
     using M = Mfma<T>;
@@ -3195,7 +3212,7 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                 const int chunks = below > 0 ? (below + crows - 1) / crows : 1;
                 if constexpr (sizeof(T) == 8) {
                     hipLaunchKernelGGL(k_big_panel_fused, dim3(chunks, L.big_count), dim3(256), kFusedPanelLds,
-                                       sb, P, arena, L.big_begin, kb, status, dscr);
+                                       sb, P, L.big_one, arena, L.big_begin, kb, status, dscr);
                 } else {
                     hipLaunchKernelGGL(k_big_panel<T>, dim3(chunks, L.big_count), dim3(256), 0, sb, P, arena,
                                        L.big_begin, kb, status, reinterpret_cast<T*>(dscr));
@@ -3211,7 +3228,7 @@ bool launch_factor_level(const DevPlan& P, const LevelInfo& L, const double* K, 
                 const int tcols = wide ? std::min(tiles, (kw + step - kb) / 64 + 1) : tiles;
                 if (tiles > 0)
                     hipLaunchKernelGGL((k_big_update<T, kPanelNB>), dim3(tiles, tcols, L.big_count), dim3(256), 0,
-                                       sb, P, arena, L.big_begin, kb, reinterpret_cast<const T*>(dscr),
+                                       sb, P, L.big_one, arena, L.big_begin, kb, reinterpret_cast<const T*>(dscr),
                                        chunks > 1 ? 1 : 0, col_end);
             }
             if (!wide) continue;
