@@ -1048,8 +1048,6 @@ template <typename T, int PW>
 __global__ void __launch_bounds__(256)
 k_big_update(DevPlan P, BigOne one, T* __restrict__ arena, int list_begin, int kb, const T* __restrict__ dscr,
              int copy_d, int col_end) {
-    __shared__ T A[PW][64];  // panel column t of the tile's rows in A[t]
-    __shared__ T B[PW][64];
     int w, f;
     int64_t loff;
     if (one.loff >= 0) {
@@ -1095,43 +1093,42 @@ k_big_update(DevPlan P, BigOne one, T* __restrict__ arena, int list_begin, int k
                 const int row = i0 + qi * 32 + a * 16 + M::row(r, lk), col = j0 + qj * 32 + b * 16 + li;
                 old[a][b][r] = (quad && row < f && col < cmax && row >= col) ? F[row + (int64_t)col * f] : T(0);
             }
+    // four waves, one 32 x 32 quadrant each, 2 x 2 MFMA tiles of 16 x 16:
+    // each wave loads its own operands of every step straight from the
+    // front (the rows of its quadrant, four panel columns per step), all
+    // issued before the first matrix-core step
+    if (!quad) return;  // quadrant above the diagonal (wave-uniform)
     {
-        constexpr int kPer = 64 * PW / 256;
-        T ta[kPer], tb[kPer];
+        constexpr int kSteps = PW / 4;
+        T av[kSteps][2], bv[kSteps][2];
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int idx = u * 256 + tid;
-            const int ii = idx % 64, t = idx / 64;
-            const int gi = i0 + ii, gj = j0 + ii;
-            ta[u] = (gi < f && t < nb) ? F[gi + (int64_t)(kb + t) * f] : T(0);
-            tb[u] = (gj < f && t < nb) ? F[gj + (int64_t)(kb + t) * f] : T(0);
-        }
+        for (int u = 0; u < kSteps; ++u) {
+            const int t = 4 * u + lk;
+            const int64_t col = (int64_t)(kb + (t < nb ? t : 0)) * f;
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int idx = u * 256 + tid;
-            A[idx / 64][idx % 64] = ta[u];
-            B[idx / 64][idx % 64] = tb[u];
+            for (int a = 0; a < 2; ++a) {
+                const int gi = i0 + qi * 32 + a * 16 + li;
+                av[u][a] = (gi < f && t < nb) ? F[gi + col] : T(0);
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int gj = j0 + qj * 32 + b * 16 + li;
+                bv[u][b] = (gj < f && t < nb) ? F[gj + col] : T(0);
+            }
         }
-    }
-    __syncthreads();
-    {
-        // four waves, one 32 x 32 quadrant each, 2 x 2 MFMA tiles of 16 x 16
-        if (!quad) return;  // quadrant above the diagonal (wave-uniform)
         typename M::acc c[2][2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) c[a][b] = M::zero();
-        for (int t = 0; t < nb; t += 4) {
-            T av[2], bv[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = A[t + lk][qi * 32 + a * 16 + li];
+        for (int u = 0; u < kSteps; ++u) {
+            if (4 * u < nb) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = B[t + lk][qj * 32 + b * 16 + li];
+                for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) c[a][b] = M::step(av[a], bv[b], c[a][b]);
+                    for (int b = 0; b < 2; ++b) c[a][b] = M::step(av[u][a], bv[u][b], c[a][b]);
+            }
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
