@@ -2456,10 +2456,26 @@ __device__ __forceinline__ void row_jx(const DevPlan& P, const SysVals& v, int r
     }
     acc = 0.0;
     mag = 0.0;
-    for (int a = a0; a < a1; ++a) {
-        const double p = jval(v, P.nnzg, a) * x[P.j_col[a]];
-        acc += p;
-        mag += fabs(p);
+    // four entries at a time: column indices, then values, then the terms
+    // added in order
+    for (int a = a0; a < a1; a += 4) {
+        int ci[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ci[u] = a + u < a1 ? P.j_col[a + u] : 0;
+        double jv[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = a + u < a1;
+            jv[u] = ok ? jval(v, P.nnzg, a + u) : 0.0;
+            xv[u] = ok ? x[ci[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (a + u < a1) {
+                const double p = jv[u] * xv[u];
+                acc += p;
+                mag += fabs(p);
+            }
     }
 }
 
@@ -2514,30 +2530,87 @@ k_resid_vars(DevPlan P, SysVals v, const double* __restrict__ x, const double* _
     double ratio = 0.0, num = 0.0;
     int inst = -1;
     if (in) {
+        // the entries of each sum four at a time: their index loads issued
+        // together, then their value loads, then the terms added in order
+        // (the same sums as one entry at a time)
         double acc = 0.0, mag = 0.0;
-        for (int k = P.wf_ptr[i]; k < P.wf_ptr[i + 1]; ++k) {
-            double p = v.w_val[P.wf_vidx[k]] * x[P.wf_col[k]];
-            acc += p;
-            mag += fabs(p);
+        const int w0 = P.wf_ptr[i], w1 = P.wf_ptr[i + 1];
+        for (int k = w0; k < w1; k += 4) {
+            int vi[4], ci[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = k + u < w1;
+                vi[u] = ok ? P.wf_vidx[k + u] : 0;
+                ci[u] = ok ? P.wf_col[k + u] : 0;
+            }
+            double wv[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = k + u < w1;
+                wv[u] = ok ? v.w_val[vi[u]] : 0.0;
+                xv[u] = ok ? x[ci[u]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k + u < w1) {
+                    const double p = wv[u] * xv[u];
+                    acc += p;
+                    mag += fabs(p);
+                }
         }
         double px = v.sigma_x[i] * x[i];
         acc += px;
         mag += fabs(px);
-        const int gend = P.jt_gend[i];
+        const int gend = P.jt_gend[i], k1 = P.jt_ptr[i + 1];
         int k0 = P.jt_ptr[i];
         if (P.hy) {
-            for (int k = k0; k < gend; ++k) {
-                double p = jval(v, P.nnzg, P.jt_vidx[k]) * y[P.jt_row[k]];
-                acc += p;
-                mag += fabs(p);
+            for (int k = k0; k < gend; k += 4) {
+                int ai[4], ri[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = k + u < gend;
+                    ai[u] = ok ? P.jt_vidx[k + u] : 0;
+                    ri[u] = ok ? P.jt_row[k + u] : 0;
+                }
+                double gv[4], yv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = k + u < gend;
+                    gv[u] = ok ? jval(v, P.nnzg, ai[u]) : 0.0;
+                    yv[u] = ok ? y[ri[u]] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (k + u < gend) {
+                        const double p = gv[u] * yv[u];
+                        acc += p;
+                        mag += fabs(p);
+                    }
             }
             k0 = gend;
         }
-        for (int k = k0; k < P.jt_ptr[i + 1]; ++k) {
-            double h = jval(v, P.nnzg, P.jt_vidx[k]);
-            int r = P.jt_row[k];
-            acc += h * t[r];
-            mag += fabs(h) * ta[r];
+        for (int k = k0; k < k1; k += 4) {
+            int ai[4], ri[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = k + u < k1;
+                ai[u] = ok ? P.jt_vidx[k + u] : 0;
+                ri[u] = ok ? P.jt_row[k + u] : 0;
+            }
+            double hv[4], tv[4], tav[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = k + u < k1;
+                hv[u] = ok ? jval(v, P.nnzg, ai[u]) : 0.0;
+                tv[u] = ok ? t[ri[u]] : 0.0;
+                tav[u] = ok ? ta[ri[u]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k + u < k1) {
+                    acc += hv[u] * tv[u];
+                    mag += fabs(hv[u]) * tav[u];
+                }
         }
         const double bi = rhs1 ? rhs1[i] : 0.0;
         double res = bi - acc;
