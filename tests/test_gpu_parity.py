@@ -170,6 +170,32 @@ def test_not_spd_status():
     assert s.info()["failed_column"] >= 0
 
 
+@pytest.mark.parametrize("shift", [1e-2, 1.0, 1e3])
+def test_not_spd_column_matches_host_run_large_fronts(shift):
+    """A matrix that is not positive definite (W's diagonal lowered), factorized
+    with most fronts forced onto the large-front path (panel and trailing-update
+    launches): the device reports the same outcome and the same first failing
+    column as the host run of the same plan (a failure in a later front can only
+    raise the column, and the device keeps the smallest)."""
+    p = workloads.network_flow(2000, seed=5)
+    rows = np.repeat(np.arange(p.n), np.diff(p.w_ptr))
+    wv = p.w_val.copy()
+    wv[rows == p.w_idx] -= shift
+    q = workloads.KKTProblem(**{**p.__dict__, "w_val": wv})
+    print_case("not_spd_large_fronts", n=q.n, shift=shift)
+    s = Solver(q, "lifted", lds_front_max=32).bind(DEV)
+    assert s.info()["n_big_fronts"] > 0
+    s.factorize(*device_values(q, DEV, "lifted"))
+    st_dev, fc_dev = s.factor_status(), s.info()["failed_column"]
+    _, st, fc = s.host_factor_solve(q.w_val, q.g_val, q.h_val, q.sigma_x, q.sigma_s, 0.0, q.b)
+    print("device", st_dev, fc_dev, "host", st, fc, flush=True)
+    assert (st_dev == 0) == (st == 0), (st_dev, st)
+    assert (st != 0) == (shift >= 1.0)  # the two larger shifts make K indefinite
+    if st != 0:
+        assert st_dev == -3
+        assert fc_dev == fc, (fc_dev, fc)
+
+
 def test_edge_no_constraints_and_single_variable():
     # m_eq = m_ineq = 0 and n = 1
     for nx, ny in ((1, 1), (2, 1)):
